@@ -1,0 +1,172 @@
+/*
+ * msb.h -- multi-shift BiCGstab(l) for the overlap operator at nonzero
+ * chemical potential, on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the partial-fraction expansion (PFE)
+ *
+ *     f(A) b  ~  y = sum_s w_s (A + sigma_s)^{-1} b,          (Eq. 1.2)
+ *
+ * for A = a (gamma5 D_w(mu))^2 with one Krylov space for all shifts
+ * (shift invariance, Section 1), in the single-pass form and in the
+ * double-pass form of Section 2 (option 1 after Eq. 2.2; Section 5), and
+ * from it sign(H) b and the overlap operator D_ov = 1 + gamma5 sign(H)
+ * (Eq. 1.1).  D_w(mu) is the Wilson-Dirac operator with the chemical
+ * potential on the time links:
+ *
+ *   (D psi)(x) = (4+m) psi(x)
+ *     - 1/2 sum_nu b_nu(x)   (1-gamma_nu) e^{+mu d_nu4} U_nu(x)     psi(x+nu)
+ *     - 1/2 sum_nu b_nu(x-nu)(1+gamma_nu) e^{-mu d_nu4} U_nu(x-nu)^+ psi(x-nu)
+ *
+ * with b_4 = bc_t on the links from t = Lt-1 to t = 0 and 1 elsewhere, and
+ * chiral gamma matrices gamma_k = [[0,-i sigma_k],[i sigma_k,0]],
+ * gamma_4 = [[0,1],[1,0]], gamma5 = diag(1,1,-1,-1).
+ *
+ * Layouts (all complex numbers are interleaved (re, im) pairs of doubles,
+ * i.e. complex128):
+ *   site     s = x + Lx*(y + Ly*(z + Lz*t))
+ *   spinor   [nrhs][k][V], k = 3*spin + colour (12 per site)
+ *   links    [nu][a][b][V], nu = 0..3 for x, y, z, t; U_nu(x)_{ab}
+ *
+ * Ownership: every vector and link pointer is a DEVICE pointer owned by the
+ * caller; the library never keeps one after a call returns (links are copied
+ * into the context by msb_create).  The library owns its workspace (seed
+ * vectors, shift vectors, reduction partials, scalar state, the double-pass
+ * tape) and grows it on demand.  Host arrays (shifts, weights, info arrays)
+ * are read or written during the call only.
+ *
+ * Streams: every call is ordered on the context's stream (a hipStream_t given
+ * at creation or by msb_set_stream; NULL = the default stream).  Calls that
+ * fill msb_solve_info or host gradient arrays synchronise that stream before
+ * returning.
+ *
+ * Errors: every entry point returns an msb_status; no C++ exception crosses
+ * the boundary.  Invalid arguments are rejected with MSB_ERR_ARG before any
+ * work is queued.  msb_last_error() gives the calling thread's message for
+ * its last non-zero status.
+ */
+#ifndef MSB_H
+#define MSB_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MSB_OK = 0,
+    MSB_ERR_ARG = 1,        /* invalid argument; nothing was launched          */
+    MSB_ERR_HIP = 2,        /* a HIP runtime call failed                        */
+    MSB_ERR_OOM = 3,        /* workspace allocation failed                      */
+    MSB_NOT_CONVERGED = 4,  /* max_outer reached; y and info are still filled   */
+    MSB_BREAKDOWN = 5       /* BiCG/MR/shift breakdown; partial y is returned   */
+} msb_status;
+
+/* flags for wilson_apply */
+#define MSB_G5_LEFT   1     /* out = gamma5 D in                                */
+#define MSB_NEG_MU    2     /* use -mu instead of mu                            */
+#define MSB_DAGGER    4     /* out = D^+ in  (= gamma5 D(-mu) gamma5 in)        */
+/* flags for the solvers */
+#define MSB_MIXED     8     /* FP32 stencil / vectors, FP64 reductions + scalars */
+#define MSB_PERSISTENT 16   /* whole solve in one cooperative launch (batched)   */
+#define MSB_OVERLAP   32    /* pfe_sign_apply: out = b + gamma5 sign(H) b        */
+#define MSB_ADJOINT   64    /* solve with A^+ = A(-mu) (used by the backward)    */
+
+typedef struct msb_ctx msb_ctx;
+
+typedef struct {
+    int dims[4];            /* Lx, Ly, Lz, Lt (each >= 1)                        */
+    double mass;            /* Wilson mass m: diagonal term 4 + m                */
+    double mu;              /* chemical potential (e^{+mu} on forward t hops)    */
+    int bc_t;               /* time boundary: -1 antiperiodic, +1 periodic       */
+} msb_lattice;
+
+/* Solve report.  All pointer members are optional caller-owned HOST arrays of
+ * length nrhs * n_shift (index rhs * n_shift + s, shifts in caller order). */
+typedef struct {
+    int status;             /* the call's msb_status                             */
+    int outer_iters;        /* max over right-hand sides of outer iterations M   */
+    int bicg_steps;         /* max over RHS of BiCG steps (2 Mv each)           */
+    long long mv_count;     /* total applications of A + sigma_0 (all RHS)       */
+    long long dot_count;    /* inner products in the paper's counting            */
+    long long axpy_count;   /* vector updates (y <- a x + y) actually executed    */
+    int reliable_updates;   /* mixed precision: FP64 residual recomputations     */
+    double bytes_model;     /* algorithmic HBM bytes of the call                 */
+    int *shift_iters;       /* out: M_s, outer iterations until shift s froze    */
+    double *shift_resid;    /* out: final collinear residual estimate            */
+    double *shift_true_resid; /* out (pass 1 only): ||b-(A+sigma_s)x_s||/||b||   */
+    const int *force_iters; /* in, test hook: freeze shift s after exactly
+                               force_iters[...] outer iterations (no early exit) */
+} msb_solve_info;
+
+/* Create a context on the current HIP device.  links: device pointer to
+ * [4][3][3][V] complex128 gauge links (copied; FP64 and FP32 internal copies).
+ * stream: hipStream_t (may be NULL). */
+int msb_create(msb_ctx **ctx, const msb_lattice *lat, const void *links,
+               void *stream);
+void msb_destroy(msb_ctx *ctx);
+int msb_set_stream(msb_ctx *ctx, void *stream);
+const char *msb_last_error(void);
+
+/* Neuberger PFE of x^{-1/2} (Fig. 1 caption): theta_s = pi (s - 1/2)/(2n),
+ * sigma_s = tan^2 theta_s, w_s = 1/(n cos^2 theta_s), s = 1..n.  Host arrays
+ * of length n. */
+int msb_neuberger_pfe(int n, double *sigma, double *weight);
+
+/* Power-iteration estimate of lambda_max(D^+ D) from the device start vector
+ * start [12][V] complex128: Rayleigh quotient after iters normalised steps.
+ * The scale convention of the solvers is a_scale = 1 / (1.01 * rho). */
+int msb_spectral_radius(msb_ctx *ctx, const void *start, int iters, double *rho);
+
+/* out = D_w(mu) in (flags MSB_G5_LEFT, MSB_NEG_MU, MSB_DAGGER, MSB_MIXED).
+ * The operator the paper names in Section 1.  in, out: device
+ * [nrhs][12][V] complex128, must not overlap. */
+int wilson_apply(msb_ctx *ctx, const void *in, void *out, int nrhs, int flags);
+
+/* y = sum_s w_s (A + sigma_s)^{-1} b by multi-shift BiCGstab(l)
+ * (Eq. 1.2, Section 2), A = a_scale (gamma5 D_w(mu))^2, tolerance tol on each
+ * shift's relative residual.
+ *   shifts, weights  host [n_sets][n_shift] doubles; n_sets = nrhs when
+ *                    per_rhs_shift_sets = 1, else 1.  Shifts must be >= 0
+ *                    after subtracting the smallest (any order).
+ *   l                degree of the MR polynomial, 1..8
+ *   pass             1: single-pass (N_s (l+1) shift vectors);
+ *                    2: double-pass (no shift vectors, 4 M l Mv)
+ *   flags            MSB_MIXED, MSB_PERSISTENT, MSB_ADJOINT
+ *   b                device [nrhs][12][V] complex128
+ *   y                device [nrhs][12][V] complex128 (written)
+ *   x_shifts         device [nrhs][n_shift][12][V] complex128 or NULL
+ *                    (pass 1 only): the individual solutions x_s
+ *   info             may be NULL.
+ * Returns MSB_NOT_CONVERGED / MSB_BREAKDOWN with y filled. */
+int mshift_bicgstabl(msb_ctx *ctx, double a_scale, int n_shift,
+                     const double *shifts, const double *weights,
+                     int per_rhs_shift_sets, int l, double tol, int max_outer,
+                     int pass, int flags, int nrhs, const void *b, void *y,
+                     void *x_shifts, msb_solve_info *info);
+
+/* out = sign(H) b = sqrt(a_scale) H y, y the PFE solve above (Section 1,
+ * sign z = z / sqrt(z^2)); with MSB_OVERLAP out = b + gamma5 sign(H) b, the
+ * overlap operator of Eq. 1.1.  Arguments as for mshift_bicgstabl. */
+int pfe_sign_apply(msb_ctx *ctx, double a_scale, int n_shift,
+                   const double *shifts, const double *weights, int l,
+                   double tol, int max_outer, int pass, int flags, int nrhs,
+                   const void *b, void *out, msb_solve_info *info);
+
+/* Gradients of the real loss L = Re <eta, y> with y = f(A) b (mode 0) or
+ * y = sign(H) b (mode 1), in the convention dL/dRe + i dL/dIm:
+ *   grad_b      device [nrhs][12][V] complex128 (written)
+ *   grad_w      host [n_shift] (written; summed over RHS)
+ *   grad_sigma  host [n_shift] (written; summed over RHS)
+ *   grad_links  device [4][3][3][V] complex128 (ADDED to)
+ * Uses adjoint multi-shift solves with A^+ = A(-mu) and a link-force kernel;
+ * a_scale is held constant.  Not in the paper: the backward of Eq. 1.2. */
+int pfe_sign_backward(msb_ctx *ctx, double a_scale, int n_shift,
+                      const double *shifts, const double *weights, int l,
+                      double tol, int max_outer, int flags, int nrhs,
+                      const void *b, const void *eta, int mode, void *grad_b,
+                      double *grad_w, double *grad_sigma, void *grad_links,
+                      msb_solve_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSB_H */

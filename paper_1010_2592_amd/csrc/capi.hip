@@ -1,0 +1,224 @@
+// The extern "C" boundary of libmsb: argument validation and marshalling
+// only; all arithmetic happens in the kernels behind msb::solve_mshift and
+// friends.  No C++ exception crosses this boundary.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "msb.h"
+#include "ctx.h"
+
+namespace msb {
+const char *last_error_msg();
+}
+
+struct msb_ctx {
+    msb::Ctx c;
+};
+
+namespace {
+
+using msb::set_error;
+
+int arg_error(const std::string &m) { return set_error(MSB_ERR_ARG, m); }
+
+bool finite_array(const double *p, long n) {
+    for (long i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// Common validation and expansion of the solver arguments.
+int make_params(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts, const double *weights,
+                int per_rhs, int l, double tol, int max_outer, int pass, int flags, int nrhs,
+                const char *who, msb::SolveParams *P) {
+    const std::string w(who);
+    if (!ctx) return arg_error(w + ": null context");
+    if (!(a_scale > 0.0) || !std::isfinite(a_scale)) return arg_error(w + ": a_scale must be finite and > 0");
+    if (n_shift < 1 || n_shift > msb::NSMAX)
+        return arg_error(w + ": n_shift must be in 1.." + std::to_string(msb::NSMAX));
+    if (!shifts || !weights) return arg_error(w + ": shifts and weights are required");
+    if (per_rhs != 0 && per_rhs != 1) return arg_error(w + ": per_rhs_shift_sets must be 0 or 1");
+    if (l < 1 || l > msb::LMAX) return arg_error(w + ": l must be in 1.." + std::to_string(msb::LMAX));
+    if (!(tol > 0.0) || !std::isfinite(tol)) return arg_error(w + ": tol must be finite and > 0");
+    if (max_outer < 1 || (long)max_outer * l > (1L << 24)) return arg_error(w + ": max_outer out of range");
+    if (pass != 1 && pass != 2) return arg_error(w + ": pass must be 1 or 2");
+    if (nrhs < 1 || nrhs > 4096) return arg_error(w + ": nrhs must be in 1..4096");
+    if (flags & ~(MSB_MIXED | MSB_PERSISTENT | MSB_ADJOINT | MSB_OVERLAP))
+        return arg_error(w + ": unknown flag bits");
+    if (flags & MSB_PERSISTENT) return arg_error(w + ": MSB_PERSISTENT is not available in this build");
+    const long nsets = per_rhs ? nrhs : 1;
+    if (!finite_array(shifts, nsets * n_shift) || !finite_array(weights, nsets * n_shift))
+        return arg_error(w + ": shifts and weights must be finite");
+    P->a_scale = a_scale;
+    P->n_shift = n_shift;
+    P->l = l;
+    P->tol = tol;
+    P->max_outer = max_outer;
+    P->pass = pass;
+    P->mixed = (flags & MSB_MIXED) != 0;
+    P->neg_mu = (flags & MSB_ADJOINT) != 0;
+    P->nrhs = nrhs;
+    P->shifts.resize((size_t)nrhs * n_shift);
+    P->weights.resize((size_t)nrhs * n_shift);
+    for (int r = 0; r < nrhs; ++r) {
+        const long src = per_rhs ? (long)r * n_shift : 0;
+        for (int s = 0; s < n_shift; ++s) {
+            P->shifts[(size_t)r * n_shift + s] = shifts[src + s];
+            P->weights[(size_t)r * n_shift + s] = weights[src + s];
+        }
+    }
+    return MSB_OK;
+}
+
+void fill_info(msb_solve_info *info, const msb::SolveReport &R, int nrhs, int n_shift, int status) {
+    if (!info) return;
+    info->status = status;
+    info->outer_iters = R.outer_max;
+    info->bicg_steps = R.steps_max;
+    info->mv_count = R.mv;
+    info->dot_count = R.dots;
+    info->axpy_count = R.axpys;
+    info->reliable_updates = R.reliable;
+    info->bytes_model = R.bytes_model;
+    const size_t m = (size_t)nrhs * n_shift;
+    if (info->shift_iters && R.shift_iters.size() == m)
+        std::memcpy(info->shift_iters, R.shift_iters.data(), m * sizeof(int));
+    if (info->shift_resid && R.shift_resid.size() == m)
+        std::memcpy(info->shift_resid, R.shift_resid.data(), m * sizeof(double));
+    if (info->shift_true_resid && R.shift_true_resid.size() == m)
+        std::memcpy(info->shift_true_resid, R.shift_true_resid.data(), m * sizeof(double));
+}
+
+int finish(int rc, const msb::SolveReport &R, msb_solve_info *info, int nrhs, int n_shift) {
+    if (rc != MSB_OK) {
+        if (info) info->status = rc;
+        return rc;
+    }
+    int st = R.status;
+    if (st == MSB_ERR_ARG) set_error(MSB_ERR_ARG, "right-hand side with a non-finite norm");
+    else if (st == MSB_NOT_CONVERGED) set_error(st, "max_outer reached before every shift converged");
+    else if (st == MSB_BREAKDOWN) set_error(st, "breakdown of the BiCG, MR or shift recurrence");
+    fill_info(info, R, nrhs, n_shift, st);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *msb_last_error(void) { return msb::last_error_msg(); }
+
+int msb_create(msb_ctx **out, const msb_lattice *lat, const void *links, void *stream) {
+    if (!out || !lat || !links) return arg_error("msb_create: null argument");
+    *out = nullptr;
+    long V = 1;
+    for (int d = 0; d < 4; ++d) {
+        if (lat->dims[d] < 1) return arg_error("msb_create: dims must be >= 1");
+        V *= lat->dims[d];
+    }
+    if (V > (1L << 26)) return arg_error("msb_create: volume too large (max 2^26 sites)");
+    if (lat->bc_t != 1 && lat->bc_t != -1) return arg_error("msb_create: bc_t must be +1 or -1");
+    if (!std::isfinite(lat->mass) || !std::isfinite(lat->mu)) return arg_error("msb_create: mass and mu must be finite");
+    msb_ctx *x = new (std::nothrow) msb_ctx;
+    if (!x) return set_error(MSB_ERR_OOM, "msb_create: out of host memory");
+    int rc = msb::ctx_create(&x->c, lat->dims, lat->mass, lat->mu, lat->bc_t, links, (hipStream_t)stream);
+    if (rc) {
+        msb::ctx_destroy(&x->c);
+        delete x;
+        return rc;
+    }
+    *out = x;
+    return MSB_OK;
+}
+
+void msb_destroy(msb_ctx *ctx) {
+    if (!ctx) return;
+    msb::ctx_destroy(&ctx->c);
+    delete ctx;
+}
+
+int msb_set_stream(msb_ctx *ctx, void *stream) {
+    if (!ctx) return arg_error("msb_set_stream: null context");
+    ctx->c.stream = (hipStream_t)stream;
+    return MSB_OK;
+}
+
+int msb_neuberger_pfe(int n, double *sigma, double *weight) {
+    if (n < 1 || !sigma || !weight) return arg_error("msb_neuberger_pfe: need n >= 1 and output arrays");
+    const double pi = 3.14159265358979323846;
+    for (int s = 1; s <= n; ++s) {
+        const double th = pi * (s - 0.5) / (2.0 * n);
+        const double t = std::tan(th), c = std::cos(th);
+        sigma[s - 1] = t * t;
+        weight[s - 1] = 1.0 / (n * c * c);
+    }
+    return MSB_OK;
+}
+
+int msb_spectral_radius(msb_ctx *ctx, const void *start, int iters, double *rho) {
+    if (!ctx || !start || !rho) return arg_error("msb_spectral_radius: null argument");
+    if (iters < 1) return arg_error("msb_spectral_radius: iters must be >= 1");
+    return msb::spectral_radius(&ctx->c, (const double2 *)start, iters, rho);
+}
+
+int wilson_apply(msb_ctx *ctx, const void *in, void *out, int nrhs, int flags) {
+    if (!ctx || !in || !out) return arg_error("wilson_apply: null argument");
+    if (in == out) return arg_error("wilson_apply: in and out must not overlap");
+    if (nrhs < 1) return arg_error("wilson_apply: nrhs must be >= 1");
+    if (flags & ~(MSB_G5_LEFT | MSB_NEG_MU | MSB_DAGGER | MSB_MIXED)) return arg_error("wilson_apply: unknown flag bits");
+    return msb::apply_wilson(&ctx->c, (const double2 *)in, (double2 *)out, nrhs, flags);
+}
+
+int mshift_bicgstabl(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
+                     const double *weights, int per_rhs_shift_sets, int l, double tol, int max_outer,
+                     int pass, int flags, int nrhs, const void *b, void *y, void *x_shifts,
+                     msb_solve_info *info) {
+    msb::SolveParams P;
+    int rc = make_params(ctx, a_scale, n_shift, shifts, weights, per_rhs_shift_sets, l, tol, max_outer,
+                         pass, flags & ~MSB_OVERLAP, nrhs, "mshift_bicgstabl", &P);
+    if (rc) return rc;
+    if (!b || !y) return arg_error("mshift_bicgstabl: b and y are required");
+    if (x_shifts && pass != 1) return arg_error("mshift_bicgstabl: x_shifts needs pass = 1");
+    if (flags & MSB_OVERLAP) return arg_error("mshift_bicgstabl: MSB_OVERLAP applies to pfe_sign_apply");
+    P.force_iters = info ? info->force_iters : nullptr;
+    msb::SolveReport R;
+    const bool want_true = info && info->shift_true_resid && pass == 1;
+    rc = msb::solve_mshift(&ctx->c, P, (const double2 *)b, (double2 *)y, (double2 *)x_shifts, want_true, &R);
+    return finish(rc, R, info, nrhs, n_shift);
+}
+
+int pfe_sign_apply(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
+                   const double *weights, int l, double tol, int max_outer, int pass, int flags,
+                   int nrhs, const void *b, void *out, msb_solve_info *info) {
+    msb::SolveParams P;
+    int rc = make_params(ctx, a_scale, n_shift, shifts, weights, 0, l, tol, max_outer, pass, flags, nrhs,
+                         "pfe_sign_apply", &P);
+    if (rc) return rc;
+    if (!b || !out) return arg_error("pfe_sign_apply: b and out are required");
+    P.force_iters = info ? info->force_iters : nullptr;
+    msb::SolveReport R;
+    rc = msb::sign_apply(&ctx->c, P, (const double2 *)b, (double2 *)out, (flags & MSB_OVERLAP) != 0, &R);
+    return finish(rc, R, info, nrhs, n_shift);
+}
+
+int pfe_sign_backward(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
+                      const double *weights, int l, double tol, int max_outer, int flags, int nrhs,
+                      const void *b, const void *eta, int mode, void *grad_b, double *grad_w,
+                      double *grad_sigma, void *grad_links, msb_solve_info *info) {
+    msb::SolveParams P;
+    int rc = make_params(ctx, a_scale, n_shift, shifts, weights, 0, l, tol, max_outer, 1, flags, nrhs,
+                         "pfe_sign_backward", &P);
+    if (rc) return rc;
+    if (!b || !eta || !grad_b || !grad_w || !grad_sigma || !grad_links)
+        return arg_error("pfe_sign_backward: b, eta and every gradient output are required");
+    if (mode != 0 && mode != 1) return arg_error("pfe_sign_backward: mode must be 0 (f(A)b) or 1 (sign)");
+    P.force_iters = info ? info->force_iters : nullptr;
+    msb::SolveReport R;
+    rc = msb::sign_backward(&ctx->c, P, (const double2 *)b, (const double2 *)eta, mode, (double2 *)grad_b,
+                            grad_w, grad_sigma, (double2 *)grad_links, &R);
+    return finish(rc, R, info, nrhs, n_shift);
+}
+
+}  // extern "C"

@@ -1,0 +1,226 @@
+// Internal definitions shared by the HIP sources of libmsb.
+//
+// Complex numbers are interleaved (re, im) pairs: double2 in FP64, float2 in
+// FP32.  Spinors are stored [rhs][k = 3*spin + colour][site] so that a
+// wavefront touching 64 consecutive sites issues one coalesced 64 x 16 B (or
+// 64 x 8 B) access per component; links are [nu][a][b][site].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace msb {
+
+constexpr int LMAX = 8;          // largest MR degree l
+constexpr int NSMAX = 64;        // largest number of shifts per right-hand side
+constexpr int BLOCK = 256;       // threads per block of every vector kernel
+constexpr int NBMAX = 2048;      // largest number of blocks per RHS in a reduction
+constexpr int PMAX = 2 * (LMAX + 1) * (LMAX + 2) / 2;  // doubles per partial row
+constexpr double BREAK_REL = 1e-14;
+constexpr double CHOL_REL = 1e-14;
+constexpr double ZETA_MIN = 1e-300;
+
+enum Status { S_OK = 0, S_ERR_ARG = 1, S_ERR_HIP = 2, S_ERR_OOM = 3,
+              S_NOT_CONVERGED = 4, S_BREAKDOWN = 5 };
+
+template <typename T> struct cx;
+template <> struct cx<double> { using t = double2; };
+template <> struct cx<float> { using t = float2; };
+template <typename T> using C = typename cx<T>::t;
+
+template <typename T> __host__ __device__ inline C<T> mk(T re, T im) { C<T> z; z.x = re; z.y = im; return z; }
+
+// complex helpers (templated on the complex type directly)
+template <typename Z> __host__ __device__ inline Z cadd(Z a, Z b) { Z r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename Z> __host__ __device__ inline Z csub(Z a, Z b) { Z r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename Z> __host__ __device__ inline Z cmul(Z a, Z b) {
+    Z r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+// conj(a) * b
+template <typename Z> __host__ __device__ inline Z cmulc(Z a, Z b) {
+    Z r; r.x = a.x * b.x + a.y * b.y; r.y = a.x * b.y - a.y * b.x; return r;
+}
+template <typename Z, typename R> __host__ __device__ inline Z cscale(Z a, R s) { Z r; r.x = a.x * s; r.y = a.y * s; return r; }
+template <typename Z> __host__ __device__ inline Z ctimes_i(Z a) { Z r; r.x = -a.y; r.y = a.x; return r; }
+template <typename Z> __host__ __device__ inline Z ctimes_mi(Z a) { Z r; r.x = a.y; r.y = -a.x; return r; }
+template <typename Z> __host__ __device__ inline Z cneg(Z a) { Z r; r.x = -a.x; r.y = -a.y; return r; }
+template <typename Z> __host__ __device__ inline Z cconj(Z a) { Z r; r.x = a.x; r.y = -a.y; return r; }
+// a + s * b   (s complex)
+template <typename Z> __host__ __device__ inline Z cfma(Z s, Z b, Z a) {
+    Z r; r.x = a.x + s.x * b.x - s.y * b.y; r.y = a.y + s.x * b.y + s.y * b.x; return r;
+}
+__host__ __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline double cabsd(double2 a) { return sqrt(a.x * a.x + a.y * a.y); }
+__host__ __device__ inline double2 cdiv(double2 a, double2 b) {
+    // Smith's algorithm: scale by the larger component of b
+    double2 r;
+    if (fabs(b.x) >= fabs(b.y)) {
+        double t = b.y / b.x, d = b.x + b.y * t;
+        r.x = (a.x + a.y * t) / d;
+        r.y = (a.y - a.x * t) / d;
+    } else {
+        double t = b.x / b.y, d = b.x * t + b.y;
+        r.x = (a.x * t + a.y) / d;
+        r.y = (a.y * t - a.x) / d;
+    }
+    return r;
+}
+__host__ __device__ inline double2 d2(double re, double im) { double2 z; z.x = re; z.y = im; return z; }
+__host__ __device__ inline bool cfinite(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+
+template <typename T> __device__ inline C<T> to_c(double2 z) { return mk<T>((T)z.x, (T)z.y); }
+
+// ---------------------------------------------------------------------------
+// Deterministic block reduction (BLOCK = 256 threads = 4 wavefronts of 64).
+// Values are reduced by a fixed shuffle tree inside each wavefront, then the
+// four wavefront sums are added in order.  Thread k < NV writes value k to
+// out[k * stride].
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ inline void block_reduce_store(double (&v)[NV], double *out, int stride) {
+    __shared__ double sh[NV][BLOCK / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) sh[k][wave] = x;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < NV; k += BLOCK) {
+        double s = sh[k][0];
+#pragma unroll
+        for (int w = 1; w < BLOCK / 64; ++w) s += sh[k][w];
+        out[(size_t)k * stride] = s;
+    }
+}
+
+// Sum of p[0..n) by all BLOCK threads of one block, returned to every thread.
+__device__ inline double block_sum(const double *p, int n) {
+    __shared__ double sh[BLOCK / 64];
+    __shared__ double result;
+    double x = 0.0;
+    for (int i = threadIdx.x; i < n; i += BLOCK) x += p[i];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    __syncthreads();
+    if (lane == 0) sh[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = sh[0];
+        for (int w = 1; w < BLOCK / 64; ++w) s += sh[w];
+        result = s;
+    }
+    __syncthreads();
+    return result;
+}
+
+// ---------------------------------------------------------------------------
+// Device-resident solver state (one per right-hand side) and the per-step
+// coefficient tables that the scalar kernels write and the vector kernels
+// read.
+// ---------------------------------------------------------------------------
+struct SeedState {
+    double2 rho0, alpha, omega, beta, rho1;
+    double2 gam[LMAX];
+    double bnorm, rtnorm, rnorm0, rnorm_j;
+    double tol;
+    int run;        // right-hand side still iterating
+    int bicg_on;    // BiCG steps continue in this outer iteration
+    int l_eff;      // BiCG steps completed in this outer iteration
+    int l_mr;       // MR terms applied in this outer iteration
+    int broken, exhausted, forced, partial;
+    int m, n;       // outer iteration, global BiCG step
+    int max_outer, max_steps;
+    int status;
+    int nact;       // active shifts
+    int nshift;
+    int mv, dots, axpys, reliable;
+    int act[NSMAX];
+};
+
+struct ShiftState {
+    double2 zeta, zeta_prev, pi_prev, psi;
+    double sp;      // sigma' = sigma_s - sigma_0
+    double res;     // last collinear residual estimate
+    int active, iters, broken, force;
+};
+
+struct StepCoef {   // one active shift, one BiCG step
+    double2 kap, beta_s, alpha_s, a1, a2;
+    double sp;
+    int s, live;
+};
+
+struct MRCoef {     // one active shift, one MR step
+    double2 kc[LMAX];   // kappa * c_k
+    double2 inv_q;
+    int s, live;
+};
+
+// Pass-1 record of the seed (read back by the host for the double-pass sweep)
+struct TapeStep {
+    double2 beta, alpha;
+    int flag;       // 0: no step, 1: u-step only (gamma breakdown), 2: full step
+    int pad;
+};
+
+// Pass-1 record of one outer iteration
+struct TapeOuter {
+    int l_eff;      // full BiCG steps
+    int l_mr;       // MR terms applied (0: no MR)
+    int partial;    // a u-step only (gamma breakdown) follows the full steps
+    int exhausted;  // Krylov space exhausted: the iteration ended early
+};
+
+// Pass-2 program entry (written by the host after the sweep)
+struct ReplayStep {
+    double2 beta, alpha, cu, cr;   // cu, cr: coefficients of the two Mv outputs
+    int flag, pad0, pad1, pad2;    // flag: 0 none, 1 u-step only, 2 full step
+};
+
+struct ReplayOuter {
+    double2 gam[LMAX];
+    int lm, pad0, pad1, pad2;
+};
+
+struct Geom {
+    int Lx, Ly, Lz, Lt, V;
+};
+
+}  // namespace msb
+
+namespace msb {
+
+// Launch gate: a kernel instance for right-hand side `rhs` does work only when
+// (seed == nullptr || seed[rhs].run && (!need_bicg || seed[rhs].bicg_on)) and
+// (flag == nullptr || flag[rhs * flag_stride] >= need).  The decision is
+// uniform across a block (one block row per right-hand side).
+struct Gate {
+    const SeedState *seed = nullptr;
+    int need_bicg = 0;
+    const int *flag = nullptr;
+    long flag_stride = 0;
+    int need = 0;
+};
+
+__device__ inline bool gate_open(const Gate &g, int rhs) {
+    if (g.seed) {
+        const SeedState &s = g.seed[rhs];
+        if (!s.run) return false;
+        if (g.need_bicg && !s.bicg_on) return false;
+    }
+    if (g.flag && g.flag[(long)rhs * g.flag_stride] < g.need) return false;
+    return true;
+}
+
+inline int nblocks_for(long n) {
+    long b = (n + BLOCK - 1) / BLOCK;
+    if (b < 1) b = 1;
+    return (int)(b > NBMAX ? NBMAX : b);
+}
+
+}  // namespace msb

@@ -1,0 +1,82 @@
+// Library context and host-side solver entry points (internal).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+
+namespace msb {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Ctx {
+    Geom g{};
+    double mass = 0, mu = 0;
+    int bc_t = -1;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    double2 *U64 = nullptr;    // links, FP64 copy [4][3][3][V]
+    float2 *U32 = nullptr;     // links, FP32 copy
+    // workspace, grown on demand and kept for later calls
+    DevBuf ws_R, ws_U, ws_tmp, ws_W, ws_X, ws_rt, ws_b, ws_y, ws_part, ws_seed, ws_shift, ws_sc,
+        ws_mc, ws_tape, ws_tape_gam, ws_tape_outer, ws_replay, ws_replay_outer, ws_wts, ws_sig0,
+        ws_cb, ws_aux1, ws_aux2, ws_aux3, ws_aux4;
+    void *host_pinned = nullptr;
+    size_t host_pinned_bytes = 0;
+};
+
+// All solver parameters of one call (shifts and weights already expanded to
+// one set per right-hand side).
+struct SolveParams {
+    double a_scale = 1;
+    int n_shift = 0;
+    std::vector<double> shifts;    // [nrhs][n_shift]
+    std::vector<double> weights;   // [nrhs][n_shift]
+    int l = 1;
+    double tol = 1e-8;
+    int max_outer = 1000;
+    int pass = 1;
+    bool mixed = false;
+    bool neg_mu = false;
+    int nrhs = 1;
+    const int *force_iters = nullptr;   // [nrhs][n_shift] or null
+};
+
+struct SolveReport {
+    int status = 0;
+    int outer_max = 0, steps_max = 0;
+    long long mv = 0, dots = 0, axpys = 0;
+    int reliable = 0;
+    double bytes_model = 0;
+    std::vector<int> shift_iters;
+    std::vector<double> shift_resid;
+    std::vector<double> shift_true_resid;
+    std::vector<int> rhs_outer;
+};
+
+// status-returning helpers; on failure they record a message
+int set_error(int status, const std::string &msg);
+int hip_check(hipError_t e, const char *what);
+int ensure(DevBuf &b, size_t bytes);
+
+int ctx_create(Ctx *c, const int dims[4], double mass, double mu, int bc_t, const void *links,
+               hipStream_t stream);
+void ctx_destroy(Ctx *c);
+
+int apply_wilson(Ctx *c, const double2 *in, double2 *out, int nrhs, int flags);
+int spectral_radius(Ctx *c, const double2 *start, int iters, double *rho);
+int solve_mshift(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2 *x_shifts,
+                 bool want_true_resid, SolveReport *rep);
+int sign_apply(Ctx *c, const SolveParams &P, const double2 *b, double2 *out, bool overlap,
+               SolveReport *rep);
+int sign_backward(Ctx *c, const SolveParams &P, const double2 *b, const double2 *eta, int mode,
+                  double2 *grad_b, double *grad_w, double *grad_sigma, double2 *grad_links,
+                  SolveReport *rep);
+
+}  // namespace msb

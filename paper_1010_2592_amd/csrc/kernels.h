@@ -1,0 +1,120 @@
+// Kernel argument blocks and launchers of libmsb (internal).
+#pragma once
+
+#include "common.h"
+
+namespace msb {
+
+enum { EPI_PLAIN = 0, EPI_MV = 1, EPI_MV_Y = 2, EPI_SV = 3 };
+
+// A per-right-hand-side complex coefficient in device memory: the value for
+// rhs r is *(const double2 *)(p + r * stride).
+struct CoefRef {
+    const char *p = nullptr;
+    long stride = 0;
+};
+__device__ inline double2 ld(const CoefRef &c, int rhs) {
+    return *(const double2 *)(c.p + (long)rhs * c.stride);
+}
+
+template <typename T>
+struct DslashArgs {
+    const C<T> *in = nullptr;
+    C<T> *out = nullptr;
+    const C<T> *U = nullptr;   // [4][3][3][V]
+    Geom g{};
+    T diag = 0, ef = 1, eb = 1, bc = -1;
+    int g5out = 0;
+    T scale = 1, sigma0 = 0;
+    const double *sigma0_rhs = nullptr;  // if set: per-rhs sigma0 (overrides sigma0)
+    const C<T> *v = nullptr;   // EPI_MV*: + sigma0 * v
+    const C<T> *rt = nullptr;  // EPI_MV: partials of <rt, out>
+    double *part = nullptr;    // [rhs][PMAX][NBMAX]
+    CoefRef ycoef;             // EPI_MV_Y: coefficient of the Mv output
+    double2 *y = nullptr;      // EPI_MV_Y accumulator (always FP64)
+    Gate gate{};
+    // element strides between right-hand sides (0: 12 V)
+    long in_rs = 0, out_rs = 0, v_rs = 0, rt_rs = 0, y_rs = 0;
+};
+
+template <typename T>
+void launch_dslash(hipStream_t st, const DslashArgs<T> &a, int nrhs, int epi, bool g5in, int nblk);
+
+// ---- vector kernels ------------------------------------------------------
+template <typename T>
+struct VecArgs {
+    long n = 0;                 // elements (complex) per vector = 12 V
+    int l = 0;                  // MR degree (vectors R_0..R_l, U_0..U_l)
+    int nshift = 0;             // shifts per rhs in the shift arrays
+    C<T> *R = nullptr;          // [rhs][l+1][n]
+    C<T> *U = nullptr;          // [rhs][l+1][n]
+    C<T> *W = nullptr;          // [rhs][nshift][l+1][n]  (pass 1)
+    C<T> *X = nullptr;          // [rhs][nshift][n]       (pass 1)
+    const C<T> *rt = nullptr;   // [rhs][n] shadow residual
+    double *part = nullptr;
+    const SeedState *seed = nullptr;
+    const StepCoef *sc = nullptr;   // [rhs][NSMAX]
+    const MRCoef *mc = nullptr;     // [rhs][NSMAX]
+    CoefRef beta, alpha;
+    CoefRef gam;                // gamma_1 at gam, gamma_i at gam.p + (i-1)*16
+    int partials = 1;
+    Gate gate{};
+};
+
+template <typename T> void launch_seed_u(hipStream_t, const VecArgs<T> &, int j, int nrhs, int nblk);
+template <typename T> void launch_r_update(hipStream_t, const VecArgs<T> &, int j, bool shifts, int nrhs, int nblk);
+template <typename T> void launch_gram(hipStream_t, const VecArgs<T> &, int nrhs, int nblk);
+template <typename T> void launch_mr_update(hipStream_t, const VecArgs<T> &, bool shifts, int nrhs, int nblk);
+
+// small utility kernels
+template <typename T>
+void launch_convert_in(hipStream_t, C<T> *dst, const double2 *src, long n, long dst_stride,
+                       long src_stride, int nrhs);
+template <typename T>
+void launch_convert_out(hipStream_t, double2 *dst, const C<T> *src, long n, long dst_stride,
+                        long src_stride, int nrhs);
+template <typename T>
+void launch_zero(hipStream_t, C<T> *dst, long n, long stride, int nrhs);
+template <typename T>
+void launch_dot_partials(hipStream_t, const C<T> *x, const C<T> *y, long n, double *part, int nrhs,
+                         int nblk, Gate gate);
+template <typename T>
+void launch_diffnorm_partials(hipStream_t, const C<T> *x, const C<T> *y, long n, long sx, long sy,
+                              double *part, int nrhs, int nblk);
+// y[rhs] = sum_s w[rhs][s] X[rhs][s]   (X stride n per shift, nshift per rhs)
+template <typename T>
+void launch_ysum(hipStream_t, double2 *y, const C<T> *X, const double *w, long n, int nshift,
+                 int nrhs, int nblk);
+// y[rhs] = c[rhs] * b[rhs]
+void launch_yinit(hipStream_t, double2 *y, const double2 *b, const double2 *c, long n, int nrhs,
+                  int nblk);
+// out = b + gamma5 w   (overlap), or out = s * w
+void launch_overlap_out(hipStream_t, double2 *out, const double2 *b, const double2 *w, long V,
+                        int nrhs, int overlap, double s, int nblk);
+// vector axpy with a host scalar: y += a * x over n complex
+void launch_axpy_host(hipStream_t, double2 *y, const double2 *x, double2 a, long n, int nblk);
+
+// ---- scalar (single block per rhs) kernels --------------------------------
+struct ScalarArgs {
+    SeedState *seed = nullptr;
+    ShiftState *sh = nullptr;       // [rhs][NSMAX]
+    StepCoef *sc = nullptr;
+    MRCoef *mc = nullptr;
+    TapeStep *tape = nullptr;       // [rhs][max_steps]
+    double2 *tape_gam = nullptr;    // [rhs][max_outer][LMAX]
+    TapeOuter *tape_outer = nullptr;  // [rhs][max_outer]
+    const double *part = nullptr;
+    int nblk = 0;                   // blocks that wrote the partials consumed
+    int nblk2 = 0;                  // blocks of the second partial source
+    int l = 0;
+    int j = 0;
+    int record = 0;                 // record the tape (double-pass)
+};
+
+void launch_sc_init(hipStream_t, const ScalarArgs &, int nrhs);
+void launch_sc_beta(hipStream_t, const ScalarArgs &, int nrhs);
+void launch_sc_alpha(hipStream_t, const ScalarArgs &, int nrhs);
+void launch_sc_mr(hipStream_t, const ScalarArgs &, int nrhs);
+void launch_sc_conv(hipStream_t, const ScalarArgs &, int nrhs);
+
+}  // namespace msb

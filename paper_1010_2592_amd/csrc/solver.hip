@@ -1,0 +1,810 @@
+// Host orchestration of multi-shift BiCGstab(l) on one GPU.
+//
+// Single-pass (pass = 1): the seed iteration and every shifted system advance
+// together; the shift vectors u^s_0..u^s_l, x^s live in HBM and are updated by
+// the fused r_update / mr_update kernels (Section 2: N_s (l+1) extra vectors,
+// sum_s M_s l (0.5 l + 4.5) extra axpys).
+//
+// Double-pass (pass = 2, Section 2 option 1 after Eq. 2.2, Section 5): pass 1
+// runs the seed and the shifts' scalar recurrences only and records the seed's
+// scalars (beta_n, alpha_n, the MR coefficients) and each shift's M_s.  The
+// single-pass program that would form y = sum_s w_s x^s is linear in its
+// sources -- b and the 2 M l Mv outputs v_t -- with coefficients fixed by
+// those scalars, so one backward sweep over the recorded program (scalar work
+// on the host, O(N_s M l^2)) gives y = c_b b + sum_t c_t v_t.  Pass 2 replays
+// the seed from b with the recorded scalars (no inner products) and adds
+// c_t v_t in the epilogue of the stencil that produces v_t.  The sweep reaches
+// the same y as the paper's closed-form coefficients (A_mj ... G_mj, x_BiCG)
+// in a different bookkeeping; no shift vector is ever stored.
+//
+// Every inner-iteration decision is taken on the device (scalar kernels), so
+// the host synchronises once per outer iteration to learn whether any
+// right-hand side is still running.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+
+namespace msb {
+
+static thread_local std::string g_err;
+const char *last_error_msg() { return g_err.c_str(); }
+
+int set_error(int status, const std::string &msg) {
+    g_err = msg;
+    return status;
+}
+
+int hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return 0;
+    return set_error(S_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        int rc_ = hip_check((x), #x);              \
+        if (rc_) return rc_;                       \
+    } while (0)
+#define CHK(x)                                     \
+    do {                                           \
+        int rc_ = (x);                             \
+        if (rc_) return rc_;                       \
+    } while (0)
+
+int ensure(DevBuf &b, size_t bytes) {
+    if (bytes < 256) bytes = 256;
+    if (b.bytes >= bytes) return 0;
+    if (b.p) {
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(S_ERR_OOM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    b.bytes = bytes;
+    return 0;
+}
+
+static int ensure_host(Ctx *c, size_t bytes) {
+    if (c->host_pinned_bytes >= bytes) return 0;
+    if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    c->host_pinned = nullptr;
+    c->host_pinned_bytes = 0;
+    HIPCHK(hipHostMalloc(&c->host_pinned, bytes, hipHostMallocDefault));
+    c->host_pinned_bytes = bytes;
+    return 0;
+}
+
+template <typename T> static const C<T> *links(const Ctx *c);
+template <> const C<double> *links<double>(const Ctx *c) { return c->U64; }
+template <> const C<float> *links<float>(const Ctx *c) { return c->U32; }
+
+template <typename T>
+static DslashArgs<T> ds_args(const Ctx *c, bool neg_mu, bool g5out) {
+    DslashArgs<T> a;
+    a.U = links<T>(c);
+    a.g = c->g;
+    a.diag = (T)(4.0 + c->mass);
+    const double mu = neg_mu ? -c->mu : c->mu;
+    a.ef = (T)std::exp(mu);
+    a.eb = (T)std::exp(-mu);
+    a.bc = (T)c->bc_t;
+    a.g5out = g5out ? 1 : 0;
+    return a;
+}
+
+int ctx_create(Ctx *c, const int dims[4], double mass, double mu, int bc_t, const void *lk,
+               hipStream_t st) {
+    c->g.Lx = dims[0];
+    c->g.Ly = dims[1];
+    c->g.Lz = dims[2];
+    c->g.Lt = dims[3];
+    c->g.V = dims[0] * dims[1] * dims[2] * dims[3];
+    c->mass = mass;
+    c->mu = mu;
+    c->bc_t = bc_t;
+    c->stream = st;
+    HIPCHK(hipGetDevice(&c->device));
+    const size_t nl = 36ull * c->g.V;
+    if (hipMalloc(&c->U64, nl * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&c->U32, nl * sizeof(float2)) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(S_ERR_OOM, "link allocation failed");
+    }
+    HIPCHK(hipMemcpyAsync(c->U64, lk, nl * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    launch_convert_in<float>(st, c->U32, c->U64, (long)nl, 0, 0, 1);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+}
+
+void ctx_destroy(Ctx *c) {
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    DevBuf *bufs[] = {&c->ws_R, &c->ws_U, &c->ws_tmp, &c->ws_W, &c->ws_X, &c->ws_rt, &c->ws_b,
+                      &c->ws_y, &c->ws_part, &c->ws_seed, &c->ws_shift, &c->ws_sc, &c->ws_mc,
+                      &c->ws_tape, &c->ws_tape_gam, &c->ws_tape_outer, &c->ws_replay,
+                      &c->ws_replay_outer, &c->ws_wts, &c->ws_sig0, &c->ws_cb, &c->ws_aux1,
+                      &c->ws_aux2, &c->ws_aux3, &c->ws_aux4};
+    for (DevBuf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (c->U64) (void)hipFree(c->U64);
+    if (c->U32) (void)hipFree(c->U32);
+    if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+}
+
+// ---------------------------------------------------------------------------
+// wilson_apply and the spectral-radius estimate
+// ---------------------------------------------------------------------------
+int apply_wilson(Ctx *c, const double2 *in, double2 *out, int nrhs, int flags) {
+    const bool g5l = flags & 1, negmu = flags & 2, dag = flags & 4, mixed = flags & 8;
+    // D^+ = gamma5 D(-mu) gamma5
+    const bool g5in = dag, g5out = g5l != dag, nm = negmu != dag;
+    const int V = c->g.V;
+    const long n = 12L * V;
+    const int nb = nblocks_for(V);
+    if (!mixed) {
+        DslashArgs<double> a = ds_args<double>(c, nm, g5out);
+        a.in = in;
+        a.out = out;
+        launch_dslash<double>(c->stream, a, nrhs, EPI_PLAIN, g5in, nb);
+    } else {
+        CHK(ensure(c->ws_aux1, (size_t)nrhs * n * sizeof(float2)));
+        CHK(ensure(c->ws_aux2, (size_t)nrhs * n * sizeof(float2)));
+        float2 *fi = (float2 *)c->ws_aux1.p, *fo = (float2 *)c->ws_aux2.p;
+        launch_convert_in<float>(c->stream, fi, in, n, n, n, nrhs);
+        DslashArgs<float> a = ds_args<float>(c, nm, g5out);
+        a.in = fi;
+        a.out = fo;
+        launch_dslash<float>(c->stream, a, nrhs, EPI_PLAIN, g5in, nb);
+        launch_convert_out<float>(c->stream, out, fo, n, n, n, nrhs);
+    }
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+// sum of partial row `slot` of rhs 0 on the host (fixed order)
+static double host_partial_sum(const double *row, int nblk) {
+    double s = 0.0;
+    for (int i = 0; i < nblk; ++i) s += row[i];
+    return s;
+}
+
+int spectral_radius(Ctx *c, const double2 *start, int iters, double *rho) {
+    const int V = c->g.V;
+    const long n = 12L * V;
+    const int nbd = nblocks_for(V), nbv = nblocks_for(n);
+    hipStream_t st = c->stream;
+    CHK(ensure(c->ws_aux1, n * sizeof(double2)));
+    CHK(ensure(c->ws_aux2, n * sizeof(double2)));
+    CHK(ensure(c->ws_aux3, n * sizeof(double2)));
+    CHK(ensure(c->ws_part, (size_t)PMAX * NBMAX * sizeof(double)));
+    CHK(ensure_host(c, 3 * NBMAX * sizeof(double)));
+    double2 *v = (double2 *)c->ws_aux1.p, *w = (double2 *)c->ws_aux2.p, *z = (double2 *)c->ws_aux3.p;
+    double *part = (double *)c->ws_part.p;
+    double *hp = (double *)c->host_pinned;
+    auto norms = [&](const double2 *x, const double2 *y, double *re, double *yy) -> int {
+        launch_dot_partials<double>(st, x, y, n, part, 1, nbv, Gate{});
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(hp, part, 3 * NBMAX * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        *re = host_partial_sum(hp, nbv);
+        *yy = host_partial_sum(hp + 2 * NBMAX, nbv);
+        return 0;
+    };
+    double re, nn;
+    CHK(norms(start, start, &re, &nn));
+    if (!(nn > 0.0)) return set_error(S_ERR_ARG, "spectral_radius: zero start vector");
+    launch_overlap_out(st, v, nullptr, start, V, 1, 0, 1.0 / std::sqrt(nn), nbv);
+    double lam = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        DslashArgs<double> a = ds_args<double>(c, false, false);
+        a.in = v;
+        a.out = w;
+        launch_dslash<double>(st, a, 1, EPI_PLAIN, false, nbd);
+        // D^+ w = gamma5 D(-mu) gamma5 w
+        DslashArgs<double> b = ds_args<double>(c, true, true);
+        b.in = w;
+        b.out = z;
+        launch_dslash<double>(st, b, 1, EPI_PLAIN, true, nbd);
+        CHK(norms(v, z, &re, &nn));
+        lam = re;
+        if (!(nn > 0.0)) break;
+        launch_overlap_out(st, v, nullptr, z, V, 1, 0, 1.0 / std::sqrt(nn), nbv);
+    }
+    HIPCHK(hipGetLastError());
+    *rho = lam;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// double-pass coefficient sweep (host, FP64)
+// ---------------------------------------------------------------------------
+using cd = std::complex<double>;
+static inline cd toc(double2 z) { return cd(z.x, z.y); }
+static inline double2 fromc(cd z) { return d2(z.real(), z.imag()); }
+
+struct SweepResult {
+    cd cb;
+    std::vector<ReplayStep> steps;     // [max_outer * l]
+    std::vector<ReplayOuter> outer;    // [max_outer]
+    int M = 0;
+};
+
+// One right-hand side.  tape: recorded full steps (and a trailing u-step on a
+// gamma breakdown); outer: per-outer-iteration record; gam: MR coefficients;
+// sp, w: relative shifts and weights; iters, broken: per-shift M_s.
+static void sweep_rhs(int l, int M, const TapeStep *tape, const TapeOuter *outer,
+                      const double2 *gam, int ns, const double *sp, const double *w,
+                      const int *iters, const int *broken, int max_outer, SweepResult *res) {
+    struct Sh {
+        cd as, bs, kap, kapn;
+        bool live;
+    };
+    struct Mr {
+        cd q, kap, c[LMAX];
+        bool live;
+    };
+    std::vector<int> n0(M + 1, 0);
+    for (int m = 0; m < M; ++m) n0[m + 1] = n0[m] + outer[m].l_eff;
+    const int nfull = n0[M];
+    std::vector<Sh> st((size_t)std::max(nfull, 1) * ns);
+    std::vector<Mr> mr((size_t)std::max(M, 1) * ns);
+    // forward: recompute the shifts' scalar recurrences
+    std::vector<cd> zeta(ns, 1.0), zprev(ns, 1.0), piprev(ns, 0.0), psi(ns, 1.0);
+    std::vector<char> alive(ns, 1);
+    for (int m = 0; m < M; ++m) {
+        std::vector<char> act(ns, 0);
+        for (int s = 0; s < ns; ++s)
+            act[s] = alive[s] && (m < iters[s] || (broken[s] && m == iters[s]));
+        for (int j = 0; j < outer[m].l_eff; ++j) {
+            const int n = n0[m] + j;
+            const cd alpha = toc(tape[n].alpha), beta = toc(tape[n].beta);
+            for (int s = 0; s < ns; ++s) {
+                Sh &h = st[(size_t)n * ns + s];
+                h.live = false;
+                if (!act[s]) continue;
+                const cd z = zeta[s], zp = zprev[s];
+                const cd pi_n = z - beta * piprev[s];
+                const cd zn = z + alpha * sp[s] * pi_n;
+                if (!std::isfinite(zn.real()) || !std::isfinite(zn.imag()) || std::abs(zn) < ZETA_MIN) {
+                    act[s] = alive[s] = 0;
+                    continue;
+                }
+                h.as = alpha * z / zn;
+                h.bs = beta * (zp / z) * (zp / z);
+                h.kap = 1.0 / (z * psi[s]);
+                h.kapn = 1.0 / (zn * psi[s]);
+                h.live = true;
+                zprev[s] = z;
+                zeta[s] = zn;
+                piprev[s] = pi_n;
+            }
+        }
+        const int lm = outer[m].l_mr;
+        for (int s = 0; s < ns; ++s) {
+            Mr &q = mr[(size_t)m * ns + s];
+            q.live = false;
+            if (!act[s] || lm == 0) continue;
+            cd qs = 1.0;
+            for (int i = 1; i <= lm; ++i) {
+                double p = 1.0;
+                for (int k = 0; k < i; ++k) p *= -sp[s];
+                qs -= toc(gam[(size_t)m * LMAX + i - 1]) * p;
+            }
+            if (!std::isfinite(qs.real()) || !std::isfinite(qs.imag()) || std::abs(qs) < ZETA_MIN) {
+                act[s] = alive[s] = 0;
+                continue;
+            }
+            q.q = qs;
+            q.kap = 1.0 / (zeta[s] * psi[s]);
+            for (int k = 0; k < LMAX; ++k) q.c[k] = 0.0;
+            for (int k = 0; k < lm; ++k) {
+                cd acc = 0.0;
+                for (int i = k + 1; i <= lm; ++i) {
+                    double p = 1.0;
+                    for (int e = 0; e < i - 1 - k; ++e) p *= -sp[s];
+                    acc += toc(gam[(size_t)m * LMAX + i - 1]) * p;
+                }
+                q.c[k] = acc / qs;
+            }
+            q.live = true;
+            psi[s] *= qs;
+        }
+    }
+    // backward: adjoint coefficients of every program variable
+    std::vector<cd> lamR(l + 1, 0.0), lamU(l + 1, 0.0), lamW((size_t)ns * (l + 1), 0.0);
+    res->steps.assign((size_t)max_outer * l, ReplayStep{});
+    res->outer.assign((size_t)max_outer, ReplayOuter{});
+    for (int m = M - 1; m >= 0; --m) {
+        const int lm = outer[m].l_mr;
+        ReplayOuter &ro = res->outer[m];
+        ro.lm = lm;
+        for (int i = 0; i < LMAX; ++i) ro.gam[i] = (i < lm) ? gam[(size_t)m * LMAX + i] : d2(0, 0);
+        // MR, reversed: u_0 update, r_0 update, then the shifts
+        for (int i = 1; i <= lm; ++i) lamU[i] += -toc(gam[(size_t)m * LMAX + i - 1]) * lamU[0];
+        for (int i = 1; i <= lm; ++i) lamR[i] += -toc(gam[(size_t)m * LMAX + i - 1]) * lamR[0];
+        for (int s = 0; s < ns; ++s) {
+            const Mr &q = mr[(size_t)m * ns + s];
+            if (!q.live) continue;
+            cd *lw = &lamW[(size_t)s * (l + 1)];
+            for (int i = 1; i <= lm; ++i) lw[i] += -toc(gam[(size_t)m * LMAX + i - 1]) * lw[0] / q.q;
+            lw[0] = lw[0] / q.q;
+            for (int k = 0; k < lm; ++k) lamR[k] += q.kap * q.c[k] * w[s];
+        }
+        const int le = outer[m].l_eff;
+        if (outer[m].partial) {
+            // trailing u-step (gamma breakdown): u_i <- r_i - beta u_i, u_{j+1} <- S u_j
+            const int j = le;
+            const TapeStep &t = tape[n0[m] + le];
+            ReplayStep &rs = res->steps[(size_t)m * l + j];
+            rs.flag = 1;
+            rs.beta = t.beta;
+            rs.cu = fromc(lamU[j + 1]);
+            lamU[j + 1] = 0.0;
+            const cd beta = toc(t.beta);
+            for (int i = 0; i <= j; ++i) {
+                lamR[i] += lamU[i];
+                lamU[i] *= -beta;
+            }
+        }
+        for (int j = le - 1; j >= 0; --j) {
+            const int n = n0[m] + j;
+            const cd alpha = toc(tape[n].alpha), beta = toc(tape[n].beta);
+            ReplayStep &rs = res->steps[(size_t)m * l + j];
+            rs.flag = 2;
+            rs.beta = tape[n].beta;
+            rs.alpha = tape[n].alpha;
+            // r_{j+1} <- S r_j
+            rs.cr = fromc(lamR[j + 1]);
+            lamR[j + 1] = 0.0;
+            // r_i <- r_i - alpha u_{i+1}
+            for (int i = 0; i <= j; ++i) lamU[i + 1] += -alpha * lamR[i];
+            // shifts (program order: u^s_i update, x^s update, u^s_{j+1})
+            for (int s = 0; s < ns; ++s) {
+                const Sh &h = st[(size_t)n * ns + s];
+                if (!h.live) continue;
+                cd *lw = &lamW[(size_t)s * (l + 1)];
+                const cd a1 = (h.kap - h.kapn) / h.as;
+                const cd a2 = h.kapn * alpha / h.as;
+                lamR[j] += a1 * lw[j + 1];
+                lamU[j + 1] += a2 * lw[j + 1];
+                lw[j] += -sp[s] * lw[j + 1];
+                lw[j + 1] = 0.0;
+                lw[0] += h.as * w[s];
+                for (int i = 0; i <= j; ++i) {
+                    lamR[i] += h.kap * lw[i];
+                    lw[i] *= -h.bs;
+                }
+            }
+            // u_{j+1} <- S u_j
+            rs.cu = fromc(lamU[j + 1]);
+            lamU[j + 1] = 0.0;
+            // u_i <- r_i - beta u_i
+            for (int i = 0; i <= j; ++i) {
+                lamR[i] += lamU[i];
+                lamU[i] *= -beta;
+            }
+        }
+    }
+    res->cb = lamR[0];
+    res->M = M;
+}
+
+// ---------------------------------------------------------------------------
+// the multi-shift solve
+// ---------------------------------------------------------------------------
+template <typename T>
+static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y,
+                      double2 *xs_out, bool want_true, SolveReport *rep) {
+    hipStream_t st = c->stream;
+    const int V = c->g.V;
+    const long n = 12L * V;
+    const int nrhs = P.nrhs, ns = P.n_shift, l = P.l;
+    const bool pass1 = P.pass == 1;
+    const int nbd = nblocks_for(V), nbv = nblocks_for(n);
+    const size_t cs = sizeof(C<T>);
+    const int max_outer = P.max_outer;
+    const int max_steps = max_outer * l;
+
+    // ---- workspace
+    CHK(ensure(c->ws_R, (size_t)nrhs * (l + 1) * n * cs));
+    CHK(ensure(c->ws_U, (size_t)nrhs * (l + 1) * n * cs));
+    CHK(ensure(c->ws_tmp, (size_t)nrhs * n * cs));
+    CHK(ensure(c->ws_part, (size_t)nrhs * PMAX * NBMAX * sizeof(double)));
+    CHK(ensure(c->ws_seed, (size_t)nrhs * sizeof(SeedState)));
+    CHK(ensure(c->ws_shift, (size_t)nrhs * NSMAX * sizeof(ShiftState)));
+    CHK(ensure(c->ws_sc, (size_t)nrhs * NSMAX * sizeof(StepCoef)));
+    CHK(ensure(c->ws_mc, (size_t)nrhs * NSMAX * sizeof(MRCoef)));
+    CHK(ensure(c->ws_sig0, (size_t)nrhs * sizeof(double)));
+    CHK(ensure(c->ws_wts, (size_t)nrhs * ns * sizeof(double)));
+    C<T> *R = (C<T> *)c->ws_R.p, *Uv = (C<T> *)c->ws_U.p, *tmp = (C<T> *)c->ws_tmp.p;
+    double *part = (double *)c->ws_part.p;
+    SeedState *seed = (SeedState *)c->ws_seed.p;
+    ShiftState *sh = (ShiftState *)c->ws_shift.p;
+    const C<T> *rt;
+    if (sizeof(T) == sizeof(double)) {
+        rt = (const C<T> *)b;
+    } else {
+        CHK(ensure(c->ws_rt, (size_t)nrhs * n * cs));
+        launch_convert_in<T>(st, (C<T> *)c->ws_rt.p, b, n, n, n, nrhs);
+        rt = (const C<T> *)c->ws_rt.p;
+    }
+    C<T> *W = nullptr, *X = nullptr;
+    if (pass1) {
+        CHK(ensure(c->ws_W, (size_t)nrhs * ns * (l + 1) * n * cs));
+        W = (C<T> *)c->ws_W.p;
+        if (sizeof(T) == sizeof(double) && xs_out) {
+            X = (C<T> *)xs_out;
+        } else {
+            CHK(ensure(c->ws_X, (size_t)nrhs * ns * n * cs));
+            X = (C<T> *)c->ws_X.p;
+        }
+    } else {
+        CHK(ensure(c->ws_tape, (size_t)nrhs * max_steps * sizeof(TapeStep)));
+        CHK(ensure(c->ws_tape_gam, (size_t)nrhs * max_outer * LMAX * sizeof(double2)));
+        CHK(ensure(c->ws_tape_outer, (size_t)nrhs * max_outer * sizeof(TapeOuter)));
+        HIPCHK(hipMemsetAsync(c->ws_tape.p, 0, (size_t)nrhs * max_steps * sizeof(TapeStep), st));
+        HIPCHK(hipMemsetAsync(c->ws_tape_outer.p, 0, (size_t)nrhs * max_outer * sizeof(TapeOuter), st));
+    }
+
+    // ---- host-side initial state
+    std::vector<SeedState> hs(nrhs);
+    std::vector<ShiftState> hsh((size_t)nrhs * NSMAX);
+    std::vector<double> sig0(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+        const double *sg = &P.shifts[(size_t)r * ns];
+        sig0[r] = *std::min_element(sg, sg + ns);
+        SeedState &S = hs[r];
+        std::memset(&S, 0, sizeof(S));
+        S.tol = P.tol;
+        S.nshift = ns;
+        S.max_outer = max_outer;
+        S.max_steps = max_steps;
+        S.forced = P.force_iters ? 1 : 0;
+        for (int s = 0; s < ns; ++s) {
+            ShiftState &H = hsh[(size_t)r * NSMAX + s];
+            std::memset(&H, 0, sizeof(H));
+            H.zeta = d2(1, 0);
+            H.zeta_prev = d2(1, 0);
+            H.pi_prev = d2(0, 0);
+            H.psi = d2(1, 0);
+            H.sp = sg[s] - sig0[r];
+            H.res = INFINITY;
+            H.active = 1;
+            H.force = P.force_iters ? P.force_iters[(size_t)r * ns + s] : 0;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(seed, hs.data(), nrhs * sizeof(SeedState), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(sh, hsh.data(), hsh.size() * sizeof(ShiftState), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->ws_sig0.p, sig0.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->ws_wts.p, P.weights.data(), (size_t)nrhs * ns * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+
+    // ---- initial vectors: r_0 = b, everything else zero
+    launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
+    launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
+    if (pass1) {
+        launch_zero<T>(st, W, (long)nrhs * ns * (l + 1) * n, 0, 1);
+        launch_zero<T>(st, X, (long)nrhs * ns * n, 0, 1);
+    }
+    launch_convert_in<T>(st, R, b, n, (long)(l + 1) * n, n, nrhs);
+    launch_dot_partials<T>(st, rt, rt, n, part, nrhs, nbv, Gate{});
+    ScalarArgs sa;
+    sa.seed = seed;
+    sa.sh = sh;
+    sa.sc = (StepCoef *)c->ws_sc.p;
+    sa.mc = (MRCoef *)c->ws_mc.p;
+    sa.tape = pass1 ? nullptr : (TapeStep *)c->ws_tape.p;
+    sa.tape_gam = pass1 ? nullptr : (double2 *)c->ws_tape_gam.p;
+    sa.tape_outer = pass1 ? nullptr : (TapeOuter *)c->ws_tape_outer.p;
+    sa.part = part;
+    sa.l = l;
+    sa.record = pass1 ? 0 : 1;
+    sa.nblk = nbv;
+    launch_sc_init(st, sa, nrhs);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+
+    // ---- argument blocks
+    VecArgs<T> va;
+    va.n = n;
+    va.l = l;
+    va.nshift = ns;
+    va.R = R;
+    va.U = Uv;
+    va.W = W;
+    va.X = X;
+    va.rt = rt;
+    va.part = part;
+    va.seed = seed;
+    va.sc = sa.sc;
+    va.mc = sa.mc;
+    va.beta = CoefRef{(const char *)&seed[0].beta, (long)sizeof(SeedState)};
+    va.alpha = CoefRef{(const char *)&seed[0].alpha, (long)sizeof(SeedState)};
+    va.gam = CoefRef{(const char *)&seed[0].gam[0], (long)sizeof(SeedState)};
+    Gate g_bicg;
+    g_bicg.seed = seed;
+    g_bicg.need_bicg = 1;
+    Gate g_run;
+    g_run.seed = seed;
+    const long vs = (long)(l + 1) * n;   // rhs stride of R and U
+    DslashArgs<T> d1 = ds_args<T>(c, P.neg_mu, true);
+    d1.in_rs = vs;
+    d1.out_rs = n;
+    DslashArgs<T> d2 = d1;
+    d2.scale = (T)P.a_scale;
+    d2.sigma0_rhs = (const double *)c->ws_sig0.p;
+    d2.in_rs = n;
+    d2.out_rs = vs;
+    d2.v_rs = vs;
+    d2.rt = rt;
+    d2.rt_rs = n;
+    d2.part = part;
+
+    CHK(ensure_host(c, (size_t)nrhs * sizeof(SeedState)));
+    SeedState *hseed = (SeedState *)c->host_pinned;
+    int m_done = 0;
+    for (int m = 0; m < max_outer; ++m) {
+        for (int j = 0; j < l; ++j) {
+            sa.j = j;
+            sa.nblk = (j == 0) ? nbv : nbd;
+            sa.nblk2 = nbv;
+            launch_sc_beta(st, sa, nrhs);
+            va.gate = g_bicg;
+            launch_seed_u<T>(st, va, j, nrhs, nbv);
+            // u_{j+1} = S u_j = a g5 D (g5 D u_j) + sigma0 u_j, <rt, u_{j+1}>
+            d1.in = Uv + (size_t)j * n;
+            d1.out = tmp;
+            d1.gate = g_bicg;
+            launch_dslash<T>(st, d1, nrhs, EPI_PLAIN, false, nbd);
+            d2.in = tmp;
+            d2.out = Uv + (size_t)(j + 1) * n;
+            d2.v = Uv + (size_t)j * n;
+            d2.gate = g_bicg;
+            launch_dslash<T>(st, d2, nrhs, EPI_MV, false, nbd);
+            sa.nblk = nbd;
+            launch_sc_alpha(st, sa, nrhs);
+            va.partials = 1;
+            launch_r_update<T>(st, va, j, pass1, nrhs, nbv);
+            // r_{j+1} = S r_j, <rt, r_{j+1}>
+            d1.in = R + (size_t)j * n;
+            launch_dslash<T>(st, d1, nrhs, EPI_PLAIN, false, nbd);
+            d2.out = R + (size_t)(j + 1) * n;
+            d2.v = R + (size_t)j * n;
+            launch_dslash<T>(st, d2, nrhs, EPI_MV, false, nbd);
+        }
+        va.gate = g_run;
+        launch_gram<T>(st, va, nrhs, nbv);
+        sa.nblk = nbv;
+        launch_sc_mr(st, sa, nrhs);
+        va.partials = 1;
+        launch_mr_update<T>(st, va, pass1, nrhs, nbv);
+        launch_sc_conv(st, sa, nrhs);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(hseed, seed, nrhs * sizeof(SeedState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        m_done = m + 1;
+        bool any = false;
+        for (int r = 0; r < nrhs; ++r) any |= hseed[r].run != 0;
+        if (!any) break;
+    }
+    (void)m_done;
+
+    // ---- results of pass 1
+    std::vector<SeedState> fs(nrhs);
+    std::vector<ShiftState> fsh((size_t)nrhs * NSMAX);
+    HIPCHK(hipMemcpy(fs.data(), seed, nrhs * sizeof(SeedState), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(fsh.data(), sh, fsh.size() * sizeof(ShiftState), hipMemcpyDeviceToHost));
+
+    rep->status = S_OK;
+    rep->outer_max = 0;
+    rep->steps_max = 0;
+    rep->mv = 0;
+    rep->dots = 0;
+    rep->shift_iters.assign((size_t)nrhs * ns, 0);
+    rep->shift_resid.assign((size_t)nrhs * ns, 0.0);
+    rep->rhs_outer.assign(nrhs, 0);
+    for (int r = 0; r < nrhs; ++r) {
+        const SeedState &S = fs[r];
+        int status = S.status;
+        if (S.run) status = S_NOT_CONVERGED;   // max_outer reached without the device noticing
+        if (status > rep->status) rep->status = status;
+        rep->outer_max = std::max(rep->outer_max, S.m);
+        rep->steps_max = std::max(rep->steps_max, S.n);
+        rep->rhs_outer[r] = S.m;
+        rep->mv += S.mv;
+        rep->dots += S.dots;
+        for (int s = 0; s < ns; ++s) {
+            const ShiftState &H = fsh[(size_t)r * NSMAX + s];
+            rep->shift_iters[(size_t)r * ns + s] = H.iters;
+            rep->shift_resid[(size_t)r * ns + s] = H.res;
+        }
+    }
+
+    if (pass1) {
+        launch_ysum<T>(st, y, X, (const double *)c->ws_wts.p, n, ns, nrhs, nbv);
+        HIPCHK(hipGetLastError());
+    } else {
+        // ---- sweep on the host, then the replay
+        std::vector<TapeStep> tp((size_t)nrhs * max_steps);
+        std::vector<double2> tg((size_t)nrhs * max_outer * LMAX);
+        std::vector<TapeOuter> to((size_t)nrhs * max_outer);
+        HIPCHK(hipMemcpy(tp.data(), c->ws_tape.p, tp.size() * sizeof(TapeStep), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(tg.data(), c->ws_tape_gam.p, tg.size() * sizeof(double2), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(to.data(), c->ws_tape_outer.p, to.size() * sizeof(TapeOuter), hipMemcpyDeviceToHost));
+        int Mmax = 0;
+        for (int r = 0; r < nrhs; ++r) Mmax = std::max(Mmax, fs[r].m);
+        const int Mcap = std::max(Mmax, 1);
+        std::vector<ReplayStep> rsteps((size_t)nrhs * Mcap * l);
+        std::vector<ReplayOuter> router((size_t)nrhs * Mcap);
+        std::vector<double2> cb(nrhs);
+        for (int r = 0; r < nrhs; ++r) {
+            std::vector<double> spv(ns), wv(ns);
+            std::vector<int> it(ns), br(ns);
+            for (int s = 0; s < ns; ++s) {
+                const ShiftState &H = fsh[(size_t)r * NSMAX + s];
+                spv[s] = H.sp;
+                wv[s] = P.weights[(size_t)r * ns + s];
+                it[s] = H.iters;
+                br[s] = H.broken;
+            }
+            SweepResult sr;
+            sweep_rhs(l, fs[r].m, &tp[(size_t)r * max_steps], &to[(size_t)r * max_outer],
+                      &tg[(size_t)r * max_outer * LMAX], ns, spv.data(), wv.data(), it.data(),
+                      br.data(), Mcap, &sr);
+            cb[r] = fromc(sr.cb);
+            std::copy(sr.steps.begin(), sr.steps.begin() + (size_t)Mcap * l, rsteps.begin() + (size_t)r * Mcap * l);
+            std::copy(sr.outer.begin(), sr.outer.begin() + Mcap, router.begin() + (size_t)r * Mcap);
+        }
+        CHK(ensure(c->ws_replay, rsteps.size() * sizeof(ReplayStep)));
+        CHK(ensure(c->ws_replay_outer, router.size() * sizeof(ReplayOuter)));
+        CHK(ensure(c->ws_cb, nrhs * sizeof(double2)));
+        ReplayStep *drs = (ReplayStep *)c->ws_replay.p;
+        ReplayOuter *dro = (ReplayOuter *)c->ws_replay_outer.p;
+        HIPCHK(hipMemcpyAsync(drs, rsteps.data(), rsteps.size() * sizeof(ReplayStep), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(dro, router.data(), router.size() * sizeof(ReplayOuter), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(c->ws_cb.p, cb.data(), nrhs * sizeof(double2), hipMemcpyHostToDevice, st));
+
+        // pass 2: regenerate the Mv outputs and accumulate y
+        launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
+        launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
+        launch_convert_in<T>(st, R, b, n, vs, n, nrhs);
+        launch_yinit(st, y, b, (const double2 *)c->ws_cb.p, n, nrhs, nbv);
+        const long rstride = (long)Mcap * l * sizeof(ReplayStep);
+        VecArgs<T> vb = va;
+        vb.partials = 0;
+        vb.seed = nullptr;
+        DslashArgs<T> e1 = d1, e2 = d2;
+        e2.rt = nullptr;
+        e2.part = nullptr;
+        e2.y = y;
+        e2.y_rs = n;
+        for (int m = 0; m < Mmax; ++m) {
+            for (int j = 0; j < l; ++j) {
+                const size_t idx = (size_t)m * l + j;
+                Gate gu;
+                gu.flag = &drs[idx].flag;
+                gu.flag_stride = rstride / (long)sizeof(int);
+                gu.need = 1;
+                Gate gr = gu;
+                gr.need = 2;
+                vb.beta = CoefRef{(const char *)&drs[idx].beta, rstride};
+                vb.alpha = CoefRef{(const char *)&drs[idx].alpha, rstride};
+                vb.gate = gu;
+                launch_seed_u<T>(st, vb, j, nrhs, nbv);
+                e1.in = Uv + (size_t)j * n;
+                e1.out = tmp;
+                e1.gate = gu;
+                launch_dslash<T>(st, e1, nrhs, EPI_PLAIN, false, nbd);
+                e2.in = tmp;
+                e2.out = Uv + (size_t)(j + 1) * n;
+                e2.v = Uv + (size_t)j * n;
+                e2.ycoef = CoefRef{(const char *)&drs[idx].cu, rstride};
+                e2.gate = gu;
+                launch_dslash<T>(st, e2, nrhs, EPI_MV_Y, false, nbd);
+                vb.gate = gr;
+                launch_r_update<T>(st, vb, j, false, nrhs, nbv);
+                e1.in = R + (size_t)j * n;
+                e1.gate = gr;
+                launch_dslash<T>(st, e1, nrhs, EPI_PLAIN, false, nbd);
+                e2.out = R + (size_t)(j + 1) * n;
+                e2.v = R + (size_t)j * n;
+                e2.ycoef = CoefRef{(const char *)&drs[idx].cr, rstride};
+                e2.gate = gr;
+                launch_dslash<T>(st, e2, nrhs, EPI_MV_Y, false, nbd);
+            }
+            Gate gm;
+            gm.flag = &dro[m].lm;
+            gm.flag_stride = (long)Mcap * sizeof(ReplayOuter) / (long)sizeof(int);
+            gm.need = 1;
+            vb.gate = gm;
+            vb.gam = CoefRef{(const char *)&dro[m].gam[0], (long)Mcap * (long)sizeof(ReplayOuter)};
+            launch_mr_update<T>(st, vb, false, nrhs, nbv);
+            HIPCHK(hipGetLastError());
+        }
+        rep->mv *= 2;
+    }
+
+    // ---- optional FP64 true residual of every shift (single-pass)
+    if (pass1 && want_true) {
+        rep->shift_true_resid.assign((size_t)nrhs * ns, 0.0);
+        CHK(ensure(c->ws_aux1, (size_t)nrhs * n * sizeof(double2)));
+        CHK(ensure(c->ws_aux2, (size_t)nrhs * n * sizeof(double2)));
+        CHK(ensure(c->ws_aux3, (size_t)nrhs * n * sizeof(double2)));
+        CHK(ensure_host(c, (size_t)std::max(nrhs * sizeof(SeedState), (size_t)NBMAX * sizeof(double))));
+        double2 *xd = (double2 *)c->ws_aux1.p, *t1 = (double2 *)c->ws_aux2.p, *t2 = (double2 *)c->ws_aux3.p;
+        std::vector<double> rowbuf(NBMAX);
+        for (int s = 0; s < ns; ++s) {
+            launch_convert_out<T>(st, xd, X + (size_t)s * n, n, n, (long)ns * n, nrhs);
+            DslashArgs<double> a1 = ds_args<double>(c, P.neg_mu, true);
+            a1.in = xd;
+            a1.out = t1;
+            launch_dslash<double>(st, a1, nrhs, EPI_PLAIN, false, nbd);
+            for (int r = 0; r < nrhs; ++r) {
+                DslashArgs<double> a2 = ds_args<double>(c, P.neg_mu, true);
+                a2.in = t1 + (size_t)r * n;
+                a2.out = t2 + (size_t)r * n;
+                a2.scale = P.a_scale;
+                a2.sigma0 = P.shifts[(size_t)r * ns + s];
+                a2.v = xd + (size_t)r * n;
+                launch_dslash<double>(st, a2, 1, EPI_SV, false, nbd);
+            }
+            launch_diffnorm_partials<double>(st, b, t2, n, n, n, part, nrhs, nbv);
+            HIPCHK(hipGetLastError());
+            for (int r = 0; r < nrhs; ++r) {
+                HIPCHK(hipMemcpyAsync(rowbuf.data(), part + (size_t)r * PMAX * NBMAX, NBMAX * sizeof(double),
+                                      hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                const double d = std::sqrt(host_partial_sum(rowbuf.data(), nbv));
+                rep->shift_true_resid[(size_t)r * ns + s] = d / fs[r].bnorm;
+            }
+        }
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+}
+
+int solve_mshift(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2 *x_shifts,
+                 bool want_true_resid, SolveReport *rep) {
+    if (P.mixed) return solve_impl<float>(c, P, b, y, x_shifts, want_true_resid, rep);
+    return solve_impl<double>(c, P, b, y, x_shifts, want_true_resid, rep);
+}
+
+// ---------------------------------------------------------------------------
+// sign(H) b = sqrt(a) H f(A) b;  D_ov b = b + gamma5 sign(H) b
+// ---------------------------------------------------------------------------
+int sign_apply(Ctx *c, const SolveParams &P, const double2 *b, double2 *out, bool overlap,
+               SolveReport *rep) {
+    const int V = c->g.V;
+    const long n = 12L * V;
+    CHK(ensure(c->ws_y, (size_t)P.nrhs * n * sizeof(double2)));
+    double2 *y = (double2 *)c->ws_y.p;
+    CHK(solve_mshift(c, P, b, y, nullptr, false, rep));
+    CHK(ensure(c->ws_aux4, (size_t)P.nrhs * n * sizeof(double2)));
+    double2 *hy = (double2 *)c->ws_aux4.p;
+    DslashArgs<double> a = ds_args<double>(c, P.neg_mu, true);   // H y = g5 D y
+    a.in = y;
+    a.out = hy;
+    launch_dslash<double>(c->stream, a, P.nrhs, EPI_PLAIN, false, nblocks_for(V));
+    launch_overlap_out(c->stream, out, b, hy, V, P.nrhs, overlap ? 1 : 0, std::sqrt(P.a_scale),
+                       nblocks_for(n));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int sign_backward(Ctx *, const SolveParams &, const double2 *, const double2 *, int, double2 *, double *,
+                  double *, double2 *, SolveReport *) {
+    return set_error(S_ERR_ARG, "pfe_sign_backward: not available in this build");
+}
+
+}  // namespace msb

@@ -1,0 +1,316 @@
+"""Thin ctypes binding of libmsb (include/msb.h): argument marshalling only.
+
+Every function here forwards to the C entry point of the same name; tensors
+are passed as raw device pointers on torch's current stream.  Nothing is
+computed in Python.  When libmsb.so is missing, importing the library raises
+-- there is no fallback path.
+
+Tensor conventions (complex128, CUDA, contiguous):
+  links     (4, 3, 3, V)          U_nu(x)_{ab}
+  spinors   (nrhs, 12, V)         k = 3*spin + colour, site x + Lx(y + Ly(z + Lz t))
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # noqa: F401  -- loads torch's HIP runtime first; libmsb binds to it
+
+__all__ = [
+    "MsbError", "Lattice", "SolveInfo", "Context", "lib", "library_path",
+    "neuberger_pfe", "wilson_apply", "mshift_bicgstabl", "pfe_sign_apply",
+    "pfe_sign_backward", "spectral_radius",
+    "G5_LEFT", "NEG_MU", "DAGGER", "MIXED", "PERSISTENT", "OVERLAP", "ADJOINT",
+    "OK", "ERR_ARG", "ERR_HIP", "ERR_OOM", "NOT_CONVERGED", "BREAKDOWN",
+]
+
+OK, ERR_ARG, ERR_HIP, ERR_OOM, NOT_CONVERGED, BREAKDOWN = 0, 1, 2, 3, 4, 5
+G5_LEFT, NEG_MU, DAGGER, MIXED, PERSISTENT, OVERLAP, ADJOINT = 1, 2, 4, 8, 16, 32, 64
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "_lib", "libmsb.so")
+
+
+class MsbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[msb status {status}] {msg}")
+        self.status = status
+
+
+class _Lattice(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("mass", ctypes.c_double),
+                ("mu", ctypes.c_double), ("bc_t", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("outer_iters", ctypes.c_int),
+                ("bicg_steps", ctypes.c_int), ("mv_count", ctypes.c_longlong),
+                ("dot_count", ctypes.c_longlong), ("axpy_count", ctypes.c_longlong),
+                ("reliable_updates", ctypes.c_int), ("bytes_model", ctypes.c_double),
+                ("shift_iters", ctypes.POINTER(ctypes.c_int)),
+                ("shift_resid", ctypes.POINTER(ctypes.c_double)),
+                ("shift_true_resid", ctypes.POINTER(ctypes.c_double)),
+                ("force_iters", ctypes.POINTER(ctypes.c_int))]
+
+
+_LIB = None
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    """Load libmsb.so (once)."""
+    global _LIB
+    if _LIB is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run `python -m paper_1010_2592_amd.build`")
+        L = ctypes.CDLL(path)
+        L.msb_last_error.restype = ctypes.c_char_p
+        L.msb_last_error.argtypes = []
+        L.msb_create.argtypes = [ctypes.POINTER(_P), ctypes.POINTER(_Lattice), _P, _P]
+        L.msb_destroy.argtypes = [_P]
+        L.msb_destroy.restype = None
+        L.msb_set_stream.argtypes = [_P, _P]
+        L.msb_neuberger_pfe.argtypes = [_I, _DP, _DP]
+        L.msb_spectral_radius.argtypes = [_P, _P, _I, _DP]
+        L.wilson_apply.argtypes = [_P, _P, _P, _I, _I]
+        L.mshift_bicgstabl.argtypes = [_P, _D, _I, _DP, _DP, _I, _I, _D, _I, _I, _I, _I,
+                                       _P, _P, _P, ctypes.POINTER(_Info)]
+        L.pfe_sign_apply.argtypes = [_P, _D, _I, _DP, _DP, _I, _D, _I, _I, _I, _I, _P, _P,
+                                     ctypes.POINTER(_Info)]
+        L.pfe_sign_backward.argtypes = [_P, _D, _I, _DP, _DP, _I, _D, _I, _I, _I, _P, _P, _I,
+                                        _P, _DP, _DP, _P, ctypes.POINTER(_Info)]
+        for f in ("msb_create", "msb_set_stream", "msb_neuberger_pfe", "msb_spectral_radius",
+                  "wilson_apply", "mshift_bicgstabl", "pfe_sign_apply", "pfe_sign_backward"):
+            getattr(L, f).restype = _I
+        _LIB = L
+    return _LIB
+
+
+def _check(rc: int, allow=(OK,)):
+    if rc not in allow:
+        raise MsbError(rc, lib().msb_last_error().decode())
+    return rc
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def _spinors(t: torch.Tensor, V: int, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3 or t.shape[1] != 12 or t.shape[2] != V:
+        raise ValueError(f"{name} must have shape (nrhs, 12, {V})")
+    return t.contiguous()
+
+
+def _stream_handle():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Lattice:
+    dims: Sequence[int]
+    mass: float = -2.0
+    mu: float = 0.0
+    bc_t: int = -1
+
+    @property
+    def volume(self) -> int:
+        return int(np.prod(self.dims))
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    outer_iters: int
+    bicg_steps: int
+    mv_count: int
+    dot_count: int
+    axpy_count: int
+    reliable_updates: int
+    bytes_model: float
+    shift_iters: np.ndarray
+    shift_resid: np.ndarray
+    shift_true_resid: Optional[np.ndarray]
+
+
+def neuberger_pfe(n: int):
+    """(sigma, w) of the n-pole Neuberger expansion, from the library."""
+    s = np.zeros(n)
+    w = np.zeros(n)
+    _check(lib().msb_neuberger_pfe(int(n), _dptr(s), _dptr(w)))
+    return s, w
+
+
+class Context:
+    """An msb_ctx: lattice geometry, D_w(mu) parameters and a copy of the links."""
+
+    def __init__(self, lat: Lattice, links: torch.Tensor):
+        V = lat.volume
+        if links.dtype != torch.complex128 or not links.is_cuda or tuple(links.shape) != (4, 3, 3, V):
+            raise ValueError(f"links must be a complex128 CUDA tensor of shape (4, 3, 3, {V})")
+        links = links.contiguous()
+        self.lat = lat
+        self.V = V
+        cl = _Lattice((ctypes.c_int * 4)(*[int(d) for d in lat.dims]), float(lat.mass),
+                      float(lat.mu), int(lat.bc_t))
+        h = _P()
+        _check(lib().msb_create(ctypes.byref(h), ctypes.byref(cl), _P(links.data_ptr()),
+                                _stream_handle()))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().msb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        _check(lib().msb_set_stream(self._h, _stream_handle()))
+
+    # -- entry points ------------------------------------------------------
+    def wilson_apply(self, x: torch.Tensor, flags: int = 0, out: Optional[torch.Tensor] = None):
+        x = _spinors(x, self.V, "in")
+        if out is None:
+            out = torch.empty_like(x)
+        self._sync_stream()
+        _check(lib().wilson_apply(self._h, _P(x.data_ptr()), _P(out.data_ptr()), x.shape[0], int(flags)))
+        return out
+
+    def spectral_radius(self, start: torch.Tensor, iters: int = 100) -> float:
+        start = _spinors(start, self.V, "start")
+        rho = ctypes.c_double(0.0)
+        self._sync_stream()
+        _check(lib().msb_spectral_radius(self._h, _P(start.data_ptr()), int(iters), ctypes.byref(rho)))
+        return rho.value
+
+    def _info(self, nrhs, ns, force_iters, true_resid):
+        info = _Info()
+        it = np.zeros(nrhs * ns, dtype=np.int32)
+        rs = np.zeros(nrhs * ns)
+        tr = np.zeros(nrhs * ns) if true_resid else None
+        info.shift_iters = it.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        info.shift_resid = _dptr(rs)
+        info.shift_true_resid = _dptr(tr) if tr is not None else ctypes.POINTER(ctypes.c_double)()
+        fi = None
+        if force_iters is not None:
+            fi = np.ascontiguousarray(np.broadcast_to(np.asarray(force_iters, dtype=np.int32),
+                                                      (nrhs, ns)).reshape(-1))
+            info.force_iters = fi.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        return info, (it, rs, tr, fi)
+
+    @staticmethod
+    def _pack_info(info, keep, nrhs, ns):
+        it, rs, tr, _ = keep
+        return SolveInfo(info.status, info.outer_iters, info.bicg_steps, info.mv_count,
+                         info.dot_count, info.axpy_count, info.reliable_updates, info.bytes_model,
+                         it.reshape(nrhs, ns).copy(), rs.reshape(nrhs, ns).copy(),
+                         None if tr is None else tr.reshape(nrhs, ns).copy())
+
+    def mshift_bicgstabl(self, b: torch.Tensor, a_scale: float, shifts, weights, l: int,
+                         tol: float, max_outer: int, pass_: int = 1, flags: int = 0,
+                         want_shifts: bool = False, force_iters=None, true_resid: bool = False,
+                         allow=(OK,)):
+        """y = sum_s w_s (A + sigma_s)^{-1} b; returns (y, info, x_shifts or None).
+
+        shifts/weights: (n_shift,) for one set, or (nrhs, n_shift) per rhs."""
+        b = _spinors(b, self.V, "b")
+        nrhs = b.shape[0]
+        sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64))
+        wt = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        per = 1 if sh.ndim == 2 else 0
+        ns = sh.shape[-1]
+        y = torch.empty_like(b)
+        xs = torch.zeros((nrhs, ns, 12, self.V), dtype=torch.complex128, device=b.device) \
+            if want_shifts else None
+        info, keep = self._info(nrhs, ns, force_iters, true_resid)
+        self._sync_stream()
+        rc = lib().mshift_bicgstabl(self._h, float(a_scale), ns, _dptr(sh), _dptr(wt), per, int(l),
+                                    float(tol), int(max_outer), int(pass_), int(flags), nrhs,
+                                    _P(b.data_ptr()), _P(y.data_ptr()),
+                                    _P(xs.data_ptr() if xs is not None else None), ctypes.byref(info))
+        _check(rc, allow)
+        return y, self._pack_info(info, keep, nrhs, ns), xs
+
+    def pfe_sign_apply(self, b: torch.Tensor, a_scale: float, shifts, weights, l: int, tol: float,
+                       max_outer: int, pass_: int = 1, flags: int = 0, force_iters=None,
+                       allow=(OK,)):
+        b = _spinors(b, self.V, "b")
+        nrhs = b.shape[0]
+        sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64))
+        wt = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        ns = sh.shape[-1]
+        out = torch.empty_like(b)
+        info, keep = self._info(nrhs, ns, force_iters, False)
+        self._sync_stream()
+        rc = lib().pfe_sign_apply(self._h, float(a_scale), ns, _dptr(sh), _dptr(wt), int(l), float(tol),
+                                  int(max_outer), int(pass_), int(flags), nrhs, _P(b.data_ptr()),
+                                  _P(out.data_ptr()), ctypes.byref(info))
+        _check(rc, allow)
+        return out, self._pack_info(info, keep, nrhs, ns)
+
+    def pfe_sign_backward(self, b: torch.Tensor, eta: torch.Tensor, a_scale: float, shifts, weights,
+                          l: int, tol: float, max_outer: int, mode: int = 0, flags: int = 0,
+                          grad_links: Optional[torch.Tensor] = None, force_iters=None, allow=(OK,)):
+        """Gradients of Re<eta, y>, y = f(A) b (mode 0) or sign(H) b (mode 1).
+
+        Returns (grad_b, grad_w, grad_sigma, grad_links, info); grad_links is
+        accumulated into the given tensor (or a fresh zero tensor)."""
+        b = _spinors(b, self.V, "b")
+        eta = _spinors(eta, self.V, "eta")
+        nrhs = b.shape[0]
+        sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64))
+        wt = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        ns = sh.shape[-1]
+        gb = torch.empty_like(b)
+        gw = np.zeros(ns)
+        gs = np.zeros(ns)
+        if grad_links is None:
+            grad_links = torch.zeros((4, 3, 3, self.V), dtype=torch.complex128, device=b.device)
+        info, keep = self._info(nrhs, ns, force_iters, False)
+        self._sync_stream()
+        rc = lib().pfe_sign_backward(self._h, float(a_scale), ns, _dptr(sh), _dptr(wt), int(l),
+                                     float(tol), int(max_outer), int(flags), nrhs, _P(b.data_ptr()),
+                                     _P(eta.data_ptr()), int(mode), _P(gb.data_ptr()), _dptr(gw),
+                                     _dptr(gs), _P(grad_links.data_ptr()), ctypes.byref(info))
+        _check(rc, allow)
+        return gb, gw, gs, grad_links, self._pack_info(info, keep, nrhs, ns)
+
+
+# module-level forms with the C names (first argument: the Context)
+def wilson_apply(ctx: Context, x, flags=0, out=None):
+    return ctx.wilson_apply(x, flags, out)
+
+
+def spectral_radius(ctx: Context, start, iters=100):
+    return ctx.spectral_radius(start, iters)
+
+
+def mshift_bicgstabl(ctx: Context, b, a_scale, shifts, weights, l, tol, max_outer, pass_=1, **kw):
+    return ctx.mshift_bicgstabl(b, a_scale, shifts, weights, l, tol, max_outer, pass_, **kw)
+
+
+def pfe_sign_apply(ctx: Context, b, a_scale, shifts, weights, l, tol, max_outer, pass_=1, **kw):
+    return ctx.pfe_sign_apply(b, a_scale, shifts, weights, l, tol, max_outer, pass_, **kw)
+
+
+def pfe_sign_backward(ctx: Context, b, eta, a_scale, shifts, weights, l, tol, max_outer, **kw):
+    return ctx.pfe_sign_backward(b, eta, a_scale, shifts, weights, l, tol, max_outer, **kw)

@@ -1,0 +1,214 @@
+"""GPU parity of the multi-shift solver against the oracle.
+
+FP64: with the freeze iterations M_s forced to the oracle's (the hook both
+sides implement), the GPU's y and every x_s match the oracle's iteration to
+1e-10 relative; unforced runs match at the solver tolerance.  Double-pass is
+checked against the oracle's double-pass and against the GPU single-pass.
+Mixed precision is checked against the FP64 oracle at the solver tolerance.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import dirac as od
+from oracle import krylov as ok
+from oracle import pfe
+from oracle import sign as osg
+from tests.helpers import A_SCALE_BOUND, cuda, host, log, problem, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def ctx_for(wk, U):
+    from paper_1010_2592_amd import msb
+    return msb.Context(msb.Lattice(wk.dims, wk.mass, wk.mu, wk.bc_t), cuda(U))
+
+
+def oracle_run(op, a, b, sig, w, l, tol, max_outer, pass_, force=None):
+    return ok.mshift_bicgstabl(lambda v: op.a_op(v, a), b, sig, w, l, tol, max_outer, pass_,
+                               force_iters=force)
+
+
+@pytest.mark.parametrize("l", [1, 2, 3, 4])
+def test_single_pass_forced_matches_oracle(l):
+    wk, U, op, a, sig, w, b = problem("4x4x4x8")
+    log(f"single-pass forced 4x4x4x8 l={l}")
+    y0, i0, X0 = oracle_run(op, a, b[0], sig, w, l, wk.tol, 2000, 1)
+    ctx = ctx_for(wk, U)
+    y, info, xs = ctx.mshift_bicgstabl(cuda(b), a, sig, w, l, wk.tol, 2000, 1,
+                                       want_shifts=True, force_iters=i0.shift_iters)
+    assert np.array_equal(info.shift_iters[0], i0.shift_iters)
+    assert info.outer_iters == i0.outer
+    assert rel(host(y)[0], y0) <= 1e-10
+    xs = host(xs)[0]
+    for s in range(len(sig)):
+        assert rel(xs[s], X0[s]) <= 1e-10, s
+    assert info.mv_count == 2 * info.outer_iters * l
+    assert info.dot_count == info.outer_iters * l * (0.5 * l + 3.5)
+
+
+@pytest.mark.parametrize("l", [1, 2, 4])
+def test_double_pass_forced_matches_oracle(l):
+    wk, U, op, a, sig, w, b = problem("4x4x4x8")
+    log(f"double-pass forced 4x4x4x8 l={l}")
+    y1, i1, _ = oracle_run(op, a, b[0], sig, w, l, wk.tol, 2000, 1)
+    y2, i2 = oracle_run(op, a, b[0], sig, w, l, wk.tol, 2000, 2, force=i1.shift_iters)
+    ctx = ctx_for(wk, U)
+    y, info, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, l, wk.tol, 2000, 2,
+                                      force_iters=i1.shift_iters)
+    assert rel(host(y)[0], y2) <= 1e-10
+    ys, infos, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, l, wk.tol, 2000, 1,
+                                        force_iters=i1.shift_iters)
+    assert rel(host(y), host(ys)) <= 1e-11
+    # Section 3 cost table: double the Mv, the same inner products
+    assert info.mv_count == 2 * infos.mv_count
+    assert info.dot_count == infos.dot_count
+
+
+@pytest.mark.parametrize("pass_", [1, 2])
+def test_unforced_matches_oracle_at_tolerance(pass_):
+    wk, U, op, a, sig, w, b = problem("4x4x4x8")
+    log(f"unforced pass {pass_}")
+    y0, i0 = oracle_run(op, a, b[0], sig, w, 2, wk.tol, 2000, pass_)[:2]
+    ctx = ctx_for(wk, U)
+    y, info, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 2, wk.tol, 2000, pass_)
+    assert info.status == 0
+    assert np.all(np.abs(info.shift_iters[0] - i0.shift_iters) <= 1)
+    assert rel(host(y)[0], y0) <= 1e-7
+    assert np.all(info.shift_resid[0] <= wk.tol)
+
+
+def test_true_residuals_meet_tolerance():
+    wk, U, op, a, sig, w, b = problem("4x4x4x8")
+    ctx = ctx_for(wk, U)
+    y, info, xs = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 2, wk.tol, 2000, 1, want_shifts=True,
+                                       true_resid=True)
+    xs = host(xs)[0]
+    S = op.seed_op(a, 0.0)
+    for s in range(len(sig)):
+        r = np.linalg.norm(b[0] - S(xs[s]) - sig[s] * xs[s]) / np.linalg.norm(b[0])
+        assert abs(r - info.shift_true_resid[0, s]) <= 1e-6 * r + 1e-15
+        assert r <= 1.5 * wk.tol
+
+
+def test_batched_rhs_with_separate_shift_sets():
+    wk, U, op, a, sig, w, b = problem("4x4x4x8")
+    log("batched rhs, two shift sets")
+    bb = wl.gaussian_source(wk.dims, 77, 3)
+    s2, w2 = pfe.neuberger(6)
+    sets_s = np.zeros((3, 10))
+    sets_w = np.zeros((3, 10))
+    # rhs 0, 2: 10-pole set; rhs 1: 6 poles padded with zero-weight copies
+    sets_s[0], sets_w[0] = sig, w
+    sets_s[2], sets_w[2] = sig, w
+    sets_s[1, :6], sets_w[1, :6] = s2, w2
+    sets_s[1, 6:], sets_w[1, 6:] = s2[-1] * 2, 0.0
+    refs, iters = [], []
+    for r in range(3):
+        yr, ir, _ = oracle_run(op, a, bb[r], sets_s[r], sets_w[r], 2, wk.tol, 2000, 1)
+        refs.append(yr)
+        iters.append(ir.shift_iters)
+    ctx = ctx_for(wk, U)
+    for pass_ in (1, 2):
+        y, info, _ = ctx.mshift_bicgstabl(cuda(bb), a, sets_s, sets_w, 2, wk.tol, 2000, pass_,
+                                          force_iters=np.stack(iters))
+        for r in range(3):
+            assert rel(host(y)[r], refs[r]) <= 1e-10, (pass_, r)
+
+
+def test_deterministic_bitwise():
+    wk, U, op, a, sig, w, b = problem("4x4x4x8")
+    ctx = ctx_for(wk, U)
+    r1 = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 2, wk.tol, 2000, 2)[0]
+    r2 = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 2, wk.tol, 2000, 2)[0]
+    assert np.array_equal(host(r1), host(r2))
+
+
+def test_free_field_plane_wave_exhausts_krylov_space():
+    from paper_1010_2592_amd import msb
+    dims = (4, 4, 4, 8)
+    Lx, Ly, Lz, Lt = dims
+    mu, m = 0.05, -2.0
+    U = wl.free_links(dims)
+    a = 1 / 36.5
+    t, z, y_, x = np.meshgrid(np.arange(Lt), np.arange(Lz), np.arange(Ly), np.arange(Lx),
+                              indexing="ij")
+    p = [2 * np.pi / Lx, 4 * np.pi / Ly, 0.0, np.pi * 7 / Lt]
+    q = np.array(p, dtype=complex)
+    q[3] -= 1j * mu
+    phase = np.exp(1j * (p[0] * x + p[1] * y_ + p[2] * z + p[3] * t)).reshape(-1)
+    b = (np.arange(1, 13) * (1 + 0.5j))[:, None] * phase[None, :]
+    lam = a * ((4 + m - np.sum(np.cos(q))) ** 2 + np.sum(np.sin(q) ** 2))
+    sig, w = pfe.neuberger(10)
+    ctx = msb.Context(msb.Lattice(dims, m, mu, -1), cuda(U))
+    for l in (1, 2, 4):
+        y, info, xs = ctx.mshift_bicgstabl(cuda(b[None]), a, sig, w, l, 1e-8, 50, 1, want_shifts=True)
+        assert info.status == 0 and info.outer_iters == 1
+        xs = host(xs)[0]
+        for s in range(10):
+            assert rel(xs[s], b / (lam + sig[s])) <= 1e-12
+        y2, info2, _ = ctx.mshift_bicgstabl(cuda(b[None]), a, sig, w, l, 1e-8, 50, 2)
+        assert rel(host(y2)[0], host(y)[0]) <= 1e-12
+
+
+def test_status_not_converged_and_nan_source():
+    from paper_1010_2592_amd import msb
+    wk, U, op, a, sig, w, b = problem("4x4x4x8")
+    ctx = ctx_for(wk, U)
+    y, info, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 2, wk.tol, 1, 1,
+                                      allow=(msb.NOT_CONVERGED,))
+    assert info.status == msb.NOT_CONVERGED and info.outer_iters == 1
+    bn = b.copy()
+    bn[0, 3, 7] = np.nan
+    with pytest.raises(msb.MsbError) as e:
+        ctx.mshift_bicgstabl(cuda(bn), a, sig, w, 2, wk.tol, 100, 1)
+    assert e.value.status == msb.ERR_ARG
+    with pytest.raises(msb.MsbError):
+        ctx.mshift_bicgstabl(cuda(b), a, sig, w, 9, wk.tol, 100, 1)   # l > 8
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_sign_apply_matches_oracle(overlap):
+    from paper_1010_2592_amd import msb
+    wk, U, op, a, sig, w, b = problem("4x4x4x8")
+    ref, rinfo = osg.pfe_sign_apply(op, a, b[0], sig, w, 2, wk.tol, 2000, 1, overlap=overlap)
+    ctx = ctx_for(wk, U)
+    out, info = ctx.pfe_sign_apply(cuda(b), a, sig, w, 2, wk.tol, 2000, 1,
+                                   flags=msb.OVERLAP if overlap else 0,
+                                   force_iters=rinfo.shift_iters)
+    assert rel(host(out)[0], ref) <= 1e-10
+
+
+@pytest.mark.parametrize("pass_", [1, 2])
+def test_mixed_precision_against_fp64_oracle(pass_):
+    from paper_1010_2592_amd import msb
+    wk, U, op, a, sig, w, b = problem("8x8x8x8")
+    log(f"mixed precision 8^4 pass {pass_}")
+    y0, i0 = oracle_run(op, a, b[0], sig, w, 4, wk.tol, 3000, 1)[:2]
+    ctx = ctx_for(wk, U)
+    y, info, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 4, wk.tol, 3000, pass_,
+                                      flags=msb.MIXED, allow=(msb.OK, msb.NOT_CONVERGED))
+    err = rel(host(y)[0], y0)
+    log(f"mixed pass {pass_}: rel err vs FP64 oracle {err:.3e}, outer {info.outer_iters} "
+        f"(oracle {i0.outer})")
+    assert err <= 1e-4
+
+
+def test_production_lattice_fixed_iterations():
+    """16^3x32 (one of the 12 point sources), 2 forced outer iterations, l = 2,
+    N_s = 30: single- and double-pass against the oracle's iteration."""
+    from paper_1010_2592_amd import msb
+    wk = wl.WORKLOADS["16x16x16x32"]
+    log("16x16x16x32 fixed-iteration parity")
+    U = wk.links()
+    op = od.Dirac(U, wk.dims, wk.mass, wk.mu, wk.bc_t)
+    b = wl.point_sources(wk.dims)[[7]]
+    sig, w = pfe.neuberger(wk.n_shift)
+    a = A_SCALE_BOUND
+    force = np.full(len(sig), 2)
+    ref = oracle_run(op, a, b[0], sig, w, 2, wk.tol, 2, 1, force=force)[0]
+    ctx = ctx_for(wk, U)
+    for pass_ in (1, 2):
+        y, info, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 2, wk.tol, 2, pass_, force_iters=force,
+                                          allow=(msb.OK, msb.NOT_CONVERGED))
+        assert rel(host(y)[0], ref) <= 1e-10, pass_
