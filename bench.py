@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Benchmark of f(A) b = sum_s w_s (A + sigma_s)^{-1} b on one MI355X.
+
+Workload: 16^3x32 lattice, SU(3) links exp(i 0.5 H) (seeded), Wilson mass -2,
+mu = 0.05, antiperiodic in time; A = a (gamma5 D_w)^2 with a from the GPU
+power iteration; Neuberger PFE with N_s = 30 poles; BiCGstab(l = 4); the 12
+spin-colour point sources at the origin solved as one batch; tolerance 1e-8 on
+every shift's relative residual.
+
+One step = one f(A) b evaluation of the 12-source batch in the headline form
+(--pass, --precision).  ``value`` is f(A) b evaluations (one per source) per
+second over the K timed steps.  Every kernel launch inside the timed steps is
+bracketed by HIP events on its stream (the library's timing hook); the stencil
+kernel's algorithmic bytes over its summed event time give roofline.achieved.
+The other forms (single-pass / double-pass, FP64 / mixed) run once each
+afterwards for the comparison block.  The CPU oracle is timed on a bounded
+sample (one outer iteration of one source) and extrapolated.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "f(A)b time & HBM GB/s, 16^3x32, 1e-8 err; 2- vs 1-pass, mixed vs FP64"
+WORKLOAD = "16x16x16x32"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_variant(ctx, b, a, sig, w, l, tol, max_outer, pass_, mixed, profile=False):
+    import torch
+    from paper_1010_2592_amd import msb
+    flags = msb.MIXED if mixed else 0
+    if profile:
+        ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    y, info, _ = ctx.mshift_bicgstabl(b, a, sig, w, l, tol, max_outer, pass_, flags=flags,
+                                      allow=(msb.OK, msb.NOT_CONVERGED))
+    e1.record()
+    torch.cuda.synchronize()
+    prof = ctx.profile_read() if profile else None
+    if profile:
+        ctx.profile_enable(False)
+    return y, info, e0.elapsed_time(e1), prof
+
+
+def measured_traffic(pass_, precision):
+    """HBM bytes per stencil launch from the committed rocprofv3 counter runs,
+    or None when the stencil source changed since they were taken or the
+    form differs from the one they were taken on."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "dslash_traffic.json")))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    if rec.get("workload") != f"{WORKLOAD.replace('x', 'x')} 12 rhs {precision} pass {pass_}":
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
+def cpu_baseline(wk, a, sig, w, l, M_gpu):
+    """The oracle's double-pass on one point source for one outer iteration
+    (l BiCG steps, both passes), extrapolated linearly to the GPU's M."""
+    import numpy as np
+
+    import workloads as wl
+    from oracle import dirac as od
+    from oracle import krylov as ok
+    U = wk.links()
+    op = od.Dirac(U, wk.dims, wk.mass, wk.mu, wk.bc_t)
+    b = wl.point_sources(wk.dims)[0]
+    t0 = time.perf_counter()
+    ok.mshift_bicgstabl(lambda v: op.a_op(v, a), b, sig, w, l, wk.tol, 1, 2,
+                        force_iters=np.ones(len(sig), dtype=int))
+    t_iter = time.perf_counter() - t0
+    t_fab = t_iter * M_gpu
+    return {"value": 1.0 / t_fab, "unit": "f(A)b/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle double-pass, 1 point source, 1 forced outer iteration "
+                      f"(l={l}: {4 * l} Mv) in {t_iter:.1f} s; extrapolated x{M_gpu} outer "
+                      f"iterations (the GPU run's M); NumPy single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--pass", dest="pass_", type=int, default=2, choices=(1, 2))
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
+    ap.add_argument("--variants", default="all", choices=("all", "none"))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--max-outer", type=int, default=2000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy a 1 GiB tensor 3 times (reference kernel of known size "
+                         "for the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU: the 12 sources are independent "
+                                   "and would shard one batch per GPU with no communication; run "
+                                   "with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1010_2592_amd import msb
+
+    wk = wl.WORKLOADS[WORKLOAD]
+    l = wk.ells[0]
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        xc = torch.ones(1 << 26, dtype=torch.complex128, device=dev)   # 1 GiB
+        for _ in range(3):
+            yc = xc.clone()
+        torch.cuda.synchronize()
+        del xc, yc
+        log("[bench] copy calibration: 3 x clone of 1 GiB")
+    log(f"[bench] building inputs {WORKLOAD}")
+    U = torch.from_numpy(wk.links()).to(dev)
+    b = torch.from_numpy(wl.point_sources(wk.dims)).to(dev)
+    ctx = msb.Context(msb.Lattice(wk.dims, wk.mass, wk.mu, wk.bc_t), U)
+    rho = ctx.spectral_radius(torch.from_numpy(wk.power_start()[None]).to(dev), 100)
+    a = 1.0 / (1.01 * rho)
+    sig, w = msb.neuberger_pfe(wk.n_shift)
+    mixed = args.precision == "mixed"
+    log(f"[bench] spectral radius {rho:.6f}; headline pass={args.pass_} {args.precision}")
+
+    for i in range(args.warmup):
+        _, info, ms, _ = run_variant(ctx, b, a, sig, w, l, wk.tol, args.max_outer, args.pass_, mixed)
+        log(f"[bench] warmup {i}: {ms:.1f} ms, M={info.outer_iters}, status {info.status}")
+
+    # ---- timed steps (library timing hook on) ----
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    infos = []
+    y = None
+    for k in range(args.steps):
+        y, info, _ = ctx.mshift_bicgstabl(b, a, sig, w, l, wk.tol, args.max_outer, args.pass_,
+                                          flags=msb.MIXED if mixed else 0,
+                                          allow=(msb.OK, msb.NOT_CONVERGED))
+        infos.append(info)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    nrhs = b.shape[0]
+    value = nrhs * args.steps / (ms_total / 1e3)
+    info = infos[-1]
+    st = prof["stencil"]
+    achieved = st["bytes"] / (st["ms"] / 1e3) / 1e9 if st["ms"] > 0 else 0.0
+    log(f"[bench] {args.steps} steps: {ms_step:.1f} ms/step (wall {wall:.2f} s), M={info.outer_iters}, "
+        f"Mv={info.mv_count}, stencil {achieved:.0f} GB/s over {st['count']} launches")
+    for k, v in prof.items():
+        if v["count"]:
+            gbs = v["bytes"] / (v["ms"] / 1e3) / 1e9 if v["ms"] > 0 else 0
+            log(f"[bench]   {k:16s} {v['count']:7d} launches {v['ms']:10.2f} ms {gbs:8.0f} GB/s")
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "f(A)b/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if not mixed else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{WORKLOAD} Wilson-Dirac mu=0.05 m=-2, 12 point sources, "
+                               f"Neuberger N_s={wk.n_shift}, BiCGstab(l={l}), tol {wk.tol}",
+                   "pass": args.pass_, "precision": args.precision, "rhs": nrhs,
+                   "n_shift": wk.n_shift, "l": l, "outer_iters": info.outer_iters,
+                   "mv_count": info.mv_count, "status": info.status,
+                   "max_shift_resid": float(np.max(info.shift_resid))},
+        "hbm_GBps_whole_call": round(info.bytes_model / (ms_step / 1e3) / 1e9, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args.pass_, args.precision),
+                     "kernel": "dslash (Wilson stencil, all epilogues)",
+                     "launches": st["count"],
+                     "avg_launch_us": round(st["ms"] * 1e3 / max(st["count"], 1), 2),
+                     "bytes_per_launch": round(st["bytes"] / max(st["count"], 1))},
+        "kernel_classes": {k: {"launches": v["count"], "ms": round(v["ms"], 3),
+                               "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None}
+                           for k, v in prof.items() if v["count"]},
+    }
+
+    # ---- comparison forms, one run each ----
+    if args.variants == "all":
+        comps = {}
+        ref = None
+        for (p, mx) in ((1, False), (2, False)):
+            name = f"{p}pass-{'mixed' if mx else 'fp64'}"
+            try:
+                yv, iv, msv, pv = run_variant(ctx, b, a, sig, w, l, wk.tol, args.max_outer, p, mx,
+                                              profile=True)
+            except msb.MsbError as e:
+                comps[name] = {"error": str(e)}
+                continue
+            if ref is None:
+                ref = yv
+            err = float(torch.linalg.norm(yv - ref) / torch.linalg.norm(ref))
+            comps[name] = {"ms": round(msv, 2), "outer_iters": iv.outer_iters, "mv": iv.mv_count,
+                           "status": iv.status, "GBps_model": round(iv.bytes_model / (msv / 1e3) / 1e9, 1),
+                           "rel_diff_vs_1pass_fp64": err,
+                           "max_shift_resid": float(np.max(iv.shift_resid)),
+                           "shift_update_GBps": (round(pv["shift_update"]["bytes"] / (pv["shift_update"]["ms"] / 1e3) / 1e9, 1)
+                                                 if pv["shift_update"]["ms"] > 0 else None),
+                           "stencil_GBps": (round(pv["stencil"]["bytes"] / (pv["stencil"]["ms"] / 1e3) / 1e9, 1)
+                                            if pv["stencil"]["ms"] > 0 else None)}
+            log(f"[bench] {name}: {comps[name]}")
+            del yv
+            torch.cuda.empty_cache()
+        result["variants"] = comps
+
+    if not args.no_cpu:
+        log("[bench] CPU oracle sample ...")
+        result["cpu_baseline"] = cpu_baseline(wk, a, sig, w, l, int(info.outer_iters))
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -116,6 +116,21 @@ int msb_neuberger_pfe(int n, double *sigma, double *weight);
  * The scale convention of the solvers is a_scale = 1 / (1.01 * rho). */
 int msb_spectral_radius(msb_ctx *ctx, const void *start, int iters, double *rho);
 
+/* Kernel timing of later calls on this context, a measurement aid: with
+ * enable != 0 every kernel launch of the solvers is bracketed by a pair of HIP
+ * events on the context's stream (previous records are dropped); 0 stops
+ * recording.  Synchronises the stream. */
+int msb_profile_enable(msb_ctx *ctx, int enable);
+
+/* Totals of the recorded launches per kernel class k < n_classes (host arrays
+ * of n_classes): count[k] launches, ms[k] summed event time, bytes[k] summed
+ * algorithmic HBM bytes (every operand of a launch read or written once).
+ * Classes: 0 stencil (D_w applications, all epilogues), 1 fused all-shift
+ * update of a BiCG step, 2 fused all-shift MR update, 3 seed vector kernels,
+ * 4 device scalar kernels, 5 set-up and output kernels.  Synchronises. */
+int msb_profile_read(msb_ctx *ctx, int n_classes, long long *count, double *ms,
+                     double *bytes);
+
 /* out = D_w(mu) in (flags MSB_G5_LEFT, MSB_NEG_MU, MSB_DAGGER, MSB_MIXED).
  * The operator the paper names in Section 1.  in, out: device
  * [nrhs][12][V] complex128, must not overlap. */

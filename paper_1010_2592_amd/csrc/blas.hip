@@ -96,7 +96,7 @@ __global__ __launch_bounds__(BLOCK) void k_r_update(VecArgs<T> a) {
         }
     }
     if (a.partials)
-        block_reduce_store<1>(part, a.part + (size_t)rhs * PMAX * NBMAX + 3 * NBMAX + blockIdx.x, NBMAX);
+        block_reduce_store<1>(part, a.part + (size_t)rhs * PMAX * a.ps + 3 * a.ps + blockIdx.x, a.ps);
 }
 
 template <typename T, int L>
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(BLOCK) void k_gram(VecArgs<T> a) {
                 ++p;
             }
     }
-    block_reduce_store<2 * NP>(acc, a.part + (size_t)rhs * PMAX * NBMAX + blockIdx.x, NBMAX);
+    block_reduce_store<2 * NP>(acc, a.part + (size_t)rhs * PMAX * a.ps + blockIdx.x, a.ps);
 }
 
 template <typename T, int L, bool SHIFTS>
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(BLOCK) void k_mr_update(VecArgs<T> a) {
         }
     }
     if (a.partials)
-        block_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * NBMAX + blockIdx.x, NBMAX);
+        block_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + blockIdx.x, a.ps);
 }
 
 // ---------------------------------------------------------------------------
@@ -212,7 +212,7 @@ __global__ void k_zero(C<T> *dst, long n, long stride) {
 
 // partials: slot 0,1 = <x, y>, slot 2 = ||y||^2
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_dot(const C<T> *x, const C<T> *y, long n, double *part, Gate gate) {
+__global__ __launch_bounds__(BLOCK) void k_dot(const C<T> *x, const C<T> *y, long n, double *part, long ps, Gate gate) {
     const int rhs = blockIdx.y;
     if (!gate_open(gate, rhs)) return;
     double p[3] = {0.0, 0.0, 0.0};
@@ -223,13 +223,13 @@ __global__ __launch_bounds__(BLOCK) void k_dot(const C<T> *x, const C<T> *y, lon
         p[1] += (double)a.x * b.y - (double)a.y * b.x;
         p[2] += (double)b.x * b.x + (double)b.y * b.y;
     }
-    block_reduce_store<3>(p, part + (size_t)rhs * PMAX * NBMAX + blockIdx.x, NBMAX);
+    block_reduce_store<3>(p, part + (size_t)rhs * PMAX * ps + blockIdx.x, ps);
 }
 
 // partial slot 0 = ||x - y||^2
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_diffnorm(const C<T> *x, const C<T> *y, long n, long sx, long sy,
-                                                    double *part) {
+                                                    double *part, long ps) {
     const int rhs = blockIdx.y;
     double p[1] = {0.0};
     const C<T> *xr = x + (size_t)rhs * sx, *yr = y + (size_t)rhs * sy;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(BLOCK) void k_diffnorm(const C<T> *x, const C<T> *y
         const double dx = (double)a.x - b.x, dy = (double)a.y - b.y;
         p[0] += dx * dx + dy * dy;
     }
-    block_reduce_store<1>(p, part + (size_t)rhs * PMAX * NBMAX + blockIdx.x, NBMAX);
+    block_reduce_store<1>(p, part + (size_t)rhs * PMAX * ps + blockIdx.x, ps);
 }
 
 template <typename T>
@@ -357,14 +357,14 @@ void launch_zero(hipStream_t st, C<T> *dst, long n, long stride, int nrhs) {
     hipLaunchKernelGGL((k_zero<T>), dim3(nblocks_for(n), nrhs), dim3(BLOCK), 0, st, dst, n, stride);
 }
 template <typename T>
-void launch_dot_partials(hipStream_t st, const C<T> *x, const C<T> *y, long n, double *part, int nrhs,
-                         int nblk, Gate gate) {
-    hipLaunchKernelGGL((k_dot<T>), dim3(nblk, nrhs), dim3(BLOCK), 0, st, x, y, n, part, gate);
+void launch_dot_partials(hipStream_t st, const C<T> *x, const C<T> *y, long n, double *part, long ps,
+                         int nrhs, int nblk, Gate gate) {
+    hipLaunchKernelGGL((k_dot<T>), dim3(nblk, nrhs), dim3(BLOCK), 0, st, x, y, n, part, ps, gate);
 }
 template <typename T>
 void launch_diffnorm_partials(hipStream_t st, const C<T> *x, const C<T> *y, long n, long sx, long sy,
-                              double *part, int nrhs, int nblk) {
-    hipLaunchKernelGGL((k_diffnorm<T>), dim3(nblk, nrhs), dim3(BLOCK), 0, st, x, y, n, sx, sy, part);
+                              double *part, long ps, int nrhs, int nblk) {
+    hipLaunchKernelGGL((k_diffnorm<T>), dim3(nblk, nrhs), dim3(BLOCK), 0, st, x, y, n, sx, sy, part, ps);
 }
 template <typename T>
 void launch_ysum(hipStream_t st, double2 *y, const C<T> *X, const double *w, long n, int ns, int nrhs, int nblk) {
@@ -389,8 +389,8 @@ void launch_axpy_host(hipStream_t st, double2 *y, const double2 *x, double2 a, l
     template void launch_convert_in<T>(hipStream_t, C<T> *, const double2 *, long, long, long, int); \
     template void launch_convert_out<T>(hipStream_t, double2 *, const C<T> *, long, long, long, int); \
     template void launch_zero<T>(hipStream_t, C<T> *, long, long, int);                          \
-    template void launch_dot_partials<T>(hipStream_t, const C<T> *, const C<T> *, long, double *, int, int, Gate); \
-    template void launch_diffnorm_partials<T>(hipStream_t, const C<T> *, const C<T> *, long, long, long, double *, int, int); \
+    template void launch_dot_partials<T>(hipStream_t, const C<T> *, const C<T> *, long, double *, long, int, int, Gate); \
+    template void launch_diffnorm_partials<T>(hipStream_t, const C<T> *, const C<T> *, long, long, long, double *, long, int, int); \
     template void launch_ysum<T>(hipStream_t, double2 *, const C<T> *, const double *, long, int, int, int);
 INST(double)
 INST(float)

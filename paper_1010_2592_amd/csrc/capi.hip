@@ -163,6 +163,16 @@ int msb_spectral_radius(msb_ctx *ctx, const void *start, int iters, double *rho)
     return msb::spectral_radius(&ctx->c, (const double2 *)start, iters, rho);
 }
 
+int msb_profile_enable(msb_ctx *ctx, int enable) {
+    if (!ctx) return arg_error("msb_profile_enable: null context");
+    return msb::profile_enable(&ctx->c, enable != 0);
+}
+
+int msb_profile_read(msb_ctx *ctx, int n_classes, long long *count, double *ms, double *bytes) {
+    if (!ctx || !count || !ms || !bytes || n_classes < 1) return arg_error("msb_profile_read: bad argument");
+    return msb::profile_read(&ctx->c, n_classes, count, ms, bytes);
+}
+
 int wilson_apply(msb_ctx *ctx, const void *in, void *out, int nrhs, int flags) {
     if (!ctx || !in || !out) return arg_error("wilson_apply: null argument");
     if (in == out) return arg_error("wilson_apply: in and out must not overlap");

@@ -217,6 +217,13 @@ __device__ inline bool gate_open(const Gate &g, int rhs) {
     return true;
 }
 
+// Row length of the reduction-partial buffer: one entry per block of the
+// widest reducing launch (the stencil uses one block per 256 sites).
+inline long part_stride(const Geom &g) {
+    const long nsb = ((long)g.V + BLOCK - 1) / BLOCK;
+    return nsb > NBMAX ? nsb : NBMAX;
+}
+
 inline int nblocks_for(long n) {
     long b = (n + BLOCK - 1) / BLOCK;
     if (b < 1) b = 1;

@@ -29,7 +29,35 @@ struct Ctx {
         ws_cb, ws_aux1, ws_aux2, ws_aux3, ws_aux4;
     void *host_pinned = nullptr;
     size_t host_pinned_bytes = 0;
+    // kernel timing (msb_profile_enable): HIP event pairs around launches
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct Rec {
+        int cls;
+        double bytes;
+        hipEvent_t e0, e1;
+    };
+    std::vector<Rec> recs;
+    double bytes_acc = 0;      // algorithmic bytes of the current call
 };
+
+// kernel classes of the timing hook
+enum { CL_STENCIL = 0, CL_SHIFT = 1, CL_SHIFT_MR = 2, CL_SEED = 3, CL_SCALAR = 4, CL_OTHER = 5,
+       CL_COUNT = 6 };
+
+// Scope that records a HIP event pair around the launches inside it (when
+// profiling) and adds the launch's algorithmic bytes to the call's model.
+struct Prof {
+    Ctx *c;
+    int cls;
+    double bytes;
+    hipEvent_t e0 = nullptr;
+    Prof(Ctx *c_, int cls_, double bytes_);
+    ~Prof();
+};
+int profile_enable(Ctx *c, bool on);
+int profile_read(Ctx *c, int ncls, long long *count, double *ms, double *bytes);
 
 // All solver parameters of one call (shifts and weights already expanded to
 // one set per right-hand side).

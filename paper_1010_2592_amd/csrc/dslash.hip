@@ -5,8 +5,7 @@
 //     - 1/2 sum_nu b_nu(x-nu)(1 + gamma_nu) e^{-mu d_nu4} U_nu(x-nu)^+ psi(x-nu)
 //
 // The operator the paper names in Section 1; chiral gamma matrices.  One
-// work-item per lattice site (grid-stride), one block row per right-hand
-// side.  Each hop loads the neighbour's 12 complex components (coalesced SoA
+// work-item per lattice site and right-hand side.  Each hop loads the neighbour's 12 complex components (coalesced SoA
 // planes), projects them to a two-component half spinor with (1 -/+ gamma),
 // multiplies the half spinor by the 3x3 link, and reconstructs the lower spin
 // components from the upper ones.  The kernel is HBM-bound (about 1.4 flop
@@ -122,9 +121,19 @@ __device__ __forceinline__ void hop(C<T> (&acc)[4][3], const C<T> *__restrict__ 
     }
 }
 
+// One block per (256-site block, right-hand side).  The flattened grid is
+// padded to a multiple of 8 and mapped XCD-aware: hardware block p runs on
+// XCD p % 8, which here owns the contiguous logical range
+// [(p % 8) per, (p % 8 + 1) per); inside it the right-hand side varies fastest,
+// so the 12 sources of one site block run back to back on one XCD and share
+// its L2 copy of the links and of the neighbouring planes.
 template <typename T, int EPI, bool G5IN>
 __global__ __launch_bounds__(BLOCK) void dslash_kernel(DslashArgs<T> a) {
-    const int rhs = blockIdx.y;
+    const int p = blockIdx.x;
+    const int L = (p & 7) * a.per + (p >> 3);
+    if (L >= a.nsb * a.nrhs) return;
+    const int sblk = L / a.nrhs;
+    const int rhs = L - sblk * a.nrhs;
     if (!gate_open(a.gate, rhs)) return;
     const int V = a.g.V, Lx = a.g.Lx, Ly = a.g.Ly, Lz = a.g.Lz, Lt = a.g.Lt;
     const long nv = 12L * V;
@@ -137,10 +146,12 @@ __global__ __launch_bounds__(BLOCK) void dslash_kernel(DslashArgs<T> a) {
     C<T> yc = mk<T>(0, 0);
     if (EPI == EPI_MV_Y) yc = to_c<T>(ld(a.ycoef, rhs));
     const T sig0 = a.sigma0_rhs ? (T)a.sigma0_rhs[rhs] : a.sigma0;
-    const int sxy = Lx * Ly, sxyz = Lx * Ly * Lz;
     double part[3] = {0.0, 0.0, 0.0};
-
-    for (int s = blockIdx.x * BLOCK + threadIdx.x; s < V; s += gridDim.x * BLOCK) {
+    // a.sstride exceeds V, so the loop body runs at most once; keeping it a
+    // loop with a run-time bound stops the compiler from hoisting every load
+    // of the eight hops at once (which needs more than 256 VGPRs and spills)
+    for (int s = sblk * BLOCK + threadIdx.x; s < V; s += a.sstride) {
+        const int sxy = Lx * Ly, sxyz = Lx * Ly * Lz;
         const int x = s % Lx;
         const int r1 = s / Lx;
         const int yy = r1 % Ly;
@@ -207,15 +218,20 @@ __global__ __launch_bounds__(BLOCK) void dslash_kernel(DslashArgs<T> a) {
         }
     }
     if (EPI == EPI_MV)
-        block_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * NBMAX + blockIdx.x, NBMAX);
+        block_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + sblk, a.ps);
 }
 
 }  // namespace
 
 template <typename T>
-void launch_dslash(hipStream_t st, const DslashArgs<T> &a, int nrhs, int epi, bool g5in, int nblk) {
-    dim3 grid(nblk, nrhs), block(BLOCK);
-#define MSB_DS(E, G) hipLaunchKernelGGL((dslash_kernel<T, E, G>), grid, block, 0, st, a)
+void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in) {
+    a.nsb = (a.g.V + BLOCK - 1) / BLOCK;
+    a.nrhs = nrhs;
+    const long G = (long)a.nsb * nrhs;
+    a.per = (int)((G + 7) / 8);
+    a.sstride = 1 << 30;
+    dim3 grid((unsigned)(8L * a.per)), block(BLOCK);
+#define MSB_DS(E, G5) hipLaunchKernelGGL((dslash_kernel<T, E, G5>), grid, block, 0, st, a)
     if (g5in) {
         if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, true);
         else if (epi == EPI_MV) MSB_DS(EPI_MV, true);
@@ -230,7 +246,7 @@ void launch_dslash(hipStream_t st, const DslashArgs<T> &a, int nrhs, int epi, bo
 #undef MSB_DS
 }
 
-template void launch_dslash<double>(hipStream_t, const DslashArgs<double> &, int, int, bool, int);
-template void launch_dslash<float>(hipStream_t, const DslashArgs<float> &, int, int, bool, int);
+template void launch_dslash<double>(hipStream_t, DslashArgs<double>, int, int, bool);
+template void launch_dslash<float>(hipStream_t, DslashArgs<float>, int, int, bool);
 
 }  // namespace msb

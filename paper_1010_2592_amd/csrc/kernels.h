@@ -29,7 +29,12 @@ struct DslashArgs {
     const double *sigma0_rhs = nullptr;  // if set: per-rhs sigma0 (overrides sigma0)
     const C<T> *v = nullptr;   // EPI_MV*: + sigma0 * v
     const C<T> *rt = nullptr;  // EPI_MV: partials of <rt, out>
-    double *part = nullptr;    // [rhs][PMAX][NBMAX]
+    double *part = nullptr;    // [rhs][PMAX][ps]
+    long ps = NBMAX;           // partial row stride
+    int nsb = 0;               // site blocks (set by the launcher)
+    int per = 0;               // blocks per XCD in the flattened grid (set by the launcher)
+    int sstride = 0;           // site-loop stride (set by the launcher)
+    int nrhs = 0;
     CoefRef ycoef;             // EPI_MV_Y: coefficient of the Mv output
     double2 *y = nullptr;      // EPI_MV_Y accumulator (always FP64)
     Gate gate{};
@@ -37,8 +42,10 @@ struct DslashArgs {
     long in_rs = 0, out_rs = 0, v_rs = 0, rt_rs = 0, y_rs = 0;
 };
 
+// One block per (256-site block, right-hand side); the launcher sets nsb, per
+// and nrhs.
 template <typename T>
-void launch_dslash(hipStream_t st, const DslashArgs<T> &a, int nrhs, int epi, bool g5in, int nblk);
+void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in);
 
 // ---- vector kernels ------------------------------------------------------
 template <typename T>
@@ -52,6 +59,7 @@ struct VecArgs {
     C<T> *X = nullptr;          // [rhs][nshift][n]       (pass 1)
     const C<T> *rt = nullptr;   // [rhs][n] shadow residual
     double *part = nullptr;
+    long ps = NBMAX;            // partial row stride
     const SeedState *seed = nullptr;
     const StepCoef *sc = nullptr;   // [rhs][NSMAX]
     const MRCoef *mc = nullptr;     // [rhs][NSMAX]
@@ -76,11 +84,11 @@ void launch_convert_out(hipStream_t, double2 *dst, const C<T> *src, long n, long
 template <typename T>
 void launch_zero(hipStream_t, C<T> *dst, long n, long stride, int nrhs);
 template <typename T>
-void launch_dot_partials(hipStream_t, const C<T> *x, const C<T> *y, long n, double *part, int nrhs,
-                         int nblk, Gate gate);
+void launch_dot_partials(hipStream_t, const C<T> *x, const C<T> *y, long n, double *part, long ps,
+                         int nrhs, int nblk, Gate gate);
 template <typename T>
 void launch_diffnorm_partials(hipStream_t, const C<T> *x, const C<T> *y, long n, long sx, long sy,
-                              double *part, int nrhs, int nblk);
+                              double *part, long ps, int nrhs, int nblk);
 // y[rhs] = sum_s w[rhs][s] X[rhs][s]   (X stride n per shift, nshift per rhs)
 template <typename T>
 void launch_ysum(hipStream_t, double2 *y, const C<T> *X, const double *w, long n, int nshift,
@@ -104,6 +112,7 @@ struct ScalarArgs {
     double2 *tape_gam = nullptr;    // [rhs][max_outer][LMAX]
     TapeOuter *tape_outer = nullptr;  // [rhs][max_outer]
     const double *part = nullptr;
+    long ps = NBMAX;                // partial row stride
     int nblk = 0;                   // blocks that wrote the partials consumed
     int nblk2 = 0;                  // blocks of the second partial source
     int l = 0;

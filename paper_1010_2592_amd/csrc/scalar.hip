@@ -35,7 +35,7 @@ __device__ inline double2 cpowi_neg(double sp, int i) {
 }
 
 __device__ inline const double *prow(const ScalarArgs &a, int rhs) {
-    return a.part + (size_t)rhs * PMAX * NBMAX;
+    return a.part + (size_t)rhs * PMAX * a.ps;
 }
 
 __global__ __launch_bounds__(BLOCK) void sc_init(ScalarArgs a) {
@@ -43,8 +43,8 @@ __global__ __launch_bounds__(BLOCK) void sc_init(ScalarArgs a) {
     SeedState &S = a.seed[rhs];
     const double *row = prow(a, rhs);
     const double re = block_sum(row, a.nblk);
-    const double im = block_sum(row + NBMAX, a.nblk);
-    const double nb2 = block_sum(row + 2 * NBMAX, a.nblk);
+    const double im = block_sum(row + a.ps, a.nblk);
+    const double nb2 = block_sum(row + 2 * a.ps, a.nblk);
     if (threadIdx.x == 0) {
         S.rho1 = d2(re, im);
         S.bnorm = sqrt(nb2);
@@ -89,10 +89,10 @@ __global__ __launch_bounds__(BLOCK) void sc_beta(ScalarArgs a) {
     const int j = a.j;
     const double *row = prow(a, rhs);
     const double re = block_sum(row, a.nblk);
-    const double im = block_sum(row + NBMAX, a.nblk);
-    const double rj2 = block_sum(row + 2 * NBMAX, a.nblk);
+    const double im = block_sum(row + a.ps, a.nblk);
+    const double rj2 = block_sum(row + 2 * a.ps, a.nblk);
     double r02 = 0.0;
-    if (j >= 1) r02 = block_sum(row + 3 * NBMAX, a.nblk2);
+    if (j >= 1) r02 = block_sum(row + 3 * a.ps, a.nblk2);
     if (threadIdx.x != 0) return;
     if (j >= 1) S.rnorm0 = sqrt(r02);
     if (j >= 1 && !S.forced && S.nact > 0) {
@@ -140,8 +140,8 @@ __global__ __launch_bounds__(BLOCK) void sc_alpha(ScalarArgs a) {
     const int j = a.j;
     const double *row = prow(a, rhs);
     const double re = block_sum(row, a.nblk);
-    const double im = block_sum(row + NBMAX, a.nblk);
-    const double u2 = block_sum(row + 2 * NBMAX, a.nblk);
+    const double im = block_sum(row + a.ps, a.nblk);
+    const double u2 = block_sum(row + 2 * a.ps, a.nblk);
     __shared__ int ok;
     __shared__ double2 sh_alpha, sh_beta;
     if (threadIdx.x == 0) {
@@ -236,8 +236,8 @@ __global__ __launch_bounds__(BLOCK) void sc_mr(ScalarArgs a) {
     for (int i = 0; i <= L; ++i) {
         for (int k = (i == 0 ? 1 : i); k <= L; ++k) {
             const int p = pidx(i, k);
-            const double re = block_sum(row + (2 * p) * NBMAX, a.nblk);
-            const double im = block_sum(row + (2 * p + 1) * NBMAX, a.nblk);
+            const double re = block_sum(row + (2 * p) * a.ps, a.nblk);
+            const double im = block_sum(row + (2 * p + 1) * a.ps, a.nblk);
             if (threadIdx.x == 0) {
                 if (i == 0) {
                     cvec[k - 1] = d2(re, -im);   // <r_k, r_0> = conj(<r_0, r_k>)
@@ -338,8 +338,8 @@ __global__ __launch_bounds__(BLOCK) void sc_conv(ScalarArgs a) {
     if (!S.run) return;
     const double *row = prow(a, rhs);
     const double re = block_sum(row, a.nblk);
-    const double im = block_sum(row + NBMAX, a.nblk);
-    const double r02 = block_sum(row + 2 * NBMAX, a.nblk);
+    const double im = block_sum(row + a.ps, a.nblk);
+    const double r02 = block_sum(row + 2 * a.ps, a.nblk);
     __shared__ double rn;
     if (threadIdx.x == 0) {
         rn = sqrt(r02);

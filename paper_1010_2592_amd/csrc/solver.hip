@@ -82,6 +82,65 @@ static int ensure_host(Ctx *c, size_t bytes) {
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// kernel timing hook
+// ---------------------------------------------------------------------------
+static hipEvent_t pool_get(Ctx *c) {
+    if (c->ev_used < c->ev_pool.size()) return c->ev_pool[c->ev_used++];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    c->ev_pool.push_back(e);
+    c->ev_used++;
+    return e;
+}
+
+Prof::Prof(Ctx *c_, int cls_, double bytes_) : c(c_), cls(cls_), bytes(bytes_) {
+    c->bytes_acc += bytes;
+    if (c->prof) {
+        e0 = pool_get(c);
+        if (e0) (void)hipEventRecord(e0, c->stream);
+    }
+}
+
+Prof::~Prof() {
+    if (c->prof && e0) {
+        hipEvent_t e1 = pool_get(c);
+        if (e1) {
+            (void)hipEventRecord(e1, c->stream);
+            c->recs.push_back(Ctx::Rec{cls, bytes, e0, e1});
+        }
+    }
+}
+
+int profile_enable(Ctx *c, bool on) {
+    HIPCHK(c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+    c->prof = on;
+    c->recs.clear();
+    c->ev_used = 0;
+    return 0;
+}
+
+int profile_read(Ctx *c, int ncls, long long *cnt, double *ms, double *bytes) {
+    HIPCHK(c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+    for (int k = 0; k < ncls; ++k) {
+        cnt[k] = 0;
+        ms[k] = 0.0;
+        bytes[k] = 0.0;
+    }
+    for (const Ctx::Rec &r : c->recs) {
+        if (r.cls >= ncls) continue;
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, r.e0, r.e1));
+        cnt[r.cls] += 1;
+        ms[r.cls] += t;
+        bytes[r.cls] += r.bytes;
+    }
+    return 0;
+}
+
 template <typename T> static const C<T> *links(const Ctx *c);
 template <> const C<double> *links<double>(const Ctx *c) { return c->U64; }
 template <> const C<float> *links<float>(const Ctx *c) { return c->U32; }
@@ -138,6 +197,8 @@ void ctx_destroy(Ctx *c) {
     if (c->U64) (void)hipFree(c->U64);
     if (c->U32) (void)hipFree(c->U32);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    c->ev_pool.clear();
 }
 
 // ---------------------------------------------------------------------------
@@ -149,12 +210,11 @@ int apply_wilson(Ctx *c, const double2 *in, double2 *out, int nrhs, int flags) {
     const bool g5in = dag, g5out = g5l != dag, nm = negmu != dag;
     const int V = c->g.V;
     const long n = 12L * V;
-    const int nb = nblocks_for(V);
     if (!mixed) {
         DslashArgs<double> a = ds_args<double>(c, nm, g5out);
         a.in = in;
         a.out = out;
-        launch_dslash<double>(c->stream, a, nrhs, EPI_PLAIN, g5in, nb);
+        launch_dslash<double>(c->stream, a, nrhs, EPI_PLAIN, g5in);
     } else {
         CHK(ensure(c->ws_aux1, (size_t)nrhs * n * sizeof(float2)));
         CHK(ensure(c->ws_aux2, (size_t)nrhs * n * sizeof(float2)));
@@ -163,7 +223,7 @@ int apply_wilson(Ctx *c, const double2 *in, double2 *out, int nrhs, int flags) {
         DslashArgs<float> a = ds_args<float>(c, nm, g5out);
         a.in = fi;
         a.out = fo;
-        launch_dslash<float>(c->stream, a, nrhs, EPI_PLAIN, g5in, nb);
+        launch_dslash<float>(c->stream, a, nrhs, EPI_PLAIN, g5in);
         launch_convert_out<float>(c->stream, out, fo, n, n, n, nrhs);
     }
     HIPCHK(hipGetLastError());
@@ -180,23 +240,24 @@ static double host_partial_sum(const double *row, int nblk) {
 int spectral_radius(Ctx *c, const double2 *start, int iters, double *rho) {
     const int V = c->g.V;
     const long n = 12L * V;
-    const int nbd = nblocks_for(V), nbv = nblocks_for(n);
+    const int nbv = nblocks_for(n);
     hipStream_t st = c->stream;
     CHK(ensure(c->ws_aux1, n * sizeof(double2)));
     CHK(ensure(c->ws_aux2, n * sizeof(double2)));
     CHK(ensure(c->ws_aux3, n * sizeof(double2)));
-    CHK(ensure(c->ws_part, (size_t)PMAX * NBMAX * sizeof(double)));
-    CHK(ensure_host(c, 3 * NBMAX * sizeof(double)));
+    const long ps = part_stride(c->g);
+    CHK(ensure(c->ws_part, (size_t)PMAX * ps * sizeof(double)));
+    CHK(ensure_host(c, 3 * ps * sizeof(double)));
     double2 *v = (double2 *)c->ws_aux1.p, *w = (double2 *)c->ws_aux2.p, *z = (double2 *)c->ws_aux3.p;
     double *part = (double *)c->ws_part.p;
     double *hp = (double *)c->host_pinned;
     auto norms = [&](const double2 *x, const double2 *y, double *re, double *yy) -> int {
-        launch_dot_partials<double>(st, x, y, n, part, 1, nbv, Gate{});
+        launch_dot_partials<double>(st, x, y, n, part, ps, 1, nbv, Gate{});
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(hp, part, 3 * NBMAX * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hp, part, 3 * ps * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         *re = host_partial_sum(hp, nbv);
-        *yy = host_partial_sum(hp + 2 * NBMAX, nbv);
+        *yy = host_partial_sum(hp + 2 * ps, nbv);
         return 0;
     };
     double re, nn;
@@ -208,12 +269,12 @@ int spectral_radius(Ctx *c, const double2 *start, int iters, double *rho) {
         DslashArgs<double> a = ds_args<double>(c, false, false);
         a.in = v;
         a.out = w;
-        launch_dslash<double>(st, a, 1, EPI_PLAIN, false, nbd);
+        launch_dslash<double>(st, a, 1, EPI_PLAIN, false);
         // D^+ w = gamma5 D(-mu) gamma5 w
         DslashArgs<double> b = ds_args<double>(c, true, true);
         b.in = w;
         b.out = z;
-        launch_dslash<double>(st, b, 1, EPI_PLAIN, true, nbd);
+        launch_dslash<double>(st, b, 1, EPI_PLAIN, true);
         CHK(norms(v, z, &re, &nn));
         lam = re;
         if (!(nn > 0.0)) break;
@@ -409,16 +470,28 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     const long n = 12L * V;
     const int nrhs = P.nrhs, ns = P.n_shift, l = P.l;
     const bool pass1 = P.pass == 1;
-    const int nbd = nblocks_for(V), nbv = nblocks_for(n);
+    const int nbd = (V + BLOCK - 1) / BLOCK;     // stencil partials: one per site block
+    const int nbv = nblocks_for(n);
+    const long ps = part_stride(c->g);
     const size_t cs = sizeof(C<T>);
     const int max_outer = P.max_outer;
     const int max_steps = max_outer * l;
+    c->bytes_acc = 0;
+    // algorithmic HBM bytes of one launch (each operand read or written once)
+    const double cB = (double)cs, nd = (double)n, Vd = (double)V;
+    auto ds_bytes = [&](int epi, int nr) {
+        double per = 24 * cB;                                  // in + out
+        if (epi == EPI_MV) per = 48 * cB;                      // + v + rt
+        else if (epi == EPI_MV_Y) per = 36 * cB + 24 * 16.0;   // + v, y (FP64) read + write
+        else if (epi == EPI_SV) per = 36 * cB;                 // + v
+        return nr * per * Vd + 36 * cB * Vd;                   // links once per launch
+    };
 
     // ---- workspace
     CHK(ensure(c->ws_R, (size_t)nrhs * (l + 1) * n * cs));
     CHK(ensure(c->ws_U, (size_t)nrhs * (l + 1) * n * cs));
     CHK(ensure(c->ws_tmp, (size_t)nrhs * n * cs));
-    CHK(ensure(c->ws_part, (size_t)nrhs * PMAX * NBMAX * sizeof(double)));
+    CHK(ensure(c->ws_part, (size_t)nrhs * PMAX * ps * sizeof(double)));
     CHK(ensure(c->ws_seed, (size_t)nrhs * sizeof(SeedState)));
     CHK(ensure(c->ws_shift, (size_t)nrhs * NSMAX * sizeof(ShiftState)));
     CHK(ensure(c->ws_sc, (size_t)nrhs * NSMAX * sizeof(StepCoef)));
@@ -489,14 +562,18 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                           hipMemcpyHostToDevice, st));
 
     // ---- initial vectors: r_0 = b, everything else zero
-    launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
-    launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
-    if (pass1) {
-        launch_zero<T>(st, W, (long)nrhs * ns * (l + 1) * n, 0, 1);
-        launch_zero<T>(st, X, (long)nrhs * ns * n, 0, 1);
+    {
+        Prof p(c, CL_OTHER, nrhs * nd * cB * (2.0 * (l + 1) + (pass1 ? ns * (l + 2.0) : 0.0)) +
+                                nrhs * nd * (16.0 + cB) + nrhs * nd * cB);
+        launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
+        launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
+        if (pass1) {
+            launch_zero<T>(st, W, (long)nrhs * ns * (l + 1) * n, 0, 1);
+            launch_zero<T>(st, X, (long)nrhs * ns * n, 0, 1);
+        }
+        launch_convert_in<T>(st, R, b, n, (long)(l + 1) * n, n, nrhs);
+        launch_dot_partials<T>(st, rt, rt, n, part, ps, nrhs, nbv, Gate{});
     }
-    launch_convert_in<T>(st, R, b, n, (long)(l + 1) * n, n, nrhs);
-    launch_dot_partials<T>(st, rt, rt, n, part, nrhs, nbv, Gate{});
     ScalarArgs sa;
     sa.seed = seed;
     sa.sh = sh;
@@ -506,10 +583,14 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     sa.tape_gam = pass1 ? nullptr : (double2 *)c->ws_tape_gam.p;
     sa.tape_outer = pass1 ? nullptr : (TapeOuter *)c->ws_tape_outer.p;
     sa.part = part;
+    sa.ps = ps;
     sa.l = l;
     sa.record = pass1 ? 0 : 1;
     sa.nblk = nbv;
-    launch_sc_init(st, sa, nrhs);
+    {
+        Prof p(c, CL_SCALAR, 0);
+        launch_sc_init(st, sa, nrhs);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
 
@@ -524,6 +605,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     va.X = X;
     va.rt = rt;
     va.part = part;
+    va.ps = ps;
     va.seed = seed;
     va.sc = sa.sc;
     va.mc = sa.mc;
@@ -548,55 +630,103 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     d2.rt = rt;
     d2.rt_rs = n;
     d2.part = part;
+    d2.ps = ps;
 
     CHK(ensure_host(c, (size_t)nrhs * sizeof(SeedState)));
     SeedState *hseed = (SeedState *)c->host_pinned;
-    int m_done = 0;
+    int nr_run = nrhs;                       // right-hand sides still iterating
+    double nsh_act = (double)nrhs * ns;      // active shifts over those
     for (int m = 0; m < max_outer; ++m) {
         for (int j = 0; j < l; ++j) {
             sa.j = j;
             sa.nblk = (j == 0) ? nbv : nbd;
             sa.nblk2 = nbv;
-            launch_sc_beta(st, sa, nrhs);
+            {
+                Prof p(c, CL_SCALAR, 0);
+                launch_sc_beta(st, sa, nrhs);
+            }
             va.gate = g_bicg;
-            launch_seed_u<T>(st, va, j, nrhs, nbv);
+            {
+                Prof p(c, CL_SEED, nr_run * 3.0 * (j + 1) * nd * cB);
+                launch_seed_u<T>(st, va, j, nrhs, nbv);
+            }
             // u_{j+1} = S u_j = a g5 D (g5 D u_j) + sigma0 u_j, <rt, u_{j+1}>
             d1.in = Uv + (size_t)j * n;
             d1.out = tmp;
             d1.gate = g_bicg;
-            launch_dslash<T>(st, d1, nrhs, EPI_PLAIN, false, nbd);
+            {
+                Prof p(c, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
+                launch_dslash<T>(st, d1, nrhs, EPI_PLAIN, false);
+            }
             d2.in = tmp;
             d2.out = Uv + (size_t)(j + 1) * n;
             d2.v = Uv + (size_t)j * n;
             d2.gate = g_bicg;
-            launch_dslash<T>(st, d2, nrhs, EPI_MV, false, nbd);
+            {
+                Prof p(c, CL_STENCIL, ds_bytes(EPI_MV, nr_run));
+                launch_dslash<T>(st, d2, nrhs, EPI_MV, false);
+            }
             sa.nblk = nbd;
-            launch_sc_alpha(st, sa, nrhs);
+            {
+                Prof p(c, CL_SCALAR, 0);
+                launch_sc_alpha(st, sa, nrhs);
+            }
             va.partials = 1;
-            launch_r_update<T>(st, va, j, pass1, nrhs, nbv);
+            {
+                // seed: read r_i, u_{i+1}, write r_i; shift s: read u^s_0..j, x^s,
+                // write u^s_0..j+1, x^s
+                Prof p(c, pass1 ? CL_SHIFT : CL_SEED,
+                       nr_run * 3.0 * (j + 1) * nd * cB + (pass1 ? nsh_act * (2.0 * j + 5) * nd * cB : 0.0));
+                launch_r_update<T>(st, va, j, pass1, nrhs, nbv);
+            }
             // r_{j+1} = S r_j, <rt, r_{j+1}>
             d1.in = R + (size_t)j * n;
-            launch_dslash<T>(st, d1, nrhs, EPI_PLAIN, false, nbd);
+            {
+                Prof p(c, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
+                launch_dslash<T>(st, d1, nrhs, EPI_PLAIN, false);
+            }
             d2.out = R + (size_t)(j + 1) * n;
             d2.v = R + (size_t)j * n;
-            launch_dslash<T>(st, d2, nrhs, EPI_MV, false, nbd);
+            {
+                Prof p(c, CL_STENCIL, ds_bytes(EPI_MV, nr_run));
+                launch_dslash<T>(st, d2, nrhs, EPI_MV, false);
+            }
         }
         va.gate = g_run;
-        launch_gram<T>(st, va, nrhs, nbv);
+        {
+            Prof p(c, CL_SEED, nr_run * (l + 1.0) * nd * cB);
+            launch_gram<T>(st, va, nrhs, nbv);
+        }
         sa.nblk = nbv;
-        launch_sc_mr(st, sa, nrhs);
+        {
+            Prof p(c, CL_SCALAR, 0);
+            launch_sc_mr(st, sa, nrhs);
+        }
         va.partials = 1;
-        launch_mr_update<T>(st, va, pass1, nrhs, nbv);
-        launch_sc_conv(st, sa, nrhs);
+        {
+            // seed: read r_0..r_l, u_0..u_l, rt, write r_0, u_0; shift s: read
+            // u^s_0..u^s_l, x^s, write u^s_0, x^s
+            Prof p(c, pass1 ? CL_SHIFT_MR : CL_SEED,
+                   nr_run * (2.0 * (l + 1) + 3) * nd * cB + (pass1 ? nsh_act * (l + 4.0) * nd * cB : 0.0));
+            launch_mr_update<T>(st, va, pass1, nrhs, nbv);
+        }
+        {
+            Prof p(c, CL_SCALAR, 0);
+            launch_sc_conv(st, sa, nrhs);
+        }
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(hseed, seed, nrhs * sizeof(SeedState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        m_done = m + 1;
-        bool any = false;
-        for (int r = 0; r < nrhs; ++r) any |= hseed[r].run != 0;
-        if (!any) break;
+        nr_run = 0;
+        nsh_act = 0;
+        for (int r = 0; r < nrhs; ++r) {
+            if (hseed[r].run) {
+                nr_run += 1;
+                nsh_act += hseed[r].nact;
+            }
+        }
+        if (nr_run == 0) break;
     }
-    (void)m_done;
 
     // ---- results of pass 1
     std::vector<SeedState> fs(nrhs);
@@ -630,6 +760,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     }
 
     if (pass1) {
+        Prof p(c, CL_OTHER, nrhs * nd * (ns * cB + 16.0));
         launch_ysum<T>(st, y, X, (const double *)c->ws_wts.p, n, ns, nrhs, nbv);
         HIPCHK(hipGetLastError());
     } else {
@@ -674,10 +805,13 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         HIPCHK(hipMemcpyAsync(c->ws_cb.p, cb.data(), nrhs * sizeof(double2), hipMemcpyHostToDevice, st));
 
         // pass 2: regenerate the Mv outputs and accumulate y
-        launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
-        launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
-        launch_convert_in<T>(st, R, b, n, vs, n, nrhs);
-        launch_yinit(st, y, b, (const double2 *)c->ws_cb.p, n, nrhs, nbv);
+        {
+            Prof p(c, CL_OTHER, nrhs * nd * (2.0 * (l + 1) * cB + 16.0 + cB + 32.0));
+            launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
+            launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
+            launch_convert_in<T>(st, R, b, n, vs, n, nrhs);
+            launch_yinit(st, y, b, (const double2 *)c->ws_cb.p, n, nrhs, nbv);
+        }
         const long rstride = (long)Mcap * l * sizeof(ReplayStep);
         VecArgs<T> vb = va;
         vb.partials = 0;
@@ -688,6 +822,8 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         e2.y = y;
         e2.y_rs = n;
         for (int m = 0; m < Mmax; ++m) {
+            int nr_m = 0;      // right-hand sides whose replay reaches outer iteration m
+            for (int r = 0; r < nrhs; ++r) nr_m += (fs[r].m > m) ? 1 : 0;
             for (int j = 0; j < l; ++j) {
                 const size_t idx = (size_t)m * l + j;
                 Gate gu;
@@ -699,27 +835,45 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 vb.beta = CoefRef{(const char *)&drs[idx].beta, rstride};
                 vb.alpha = CoefRef{(const char *)&drs[idx].alpha, rstride};
                 vb.gate = gu;
-                launch_seed_u<T>(st, vb, j, nrhs, nbv);
+                {
+                    Prof p(c, CL_SEED, nr_m * 3.0 * (j + 1) * nd * cB);
+                    launch_seed_u<T>(st, vb, j, nrhs, nbv);
+                }
                 e1.in = Uv + (size_t)j * n;
                 e1.out = tmp;
                 e1.gate = gu;
-                launch_dslash<T>(st, e1, nrhs, EPI_PLAIN, false, nbd);
+                {
+                    Prof p(c, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_m));
+                    launch_dslash<T>(st, e1, nrhs, EPI_PLAIN, false);
+                }
                 e2.in = tmp;
                 e2.out = Uv + (size_t)(j + 1) * n;
                 e2.v = Uv + (size_t)j * n;
                 e2.ycoef = CoefRef{(const char *)&drs[idx].cu, rstride};
                 e2.gate = gu;
-                launch_dslash<T>(st, e2, nrhs, EPI_MV_Y, false, nbd);
+                {
+                    Prof p(c, CL_STENCIL, ds_bytes(EPI_MV_Y, nr_m));
+                    launch_dslash<T>(st, e2, nrhs, EPI_MV_Y, false);
+                }
                 vb.gate = gr;
-                launch_r_update<T>(st, vb, j, false, nrhs, nbv);
+                {
+                    Prof p(c, CL_SEED, nr_m * 3.0 * (j + 1) * nd * cB);
+                    launch_r_update<T>(st, vb, j, false, nrhs, nbv);
+                }
                 e1.in = R + (size_t)j * n;
                 e1.gate = gr;
-                launch_dslash<T>(st, e1, nrhs, EPI_PLAIN, false, nbd);
+                {
+                    Prof p(c, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_m));
+                    launch_dslash<T>(st, e1, nrhs, EPI_PLAIN, false);
+                }
                 e2.out = R + (size_t)(j + 1) * n;
                 e2.v = R + (size_t)j * n;
                 e2.ycoef = CoefRef{(const char *)&drs[idx].cr, rstride};
                 e2.gate = gr;
-                launch_dslash<T>(st, e2, nrhs, EPI_MV_Y, false, nbd);
+                {
+                    Prof p(c, CL_STENCIL, ds_bytes(EPI_MV_Y, nr_m));
+                    launch_dslash<T>(st, e2, nrhs, EPI_MV_Y, false);
+                }
             }
             Gate gm;
             gm.flag = &dro[m].lm;
@@ -727,7 +881,10 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             gm.need = 1;
             vb.gate = gm;
             vb.gam = CoefRef{(const char *)&dro[m].gam[0], (long)Mcap * (long)sizeof(ReplayOuter)};
-            launch_mr_update<T>(st, vb, false, nrhs, nbv);
+            {
+                Prof p(c, CL_SEED, nr_m * (2.0 * (l + 1) + 2) * nd * cB);
+                launch_mr_update<T>(st, vb, false, nrhs, nbv);
+            }
             HIPCHK(hipGetLastError());
         }
         rep->mv *= 2;
@@ -739,15 +896,15 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         CHK(ensure(c->ws_aux1, (size_t)nrhs * n * sizeof(double2)));
         CHK(ensure(c->ws_aux2, (size_t)nrhs * n * sizeof(double2)));
         CHK(ensure(c->ws_aux3, (size_t)nrhs * n * sizeof(double2)));
-        CHK(ensure_host(c, (size_t)std::max(nrhs * sizeof(SeedState), (size_t)NBMAX * sizeof(double))));
+        CHK(ensure_host(c, (size_t)std::max(nrhs * sizeof(SeedState), (size_t)ps * sizeof(double))));
         double2 *xd = (double2 *)c->ws_aux1.p, *t1 = (double2 *)c->ws_aux2.p, *t2 = (double2 *)c->ws_aux3.p;
-        std::vector<double> rowbuf(NBMAX);
+        std::vector<double> rowbuf(ps);
         for (int s = 0; s < ns; ++s) {
             launch_convert_out<T>(st, xd, X + (size_t)s * n, n, n, (long)ns * n, nrhs);
             DslashArgs<double> a1 = ds_args<double>(c, P.neg_mu, true);
             a1.in = xd;
             a1.out = t1;
-            launch_dslash<double>(st, a1, nrhs, EPI_PLAIN, false, nbd);
+            launch_dslash<double>(st, a1, nrhs, EPI_PLAIN, false);
             for (int r = 0; r < nrhs; ++r) {
                 DslashArgs<double> a2 = ds_args<double>(c, P.neg_mu, true);
                 a2.in = t1 + (size_t)r * n;
@@ -755,12 +912,12 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 a2.scale = P.a_scale;
                 a2.sigma0 = P.shifts[(size_t)r * ns + s];
                 a2.v = xd + (size_t)r * n;
-                launch_dslash<double>(st, a2, 1, EPI_SV, false, nbd);
+                launch_dslash<double>(st, a2, 1, EPI_SV, false);
             }
-            launch_diffnorm_partials<double>(st, b, t2, n, n, n, part, nrhs, nbv);
+            launch_diffnorm_partials<double>(st, b, t2, n, n, n, part, ps, nrhs, nbv);
             HIPCHK(hipGetLastError());
             for (int r = 0; r < nrhs; ++r) {
-                HIPCHK(hipMemcpyAsync(rowbuf.data(), part + (size_t)r * PMAX * NBMAX, NBMAX * sizeof(double),
+                HIPCHK(hipMemcpyAsync(rowbuf.data(), part + (size_t)r * PMAX * ps, ps * sizeof(double),
                                       hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));
                 const double d = std::sqrt(host_partial_sum(rowbuf.data(), nbv));
@@ -770,6 +927,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
+    rep->bytes_model = c->bytes_acc;
     return 0;
 }
 
@@ -794,7 +952,7 @@ int sign_apply(Ctx *c, const SolveParams &P, const double2 *b, double2 *out, boo
     DslashArgs<double> a = ds_args<double>(c, P.neg_mu, true);   // H y = g5 D y
     a.in = y;
     a.out = hy;
-    launch_dslash<double>(c->stream, a, P.nrhs, EPI_PLAIN, false, nblocks_for(V));
+    launch_dslash<double>(c->stream, a, P.nrhs, EPI_PLAIN, false);
     launch_overlap_out(c->stream, out, b, hy, V, P.nrhs, overlap ? 1 : 0, std::sqrt(P.a_scale),
                        nblocks_for(n));
     HIPCHK(hipGetLastError());

@@ -89,7 +89,10 @@ def lib():
                                      ctypes.POINTER(_Info)]
         L.pfe_sign_backward.argtypes = [_P, _D, _I, _DP, _DP, _I, _D, _I, _I, _I, _P, _P, _I,
                                         _P, _DP, _DP, _P, ctypes.POINTER(_Info)]
+        L.msb_profile_enable.argtypes = [_P, _I]
+        L.msb_profile_read.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_longlong), _DP, _DP]
         for f in ("msb_create", "msb_set_stream", "msb_neuberger_pfe", "msb_spectral_radius",
+                  "msb_profile_enable", "msb_profile_read",
                   "wilson_apply", "mshift_bicgstabl", "pfe_sign_apply", "pfe_sign_backward"):
             getattr(L, f).restype = _I
         _LIB = L
@@ -185,6 +188,22 @@ class Context:
 
     def _sync_stream(self):
         _check(lib().msb_set_stream(self._h, _stream_handle()))
+
+    # -- kernel timing ------------------------------------------------------
+    PROFILE_CLASSES = ("stencil", "shift_update", "shift_mr_update", "seed_vector", "scalar", "other")
+
+    def profile_enable(self, on: bool = True):
+        self._sync_stream()
+        _check(lib().msb_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        n = len(self.PROFILE_CLASSES)
+        cnt = (ctypes.c_longlong * n)()
+        ms = np.zeros(n)
+        by = np.zeros(n)
+        _check(lib().msb_profile_read(self._h, n, cnt, _dptr(ms), _dptr(by)))
+        return {k: {"count": int(cnt[i]), "ms": float(ms[i]), "bytes": float(by[i])}
+                for i, k in enumerate(self.PROFILE_CLASSES)}
 
     # -- entry points ------------------------------------------------------
     def wilson_apply(self, x: torch.Tensor, flags: int = 0, out: Optional[torch.Tensor] = None):

@@ -29,6 +29,17 @@ def oracle_run(op, a, b, sig, w, l, tol, max_outer, pass_, force=None):
                                force_iters=force)
 
 
+def parity_bound(op, a, b, sig, w, l, tol, force, y_ref):
+    """1e-10, or -- where the iteration itself amplifies rounding more than
+    that -- 30x the change of the oracle's own y when b is perturbed by 1e-15
+    relative (same forced freeze iterations).  BiCGstab(1) on these spectra
+    amplifies rounding by ~1e7; l >= 2 stays below 1e-10."""
+    rng = np.random.default_rng(12345)
+    bp = b * (1 + 1e-15 * rng.standard_normal(b.shape))
+    yp = oracle_run(op, a, bp, sig, w, l, tol, 100000, 1, force=force)[0]
+    return max(1e-10, 30 * rel(yp, y_ref))
+
+
 @pytest.mark.parametrize("l", [1, 2, 3, 4])
 def test_single_pass_forced_matches_oracle(l):
     wk, U, op, a, sig, w, b = problem("4x4x4x8")
@@ -39,10 +50,12 @@ def test_single_pass_forced_matches_oracle(l):
                                        want_shifts=True, force_iters=i0.shift_iters)
     assert np.array_equal(info.shift_iters[0], i0.shift_iters)
     assert info.outer_iters == i0.outer
-    assert rel(host(y)[0], y0) <= 1e-10
+    bound = parity_bound(op, a, b[0], sig, w, l, wk.tol, i0.shift_iters, y0)
+    log(f"  bound {bound:.2e}, rel err {rel(host(y)[0], y0):.2e}")
+    assert rel(host(y)[0], y0) <= bound
     xs = host(xs)[0]
     for s in range(len(sig)):
-        assert rel(xs[s], X0[s]) <= 1e-10, s
+        assert rel(xs[s], X0[s]) <= bound, s
     assert info.mv_count == 2 * info.outer_iters * l
     assert info.dot_count == info.outer_iters * l * (0.5 * l + 3.5)
 
@@ -56,7 +69,9 @@ def test_double_pass_forced_matches_oracle(l):
     ctx = ctx_for(wk, U)
     y, info, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, l, wk.tol, 2000, 2,
                                       force_iters=i1.shift_iters)
-    assert rel(host(y)[0], y2) <= 1e-10
+    bound = parity_bound(op, a, b[0], sig, w, l, wk.tol, i1.shift_iters, y1)
+    log(f"  bound {bound:.2e}, rel err {rel(host(y)[0], y2):.2e}")
+    assert rel(host(y)[0], y2) <= bound
     ys, infos, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, l, wk.tol, 2000, 1,
                                         force_iters=i1.shift_iters)
     assert rel(host(y), host(ys)) <= 1e-11
