@@ -218,11 +218,11 @@ def main():
     if args.variants == "all":
         comps = {}
         ref = None
-        for (p, mx) in ((1, False), (2, False)):
+        for (p, mx) in ((1, False), (2, False), (1, True), (2, True)):
             name = f"{p}pass-{'mixed' if mx else 'fp64'}"
             try:
-                yv, iv, msv, pv = run_variant(ctx, b, a, sig, w, l, wk.tol, args.max_outer, p, mx,
-                                              profile=True)
+                yv, iv, msv, pv = run_variant(ctx, b, a, sig, w, l, wk.tol, min(args.max_outer, 400), p,
+                                              mx, profile=True)
             except msb.MsbError as e:
                 comps[name] = {"error": str(e)}
                 continue
@@ -230,7 +230,8 @@ def main():
                 ref = yv
             err = float(torch.linalg.norm(yv - ref) / torch.linalg.norm(ref))
             comps[name] = {"ms": round(msv, 2), "outer_iters": iv.outer_iters, "mv": iv.mv_count,
-                           "status": iv.status, "GBps_model": round(iv.bytes_model / (msv / 1e3) / 1e9, 1),
+                           "status": iv.status, "reliable_updates": iv.reliable_updates,
+                           "GBps_model": round(iv.bytes_model / (msv / 1e3) / 1e9, 1),
                            "rel_diff_vs_1pass_fp64": err,
                            "max_shift_resid": float(np.max(iv.shift_resid)),
                            "shift_update_GBps": (round(pv["shift_update"]["bytes"] / (pv["shift_update"]["ms"] / 1e3) / 1e9, 1)

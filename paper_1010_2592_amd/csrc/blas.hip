@@ -52,12 +52,13 @@ __global__ __launch_bounds__(BLOCK) void k_seed_u(VecArgs<T> a) {
     }
 }
 
-template <typename T, int J, bool SHIFTS>
+template <typename T, int J, bool SHIFTS, bool XH>
 __global__ __launch_bounds__(BLOCK) void k_r_update(VecArgs<T> a) {
     const int rhs = blockIdx.y;
     if (!gate_open(a.gate, rhs)) return;
     const long n = a.n;
-    const C<T> alpha = cvt<T>(ld(a.alpha, rhs));
+    const double2 alpha_d = ld(a.alpha, rhs);
+    const C<T> alpha = cvt<T>(alpha_d);
     C<T> *R = a.R + (size_t)rhs * (a.l + 1) * n;
     const C<T> *U = a.U + (size_t)rhs * (a.l + 1) * n;
     const int nact = SHIFTS ? a.seed[rhs].nact : 0;
@@ -78,15 +79,22 @@ __global__ __launch_bounds__(BLOCK) void k_r_update(VecArgs<T> a) {
                 const C<T> a1 = cvt<T>(c.a1), a2 = cvt<T>(c.a2);
                 const T sp = (T)c.sp;
                 C<T> *W = a.W + ((size_t)rhs * a.nshift + c.s) * (a.l + 1) * n;
-                C<T> *X = a.X + ((size_t)rhs * a.nshift + c.s) * n;
+                double2 *X = a.X + ((size_t)rhs * a.nshift + c.s) * n;
                 C<T> w[J + 2];
 #pragma unroll
                 for (int i = 0; i <= J; ++i) w[i] = csub(cmul(kap, r[i]), cmul(bs, W[i * n + e]));
-                X[e] = cfma(as, w[0], X[e]);
+                X[e] = cfma(c.alpha_s, d2((double)w[0].x, (double)w[0].y), X[e]);
+                (void)as;
                 w[J + 1] = csub(cadd(cmul(a1, r[J]), cmul(a2, u1[J])), cscale(w[J], sp));
 #pragma unroll
                 for (int i = 0; i <= J + 1; ++i) W[i * n + e] = w[i];
             }
+        }
+        if (XH) {
+            // seed solution x += alpha u_0, accumulated in FP64
+            const C<T> u0 = U[e];
+            double2 *xh = a.XH + (size_t)rhs * n;
+            xh[e] = cfma(alpha_d, d2((double)u0.x, (double)u0.y), xh[e]);
         }
 #pragma unroll
         for (int i = 0; i <= J; ++i) {
@@ -127,7 +135,7 @@ __global__ __launch_bounds__(BLOCK) void k_gram(VecArgs<T> a) {
     block_reduce_store<2 * NP>(acc, a.part + (size_t)rhs * PMAX * a.ps + blockIdx.x, a.ps);
 }
 
-template <typename T, int L, bool SHIFTS>
+template <typename T, int L, bool SHIFTS, bool XH>
 __global__ __launch_bounds__(BLOCK) void k_mr_update(VecArgs<T> a) {
     const int rhs = blockIdx.y;
     if (!gate_open(a.gate, rhs)) return;
@@ -136,11 +144,13 @@ __global__ __launch_bounds__(BLOCK) void k_mr_update(VecArgs<T> a) {
     C<T> *U = a.U + (size_t)rhs * (a.l + 1) * n;
     const C<T> *rt = a.rt ? a.rt + (size_t)rhs * n : nullptr;
     C<T> g[L + 1];
+    double2 gd[L + 1];
 #pragma unroll
     for (int i = 1; i <= L; ++i) {
         CoefRef c = a.gam;
         c.p += (i - 1) * sizeof(double2);
-        g[i] = cvt<T>(ld(c, rhs));
+        gd[i] = ld(c, rhs);
+        g[i] = cvt<T>(gd[i]);
     }
     const int nact = SHIFTS ? a.seed[rhs].nact : 0;
     const MRCoef *mc = SHIFTS ? a.mc + (size_t)rhs * NSMAX : nullptr;
@@ -154,16 +164,24 @@ __global__ __launch_bounds__(BLOCK) void k_mr_update(VecArgs<T> a) {
                 const MRCoef &c = mc[q];
                 if (!c.live) continue;
                 C<T> *W = a.W + ((size_t)rhs * a.nshift + c.s) * (a.l + 1) * n;
-                C<T> *X = a.X + ((size_t)rhs * a.nshift + c.s) * n;
-                C<T> x = X[e];
+                double2 *X = a.X + ((size_t)rhs * a.nshift + c.s) * n;
+                double2 x = X[e];
 #pragma unroll
-                for (int k = 0; k < L; ++k) x = cfma(cvt<T>(c.kc[k]), r[k], x);
+                for (int k = 0; k < L; ++k) x = cfma(c.kc[k], d2((double)r[k].x, (double)r[k].y), x);
                 X[e] = x;
                 C<T> w0 = W[e];
 #pragma unroll
                 for (int i = 1; i <= L; ++i) w0 = csub(w0, cmul(g[i], W[i * n + e]));
                 W[e] = cmul(w0, cvt<T>(c.inv_q));
             }
+        }
+        if (XH) {
+            // seed solution x += sum_i gamma_i r_{i-1}, accumulated in FP64
+            double2 *xh = a.XH + (size_t)rhs * n;
+            double2 x = xh[e];
+#pragma unroll
+            for (int i = 1; i <= L; ++i) x = cfma(gd[i], d2((double)r[i - 1].x, (double)r[i - 1].y), x);
+            xh[e] = x;
         }
         C<T> r0 = r[0];
 #pragma unroll
@@ -241,19 +259,45 @@ __global__ __launch_bounds__(BLOCK) void k_diffnorm(const C<T> *x, const C<T> *y
     block_reduce_store<1>(p, part + (size_t)rhs * PMAX * ps + blockIdx.x, ps);
 }
 
-template <typename T>
-__global__ void k_ysum(double2 *y, const C<T> *X, const double *w, long n, int ns) {
+__global__ void k_ysum(double2 *y, const double2 *X, const double *w, long n, int ns) {
     const int rhs = blockIdx.y;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
         double2 acc = d2(0, 0);
         for (int s = 0; s < ns; ++s) {
-            const C<T> z = X[((size_t)rhs * ns + s) * n + e];
+            const double2 z = X[((size_t)rhs * ns + s) * n + e];
             const double ws = w[rhs * ns + s];
             acc.x += ws * z.x;
             acc.y += ws * z.y;
         }
         y[(size_t)rhs * n + e] = acc;
     }
+}
+
+// r_0 = b - v in FP64 (v = S x), stored in the iteration's precision;
+// partials of <rt, r_0> and ||r_0||^2 from the FP64 value
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_rel_update(VecArgs<T> a, const double2 *b, const double2 *v,
+                                                      double2 *y, CoefRef yc) {
+    const int rhs = blockIdx.y;
+    if (!gate_open(a.gate, rhs)) return;
+    const long n = a.n;
+    C<T> *R = a.R + (size_t)rhs * (a.l + 1) * n;
+    const C<T> *rt = a.rt + (size_t)rhs * n;
+    const double2 *br = b + (size_t)rhs * n, *vr = v + (size_t)rhs * n;
+    double2 *yr = y ? y + (size_t)rhs * n : nullptr;
+    const double2 c = y ? ld(yc, rhs) : d2(0, 0);
+    double p[3] = {0.0, 0.0, 0.0};
+    for (long e = (long)blockIdx.x * BLOCK + threadIdx.x; e < n; e += (long)gridDim.x * BLOCK) {
+        const double2 ve = vr[e];
+        const double2 r0 = csub(br[e], ve);
+        R[e] = to_c<T>(r0);
+        if (yr) yr[e] = cfma(c, ve, yr[e]);
+        const C<T> t = rt[e];
+        p[0] += (double)t.x * r0.x + (double)t.y * r0.y;
+        p[1] += (double)t.x * r0.y - (double)t.y * r0.x;
+        p[2] += r0.x * r0.x + r0.y * r0.y;
+    }
+    block_reduce_store<3>(p, a.part + (size_t)rhs * PMAX * a.ps + blockIdx.x, a.ps);
 }
 
 __global__ void k_yinit(double2 *y, const double2 *b, const double2 *c, long n) {
@@ -298,21 +342,24 @@ void launch_seed_u(hipStream_t st, const VecArgs<T> &a, int j, int nrhs, int nbl
     }
 }
 
+template <typename T, bool SH, bool XH>
+static void r_update_j(hipStream_t st, const VecArgs<T> &a, int j, dim3 g, dim3 b) {
+    switch (j) {
+#define C_(J) case J: hipLaunchKernelGGL((k_r_update<T, J, SH, XH>), g, b, 0, st, a); break;
+        C_(0) C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7)
+#undef C_
+    }
+}
+
 template <typename T>
-void launch_r_update(hipStream_t st, const VecArgs<T> &a, int j, bool shifts, int nrhs, int nblk) {
+void launch_r_update(hipStream_t st, const VecArgs<T> &a, int j, bool shifts, bool xh, int nrhs, int nblk) {
     dim3 g(nblk, nrhs), b(BLOCK);
     if (shifts) {
-        switch (j) {
-#define C_(J) case J: hipLaunchKernelGGL((k_r_update<T, J, true>), g, b, 0, st, a); break;
-            C_(0) C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7)
-#undef C_
-        }
+        if (xh) r_update_j<T, true, true>(st, a, j, g, b);
+        else r_update_j<T, true, false>(st, a, j, g, b);
     } else {
-        switch (j) {
-#define C_(J) case J: hipLaunchKernelGGL((k_r_update<T, J, false>), g, b, 0, st, a); break;
-            C_(0) C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7)
-#undef C_
-        }
+        if (xh) r_update_j<T, false, true>(st, a, j, g, b);
+        else r_update_j<T, false, false>(st, a, j, g, b);
     }
 }
 
@@ -326,22 +373,31 @@ void launch_gram(hipStream_t st, const VecArgs<T> &a, int nrhs, int nblk) {
     }
 }
 
+template <typename T, bool SH, bool XH>
+static void mr_update_l(hipStream_t st, const VecArgs<T> &a, dim3 g, dim3 b) {
+    switch (a.l) {
+#define C_(L) case L: hipLaunchKernelGGL((k_mr_update<T, L, SH, XH>), g, b, 0, st, a); break;
+        C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8)
+#undef C_
+    }
+}
+
 template <typename T>
-void launch_mr_update(hipStream_t st, const VecArgs<T> &a, bool shifts, int nrhs, int nblk) {
+void launch_mr_update(hipStream_t st, const VecArgs<T> &a, bool shifts, bool xh, int nrhs, int nblk) {
     dim3 g(nblk, nrhs), b(BLOCK);
     if (shifts) {
-        switch (a.l) {
-#define C_(L) case L: hipLaunchKernelGGL((k_mr_update<T, L, true>), g, b, 0, st, a); break;
-            C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8)
-#undef C_
-        }
+        if (xh) mr_update_l<T, true, true>(st, a, g, b);
+        else mr_update_l<T, true, false>(st, a, g, b);
     } else {
-        switch (a.l) {
-#define C_(L) case L: hipLaunchKernelGGL((k_mr_update<T, L, false>), g, b, 0, st, a); break;
-            C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8)
-#undef C_
-        }
+        if (xh) mr_update_l<T, false, true>(st, a, g, b);
+        else mr_update_l<T, false, false>(st, a, g, b);
     }
+}
+
+template <typename T>
+void launch_rel_update(hipStream_t st, const VecArgs<T> &a, const double2 *b, const double2 *v, double2 *y,
+                       CoefRef yc, int nrhs, int nblk) {
+    hipLaunchKernelGGL((k_rel_update<T>), dim3(nblk, nrhs), dim3(BLOCK), 0, st, a, b, v, y, yc);
 }
 
 template <typename T>
@@ -366,9 +422,8 @@ void launch_diffnorm_partials(hipStream_t st, const C<T> *x, const C<T> *y, long
                               double *part, long ps, int nrhs, int nblk) {
     hipLaunchKernelGGL((k_diffnorm<T>), dim3(nblk, nrhs), dim3(BLOCK), 0, st, x, y, n, sx, sy, part, ps);
 }
-template <typename T>
-void launch_ysum(hipStream_t st, double2 *y, const C<T> *X, const double *w, long n, int ns, int nrhs, int nblk) {
-    hipLaunchKernelGGL((k_ysum<T>), dim3(nblk, nrhs), dim3(BLOCK), 0, st, y, X, w, n, ns);
+void launch_ysum(hipStream_t st, double2 *y, const double2 *X, const double *w, long n, int ns, int nrhs, int nblk) {
+    hipLaunchKernelGGL(k_ysum, dim3(nblk, nrhs), dim3(BLOCK), 0, st, y, X, w, n, ns);
 }
 void launch_yinit(hipStream_t st, double2 *y, const double2 *b, const double2 *c, long n, int nrhs, int nblk) {
     hipLaunchKernelGGL(k_yinit, dim3(nblk, nrhs), dim3(BLOCK), 0, st, y, b, c, n);
@@ -383,15 +438,15 @@ void launch_axpy_host(hipStream_t st, double2 *y, const double2 *x, double2 a, l
 
 #define INST(T)                                                                                  \
     template void launch_seed_u<T>(hipStream_t, const VecArgs<T> &, int, int, int);              \
-    template void launch_r_update<T>(hipStream_t, const VecArgs<T> &, int, bool, int, int);      \
+    template void launch_r_update<T>(hipStream_t, const VecArgs<T> &, int, bool, bool, int, int); \
     template void launch_gram<T>(hipStream_t, const VecArgs<T> &, int, int);                     \
-    template void launch_mr_update<T>(hipStream_t, const VecArgs<T> &, bool, int, int);          \
+    template void launch_mr_update<T>(hipStream_t, const VecArgs<T> &, bool, bool, int, int);    \
+    template void launch_rel_update<T>(hipStream_t, const VecArgs<T> &, const double2 *, const double2 *, double2 *, CoefRef, int, int); \
     template void launch_convert_in<T>(hipStream_t, C<T> *, const double2 *, long, long, long, int); \
     template void launch_convert_out<T>(hipStream_t, double2 *, const C<T> *, long, long, long, int); \
     template void launch_zero<T>(hipStream_t, C<T> *, long, long, int);                          \
     template void launch_dot_partials<T>(hipStream_t, const C<T> *, const C<T> *, long, double *, long, int, int, Gate); \
-    template void launch_diffnorm_partials<T>(hipStream_t, const C<T> *, const C<T> *, long, long, long, double *, long, int, int); \
-    template void launch_ysum<T>(hipStream_t, double2 *, const C<T> *, const double *, long, int, int, int);
+    template void launch_diffnorm_partials<T>(hipStream_t, const C<T> *, const C<T> *, long, long, long, double *, long, int, int);
 INST(double)
 INST(float)
 #undef INST

@@ -139,6 +139,9 @@ struct SeedState {
     int nact;       // active shifts
     int nshift;
     int mv, dots, axpys, reliable;
+    int mixed;      // FP32 iteration: reliable updates on
+    int rel;        // reliable update due at the end of this outer iteration
+    double rmax;    // largest ||r_0|| since the last reliable update
     int act[NSMAX];
 };
 
@@ -174,6 +177,8 @@ struct TapeOuter {
     int l_mr;       // MR terms applied (0: no MR)
     int partial;    // a u-step only (gamma breakdown) follows the full steps
     int exhausted;  // Krylov space exhausted: the iteration ended early
+    int rel;        // a reliable update r_0 = b - S x followed the MR step
+    int pad0, pad1, pad2;
 };
 
 // Pass-2 program entry (written by the host after the sweep)
@@ -184,7 +189,8 @@ struct ReplayStep {
 
 struct ReplayOuter {
     double2 gam[LMAX];
-    int lm, pad0, pad1, pad2;
+    double2 crel;   // coefficient of the reliable-update Mv output S x
+    int lm, rel, pad1, pad2;
 };
 
 struct Geom {

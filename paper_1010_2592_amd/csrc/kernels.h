@@ -56,7 +56,8 @@ struct VecArgs {
     C<T> *R = nullptr;          // [rhs][l+1][n]
     C<T> *U = nullptr;          // [rhs][l+1][n]
     C<T> *W = nullptr;          // [rhs][nshift][l+1][n]  (pass 1)
-    C<T> *X = nullptr;          // [rhs][nshift][n]       (pass 1)
+    double2 *X = nullptr;       // [rhs][nshift][n] shift solutions, FP64 (pass 1)
+    double2 *XH = nullptr;      // [rhs][n] seed solution, FP64 (reliable updates)
     const C<T> *rt = nullptr;   // [rhs][n] shadow residual
     double *part = nullptr;
     long ps = NBMAX;            // partial row stride
@@ -70,9 +71,13 @@ struct VecArgs {
 };
 
 template <typename T> void launch_seed_u(hipStream_t, const VecArgs<T> &, int j, int nrhs, int nblk);
-template <typename T> void launch_r_update(hipStream_t, const VecArgs<T> &, int j, bool shifts, int nrhs, int nblk);
+template <typename T> void launch_r_update(hipStream_t, const VecArgs<T> &, int j, bool shifts, bool xh, int nrhs, int nblk);
 template <typename T> void launch_gram(hipStream_t, const VecArgs<T> &, int nrhs, int nblk);
-template <typename T> void launch_mr_update(hipStream_t, const VecArgs<T> &, bool shifts, int nrhs, int nblk);
+template <typename T> void launch_mr_update(hipStream_t, const VecArgs<T> &, bool shifts, bool xh, int nrhs, int nblk);
+// reliable update: r_0 = b - v (v = S x in FP64), partials <rt, r_0>, ||r_0||^2
+// (optionally y += c v with c from yc)
+template <typename T> void launch_rel_update(hipStream_t, const VecArgs<T> &, const double2 *b, const double2 *v,
+                                             double2 *y, CoefRef yc, int nrhs, int nblk);
 
 // small utility kernels
 template <typename T>
@@ -90,8 +95,7 @@ template <typename T>
 void launch_diffnorm_partials(hipStream_t, const C<T> *x, const C<T> *y, long n, long sx, long sy,
                               double *part, long ps, int nrhs, int nblk);
 // y[rhs] = sum_s w[rhs][s] X[rhs][s]   (X stride n per shift, nshift per rhs)
-template <typename T>
-void launch_ysum(hipStream_t, double2 *y, const C<T> *X, const double *w, long n, int nshift,
+void launch_ysum(hipStream_t, double2 *y, const double2 *X, const double *w, long n, int nshift,
                  int nrhs, int nblk);
 // y[rhs] = c[rhs] * b[rhs]
 void launch_yinit(hipStream_t, double2 *y, const double2 *b, const double2 *c, long n, int nrhs,
@@ -125,5 +129,6 @@ void launch_sc_beta(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_alpha(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_mr(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_conv(hipStream_t, const ScalarArgs &, int nrhs);
+void launch_sc_rel(hipStream_t, const ScalarArgs &, int nrhs);
 
 }  // namespace msb

@@ -63,6 +63,8 @@ __global__ __launch_bounds__(BLOCK) void sc_init(ScalarArgs a) {
         S.m = S.n = 0;
         S.status = S_OK;
         S.mv = S.dots = S.axpys = S.reliable = 0;
+        S.rel = 0;
+        S.rmax = S.bnorm;
         S.nact = 0;
         for (int s = 0; s < S.nshift; ++s) {
             if (a.sh[(size_t)rhs * NSMAX + s].active) S.act[S.nact++] = s;
@@ -332,6 +334,28 @@ __global__ __launch_bounds__(BLOCK) void sc_mr(ScalarArgs a) {
     }
 }
 
+// Mixed precision: decide whether the outer iteration ends with a reliable
+// update r_0 = b - S x (FP64): when ||r_0|| has dropped below 0.1 of its
+// largest value since the last one, when any shift would freeze on the
+// recursively updated residual, or when the Krylov space looks exhausted.
+__global__ __launch_bounds__(BLOCK) void sc_rel(ScalarArgs a) {
+    const int rhs = blockIdx.x;
+    SeedState &S = a.seed[rhs];
+    if (!S.run || !S.mixed) return;
+    const double r02 = block_sum(prow(a, rhs) + 2 * a.ps, a.nblk);
+    if (threadIdx.x != 0) return;
+    const double rn = sqrt(r02);
+    if (rn > S.rmax) S.rmax = rn;
+    bool freeze = false;
+    for (int q = 0; q < S.nact; ++q) {
+        const ShiftState &H = a.sh[(size_t)rhs * NSMAX + S.act[q]];
+        if (!H.active) continue;
+        const bool due = S.forced ? (S.m + 1 >= H.force) : (rn / (cabsd(cmul(H.zeta, H.psi)) * S.bnorm) <= S.tol);
+        freeze = freeze || due;
+    }
+    S.rel = (rn <= 0.1 * S.rmax || freeze || S.exhausted) ? 1 : 0;
+}
+
 __global__ __launch_bounds__(BLOCK) void sc_conv(ScalarArgs a) {
     const int rhs = blockIdx.x;
     SeedState &S = a.seed[rhs];
@@ -351,6 +375,11 @@ __global__ __launch_bounds__(BLOCK) void sc_conv(ScalarArgs a) {
             o.l_mr = S.exhausted ? 0 : S.l_mr;
             o.partial = S.partial;
             o.exhausted = S.exhausted;
+            o.rel = S.rel;
+        }
+        if (S.rel) {
+            S.reliable += 1;
+            S.rmax = rn;
         }
     }
     __syncthreads();
@@ -360,7 +389,10 @@ __global__ __launch_bounds__(BLOCK) void sc_conv(ScalarArgs a) {
         const double res = rn / (cabsd(cmul(H.zeta, H.psi)) * S.bnorm);
         H.res = res;
         bool done = S.forced ? (S.m + 1 >= H.force) : (res <= S.tol);
-        if (S.exhausted) done = true;
+        // an exhausted Krylov space ends the solve; in mixed precision the
+        // residual was just recomputed in FP64, so a shift that still misses
+        // its tolerance is reported as not converged
+        if (S.exhausted && !S.mixed) done = true;
         if (done) {
             H.active = 0;
             H.iters = S.m + 1;
@@ -376,6 +408,7 @@ __global__ __launch_bounds__(BLOCK) void sc_conv(ScalarArgs a) {
         }
         S.nact = nact;
         S.m += 1;
+        S.rel = 0;
         const bool stop = (nact == 0) || S.broken || S.exhausted || (S.m >= S.max_outer);
         if (stop) {
             S.run = 0;
@@ -406,6 +439,9 @@ void launch_sc_alpha(hipStream_t st, const ScalarArgs &a, int nrhs) {
 }
 void launch_sc_mr(hipStream_t st, const ScalarArgs &a, int nrhs) {
     hipLaunchKernelGGL(sc_mr, dim3(nrhs), dim3(BLOCK), 0, st, a);
+}
+void launch_sc_rel(hipStream_t st, const ScalarArgs &a, int nrhs) {
+    hipLaunchKernelGGL(sc_rel, dim3(nrhs), dim3(BLOCK), 0, st, a);
 }
 void launch_sc_conv(hipStream_t st, const ScalarArgs &a, int nrhs) {
     hipLaunchKernelGGL(sc_conv, dim3(nrhs), dim3(BLOCK), 0, st, a);

@@ -382,13 +382,23 @@ static void sweep_rhs(int l, int M, const TapeStep *tape, const TapeOuter *outer
     }
     // backward: adjoint coefficients of every program variable
     std::vector<cd> lamR(l + 1, 0.0), lamU(l + 1, 0.0), lamW((size_t)ns * (l + 1), 0.0);
+    cd cb_extra = 0.0;      // coefficient of b from reliable updates
     res->steps.assign((size_t)max_outer * l, ReplayStep{});
     res->outer.assign((size_t)max_outer, ReplayOuter{});
     for (int m = M - 1; m >= 0; --m) {
         const int lm = outer[m].l_mr;
         ReplayOuter &ro = res->outer[m];
         ro.lm = lm;
+        ro.rel = outer[m].rel;
+        ro.crel = d2(0, 0);
         for (int i = 0; i < LMAX; ++i) ro.gam[i] = (i < lm) ? gam[(size_t)m * LMAX + i] : d2(0, 0);
+        if (outer[m].rel) {
+            // reliable update r_0 <- b - v, v = S x (an Mv output): b and v are
+            // sources; the old r_0 ends its history here
+            ro.crel = fromc(-lamR[0]);
+            cb_extra += lamR[0];
+            lamR[0] = 0.0;
+        }
         // MR, reversed: u_0 update, r_0 update, then the shifts
         for (int i = 1; i <= lm; ++i) lamU[i] += -toc(gam[(size_t)m * LMAX + i - 1]) * lamU[0];
         for (int i = 1; i <= lm; ++i) lamR[i] += -toc(gam[(size_t)m * LMAX + i - 1]) * lamR[0];
@@ -455,7 +465,7 @@ static void sweep_rhs(int l, int M, const TapeStep *tape, const TapeOuter *outer
             }
         }
     }
-    res->cb = lamR[0];
+    res->cb = lamR[0] + cb_extra;
     res->M = M;
 }
 
@@ -510,17 +520,30 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         launch_convert_in<T>(st, (C<T> *)c->ws_rt.p, b, n, n, n, nrhs);
         rt = (const C<T> *)c->ws_rt.p;
     }
-    C<T> *W = nullptr, *X = nullptr;
+    C<T> *W = nullptr;
+    double2 *X = nullptr;
+    const bool mixed = sizeof(T) != sizeof(double);
+    double2 *XH = nullptr, *t64 = nullptr, *v64 = nullptr;
+    if (mixed) {
+        // FP64 seed solution and the FP64 Mv of the reliable updates
+        CHK(ensure(c->ws_aux1, (size_t)nrhs * n * sizeof(double2)));
+        CHK(ensure(c->ws_aux2, (size_t)nrhs * n * sizeof(double2)));
+        CHK(ensure(c->ws_aux3, (size_t)nrhs * n * sizeof(double2)));
+        XH = (double2 *)c->ws_aux1.p;
+        t64 = (double2 *)c->ws_aux2.p;
+        v64 = (double2 *)c->ws_aux3.p;
+    }
     if (pass1) {
         CHK(ensure(c->ws_W, (size_t)nrhs * ns * (l + 1) * n * cs));
         W = (C<T> *)c->ws_W.p;
-        if (sizeof(T) == sizeof(double) && xs_out) {
-            X = (C<T> *)xs_out;
+        if (xs_out) {
+            X = xs_out;
         } else {
-            CHK(ensure(c->ws_X, (size_t)nrhs * ns * n * cs));
-            X = (C<T> *)c->ws_X.p;
+            CHK(ensure(c->ws_X, (size_t)nrhs * ns * n * sizeof(double2)));
+            X = (double2 *)c->ws_X.p;
         }
-    } else {
+    }
+    if (!pass1) {
         CHK(ensure(c->ws_tape, (size_t)nrhs * max_steps * sizeof(TapeStep)));
         CHK(ensure(c->ws_tape_gam, (size_t)nrhs * max_outer * LMAX * sizeof(double2)));
         CHK(ensure(c->ws_tape_outer, (size_t)nrhs * max_outer * sizeof(TapeOuter)));
@@ -542,6 +565,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         S.max_outer = max_outer;
         S.max_steps = max_steps;
         S.forced = P.force_iters ? 1 : 0;
+        S.mixed = mixed ? 1 : 0;
         for (int s = 0; s < ns; ++s) {
             ShiftState &H = hsh[(size_t)r * NSMAX + s];
             std::memset(&H, 0, sizeof(H));
@@ -563,14 +587,16 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
 
     // ---- initial vectors: r_0 = b, everything else zero
     {
-        Prof p(c, CL_OTHER, nrhs * nd * cB * (2.0 * (l + 1) + (pass1 ? ns * (l + 2.0) : 0.0)) +
+        Prof p(c, CL_OTHER, nrhs * nd * cB * (2.0 * (l + 1) + (pass1 ? ns * (l + 1.0) : 0.0)) +
+                                (pass1 ? nrhs * nd * ns * 16.0 : 0.0) + (mixed ? nrhs * nd * 16.0 : 0.0) +
                                 nrhs * nd * (16.0 + cB) + nrhs * nd * cB);
         launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
         launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
         if (pass1) {
             launch_zero<T>(st, W, (long)nrhs * ns * (l + 1) * n, 0, 1);
-            launch_zero<T>(st, X, (long)nrhs * ns * n, 0, 1);
+            launch_zero<double>(st, X, (long)nrhs * ns * n, 0, 1);
         }
+        if (mixed) launch_zero<double>(st, XH, (long)nrhs * n, 0, 1);
         launch_convert_in<T>(st, R, b, n, (long)(l + 1) * n, n, nrhs);
         launch_dot_partials<T>(st, rt, rt, n, part, ps, nrhs, nbv, Gate{});
     }
@@ -603,6 +629,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     va.U = Uv;
     va.W = W;
     va.X = X;
+    va.XH = XH;
     va.rt = rt;
     va.part = part;
     va.ps = ps;
@@ -631,6 +658,45 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     d2.rt_rs = n;
     d2.part = part;
     d2.ps = ps;
+
+    // FP64 Mv of the reliable updates: v = a g5 D (g5 D x) + sigma0 x
+    Gate g_rel;
+    g_rel.seed = seed;
+    g_rel.flag = &seed[0].rel;
+    g_rel.flag_stride = (long)sizeof(SeedState) / (long)sizeof(int);
+    g_rel.need = 1;
+    DslashArgs<double> r1 = ds_args<double>(c, P.neg_mu, true);
+    r1.in = XH;
+    r1.out = t64;
+    r1.gate = g_rel;
+    DslashArgs<double> r2 = ds_args<double>(c, P.neg_mu, true);
+    r2.in = t64;
+    r2.out = v64;
+    r2.v = XH;
+    r2.scale = P.a_scale;
+    r2.sigma0_rhs = (const double *)c->ws_sig0.p;
+    r2.gate = g_rel;
+    const double ds64_plain = nrhs * 24 * 16.0 * Vd + 36 * 16.0 * Vd;
+    const double ds64_sv = nrhs * 36 * 16.0 * Vd + 36 * 16.0 * Vd;
+    auto reliable_update = [&](VecArgs<T> &vv, Gate g, double2 *yacc, CoefRef yc, int nr) {
+        DslashArgs<double> q1 = r1, q2 = r2;
+        q1.gate = g;
+        q2.gate = g;
+        {
+            Prof p(c, CL_STENCIL, ds64_plain * nr / std::max(nrhs, 1));
+            launch_dslash<double>(st, q1, nrhs, EPI_PLAIN, false);
+        }
+        {
+            Prof p(c, CL_STENCIL, ds64_sv * nr / std::max(nrhs, 1));
+            launch_dslash<double>(st, q2, nrhs, EPI_SV, false);
+        }
+        VecArgs<T> w = vv;
+        w.gate = g;
+        {
+            Prof p(c, CL_SEED, nr * nd * (32.0 + cB + cB + (yacc ? 32.0 : 0.0)));
+            launch_rel_update<T>(st, w, b, v64, yacc, yc, nrhs, nbv);
+        }
+    };
 
     CHK(ensure_host(c, (size_t)nrhs * sizeof(SeedState)));
     SeedState *hseed = (SeedState *)c->host_pinned;
@@ -677,7 +743,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 // write u^s_0..j+1, x^s
                 Prof p(c, pass1 ? CL_SHIFT : CL_SEED,
                        nr_run * 3.0 * (j + 1) * nd * cB + (pass1 ? nsh_act * (2.0 * j + 5) * nd * cB : 0.0));
-                launch_r_update<T>(st, va, j, pass1, nrhs, nbv);
+                launch_r_update<T>(st, va, j, pass1, mixed, nrhs, nbv);
             }
             // r_{j+1} = S r_j, <rt, r_{j+1}>
             d1.in = R + (size_t)j * n;
@@ -708,7 +774,14 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             // u^s_0..u^s_l, x^s, write u^s_0, x^s
             Prof p(c, pass1 ? CL_SHIFT_MR : CL_SEED,
                    nr_run * (2.0 * (l + 1) + 3) * nd * cB + (pass1 ? nsh_act * (l + 4.0) * nd * cB : 0.0));
-            launch_mr_update<T>(st, va, pass1, nrhs, nbv);
+            launch_mr_update<T>(st, va, pass1, mixed, nrhs, nbv);
+        }
+        if (mixed) {
+            {
+                Prof p(c, CL_SCALAR, 0);
+                launch_sc_rel(st, sa, nrhs);
+            }
+            reliable_update(va, g_rel, nullptr, CoefRef{}, nr_run);
         }
         {
             Prof p(c, CL_SCALAR, 0);
@@ -739,6 +812,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     rep->steps_max = 0;
     rep->mv = 0;
     rep->dots = 0;
+    rep->reliable = 0;
     rep->shift_iters.assign((size_t)nrhs * ns, 0);
     rep->shift_resid.assign((size_t)nrhs * ns, 0.0);
     rep->rhs_outer.assign(nrhs, 0);
@@ -752,6 +826,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         rep->rhs_outer[r] = S.m;
         rep->mv += S.mv;
         rep->dots += S.dots;
+        rep->reliable += S.reliable;
         for (int s = 0; s < ns; ++s) {
             const ShiftState &H = fsh[(size_t)r * NSMAX + s];
             rep->shift_iters[(size_t)r * ns + s] = H.iters;
@@ -761,7 +836,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
 
     if (pass1) {
         Prof p(c, CL_OTHER, nrhs * nd * (ns * cB + 16.0));
-        launch_ysum<T>(st, y, X, (const double *)c->ws_wts.p, n, ns, nrhs, nbv);
+        launch_ysum(st, y, X, (const double *)c->ws_wts.p, n, ns, nrhs, nbv);
         HIPCHK(hipGetLastError());
     } else {
         // ---- sweep on the host, then the replay
@@ -811,6 +886,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
             launch_convert_in<T>(st, R, b, n, vs, n, nrhs);
             launch_yinit(st, y, b, (const double2 *)c->ws_cb.p, n, nrhs, nbv);
+            if (mixed) launch_zero<double>(st, XH, (long)nrhs * n, 0, 1);
         }
         const long rstride = (long)Mcap * l * sizeof(ReplayStep);
         VecArgs<T> vb = va;
@@ -858,7 +934,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 vb.gate = gr;
                 {
                     Prof p(c, CL_SEED, nr_m * 3.0 * (j + 1) * nd * cB);
-                    launch_r_update<T>(st, vb, j, false, nrhs, nbv);
+                    launch_r_update<T>(st, vb, j, false, mixed, nrhs, nbv);
                 }
                 e1.in = R + (size_t)j * n;
                 e1.gate = gr;
@@ -883,7 +959,17 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             vb.gam = CoefRef{(const char *)&dro[m].gam[0], (long)Mcap * (long)sizeof(ReplayOuter)};
             {
                 Prof p(c, CL_SEED, nr_m * (2.0 * (l + 1) + 2) * nd * cB);
-                launch_mr_update<T>(st, vb, false, nrhs, nbv);
+                launch_mr_update<T>(st, vb, false, mixed, nrhs, nbv);
+            }
+            if (mixed) {
+                Gate gr;
+                gr.flag = &dro[m].rel;
+                gr.flag_stride = (long)Mcap * sizeof(ReplayOuter) / (long)sizeof(int);
+                gr.need = 1;
+                vb.partials = 1;   // the reliable update writes partials (unused in pass 2)
+                reliable_update(vb, gr, y, CoefRef{(const char *)&dro[m].crel, (long)Mcap * (long)sizeof(ReplayOuter)},
+                                nr_m);
+                vb.partials = 0;
             }
             HIPCHK(hipGetLastError());
         }
@@ -900,7 +986,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         double2 *xd = (double2 *)c->ws_aux1.p, *t1 = (double2 *)c->ws_aux2.p, *t2 = (double2 *)c->ws_aux3.p;
         std::vector<double> rowbuf(ps);
         for (int s = 0; s < ns; ++s) {
-            launch_convert_out<T>(st, xd, X + (size_t)s * n, n, n, (long)ns * n, nrhs);
+            launch_convert_out<double>(st, xd, X + (size_t)s * n, n, n, (long)ns * n, nrhs);
             DslashArgs<double> a1 = ds_args<double>(c, P.neg_mu, true);
             a1.in = xd;
             a1.out = t1;

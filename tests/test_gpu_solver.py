@@ -194,19 +194,36 @@ def test_sign_apply_matches_oracle(overlap):
     assert rel(host(out)[0], ref) <= 1e-10
 
 
-@pytest.mark.parametrize("pass_", [1, 2])
-def test_mixed_precision_against_fp64_oracle(pass_):
+@pytest.mark.parametrize("name", ["4x4x4x8", "8x8x8x8"])
+def test_mixed_precision_against_fp64_oracle(name):
+    """FP32 stencil and vectors, FP64 reductions, scalars and solution
+    accumulators, reliable updates of the seed residual.  Pinned against the
+    FP64 oracle: the seed shift's true residual (computed by the oracle's
+    operator on the GPU's x) meets the tolerance; every other shift's true
+    residual and the error of y are stated and bounded by the FP32 floor
+    (measured: shifts <= 2.4e-6, y <= 8e-7 on these workloads)."""
     from paper_1010_2592_amd import msb
-    wk, U, op, a, sig, w, b = problem("8x8x8x8")
-    log(f"mixed precision 8^4 pass {pass_}")
-    y0, i0 = oracle_run(op, a, b[0], sig, w, 4, wk.tol, 3000, 1)[:2]
+    wk, U, op, a, sig, w, b = problem(name)
+    l = wk.ells[0]
+    log(f"mixed precision {name}")
+    y0 = oracle_run(op, a, b[0], sig, w, l, wk.tol, 3000, 1)[0]
     ctx = ctx_for(wk, U)
-    y, info, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 4, wk.tol, 3000, pass_,
-                                      flags=msb.MIXED, allow=(msb.OK, msb.NOT_CONVERGED))
-    err = rel(host(y)[0], y0)
-    log(f"mixed pass {pass_}: rel err vs FP64 oracle {err:.3e}, outer {info.outer_iters} "
-        f"(oracle {i0.outer})")
-    assert err <= 1e-4
+    y1, i1, xs = ctx.mshift_bicgstabl(cuda(b), a, sig, w, l, wk.tol, 3000, 1, flags=msb.MIXED,
+                                      want_shifts=True, true_resid=True)
+    y2, i2, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, l, wk.tol, 3000, 2, flags=msb.MIXED)
+    assert i1.reliable_updates > 0 and i1.status == 0 and i2.status == 0
+    xs = host(xs)[0]
+    s0 = int(np.argmin(sig))
+    S = op.seed_op(a, 0.0)
+    true_res = np.array([np.linalg.norm(b[0] - S(xs[s]) - sig[s] * xs[s]) / np.linalg.norm(b[0])
+                         for s in range(len(sig))])
+    e1, e2 = rel(host(y1)[0], y0), rel(host(y2)[0], y0)
+    log(f"  {name}: mixed pass 1 err {e1:.2e}, pass 2 err {e2:.2e}, reliable updates {i1.reliable_updates}, "
+        f"shift true residuals max {true_res.max():.2e} (seed {true_res[s0]:.2e})")
+    assert np.allclose(true_res, i1.shift_true_resid[0], rtol=1e-3, atol=1e-15)
+    assert true_res[s0] <= 1.5 * wk.tol
+    assert true_res.max() <= 1e-5
+    assert e1 <= 5e-6 and e2 <= 5e-6
 
 
 def test_production_lattice_fixed_iterations():
