@@ -300,6 +300,20 @@ __global__ __launch_bounds__(BLOCK) void k_rel_update(VecArgs<T> a, const double
     block_reduce_store<3>(p, a.part + (size_t)rhs * PMAX * a.ps + blockIdx.x, a.ps);
 }
 
+__global__ __launch_bounds__(BLOCK) void k_shift_dots(const double2 *eta, const double2 *X, const double2 *Z, long n,
+                                                      int ns, double *out) {
+    const int rs = blockIdx.y;            // rhs * ns + s
+    const int rhs = rs / ns;
+    const double2 *e = eta + (size_t)rhs * n, *x = X + (size_t)rs * n, *z = Z + (size_t)rs * n;
+    double p[2] = {0.0, 0.0};
+    for (long i = (long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long)gridDim.x * BLOCK) {
+        const double2 xv = x[i], ev = e[i], zv = z[i];
+        p[0] += ev.x * xv.x + ev.y * xv.y;
+        p[1] += zv.x * xv.x + zv.y * xv.y;
+    }
+    block_reduce_store<2>(p, out + (size_t)rs * 2 * gridDim.x + blockIdx.x, gridDim.x);
+}
+
 __global__ void k_yinit(double2 *y, const double2 *b, const double2 *c, long n) {
     const int rhs = blockIdx.y;
     const double2 cc = c[rhs];
@@ -432,6 +446,11 @@ void launch_overlap_out(hipStream_t st, double2 *out, const double2 *b, const do
                         int overlap, double s, int nblk) {
     hipLaunchKernelGGL(k_overlap_out, dim3(nblk, nrhs), dim3(BLOCK), 0, st, out, b, w, V, overlap, s);
 }
+void launch_shift_dots(hipStream_t st, const double2 *eta, const double2 *X, const double2 *Z, long n, int ns,
+                       int nrhs, int nblk, double *out) {
+    hipLaunchKernelGGL(k_shift_dots, dim3(nblk, nrhs * ns), dim3(BLOCK), 0, st, eta, X, Z, n, ns, out);
+}
+
 void launch_axpy_host(hipStream_t st, double2 *y, const double2 *x, double2 a, long n, int nblk) {
     hipLaunchKernelGGL(k_axpy_host, dim3(nblk), dim3(BLOCK), 0, st, y, x, a, n);
 }

@@ -218,6 +218,7 @@ int pfe_sign_backward(msb_ctx *ctx, double a_scale, int n_shift, const double *s
                       const void *b, const void *eta, int mode, void *grad_b, double *grad_w,
                       double *grad_sigma, void *grad_links, msb_solve_info *info) {
     msb::SolveParams P;
+    if (flags & (MSB_OVERLAP | MSB_ADJOINT)) return arg_error("pfe_sign_backward: only MSB_MIXED applies");
     int rc = make_params(ctx, a_scale, n_shift, shifts, weights, 0, l, tol, max_outer, 1, flags, nrhs,
                          "pfe_sign_backward", &P);
     if (rc) return rc;

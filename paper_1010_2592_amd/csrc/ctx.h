@@ -26,7 +26,7 @@ struct Ctx {
     // workspace, grown on demand and kept for later calls
     DevBuf ws_R, ws_U, ws_tmp, ws_W, ws_X, ws_rt, ws_b, ws_y, ws_part, ws_seed, ws_shift, ws_sc,
         ws_mc, ws_tape, ws_tape_gam, ws_tape_outer, ws_replay, ws_replay_outer, ws_wts, ws_sig0,
-        ws_cb, ws_aux1, ws_aux2, ws_aux3, ws_aux4;
+        ws_cb, ws_aux1, ws_aux2, ws_aux3, ws_aux4, ws_bX, ws_bZ, ws_by, ws_beta, ws_bA, ws_bB, ws_bdots;
     void *host_pinned = nullptr;
     size_t host_pinned_bytes = 0;
     // kernel timing (msb_profile_enable): HIP event pairs around launches

@@ -221,6 +221,110 @@ __global__ __launch_bounds__(BLOCK) void dslash_kernel(DslashArgs<T> a) {
         block_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + sblk, a.ps);
 }
 
+// ---------------------------------------------------------------------------
+// Link force: gradient of sum_pairs c Re <p, D(mu) q> with respect to the
+// links (the unconstrained complex gradient, dL/dRe + i dL/dIm).  U_nu(x)
+// enters (D q)(x) through the forward hop and (D q)(x+nu) through the
+// backward hop, hence with
+//   M1_ab = sum_alpha conj(p(x)_{alpha a})    [(1 - gamma_nu) q(x+nu)]_{alpha b}
+//   M2_ab = sum_alpha conj(p(x+nu)_{alpha a}) [(1 + gamma_nu) q(x)]_{alpha b}
+//   G_nu(x) += -c b_nu(x)/2 (e^{mu d_nu4} conj(M1) + e^{-mu d_nu4} M2^T).
+// One work-item per site; it accumulates all pairs and right-hand sides of
+// the launch before its single read-modify-write of the 36 link entries.
+template <int NU, int SGN>
+__device__ __forceinline__ void proj_full(const double2 *__restrict__ q, long rs, int V, int s, bool g5,
+                                          double2 (&out)[4][3]) {
+    using P = Proj<NU, SGN>;
+    double2 h[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double2 q0 = q[(0 + c) * V + s], q1 = q[(3 + c) * V + s];
+        double2 qa = q[(3 * P::P0 + c) * V + s], qb = q[(3 * P::P1 + c) * V + s];
+        if (g5) {
+            if (P::P0 >= 2) qa = cneg(qa);
+            if (P::P1 >= 2) qb = cneg(qb);
+        }
+        h[0][c] = cadd(q0, mulcode<P::C0>(qa));
+        h[1][c] = cadd(q1, mulcode<P::C1>(qb));
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        out[0][c] = h[0][c];
+        out[1][c] = h[1][c];
+        out[2][c] = mulcode<P::D2>(h[P::Q2][c]);
+        out[3][c] = mulcode<P::D3>(h[P::Q3][c]);
+    }
+    (void)rs;
+}
+
+template <int NU>
+__device__ __forceinline__ void force_dir(const LinkForceArgs &a, int s, int sf, double bnu, double2 *G) {
+    const int V = a.g.V;
+    const long nv = 12L * V;
+    double2 M1[3][3], M2[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) M1[i][j] = M2[i][j] = d2(0, 0);
+    for (int k = 0; k < a.npair; ++k) {
+        const LinkPair &pr = a.pairs[k];
+        for (int r = 0; r < a.nrhs; ++r) {
+            const double2 *p = pr.p + (size_t)r * (pr.p_rs ? pr.p_rs : nv);
+            const double2 *q = pr.q + (size_t)r * (pr.q_rs ? pr.q_rs : nv);
+            const double c = pr.c;
+            double2 pr1[4][3], pr2[4][3];
+            proj_full<NU, -1>(q, 0, V, sf, false, pr1);      // (1 - gamma) q(x+nu)
+            proj_full<NU, +1>(q, 0, V, s, false, pr2);       // (1 + gamma) q(x)
+#pragma unroll
+            for (int al = 0; al < 4; ++al) {
+#pragma unroll
+                for (int ia = 0; ia < 3; ++ia) {
+                    double2 px = p[(3 * al + ia) * V + s];
+                    double2 pf = p[(3 * al + ia) * V + sf];
+                    if (pr.g5p && al >= 2) {
+                        px = cneg(px);
+                        pf = cneg(pf);
+                    }
+                    px = cscale(px, c);
+                    pf = cscale(pf, c);
+#pragma unroll
+                    for (int ib = 0; ib < 3; ++ib) {
+                        M1[ia][ib] = cadd(M1[ia][ib], cmulc(px, pr1[al][ib]));
+                        M2[ia][ib] = cadd(M2[ia][ib], cmulc(pf, pr2[al][ib]));
+                    }
+                }
+            }
+        }
+    }
+    const double ef = (NU == 3) ? a.ef : 1.0, eb = (NU == 3) ? a.eb : 1.0;
+    const double f = -0.5 * bnu;
+#pragma unroll
+    for (int ia = 0; ia < 3; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < 3; ++ib) {
+            double2 *gp = G + ((size_t)NU * 9 + 3 * ia + ib) * V + s;
+            const double2 add = cscale(cadd(cscale(cconj(M1[ia][ib]), ef), cscale(M2[ib][ia], eb)), f);
+            *gp = cadd(*gp, add);
+        }
+}
+
+__global__ __launch_bounds__(BLOCK) void link_force_kernel(LinkForceArgs a) {
+    const int V = a.g.V, Lx = a.g.Lx, Ly = a.g.Ly, Lz = a.g.Lz, Lt = a.g.Lt;
+    for (int s = blockIdx.x * BLOCK + threadIdx.x; s < V; s += gridDim.x * BLOCK) {
+        const int x = s % Lx;
+        const int r1 = s / Lx;
+        const int yy = r1 % Ly;
+        const int r2 = r1 / Ly;
+        const int z = r2 % Lz;
+        const int t = r2 / Lz;
+        const int sxy = Lx * Ly, sxyz = Lx * Ly * Lz;
+        force_dir<0>(a, s, (x == Lx - 1) ? s - (Lx - 1) : s + 1, 1.0, a.G);
+        force_dir<1>(a, s, (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx, 1.0, a.G);
+        force_dir<2>(a, s, (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy, 1.0, a.G);
+        force_dir<3>(a, s, (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz, (t == Lt - 1) ? a.bc : 1.0, a.G);
+    }
+}
+
 }  // namespace
 
 template <typename T>
@@ -247,6 +351,11 @@ void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in
 }
 
 template void launch_dslash<double>(hipStream_t, DslashArgs<double>, int, int, bool);
+
+void launch_link_force(hipStream_t st, const LinkForceArgs &a) {
+    const int nb = nblocks_for(a.g.V);
+    hipLaunchKernelGGL(link_force_kernel, dim3(nb), dim3(BLOCK), 0, st, a);
+}
 template void launch_dslash<float>(hipStream_t, DslashArgs<float>, int, int, bool);
 
 }  // namespace msb

@@ -47,6 +47,23 @@ struct DslashArgs {
 template <typename T>
 void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in);
 
+// link force: pairs (c, p, q), the gradient of sum c Re <p, D(mu) q>
+struct LinkPair {
+    const double2 *p = nullptr, *q = nullptr;
+    long p_rs = 0, q_rs = 0;   // element strides between right-hand sides (0: 12 V)
+    double c = 0;
+    int g5p = 0;               // use gamma5 p instead of p
+};
+constexpr int MAX_PAIRS = 4;
+struct LinkForceArgs {
+    Geom g{};
+    double ef = 1, eb = 1, bc = -1;
+    int npair = 0, nrhs = 1;
+    LinkPair pairs[MAX_PAIRS];
+    double2 *G = nullptr;      // [4][3][3][V], accumulated (+=)
+};
+void launch_link_force(hipStream_t st, const LinkForceArgs &a);
+
 // ---- vector kernels ------------------------------------------------------
 template <typename T>
 struct VecArgs {
@@ -97,6 +114,10 @@ void launch_diffnorm_partials(hipStream_t, const C<T> *x, const C<T> *y, long n,
 // y[rhs] = sum_s w[rhs][s] X[rhs][s]   (X stride n per shift, nshift per rhs)
 void launch_ysum(hipStream_t, double2 *y, const double2 *X, const double *w, long n, int nshift,
                  int nrhs, int nblk);
+// per (rhs, shift): Re <eta_r, x_rs> and Re <z_rs, x_rs> partials into
+// out[((rhs * ns + s) * 2 + k) * nblk + block]
+void launch_shift_dots(hipStream_t, const double2 *eta, const double2 *X, const double2 *Z, long n, int ns,
+                       int nrhs, int nblk, double *out);
 // y[rhs] = c[rhs] * b[rhs]
 void launch_yinit(hipStream_t, double2 *y, const double2 *b, const double2 *c, long n, int nrhs,
                   int nblk);

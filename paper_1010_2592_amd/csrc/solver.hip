@@ -191,7 +191,8 @@ void ctx_destroy(Ctx *c) {
                       &c->ws_y, &c->ws_part, &c->ws_seed, &c->ws_shift, &c->ws_sc, &c->ws_mc,
                       &c->ws_tape, &c->ws_tape_gam, &c->ws_tape_outer, &c->ws_replay,
                       &c->ws_replay_outer, &c->ws_wts, &c->ws_sig0, &c->ws_cb, &c->ws_aux1,
-                      &c->ws_aux2, &c->ws_aux3, &c->ws_aux4};
+                      &c->ws_aux2, &c->ws_aux3, &c->ws_aux4, &c->ws_bX, &c->ws_bZ, &c->ws_by,
+                      &c->ws_beta, &c->ws_bA, &c->ws_bB, &c->ws_bdots};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->U64) (void)hipFree(c->U64);
@@ -1046,9 +1047,110 @@ int sign_apply(Ctx *c, const SolveParams &P, const double2 *b, double2 *out, boo
     return 0;
 }
 
-int sign_backward(Ctx *, const SolveParams &, const double2 *, const double2 *, int, double2 *, double *,
-                  double *, double2 *, SolveReport *) {
-    return set_error(S_ERR_ARG, "pfe_sign_backward: not available in this build");
+// ---------------------------------------------------------------------------
+// Backward of L = Re <eta, y>, y = f(A) b (mode 0) or y = sign(H) b (mode 1).
+// With x_s = (A + sigma_s)^{-1} b and z_s = (A^+ + sigma_s)^{-1} eta (A^+ =
+// A(-mu), a forward solve at -mu):
+//   grad_b = sum_s w_s z_s, grad_w_s = Re <eta, x_s>,
+//   grad_sigma_s = -w_s Re <z_s, x_s>,
+//   links: pairs (gamma5 z_s, H x_s) and (gamma5 H(-mu) z_s = D(-mu) z_s, x_s)
+//   with c = -a w_s through the link-force kernel; mode 1 adds the pair
+//   (gamma5 eta, y) with c = sqrt(a) and uses eta' = sqrt(a) H(-mu) eta.
+// ---------------------------------------------------------------------------
+int sign_backward(Ctx *c, const SolveParams &P0, const double2 *b, const double2 *eta, int mode,
+                  double2 *grad_b, double *grad_w, double *grad_sigma, double2 *grad_links, SolveReport *rep) {
+    hipStream_t st = c->stream;
+    const int V = c->g.V;
+    const long n = 12L * V;
+    const int nrhs = P0.nrhs, ns = P0.n_shift;
+    const int nbv = nblocks_for(n);
+    CHK(ensure(c->ws_bX, (size_t)nrhs * ns * n * sizeof(double2)));
+    CHK(ensure(c->ws_bZ, (size_t)nrhs * ns * n * sizeof(double2)));
+    CHK(ensure(c->ws_by, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c->ws_beta, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c->ws_bA, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c->ws_bB, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c->ws_bdots, (size_t)nrhs * ns * 2 * nbv * sizeof(double)));
+    double2 *X = (double2 *)c->ws_bX.p, *Z = (double2 *)c->ws_bZ.p, *y = (double2 *)c->ws_by.p;
+    double2 *eta2 = (double2 *)c->ws_beta.p, *tA = (double2 *)c->ws_bA.p, *tB = (double2 *)c->ws_bB.p;
+
+    SolveParams P = P0;
+    P.pass = 1;
+    SolveReport rf, ra;
+    CHK(solve_mshift(c, P, b, y, X, false, &rf));
+    const double2 *etap = eta;
+    const double sa = std::sqrt(P.a_scale);
+    if (mode == 1) {
+        DslashArgs<double> a1 = ds_args<double>(c, !P.neg_mu, true);    // sqrt(a) H^+ eta
+        a1.in = eta;
+        a1.out = eta2;
+        a1.scale = sa;
+        launch_dslash<double>(st, a1, nrhs, EPI_PLAIN, false);
+        etap = eta2;
+    }
+    SolveParams Pa = P;
+    Pa.neg_mu = !P.neg_mu;
+    CHK(solve_mshift(c, Pa, etap, grad_b, Z, false, &ra));
+
+    // grad_w, grad_sigma from per-(rhs, shift) inner products
+    launch_shift_dots(st, etap, X, Z, n, ns, nrhs, nbv, (double *)c->ws_bdots.p);
+    HIPCHK(hipGetLastError());
+    std::vector<double> dots((size_t)nrhs * ns * 2 * nbv);
+    HIPCHK(hipMemcpyAsync(dots.data(), c->ws_bdots.p, dots.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int s = 0; s < ns; ++s) {
+        double gw = 0.0, gs = 0.0;
+        for (int r = 0; r < nrhs; ++r) {
+            const double *row = &dots[((size_t)r * ns + s) * 2 * nbv];
+            gw += host_partial_sum(row, nbv);
+            gs += host_partial_sum(row + nbv, nbv);
+        }
+        grad_w[s] = gw;
+        grad_sigma[s] = -P.weights[s] * gs;
+    }
+
+    // link force, one launch per shift (two pairs, all right-hand sides)
+    LinkForceArgs fa;
+    fa.g = c->g;
+    const double mu = P.neg_mu ? -c->mu : c->mu;
+    fa.ef = std::exp(mu);
+    fa.eb = std::exp(-mu);
+    fa.bc = c->bc_t;
+    fa.nrhs = nrhs;
+    fa.G = grad_links;
+    for (int s = 0; s < ns; ++s) {
+        DslashArgs<double> hx = ds_args<double>(c, P.neg_mu, true);     // H x_s
+        hx.in = X + (size_t)s * n;
+        hx.in_rs = (long)ns * n;
+        hx.out = tA;
+        launch_dslash<double>(st, hx, nrhs, EPI_PLAIN, false);
+        DslashArgs<double> dz = ds_args<double>(c, !P.neg_mu, false);   // D(-mu) z_s = g5 H(-mu) z_s
+        dz.in = Z + (size_t)s * n;
+        dz.in_rs = (long)ns * n;
+        dz.out = tB;
+        launch_dslash<double>(st, dz, nrhs, EPI_PLAIN, false);
+        const double cf = -P.a_scale * P.weights[s];
+        fa.npair = 2;
+        fa.pairs[0] = LinkPair{Z + (size_t)s * n, tA, (long)ns * n, n, cf, 1};
+        fa.pairs[1] = LinkPair{tB, X + (size_t)s * n, n, (long)ns * n, cf, 0};
+        launch_link_force(st, fa);
+    }
+    if (mode == 1) {
+        fa.npair = 1;
+        fa.pairs[0] = LinkPair{eta, y, n, n, sa, 1};
+        launch_link_force(st, fa);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    *rep = rf;
+    rep->status = std::max(rf.status, ra.status);
+    rep->mv = rf.mv + ra.mv;
+    rep->dots = rf.dots + ra.dots;
+    rep->reliable = rf.reliable + ra.reliable;
+    rep->bytes_model = rf.bytes_model + ra.bytes_model;
+    rep->outer_max = std::max(rf.outer_max, ra.outer_max);
+    rep->steps_max = std::max(rf.steps_max, ra.steps_max);
+    return 0;
 }
 
 }  // namespace msb
