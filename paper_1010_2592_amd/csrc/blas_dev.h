@@ -1,0 +1,209 @@
+// Device bodies of the streaming vector stages of multi-shift BiCGstab(l)
+// (see blas.hip for what each computes).  bx and gx are the element block and
+// the number of element blocks, rhs the right-hand side: the one-launch-per-
+// stage kernels pass blockIdx.x, gridDim.x and blockIdx.y, the persistent
+// kernel its virtual block coordinates.
+#pragma once
+#include "common.h"
+#include "kernels.h"
+
+namespace msb {
+namespace dev {
+
+template <typename T>
+__device__ __forceinline__ C<T> cvt(double2 z) { return to_c<T>(z); }
+
+// ---------------------------------------------------------------------------
+template <typename T, int J>
+__device__ __forceinline__ void seed_u_body(const VecArgs<T> &a, int bx, int gx, int rhs) {
+    if (!gate_open(a.gate, rhs)) return;
+    const long n = a.n;
+    const C<T> beta = cvt<T>(ld(a.beta, rhs));
+    C<T> *R = a.R + (size_t)rhs * (a.l + 1) * n;
+    C<T> *U = a.U + (size_t)rhs * (a.l + 1) * n;
+    for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
+#pragma unroll
+        for (int i = 0; i <= J; ++i) {
+            const C<T> r = R[i * n + e];
+            const C<T> u = U[i * n + e];
+            U[i * n + e] = csub(r, cmul(beta, u));
+        }
+    }
+}
+
+template <typename T, int J, bool SHIFTS, bool XH>
+__device__ __forceinline__ void r_update_body(const VecArgs<T> &a, int bx, int gx, int rhs) {
+    if (!gate_open(a.gate, rhs)) return;
+    const long n = a.n;
+    const double2 alpha_d = ld(a.alpha, rhs);
+    const C<T> alpha = cvt<T>(alpha_d);
+    C<T> *R = a.R + (size_t)rhs * (a.l + 1) * n;
+    const C<T> *U = a.U + (size_t)rhs * (a.l + 1) * n;
+    const int nact = SHIFTS ? a.seed[rhs].nact : 0;
+    const StepCoef *sc = SHIFTS ? a.sc + (size_t)rhs * NSMAX : nullptr;
+    double part[1] = {0.0};
+    for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
+        C<T> r[J + 1], u1[J + 1];
+#pragma unroll
+        for (int i = 0; i <= J; ++i) {
+            r[i] = R[i * n + e];
+            u1[i] = U[(i + 1) * n + e];
+        }
+        if (SHIFTS) {
+            for (int q = 0; q < nact; ++q) {
+                const StepCoef c = sc[q];
+                if (!c.live) continue;
+                const C<T> kap = cvt<T>(c.kap), bs = cvt<T>(c.beta_s), as = cvt<T>(c.alpha_s);
+                const C<T> a1 = cvt<T>(c.a1), a2 = cvt<T>(c.a2);
+                const T sp = (T)c.sp;
+                C<T> *W = a.W + ((size_t)rhs * a.nshift + c.s) * (a.l + 1) * n;
+                double2 *X = a.X + ((size_t)rhs * a.nshift + c.s) * n;
+                C<T> w[J + 2];
+#pragma unroll
+                for (int i = 0; i <= J; ++i) w[i] = csub(cmul(kap, r[i]), cmul(bs, W[i * n + e]));
+                X[e] = cfma(c.alpha_s, d2((double)w[0].x, (double)w[0].y), X[e]);
+                (void)as;
+                w[J + 1] = csub(cadd(cmul(a1, r[J]), cmul(a2, u1[J])), cscale(w[J], sp));
+#pragma unroll
+                for (int i = 0; i <= J + 1; ++i) W[i * n + e] = w[i];
+            }
+        }
+        if (XH) {
+            // seed solution x += alpha u_0, accumulated in FP64
+            const C<T> u0 = U[e];
+            double2 *xh = a.XH + (size_t)rhs * n;
+            xh[e] = cfma(alpha_d, d2((double)u0.x, (double)u0.y), xh[e]);
+        }
+#pragma unroll
+        for (int i = 0; i <= J; ++i) {
+            const C<T> rn = csub(r[i], cmul(alpha, u1[i]));
+            R[i * n + e] = rn;
+            if (i == 0) part[0] += (double)rn.x * rn.x + (double)rn.y * rn.y;
+        }
+    }
+    if (a.partials)
+        block_reduce_store<1>(part, a.part + (size_t)rhs * PMAX * a.ps + 3 * a.ps + bx, a.ps);
+}
+
+template <typename T, int L>
+__device__ __forceinline__ void gram_body(const VecArgs<T> &a, int bx, int gx, int rhs) {
+    if (!gate_open(a.gate, rhs)) return;
+    constexpr int NP = (L + 1) * (L + 2) / 2;
+    const long n = a.n;
+    const C<T> *R = a.R + (size_t)rhs * (a.l + 1) * n;
+    double acc[2 * NP];
+#pragma unroll
+    for (int p = 0; p < 2 * NP; ++p) acc[p] = 0.0;
+    for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
+        C<T> r[L + 1];
+#pragma unroll
+        for (int i = 0; i <= L; ++i) r[i] = R[i * n + e];
+        int p = 0;
+#pragma unroll
+        for (int i = 0; i <= L; ++i)
+#pragma unroll
+            for (int k = i; k <= L; ++k) {
+                // conj(r_i) r_k
+                acc[2 * p] += (double)r[i].x * r[k].x + (double)r[i].y * r[k].y;
+                acc[2 * p + 1] += (double)r[i].x * r[k].y - (double)r[i].y * r[k].x;
+                ++p;
+            }
+    }
+    block_reduce_store<2 * NP>(acc, a.part + (size_t)rhs * PMAX * a.ps + bx, a.ps);
+}
+
+template <typename T, int L, bool SHIFTS, bool XH>
+__device__ __forceinline__ void mr_update_body(const VecArgs<T> &a, int bx, int gx, int rhs) {
+    if (!gate_open(a.gate, rhs)) return;
+    const long n = a.n;
+    C<T> *R = a.R + (size_t)rhs * (a.l + 1) * n;
+    C<T> *U = a.U + (size_t)rhs * (a.l + 1) * n;
+    const C<T> *rt = a.rt ? a.rt + (size_t)rhs * n : nullptr;
+    C<T> g[L + 1];
+    double2 gd[L + 1];
+#pragma unroll
+    for (int i = 1; i <= L; ++i) {
+        CoefRef c = a.gam;
+        c.p += (i - 1) * sizeof(double2);
+        gd[i] = ld(c, rhs);
+        g[i] = cvt<T>(gd[i]);
+    }
+    const int nact = SHIFTS ? a.seed[rhs].nact : 0;
+    const MRCoef *mc = SHIFTS ? a.mc + (size_t)rhs * NSMAX : nullptr;
+    double part[3] = {0.0, 0.0, 0.0};
+    for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
+        C<T> r[L + 1];
+#pragma unroll
+        for (int i = 0; i <= L; ++i) r[i] = R[i * n + e];
+        if (SHIFTS) {
+            for (int q = 0; q < nact; ++q) {
+                const MRCoef &c = mc[q];
+                if (!c.live) continue;
+                C<T> *W = a.W + ((size_t)rhs * a.nshift + c.s) * (a.l + 1) * n;
+                double2 *X = a.X + ((size_t)rhs * a.nshift + c.s) * n;
+                double2 x = X[e];
+#pragma unroll
+                for (int k = 0; k < L; ++k) x = cfma(c.kc[k], d2((double)r[k].x, (double)r[k].y), x);
+                X[e] = x;
+                C<T> w0 = W[e];
+#pragma unroll
+                for (int i = 1; i <= L; ++i) w0 = csub(w0, cmul(g[i], W[i * n + e]));
+                W[e] = cmul(w0, cvt<T>(c.inv_q));
+            }
+        }
+        if (XH) {
+            // seed solution x += sum_i gamma_i r_{i-1}, accumulated in FP64
+            double2 *xh = a.XH + (size_t)rhs * n;
+            double2 x = xh[e];
+#pragma unroll
+            for (int i = 1; i <= L; ++i) x = cfma(gd[i], d2((double)r[i - 1].x, (double)r[i - 1].y), x);
+            xh[e] = x;
+        }
+        C<T> r0 = r[0];
+#pragma unroll
+        for (int i = 1; i <= L; ++i) r0 = csub(r0, cmul(g[i], r[i]));
+        R[e] = r0;
+        C<T> u0 = U[e];
+#pragma unroll
+        for (int i = 1; i <= L; ++i) u0 = csub(u0, cmul(g[i], U[i * n + e]));
+        U[e] = u0;
+        if (a.partials) {
+            if (rt) {
+                const C<T> t = rt[e];
+                part[0] += (double)t.x * r0.x + (double)t.y * r0.y;
+                part[1] += (double)t.x * r0.y - (double)t.y * r0.x;
+            }
+            part[2] += (double)r0.x * r0.x + (double)r0.y * r0.y;
+        }
+    }
+    if (a.partials)
+        block_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + bx, a.ps);
+}
+
+// r_0 = b - v in FP64 (v = S x), stored in the iteration's precision;
+// partials of <rt, r_0> and ||r_0||^2 from the FP64 value
+template <typename T>
+__device__ __forceinline__ void rel_update_body(const VecArgs<T> &a, const double2 *b, const double2 *v,                                                       double2 *y, CoefRef yc, int bx, int gx, int rhs) {
+    if (!gate_open(a.gate, rhs)) return;
+    const long n = a.n;
+    C<T> *R = a.R + (size_t)rhs * (a.l + 1) * n;
+    const C<T> *rt = a.rt + (size_t)rhs * n;
+    const double2 *br = b + (size_t)rhs * n, *vr = v + (size_t)rhs * n;
+    double2 *yr = y ? y + (size_t)rhs * n : nullptr;
+    const double2 c = y ? ld(yc, rhs) : d2(0, 0);
+    double p[3] = {0.0, 0.0, 0.0};
+    for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
+        const double2 ve = vr[e];
+        const double2 r0 = csub(br[e], ve);
+        R[e] = to_c<T>(r0);
+        if (yr) yr[e] = cfma(c, ve, yr[e]);
+        const C<T> t = rt[e];
+        p[0] += (double)t.x * r0.x + (double)t.y * r0.y;
+        p[1] += (double)t.x * r0.y - (double)t.y * r0.x;
+        p[2] += r0.x * r0.x + r0.y * r0.y;
+    }
+    block_reduce_store<3>(p, a.part + (size_t)rhs * PMAX * a.ps + bx, a.ps);
+}
+
+}  // namespace dev
+}  // namespace msb

@@ -47,7 +47,8 @@ int make_params(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
     if (nrhs < 1 || nrhs > 4096) return arg_error(w + ": nrhs must be in 1..4096");
     if (flags & ~(MSB_MIXED | MSB_PERSISTENT | MSB_ADJOINT | MSB_OVERLAP))
         return arg_error(w + ": unknown flag bits");
-    if (flags & MSB_PERSISTENT) return arg_error(w + ": MSB_PERSISTENT is not available in this build");
+    if ((flags & MSB_PERSISTENT) && l > msb::PERSIST_LMAX)
+        return arg_error(w + ": MSB_PERSISTENT needs l <= " + std::to_string(msb::PERSIST_LMAX));
     const long nsets = per_rhs ? nrhs : 1;
     if (!finite_array(shifts, nsets * n_shift) || !finite_array(weights, nsets * n_shift))
         return arg_error(w + ": shifts and weights must be finite");
@@ -59,6 +60,7 @@ int make_params(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
     P->pass = pass;
     P->mixed = (flags & MSB_MIXED) != 0;
     P->neg_mu = (flags & MSB_ADJOINT) != 0;
+    P->persistent = (flags & MSB_PERSISTENT) != 0;
     P->nrhs = nrhs;
     P->shifts.resize((size_t)nrhs * n_shift);
     P->weights.resize((size_t)nrhs * n_shift);

@@ -81,6 +81,7 @@ template <int NV>
 __device__ inline void block_reduce_store(double (&v)[NV], double *out, int stride) {
     __shared__ double sh[NV][BLOCK / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();   // a block may call this back to back (persistent stages)
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double x = v[k];

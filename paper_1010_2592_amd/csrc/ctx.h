@@ -26,7 +26,9 @@ struct Ctx {
     // workspace, grown on demand and kept for later calls
     DevBuf ws_R, ws_U, ws_tmp, ws_W, ws_X, ws_rt, ws_b, ws_y, ws_part, ws_seed, ws_shift, ws_sc,
         ws_mc, ws_tape, ws_tape_gam, ws_tape_outer, ws_replay, ws_replay_outer, ws_wts, ws_sig0,
-        ws_cb, ws_aux1, ws_aux2, ws_aux3, ws_aux4, ws_bX, ws_bZ, ws_by, ws_beta, ws_bA, ws_bB, ws_bdots;
+        ws_cb, ws_aux1, ws_aux2, ws_aux3, ws_aux4, ws_bX, ws_bZ, ws_by, ws_beta, ws_bA, ws_bB, ws_bdots,
+        ws_ops, ws_pctl;
+    int pgrid[32] = {};        // co-resident grid of the persistent kernel, per (precision, l)
     void *host_pinned = nullptr;
     size_t host_pinned_bytes = 0;
     // kernel timing (msb_profile_enable): HIP event pairs around launches
@@ -39,6 +41,15 @@ struct Ctx {
         hipEvent_t e0, e1;
     };
     std::vector<Rec> recs;
+    // stage times measured inside a persistent launch (wall clock per class);
+    // pending: bytes not yet attached
+    struct SRec {
+        int cls;
+        long long count;
+        double ms, bytes;
+        bool pending = true;
+    };
+    std::vector<SRec> srecs;
     double bytes_acc = 0;      // algorithmic bytes of the current call
 };
 
@@ -72,6 +83,7 @@ struct SolveParams {
     int pass = 1;
     bool mixed = false;
     bool neg_mu = false;
+    bool persistent = false;           // one cooperative launch per pass
     int nrhs = 1;
     const int *force_iters = nullptr;   // [nrhs][n_shift] or null
 };

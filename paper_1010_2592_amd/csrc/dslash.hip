@@ -21,204 +21,17 @@
 // Which operands exist is a compile-time property of the mode: run-time null
 // checks inside the unrolled epilogue made the compiler keep every epilogue
 // load live at once and spill.
-#include "common.h"
-#include "kernels.h"
+#include "stencil_dev.h"
 
 namespace msb {
 
 namespace {
 
-// multiply by one of {+1, -1, +i, -i}
-template <int CODE, typename Z>
-__device__ __forceinline__ Z mulcode(Z z) {
-    if constexpr (CODE == 0) return z;
-    else if constexpr (CODE == 1) return cneg(z);
-    else if constexpr (CODE == 2) return ctimes_i(z);
-    else return ctimes_mi(z);
-}
+using namespace dev;
 
-constexpr int ONE = 0, NEG = 1, I = 2, MI = 3;
-
-// Spin projection (1 + SGN gamma_NU) psi = (h0, h1, D2 h_Q2, D3 h_Q3) with
-// h0 = psi_0 + C0 psi_P0, h1 = psi_1 + C1 psi_P1 (chiral basis).
-template <int NU, int SGN> struct Proj;
-template <> struct Proj<0, -1> { static constexpr int P0 = 3, C0 = I, P1 = 2, C1 = I, Q2 = 1, D2 = MI, Q3 = 0, D3 = MI; };
-template <> struct Proj<0, +1> { static constexpr int P0 = 3, C0 = MI, P1 = 2, C1 = MI, Q2 = 1, D2 = I, Q3 = 0, D3 = I; };
-template <> struct Proj<1, -1> { static constexpr int P0 = 3, C0 = ONE, P1 = 2, C1 = NEG, Q2 = 1, D2 = NEG, Q3 = 0, D3 = ONE; };
-template <> struct Proj<1, +1> { static constexpr int P0 = 3, C0 = NEG, P1 = 2, C1 = ONE, Q2 = 1, D2 = ONE, Q3 = 0, D3 = NEG; };
-template <> struct Proj<2, -1> { static constexpr int P0 = 2, C0 = I, P1 = 3, C1 = MI, Q2 = 0, D2 = MI, Q3 = 1, D3 = I; };
-template <> struct Proj<2, +1> { static constexpr int P0 = 2, C0 = MI, P1 = 3, C1 = I, Q2 = 0, D2 = I, Q3 = 1, D3 = MI; };
-template <> struct Proj<3, -1> { static constexpr int P0 = 2, C0 = NEG, P1 = 3, C1 = NEG, Q2 = 0, D2 = NEG, Q3 = 1, D3 = NEG; };
-template <> struct Proj<3, +1> { static constexpr int P0 = 2, C0 = ONE, P1 = 3, C1 = ONE, Q2 = 0, D2 = ONE, Q3 = 1, D3 = ONE; };
-
-// Load spin component `sp` (3 colours) of site `s`; with G5IN the lower two
-// spins are negated (gamma5 applied on the fly).
-template <typename T, bool G5IN>
-__device__ __forceinline__ void load_spin(const C<T> *__restrict__ in, int V, int s, int sp, C<T> (&c)[3]) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        C<T> z = in[(3 * sp + a) * V + s];
-        if (G5IN && sp >= 2) z = cneg(z);
-        c[a] = z;
-    }
-}
-
-// acc += f * (1 + SGN gamma_NU) Umat psi(sn), Umat = U_NU(sl) (DAG=false) or
-// U_NU(sl)^+ (DAG=true)
-template <typename T, int NU, int SGN, bool DAG, bool G5IN>
-__device__ __forceinline__ void hop(C<T> (&acc)[4][3], const C<T> *__restrict__ in,
-                                   const C<T> *__restrict__ U, int V, int sn, int sl, T f) {
-    using P = Proj<NU, SGN>;
-    C<T> h[2][3];
-    {
-        C<T> p0[3], p1[3], q0[3], q1[3];
-        load_spin<T, G5IN>(in, V, sn, 0, p0);
-        load_spin<T, G5IN>(in, V, sn, 1, p1);
-        load_spin<T, G5IN>(in, V, sn, P::P0, q0);
-        load_spin<T, G5IN>(in, V, sn, P::P1, q1);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            h[0][a] = cadd(p0[a], mulcode<P::C0>(q0[a]));
-            h[1][a] = cadd(p1[a], mulcode<P::C1>(q1[a]));
-        }
-    }
-    const C<T> *Un = U + (size_t)NU * 9 * V + sl;
-    C<T> g[2][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        C<T> u0, u1, u2;
-        if (!DAG) {
-            u0 = Un[(3 * a + 0) * V];
-            u1 = Un[(3 * a + 1) * V];
-            u2 = Un[(3 * a + 2) * V];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                C<T> r = cmul(u0, h[i][0]);
-                r = cfma(u1, h[i][1], r);
-                r = cfma(u2, h[i][2], r);
-                g[i][a] = r;
-            }
-        } else {
-            // (U^+)_{ab} = conj(U_{ba})
-            u0 = Un[(0 * 3 + a) * V];
-            u1 = Un[(1 * 3 + a) * V];
-            u2 = Un[(2 * 3 + a) * V];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                C<T> r = cmulc(u0, h[i][0]);
-                r = cadd(r, cmulc(u1, h[i][1]));
-                r = cadd(r, cmulc(u2, h[i][2]));
-                g[i][a] = r;
-            }
-        }
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        acc[0][a] = cadd(acc[0][a], cscale(g[0][a], f));
-        acc[1][a] = cadd(acc[1][a], cscale(g[1][a], f));
-        acc[2][a] = cadd(acc[2][a], cscale(mulcode<P::D2>(g[P::Q2][a]), f));
-        acc[3][a] = cadd(acc[3][a], cscale(mulcode<P::D3>(g[P::Q3][a]), f));
-    }
-}
-
-// One block per (256-site block, right-hand side).  The flattened grid is
-// padded to a multiple of 8 and mapped XCD-aware: hardware block p runs on
-// XCD p % 8, which here owns the contiguous logical range
-// [(p % 8) per, (p % 8 + 1) per); inside it the right-hand side varies fastest,
-// so the 12 sources of one site block run back to back on one XCD and share
-// its L2 copy of the links and of the neighbouring planes.
 template <typename T, int EPI, bool G5IN>
 __global__ __launch_bounds__(BLOCK) void dslash_kernel(DslashArgs<T> a) {
-    const int p = blockIdx.x;
-    const int L = (p & 7) * a.per + (p >> 3);
-    if (L >= a.nsb * a.nrhs) return;
-    const int sblk = L / a.nrhs;
-    const int rhs = L - sblk * a.nrhs;
-    if (!gate_open(a.gate, rhs)) return;
-    const int V = a.g.V, Lx = a.g.Lx, Ly = a.g.Ly, Lz = a.g.Lz, Lt = a.g.Lt;
-    const long nv = 12L * V;
-    const C<T> *__restrict__ in = a.in + (size_t)rhs * (a.in_rs ? a.in_rs : nv);
-    C<T> *__restrict__ out = a.out + (size_t)rhs * (a.out_rs ? a.out_rs : nv);
-    const C<T> *__restrict__ U = a.U;
-    const C<T> *__restrict__ v = a.v ? a.v + (size_t)rhs * (a.v_rs ? a.v_rs : nv) : nullptr;
-    const C<T> *__restrict__ rt = a.rt ? a.rt + (size_t)rhs * (a.rt_rs ? a.rt_rs : nv) : nullptr;
-    double2 *__restrict__ y = a.y ? a.y + (size_t)rhs * (a.y_rs ? a.y_rs : nv) : nullptr;
-    C<T> yc = mk<T>(0, 0);
-    if (EPI == EPI_MV_Y) yc = to_c<T>(ld(a.ycoef, rhs));
-    const T sig0 = a.sigma0_rhs ? (T)a.sigma0_rhs[rhs] : a.sigma0;
-    double part[3] = {0.0, 0.0, 0.0};
-    // a.sstride exceeds V, so the loop body runs at most once; keeping it a
-    // loop with a run-time bound stops the compiler from hoisting every load
-    // of the eight hops at once (which needs more than 256 VGPRs and spills)
-    for (int s = sblk * BLOCK + threadIdx.x; s < V; s += a.sstride) {
-        const int sxy = Lx * Ly, sxyz = Lx * Ly * Lz;
-        const int x = s % Lx;
-        const int r1 = s / Lx;
-        const int yy = r1 % Ly;
-        const int r2 = r1 / Ly;
-        const int z = r2 % Lz;
-        const int t = r2 / Lz;
-        C<T> acc[4][3];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) acc[i][c] = mk<T>(0, 0);
-
-        int sf, sb;
-        sf = (x == Lx - 1) ? s - (Lx - 1) : s + 1;
-        sb = (x == 0) ? s + (Lx - 1) : s - 1;
-        hop<T, 0, -1, false, G5IN>(acc, in, U, V, sf, s, (T)1);
-        hop<T, 0, +1, true, G5IN>(acc, in, U, V, sb, sb, (T)1);
-        sf = (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx;
-        sb = (yy == 0) ? s + (Ly - 1) * Lx : s - Lx;
-        hop<T, 1, -1, false, G5IN>(acc, in, U, V, sf, s, (T)1);
-        hop<T, 1, +1, true, G5IN>(acc, in, U, V, sb, sb, (T)1);
-        sf = (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy;
-        sb = (z == 0) ? s + (Lz - 1) * sxy : s - sxy;
-        hop<T, 2, -1, false, G5IN>(acc, in, U, V, sf, s, (T)1);
-        hop<T, 2, +1, true, G5IN>(acc, in, U, V, sb, sb, (T)1);
-        sf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
-        sb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
-        const T ff = (t == Lt - 1) ? a.ef * a.bc : a.ef;
-        const T fb = (t == 0) ? a.eb * a.bc : a.eb;
-        hop<T, 3, -1, false, G5IN>(acc, in, U, V, sf, s, ff);
-        hop<T, 3, +1, true, G5IN>(acc, in, U, V, sb, sb, fb);
-
-        // out = scale * [gamma5] ((4+m) psi(x) - acc / 2), formed in place
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp) {
-            C<T> ps[3];
-            load_spin<T, G5IN>(in, V, s, sp, ps);
-            const T sg = ((a.g5out && sp >= 2) ? (T)-1 : (T)1) * a.scale;
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                acc[sp][c] = cscale(csub(cscale(ps[c], a.diag), cscale(acc[sp][c], (T)0.5)), sg);
-        }
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int k = 3 * sp + c;
-                C<T> o = acc[sp][c];
-                if (EPI != EPI_PLAIN) o = cadd(o, cscale(v[k * V + s], sig0));
-                out[k * V + s] = o;
-                if (EPI == EPI_MV) {
-                    const C<T> r = rt[k * V + s];
-                    part[0] += (double)r.x * o.x + (double)r.y * o.y;
-                    part[1] += (double)r.x * o.y - (double)r.y * o.x;
-                    part[2] += (double)o.x * o.x + (double)o.y * o.y;
-                }
-                if (EPI == EPI_MV_Y) {
-                    double2 yv = y[k * V + s];
-                    yv.x += (double)yc.x * o.x - (double)yc.y * o.y;
-                    yv.y += (double)yc.x * o.y + (double)yc.y * o.x;
-                    y[k * V + s] = yv;
-                }
-            }
-        }
-    }
-    if (EPI == EPI_MV)
-        block_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + sblk, a.ps);
+    dslash_body<T, EPI, G5IN>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -329,12 +142,7 @@ __global__ __launch_bounds__(BLOCK) void link_force_kernel(LinkForceArgs a) {
 
 template <typename T>
 void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in) {
-    a.nsb = (a.g.V + BLOCK - 1) / BLOCK;
-    a.nrhs = nrhs;
-    const long G = (long)a.nsb * nrhs;
-    a.per = (int)((G + 7) / 8);
-    a.sstride = 1 << 30;
-    dim3 grid((unsigned)(8L * a.per)), block(BLOCK);
+    dim3 grid((unsigned)dslash_prepare(a, nrhs)), block(BLOCK);
 #define MSB_DS(E, G5) hipLaunchKernelGGL((dslash_kernel<T, E, G5>), grid, block, 0, st, a)
     if (g5in) {
         if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, true);

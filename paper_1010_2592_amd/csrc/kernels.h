@@ -47,6 +47,18 @@ struct DslashArgs {
 template <typename T>
 void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in);
 
+// Launch geometry of the stencil: sets nsb, nrhs, per and sstride and returns
+// the number of (virtual) blocks, 8 per, so that block p runs on XCD p % 8.
+template <typename T>
+inline long dslash_prepare(DslashArgs<T> &a, int nrhs) {
+    a.nsb = (a.g.V + BLOCK - 1) / BLOCK;
+    a.nrhs = nrhs;
+    const long G = (long)a.nsb * nrhs;
+    a.per = (int)((G + 7) / 8);
+    a.sstride = 1 << 30;
+    return 8L * a.per;
+}
+
 // link force: pairs (c, p, q), the gradient of sum c Re <p, D(mu) q>
 struct LinkPair {
     const double2 *p = nullptr, *q = nullptr;
@@ -151,5 +163,61 @@ void launch_sc_alpha(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_mr(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_conv(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_rel(hipStream_t, const ScalarArgs &, int nrhs);
+
+// ---- persistent execution --------------------------------------------------
+// The stages of a solve, recorded as a table of operations that one
+// cooperative launch executes in order, with a grid-wide barrier between
+// consecutive operations.  Each operation is split into virtual blocks (the
+// blocks its own launch would have had); resident block b takes the virtual
+// blocks b, b + P, b + 2P, ... (P, the resident grid, is a multiple of 8, so
+// a virtual block stays on the XCD its own launch would have used).
+enum OpKind : int {
+    OP_DS = 1,        // stencil in the iteration's precision (blob: DslashArgs<T>)
+    OP_DS64,          // FP64 stencil of a reliable update (blob: DslashArgs<double>)
+    OP_SEED_U,        // blob: VecArgs<T>
+    OP_R_UPDATE,
+    OP_GRAM,
+    OP_MR_UPDATE,
+    OP_REL_UPDATE,
+    OP_SC_BETA,       // blob: ScalarArgs
+    OP_SC_ALPHA,
+    OP_SC_MR,
+    OP_SC_REL,
+    OP_SC_CONV,
+};
+constexpr int POP_BLOB = 512;
+struct alignas(16) POp {
+    int kind = 0;
+    int cls = 0;                 // timing class
+    int epi = 0;                 // OP_DS, OP_DS64
+    int j = 0;                   // OP_SEED_U, OP_R_UPDATE: BiCG step
+    int shifts = 0;              // OP_R_UPDATE, OP_MR_UPDATE: update the shift vectors
+    int nvb = 0;                 // virtual blocks
+    int nblk = 0;                // vector ops: element blocks per right-hand side
+    int pad = 0;
+    const double2 *b = nullptr;  // OP_REL_UPDATE operands
+    const double2 *v = nullptr;
+    double2 *y = nullptr;
+    CoefRef yc{};
+    alignas(16) unsigned char blob[POP_BLOB];
+};
+constexpr int PERSIST_CLASSES = 8;
+struct PersistArgs {
+    const POp *ops = nullptr;
+    int nops = 0;                // operations per iteration of the table
+    int iters = 1;               // repetitions of the table
+    int loop = 0;                // 1: stop after a repetition when no seed runs
+    const SeedState *seed = nullptr;
+    int nrhs = 0;
+    unsigned long long *bar = nullptr;  // barrier counter, zero at launch
+    int *abort = nullptr;        // set when a barrier wait exceeds its bound
+    unsigned long long *ticks = nullptr;  // [PERSIST_CLASSES] wall-clock ticks per class, or null
+    unsigned long long *execs = nullptr;  // [PERSIST_CLASSES] operations executed per class
+};
+// Largest co-resident grid of the persistent kernel of MR degree l (a
+// multiple of 8; 0 when l is outside 1..PERSIST_LMAX).
+constexpr int PERSIST_LMAX = 6;
+template <typename T> int persistent_grid(int device, int l);
+template <typename T> hipError_t launch_persistent(hipStream_t st, const PersistArgs &pa, int grid, int l);
 
 }  // namespace msb

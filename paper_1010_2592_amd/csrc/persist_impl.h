@@ -1,0 +1,241 @@
+// Persistent execution of a solve: one cooperative launch runs a table of
+// stage operations (stencil, seed and shift vector updates, Gram partials,
+// device scalar steps) in order, with a grid-wide barrier between consecutive
+// operations.  The 12 right-hand sides of a batch share every stage, so the
+// links each stencil stage loads are shared by all of them, and the host
+// issues one launch for the whole iteration instead of about 9 l + 5 launches
+// and a synchronisation per outer iteration.
+//
+// The table repeats (one outer iteration of the single-pass or double-pass
+// first pass) until no right-hand side is still running, or runs once (the
+// double-pass replay, whose every outer iteration is known in advance).
+//
+// Grid barrier: a monotone counter in device memory.  Every work-item issues
+// an agent-scope release fence (its stores leave the CU and are written back
+// from its XCD's L2), the block's first work-item adds one to the counter and
+// waits until it reaches (barrier number) x (grid size), then an agent-scope
+// acquire fence invalidates the stale cache lines.  The launch is cooperative,
+// so every block is resident and each wait ends; a wait that still exceeds its
+// bound raises the abort flag, which every waiting block sees and leaves on,
+// so no wave can stay behind after a fault elsewhere.
+#pragma once
+#include "blas_dev.h"
+#include "scalar_dev.h"
+#include "stencil_dev.h"
+
+namespace msb {
+
+namespace {
+
+using namespace dev;
+
+constexpr unsigned SPIN_LIMIT = 1u << 24;   // seconds of polling; a stage takes milliseconds
+
+__device__ __forceinline__ bool grid_barrier(const PersistArgs &pa, unsigned long long number) {
+    __shared__ int ok_sh;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __hip_atomic_fetch_add(pa.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long target = number * gridDim.x;
+        unsigned spins = 0;
+        while (__hip_atomic_load(pa.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(pa.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            if (++spins > SPIN_LIMIT) {
+                __hip_atomic_store(pa.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+        ok_sh = ok;
+    }
+    __syncthreads();
+    return ok_sh != 0;
+}
+
+// virtual block vb of a vector op: element block vb % nblk of rhs vb / nblk
+#define VLOOP_VEC(CALL)                                                       \
+    for (int vb = blockIdx.x; vb < op.nvb; vb += gridDim.x) {                 \
+        const int rhs = vb / op.nblk, bx = vb - rhs * op.nblk, gx = op.nblk;  \
+        CALL;                                                                 \
+        __syncthreads();                                                      \
+    }
+#define VLOOP(CALL)                                                           \
+    for (int vb = blockIdx.x; vb < op.nvb; vb += gridDim.x) {                 \
+        CALL;                                                                 \
+        __syncthreads();                                                      \
+    }
+
+// The scalar stages run in one block per right-hand side and are latency
+// bound; as separate functions their registers do not enter the allocation of
+// the stencil and vector stages inlined into the kernel.
+__device__ __noinline__ void call_sc_beta(const ScalarArgs *a, int rhs) { sc_beta_body(*a, rhs); }
+__device__ __noinline__ void call_sc_alpha(const ScalarArgs *a, int rhs) { sc_alpha_body(*a, rhs); }
+__device__ __noinline__ void call_sc_mr(const ScalarArgs *a, int rhs) { sc_mr_body(*a, rhs); }
+__device__ __noinline__ void call_sc_rel(const ScalarArgs *a, int rhs) { sc_rel_body(*a, rhs); }
+__device__ __noinline__ void call_sc_conv(const ScalarArgs *a, int rhs) { sc_conv_body(*a, rhs); }
+
+template <typename T, int L, bool XH, int J>
+__device__ __forceinline__ void exec_r_update_j(const POp &op, const VecArgs<T> &a) {
+    if constexpr (J < L) {
+        if (op.j == J) {
+            if (op.shifts) VLOOP_VEC((r_update_body<T, J, true, XH>(a, bx, gx, rhs)))
+            else VLOOP_VEC((r_update_body<T, J, false, XH>(a, bx, gx, rhs)))
+            return;
+        }
+        exec_r_update_j<T, L, XH, J + 1>(op, a);
+    }
+}
+
+template <typename T, int L, bool XH, int J>
+__device__ __forceinline__ void exec_seed_u_j(const POp &op, const VecArgs<T> &a) {
+    if constexpr (J < L) {
+        if (op.j == J) {
+            VLOOP_VEC((seed_u_body<T, J>(a, bx, gx, rhs)))
+            return;
+        }
+        exec_seed_u_j<T, L, XH, J + 1>(op, a);
+    }
+}
+
+// One instance per MR degree L keeps the kernel's register budget at that of
+// its largest stage for this L (the Gram stage of L = 7, 8 alone needs more
+// than 220 VGPRs).
+template <typename T, int L>
+__device__ __forceinline__ void exec_op(const POp &op) {
+    // FP32 iterations keep FP64 seed solutions (reliable updates); FP64 ones do not
+    constexpr bool XH = sizeof(T) != sizeof(double);
+    switch (op.kind) {
+    case OP_DS: {
+        const DslashArgs<T> &a = *reinterpret_cast<const DslashArgs<T> *>(op.blob);
+        if (op.epi == EPI_PLAIN) VLOOP((dslash_body<T, EPI_PLAIN, false>(a, vb)))
+        else if (op.epi == EPI_MV) VLOOP((dslash_body<T, EPI_MV, false>(a, vb)))
+        else VLOOP((dslash_body<T, EPI_MV_Y, false>(a, vb)))
+        break;
+    }
+    case OP_DS64: {
+        if constexpr (XH) {
+            const DslashArgs<double> &a = *reinterpret_cast<const DslashArgs<double> *>(op.blob);
+            if (op.epi == EPI_PLAIN) VLOOP((dslash_body<double, EPI_PLAIN, false>(a, vb)))
+            else VLOOP((dslash_body<double, EPI_SV, false>(a, vb)))
+        }
+        break;
+    }
+    case OP_SEED_U: {
+        exec_seed_u_j<T, L, XH, 0>(op, *reinterpret_cast<const VecArgs<T> *>(op.blob));
+        break;
+    }
+    case OP_R_UPDATE:
+        exec_r_update_j<T, L, XH, 0>(op, *reinterpret_cast<const VecArgs<T> *>(op.blob));
+        break;
+    case OP_GRAM: {
+        const VecArgs<T> &a = *reinterpret_cast<const VecArgs<T> *>(op.blob);
+        VLOOP_VEC((gram_body<T, L>(a, bx, gx, rhs)))
+        break;
+    }
+    case OP_MR_UPDATE: {
+        const VecArgs<T> &a = *reinterpret_cast<const VecArgs<T> *>(op.blob);
+        if (op.shifts) VLOOP_VEC((mr_update_body<T, L, true, XH>(a, bx, gx, rhs)))
+        else VLOOP_VEC((mr_update_body<T, L, false, XH>(a, bx, gx, rhs)))
+        break;
+    }
+    case OP_REL_UPDATE: {
+        if constexpr (XH) {
+            const VecArgs<T> &a = *reinterpret_cast<const VecArgs<T> *>(op.blob);
+            VLOOP_VEC((rel_update_body<T>(a, op.b, op.v, op.y, op.yc, bx, gx, rhs)))
+        }
+        break;
+    }
+    case OP_SC_BETA: {
+        const ScalarArgs &a = *reinterpret_cast<const ScalarArgs *>(op.blob);
+        VLOOP((call_sc_beta(&a, vb)))
+        break;
+    }
+    case OP_SC_ALPHA: {
+        const ScalarArgs &a = *reinterpret_cast<const ScalarArgs *>(op.blob);
+        VLOOP((call_sc_alpha(&a, vb)))
+        break;
+    }
+    case OP_SC_MR: {
+        const ScalarArgs &a = *reinterpret_cast<const ScalarArgs *>(op.blob);
+        VLOOP((call_sc_mr(&a, vb)))
+        break;
+    }
+    case OP_SC_REL: {
+        const ScalarArgs &a = *reinterpret_cast<const ScalarArgs *>(op.blob);
+        VLOOP((call_sc_rel(&a, vb)))
+        break;
+    }
+    case OP_SC_CONV: {
+        const ScalarArgs &a = *reinterpret_cast<const ScalarArgs *>(op.blob);
+        VLOOP((call_sc_conv(&a, vb)))
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(BLOCK) void k_persistent(PersistArgs pa) {
+    unsigned long long number = 0;
+    const bool timer = pa.ticks && blockIdx.x == 0 && threadIdx.x == 0;
+    long long t0 = timer ? wall_clock64() : 0;
+    for (int it = 0; it < pa.iters; ++it) {
+        for (int k = 0; k < pa.nops; ++k) {
+            const POp &op = pa.ops[k];
+            exec_op<T, L>(op);
+            if (!grid_barrier(pa, ++number)) return;
+            if (timer) {
+                const long long t1 = wall_clock64();
+                pa.ticks[op.cls] += (unsigned long long)(t1 - t0);
+                pa.execs[op.cls] += 1;
+                t0 = t1;
+            }
+        }
+        if (pa.loop) {
+            // SeedState::run changes only in the convergence step, which ends
+            // the table, so every block reads the same values here
+            int any = 0;
+            for (int r = 0; r < pa.nrhs; ++r)
+                any |= __hip_atomic_load(&pa.seed[r].run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!any) break;
+        }
+    }
+}
+
+}  // namespace
+
+// Entry points of one MR degree L (persist_l<L>.hip instantiates them).
+template <typename T, int L>
+int persistent_grid_l(int device) {
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_persistent<T, L>), BLOCK,
+                                                     0) != hipSuccess)
+        return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    const long g = ((long)per_cu * ncu / 8) * 8;
+    return (int)g;
+}
+
+template <typename T, int L>
+hipError_t launch_persistent_l(hipStream_t st, const PersistArgs &pa, int grid) {
+    PersistArgs copy = pa;
+    void *args[] = {&copy};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_persistent<T, L>), dim3(grid), dim3(BLOCK), args,
+                                      0, st);
+}
+
+#define MSB_PERSIST_INSTANTIATE(L)                                                            \
+    template int persistent_grid_l<double, L>(int);                                           \
+    template int persistent_grid_l<float, L>(int);                                            \
+    template hipError_t launch_persistent_l<double, L>(hipStream_t, const PersistArgs &, int); \
+    template hipError_t launch_persistent_l<float, L>(hipStream_t, const PersistArgs &, int);
+
+}  // namespace msb

@@ -1,0 +1,6 @@
+// Persistent solve kernel for MR degree l = 6 (see persist_impl.h).
+#include "persist_impl.h"
+
+namespace msb {
+MSB_PERSIST_INSTANTIATE(6)
+}  // namespace msb

@@ -20,411 +20,20 @@
 // Convergence at the end of each outer iteration: shift s freezes when
 // ||r_0|| / (|zeta psi| ||b||) <= tol (its outer-iteration count is the
 // paper's M_s, Section 2); the iteration stops when no shift is left.
-#include "common.h"
-#include "kernels.h"
+#include "scalar_dev.h"
 
 namespace msb {
 
 namespace {
 
-__device__ inline double2 cpowi_neg(double sp, int i) {
-    // (-sp)^i for integer i >= 0
-    double p = 1.0;
-    for (int k = 0; k < i; ++k) p *= -sp;
-    return d2(p, 0.0);
-}
+using namespace dev;
 
-__device__ inline const double *prow(const ScalarArgs &a, int rhs) {
-    return a.part + (size_t)rhs * PMAX * a.ps;
-}
-
-__global__ __launch_bounds__(BLOCK) void sc_init(ScalarArgs a) {
-    const int rhs = blockIdx.x;
-    SeedState &S = a.seed[rhs];
-    const double *row = prow(a, rhs);
-    const double re = block_sum(row, a.nblk);
-    const double im = block_sum(row + a.ps, a.nblk);
-    const double nb2 = block_sum(row + 2 * a.ps, a.nblk);
-    if (threadIdx.x == 0) {
-        S.rho1 = d2(re, im);
-        S.bnorm = sqrt(nb2);
-        S.rtnorm = S.bnorm;
-        S.rnorm0 = S.bnorm;
-        S.rnorm_j = S.bnorm;
-        S.rho0 = d2(1, 0);
-        S.alpha = d2(0, 0);
-        S.omega = d2(1, 0);
-        S.beta = d2(0, 0);
-        for (int i = 0; i < LMAX; ++i) S.gam[i] = d2(0, 0);
-        S.bicg_on = 1;
-        S.l_eff = 0;
-        S.l_mr = 0;
-        S.broken = S.exhausted = S.partial = 0;
-        S.m = S.n = 0;
-        S.status = S_OK;
-        S.mv = S.dots = S.axpys = S.reliable = 0;
-        S.rel = 0;
-        S.rmax = S.bnorm;
-        S.nact = 0;
-        for (int s = 0; s < S.nshift; ++s) {
-            if (a.sh[(size_t)rhs * NSMAX + s].active) S.act[S.nact++] = s;
-        }
-        S.dots = 0;
-        S.run = (S.bnorm > 0.0 && S.nact > 0 && isfinite(S.bnorm)) ? 1 : 0;
-        if (!isfinite(S.bnorm)) S.status = S_ERR_ARG;
-        if (!(S.bnorm > 0.0) || !isfinite(S.bnorm)) {
-            for (int s = 0; s < S.nshift; ++s) {
-                ShiftState &H = a.sh[(size_t)rhs * NSMAX + s];
-                H.active = 0;
-                H.iters = 0;
-                H.res = 0.0;
-            }
-            S.nact = 0;
-        }
-    }
-}
-
-__global__ __launch_bounds__(BLOCK) void sc_beta(ScalarArgs a) {
-    const int rhs = blockIdx.x;
-    SeedState &S = a.seed[rhs];
-    if (!S.run || !S.bicg_on) return;
-    const int j = a.j;
-    const double *row = prow(a, rhs);
-    const double re = block_sum(row, a.nblk);
-    const double im = block_sum(row + a.ps, a.nblk);
-    const double rj2 = block_sum(row + 2 * a.ps, a.nblk);
-    double r02 = 0.0;
-    if (j >= 1) r02 = block_sum(row + 3 * a.ps, a.nblk2);
-    if (threadIdx.x != 0) return;
-    if (j >= 1) S.rnorm0 = sqrt(r02);
-    if (j >= 1 && !S.forced && S.nact > 0) {
-        // Krylov space exhausted: every active shift already meets its
-        // tolerance after the previous step's r-update
-        double mn = 1e308;
-        for (int q = 0; q < S.nact; ++q) {
-            const ShiftState &H = a.sh[(size_t)rhs * NSMAX + S.act[q]];
-            if (!H.active) continue;
-            const double sc = cabsd(cmul(H.zeta, H.psi));
-            mn = sc < mn ? sc : mn;
-        }
-        if (S.rnorm0 <= S.tol * S.bnorm * mn) {
-            S.exhausted = 1;
-            S.bicg_on = 0;
-            S.l_eff = j;
-            return;
-        }
-    }
-    if (j == 0) S.rho0 = cneg(cmul(S.omega, S.rho0));
-    const double2 rho1 = d2(re, im);
-    S.dots += 1;
-    if ((rho1.x == 0.0 && rho1.y == 0.0) || !cfinite(rho1) ||
-        cabsd(rho1) <= BREAK_REL * S.rtnorm * sqrt(rj2)) {
-        S.broken = 1;
-        S.bicg_on = 0;
-        S.l_eff = j;
-        return;
-    }
-    const double2 beta = cdiv(cmul(S.alpha, rho1), S.rho0);
-    S.rho0 = rho1;
-    S.beta = beta;
-    if (a.record && S.n < S.max_steps) {
-        TapeStep &t = a.tape[(size_t)rhs * S.max_steps + S.n];
-        t.beta = beta;
-        t.alpha = d2(0, 0);
-        t.flag = 0;
-    }
-}
-
-__global__ __launch_bounds__(BLOCK) void sc_alpha(ScalarArgs a) {
-    const int rhs = blockIdx.x;
-    SeedState &S = a.seed[rhs];
-    if (!S.run || !S.bicg_on) return;
-    const int j = a.j;
-    const double *row = prow(a, rhs);
-    const double re = block_sum(row, a.nblk);
-    const double im = block_sum(row + a.ps, a.nblk);
-    const double u2 = block_sum(row + 2 * a.ps, a.nblk);
-    __shared__ int ok;
-    __shared__ double2 sh_alpha, sh_beta;
-    if (threadIdx.x == 0) {
-        const double2 gam = d2(re, im);
-        S.dots += 1;
-        S.mv += 1;
-        ok = 1;
-        if ((gam.x == 0.0 && gam.y == 0.0) || !cfinite(gam) ||
-            cabsd(gam) <= BREAK_REL * S.rtnorm * sqrt(u2)) {
-            S.broken = 1;
-            S.partial = 1;
-            S.bicg_on = 0;
-            S.l_eff = j;
-            if (a.record && S.n < S.max_steps) a.tape[(size_t)rhs * S.max_steps + S.n].flag = 1;
-            ok = 0;
-        } else {
-            const double2 alpha = cdiv(S.rho0, gam);
-            S.alpha = alpha;
-            if (a.record && S.n < S.max_steps) {
-                TapeStep &t = a.tape[(size_t)rhs * S.max_steps + S.n];
-                t.alpha = alpha;
-                t.flag = 2;
-            }
-        }
-        sh_alpha = S.alpha;
-        sh_beta = S.beta;
-    }
-    __syncthreads();
-    if (!ok) return;
-    const double2 alpha = sh_alpha, beta = sh_beta;
-    const int nact = S.nact;
-    for (int q = threadIdx.x; q < nact; q += BLOCK) {
-        const int s = S.act[q];
-        ShiftState &H = a.sh[(size_t)rhs * NSMAX + s];
-        StepCoef &c = a.sc[(size_t)rhs * NSMAX + q];
-        c.s = s;
-        if (!H.active) {
-            c.live = 0;
-            continue;
-        }
-        const double2 z = H.zeta, zp = H.zeta_prev, pp = H.pi_prev, ps = H.psi;
-        const double sp = H.sp;
-        const double2 pi_n = csub(z, cmul(beta, pp));
-        const double2 z_next = cadd(z, cscale(cmul(alpha, pi_n), sp));
-        if (!cfinite(z_next) || cabsd(z_next) < ZETA_MIN) {
-            H.active = 0;
-            H.broken = 1;
-            H.iters = S.m;
-            c.live = 0;
-            continue;
-        }
-        const double2 alpha_s = cdiv(cmul(alpha, z), z_next);
-        const double2 rz = cdiv(zp, z);
-        const double2 beta_s = cmul(beta, cmul(rz, rz));
-        const double2 kap = cdiv(d2(1, 0), cmul(z, ps));
-        const double2 kap_next = cdiv(d2(1, 0), cmul(z_next, ps));
-        c.kap = kap;
-        c.beta_s = beta_s;
-        c.alpha_s = alpha_s;
-        c.a1 = cdiv(csub(kap, kap_next), alpha_s);
-        c.a2 = cdiv(cmul(kap_next, alpha), alpha_s);
-        c.sp = sp;
-        c.live = 1;
-        H.zeta_prev = z;
-        H.zeta = z_next;
-        H.pi_prev = pi_n;
-    }
-    if (threadIdx.x == 0) {
-        S.mv += 1;
-        S.n += 1;
-        S.l_eff = j + 1;
-    }
-}
-
-__global__ __launch_bounds__(BLOCK) void sc_mr(ScalarArgs a) {
-    const int rhs = blockIdx.x;
-    SeedState &S = a.seed[rhs];
-    if (!S.run) return;
-    const int l = a.l;
-    const int L = S.exhausted ? 0 : S.l_eff;
-    __shared__ double2 G[LMAX][LMAX];
-    __shared__ double2 cvec[LMAX];
-    __shared__ double2 g[LMAX];
-    __shared__ int lmr_sh;
-    const double *row = prow(a, rhs);
-    // pair index of (i, k), i <= k, in the gram kernel's order over 0..l
-    auto pidx = [l](int i, int k) {
-        int p = 0;
-        for (int ii = 0; ii < i; ++ii) p += l + 1 - ii;
-        return p + (k - i);
-    };
-    for (int i = 0; i <= L; ++i) {
-        for (int k = (i == 0 ? 1 : i); k <= L; ++k) {
-            const int p = pidx(i, k);
-            const double re = block_sum(row + (2 * p) * a.ps, a.nblk);
-            const double im = block_sum(row + (2 * p + 1) * a.ps, a.nblk);
-            if (threadIdx.x == 0) {
-                if (i == 0) {
-                    cvec[k - 1] = d2(re, -im);   // <r_k, r_0> = conj(<r_0, r_k>)
-                } else {
-                    G[i - 1][k - 1] = d2(re, im);
-                    G[k - 1][i - 1] = d2(re, -im);
-                }
-            }
-        }
-    }
-    if (threadIdx.x == 0) {
-        int n = L;
-        double2 Lm[LMAX][LMAX];
-        int kok = n;
-        if (n > 0) {
-            double dmax = 0.0;
-            for (int i = 0; i < n; ++i) dmax = G[i][i].x > dmax ? G[i][i].x : dmax;
-            for (int i = 0; i < n; ++i) {
-                double d = G[i][i].x;
-                for (int p = 0; p < i; ++p) d -= cabs2(Lm[i][p]);
-                if (!(d > CHOL_REL * dmax)) {
-                    kok = i;
-                    break;
-                }
-                const double dd = sqrt(d);
-                Lm[i][i] = d2(dd, 0.0);
-                for (int r = i + 1; r < n; ++r) {
-                    double2 acc = G[r][i];
-                    for (int p = 0; p < i; ++p) acc = csub(acc, cmul(Lm[r][p], cconj(Lm[i][p])));
-                    Lm[r][i] = cscale(acc, 1.0 / dd);
-                }
-            }
-        }
-        n = kok;
-        double2 zz[LMAX];
-        for (int i = 0; i < n; ++i) {
-            double2 acc = cvec[i];
-            for (int p = 0; p < i; ++p) acc = csub(acc, cmul(Lm[i][p], zz[p]));
-            zz[i] = cscale(acc, 1.0 / Lm[i][i].x);
-        }
-        for (int i = n - 1; i >= 0; --i) {
-            double2 acc = zz[i];
-            for (int p = i + 1; p < n; ++p) acc = csub(acc, cmul(cconj(Lm[p][i]), g[p]));
-            g[i] = cscale(acc, 1.0 / Lm[i][i].x);
-        }
-        for (int i = n; i < LMAX; ++i) g[i] = d2(0, 0);
-        for (int i = 0; i < LMAX; ++i) S.gam[i] = g[i];
-        S.l_mr = n;
-        lmr_sh = n;
-        if (L >= 1) S.dots += L * (L + 3) / 2;
-        if (!S.exhausted) {
-            if (n < l) S.broken = 1;
-            if (n == l) S.omega = g[l - 1];
-        }
-        if (a.record && S.m < S.max_outer) {
-            for (int i = 0; i < LMAX; ++i) a.tape_gam[((size_t)rhs * S.max_outer + S.m) * LMAX + i] = g[i];
-        }
-    }
-    __syncthreads();
-    const int lm = lmr_sh;
-    for (int q = threadIdx.x; q < S.nact; q += BLOCK) {
-        const int s = S.act[q];
-        ShiftState &H = a.sh[(size_t)rhs * NSMAX + s];
-        MRCoef &c = a.mc[(size_t)rhs * NSMAX + q];
-        c.s = s;
-        for (int k = 0; k < LMAX; ++k) c.kc[k] = d2(0, 0);
-        c.inv_q = d2(1, 0);
-        if (!H.active || lm == 0) {
-            c.live = 0;
-            continue;
-        }
-        const double sp = H.sp;
-        double2 qs = d2(1, 0);
-        for (int i = 1; i <= lm; ++i) qs = csub(qs, cmul(g[i - 1], cpowi_neg(sp, i)));
-        if (!cfinite(qs) || cabsd(qs) < ZETA_MIN) {
-            H.active = 0;
-            H.broken = 1;
-            H.iters = S.m;
-            c.live = 0;
-            continue;
-        }
-        const double2 inv_q = cdiv(d2(1, 0), qs);
-        const double2 kap = cdiv(d2(1, 0), cmul(H.zeta, H.psi));
-        for (int k = 0; k < lm; ++k) {
-            double2 acc = d2(0, 0);
-            for (int i = k + 1; i <= lm; ++i) acc = cadd(acc, cmul(g[i - 1], cpowi_neg(sp, i - 1 - k)));
-            c.kc[k] = cmul(kap, cmul(acc, inv_q));
-        }
-        c.inv_q = inv_q;
-        c.live = 1;
-        H.psi = cmul(H.psi, qs);
-    }
-}
-
-// Mixed precision: decide whether the outer iteration ends with a reliable
-// update r_0 = b - S x (FP64): when ||r_0|| has dropped below 0.1 of its
-// largest value since the last one, when any shift would freeze on the
-// recursively updated residual, or when the Krylov space looks exhausted.
-__global__ __launch_bounds__(BLOCK) void sc_rel(ScalarArgs a) {
-    const int rhs = blockIdx.x;
-    SeedState &S = a.seed[rhs];
-    if (!S.run || !S.mixed) return;
-    const double r02 = block_sum(prow(a, rhs) + 2 * a.ps, a.nblk);
-    if (threadIdx.x != 0) return;
-    const double rn = sqrt(r02);
-    if (rn > S.rmax) S.rmax = rn;
-    bool freeze = false;
-    for (int q = 0; q < S.nact; ++q) {
-        const ShiftState &H = a.sh[(size_t)rhs * NSMAX + S.act[q]];
-        if (!H.active) continue;
-        const bool due = S.forced ? (S.m + 1 >= H.force) : (rn / (cabsd(cmul(H.zeta, H.psi)) * S.bnorm) <= S.tol);
-        freeze = freeze || due;
-    }
-    S.rel = (rn <= 0.1 * S.rmax || freeze || S.exhausted) ? 1 : 0;
-}
-
-__global__ __launch_bounds__(BLOCK) void sc_conv(ScalarArgs a) {
-    const int rhs = blockIdx.x;
-    SeedState &S = a.seed[rhs];
-    if (!S.run) return;
-    const double *row = prow(a, rhs);
-    const double re = block_sum(row, a.nblk);
-    const double im = block_sum(row + a.ps, a.nblk);
-    const double r02 = block_sum(row + 2 * a.ps, a.nblk);
-    __shared__ double rn;
-    if (threadIdx.x == 0) {
-        rn = sqrt(r02);
-        S.rnorm0 = rn;
-        S.rho1 = d2(re, im);
-        if (a.record && S.m < S.max_outer) {
-            TapeOuter &o = a.tape_outer[(size_t)rhs * S.max_outer + S.m];
-            o.l_eff = S.l_eff;
-            o.l_mr = S.exhausted ? 0 : S.l_mr;
-            o.partial = S.partial;
-            o.exhausted = S.exhausted;
-            o.rel = S.rel;
-        }
-        if (S.rel) {
-            S.reliable += 1;
-            S.rmax = rn;
-        }
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < S.nact; q += BLOCK) {
-        ShiftState &H = a.sh[(size_t)rhs * NSMAX + S.act[q]];
-        if (!H.active) continue;
-        const double res = rn / (cabsd(cmul(H.zeta, H.psi)) * S.bnorm);
-        H.res = res;
-        bool done = S.forced ? (S.m + 1 >= H.force) : (res <= S.tol);
-        // an exhausted Krylov space ends the solve; in mixed precision the
-        // residual was just recomputed in FP64, so a shift that still misses
-        // its tolerance is reported as not converged
-        if (S.exhausted && !S.mixed) done = true;
-        if (done) {
-            H.active = 0;
-            H.iters = S.m + 1;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int nact = 0, anybroken = 0;
-        for (int s = 0; s < S.nshift; ++s) {
-            const ShiftState &H = a.sh[(size_t)rhs * NSMAX + s];
-            if (H.active) S.act[nact++] = s;
-            anybroken |= H.broken;
-        }
-        S.nact = nact;
-        S.m += 1;
-        S.rel = 0;
-        const bool stop = (nact == 0) || S.broken || S.exhausted || (S.m >= S.max_outer);
-        if (stop) {
-            S.run = 0;
-            if (nact > 0) {
-                S.status = S.broken ? S_BREAKDOWN : S_NOT_CONVERGED;
-                for (int q = 0; q < nact; ++q) a.sh[(size_t)rhs * NSMAX + S.act[q]].iters = S.m;
-            } else {
-                S.status = anybroken ? S_BREAKDOWN : S_OK;
-            }
-        }
-        S.bicg_on = 1;
-        S.l_eff = 0;
-        S.l_mr = 0;
-        S.partial = 0;
-    }
-}
+__global__ __launch_bounds__(BLOCK) void sc_init(ScalarArgs a) { sc_init_body(a, blockIdx.x); }
+__global__ __launch_bounds__(BLOCK) void sc_beta(ScalarArgs a) { sc_beta_body(a, blockIdx.x); }
+__global__ __launch_bounds__(BLOCK) void sc_alpha(ScalarArgs a) { sc_alpha_body(a, blockIdx.x); }
+__global__ __launch_bounds__(BLOCK) void sc_mr(ScalarArgs a) { sc_mr_body(a, blockIdx.x); }
+__global__ __launch_bounds__(BLOCK) void sc_rel(ScalarArgs a) { sc_rel_body(a, blockIdx.x); }
+__global__ __launch_bounds__(BLOCK) void sc_conv(ScalarArgs a) { sc_conv_body(a, blockIdx.x); }
 
 }  // namespace
 

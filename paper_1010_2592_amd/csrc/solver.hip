@@ -119,6 +119,7 @@ int profile_enable(Ctx *c, bool on) {
     HIPCHK(c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
     c->prof = on;
     c->recs.clear();
+    c->srecs.clear();
     c->ev_used = 0;
     return 0;
 }
@@ -129,6 +130,12 @@ int profile_read(Ctx *c, int ncls, long long *cnt, double *ms, double *bytes) {
         cnt[k] = 0;
         ms[k] = 0.0;
         bytes[k] = 0.0;
+    }
+    for (const Ctx::SRec &r : c->srecs) {
+        if (r.cls >= ncls) continue;
+        cnt[r.cls] += r.count;
+        ms[r.cls] += r.ms;
+        bytes[r.cls] += r.bytes;
     }
     for (const Ctx::Rec &r : c->recs) {
         if (r.cls >= ncls) continue;
@@ -471,6 +478,192 @@ static void sweep_rhs(int l, int M, const TapeStep *tape, const TapeOuter *outer
 }
 
 // ---------------------------------------------------------------------------
+// Stage emitter: the solve's stage sequence is written once and either
+// launched stage by stage (LAUNCH), recorded as an operation table for the
+// persistent kernel (RECORD), or only priced for the byte model (COUNT).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Emit {
+    enum Mode { LAUNCH, RECORD, COUNT };
+    Ctx *c;
+    hipStream_t st;
+    Mode mode;
+    bool count_bytes;                  // RECORD: add each op's bytes to the call's model
+    std::vector<POp> ops;
+    double cls_bytes[CL_COUNT] = {};   // RECORD / COUNT: bytes per timing class
+    Emit(Ctx *c_, Mode m, bool cb = false) : c(c_), st(c_->stream), mode(m), count_bytes(cb) {}
+
+    bool launching(int cls, double bytes) {
+        if (mode == LAUNCH) return true;
+        if (mode == COUNT || count_bytes) {
+            c->bytes_acc += bytes;
+            cls_bytes[cls] += bytes;
+        }
+        return false;
+    }
+    template <typename A>
+    void record(POp o, const A &a) {
+        static_assert(sizeof(A) <= POP_BLOB, "operation arguments exceed the blob");
+        std::memcpy(o.blob, &a, sizeof(A));
+        ops.push_back(o);
+    }
+    static POp op(int kind, int cls, int nvb) {
+        POp o;
+        std::memset(&o, 0, sizeof(o));
+        o.kind = kind;
+        o.cls = cls;
+        o.nvb = nvb;
+        return o;
+    }
+    void ds(DslashArgs<T> a, int nrhs, int epi, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_dslash<T>(st, a, nrhs, epi, false);
+        } else if (mode == RECORD) {
+            POp o = op(OP_DS, cls, (int)dslash_prepare(a, nrhs));
+            o.epi = epi;
+            record(o, a);
+        }
+    }
+    void ds64(DslashArgs<double> a, int nrhs, int epi, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_dslash<double>(st, a, nrhs, epi, false);
+        } else if (mode == RECORD) {
+            POp o = op(OP_DS64, cls, (int)dslash_prepare(a, nrhs));
+            o.epi = epi;
+            record(o, a);
+        }
+    }
+    void seed_u(const VecArgs<T> &a, int j, int nrhs, int nblk, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_seed_u<T>(st, a, j, nrhs, nblk);
+        } else if (mode == RECORD) {
+            POp o = op(OP_SEED_U, cls, nblk * nrhs);
+            o.j = j;
+            o.nblk = nblk;
+            record(o, a);
+        }
+    }
+    void r_update(const VecArgs<T> &a, int j, bool shifts, bool xh, int nrhs, int nblk, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_r_update<T>(st, a, j, shifts, xh, nrhs, nblk);
+        } else if (mode == RECORD) {
+            POp o = op(OP_R_UPDATE, cls, nblk * nrhs);
+            o.j = j;
+            o.shifts = shifts ? 1 : 0;
+            o.nblk = nblk;
+            record(o, a);
+        }
+    }
+    void gram(const VecArgs<T> &a, int nrhs, int nblk, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_gram<T>(st, a, nrhs, nblk);
+        } else if (mode == RECORD) {
+            POp o = op(OP_GRAM, cls, nblk * nrhs);
+            o.nblk = nblk;
+            record(o, a);
+        }
+    }
+    void mr_update(const VecArgs<T> &a, bool shifts, bool xh, int nrhs, int nblk, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_mr_update<T>(st, a, shifts, xh, nrhs, nblk);
+        } else if (mode == RECORD) {
+            POp o = op(OP_MR_UPDATE, cls, nblk * nrhs);
+            o.shifts = shifts ? 1 : 0;
+            o.nblk = nblk;
+            record(o, a);
+        }
+    }
+    void rel_update(const VecArgs<T> &a, const double2 *bb, const double2 *v, double2 *yy, CoefRef yc, int nrhs,
+                    int nblk, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_rel_update<T>(st, a, bb, v, yy, yc, nrhs, nblk);
+        } else if (mode == RECORD) {
+            POp o = op(OP_REL_UPDATE, cls, nblk * nrhs);
+            o.nblk = nblk;
+            o.b = bb;
+            o.v = v;
+            o.y = yy;
+            o.yc = yc;
+            record(o, a);
+        }
+    }
+    void scalar(int kind, const ScalarArgs &a, int nrhs) {
+        if (launching(CL_SCALAR, 0.0)) {
+            Prof p(c, CL_SCALAR, 0);
+            switch (kind) {
+            case OP_SC_BETA: launch_sc_beta(st, a, nrhs); break;
+            case OP_SC_ALPHA: launch_sc_alpha(st, a, nrhs); break;
+            case OP_SC_MR: launch_sc_mr(st, a, nrhs); break;
+            case OP_SC_REL: launch_sc_rel(st, a, nrhs); break;
+            case OP_SC_CONV: launch_sc_conv(st, a, nrhs); break;
+            default: break;
+            }
+        } else if (mode == RECORD) {
+            record(op(kind, CL_SCALAR, nrhs), a);
+        }
+    }
+};
+
+// Runs an operation table in one cooperative launch: the table `iters` times
+// (loop: until no right-hand side runs), then waits for it.  With the timing
+// hook on, the kernel's per-class wall-clock stage times become records of
+// the hook, priced with cls_bytes.
+template <typename T>
+static int run_persistent(Ctx *c, const std::vector<POp> &ops, int iters, bool loop, int l, const SeedState *seed,
+                          int nrhs, const double *cls_bytes) {
+    if (ops.empty()) return 0;
+    hipStream_t st = c->stream;
+    const int key = (sizeof(T) == sizeof(double) ? 0 : 1) * 16 + l;
+    int &grid = c->pgrid[key];
+    if (grid == 0) grid = persistent_grid<T>(c->device, l);
+    if (grid < 8) return set_error(S_ERR_HIP, "persistent launch: no co-resident grid for l = " + std::to_string(l));
+    CHK(ensure(c->ws_ops, ops.size() * sizeof(POp)));
+    constexpr size_t CTL = 256;   // barrier counter, abort flag, ticks[8], execs[8]
+    CHK(ensure(c->ws_pctl, CTL));
+    HIPCHK(hipMemcpyAsync(c->ws_ops.p, ops.data(), ops.size() * sizeof(POp), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(c->ws_pctl.p, 0, CTL, st));
+    char *ctl = (char *)c->ws_pctl.p;
+    PersistArgs pa;
+    pa.ops = (const POp *)c->ws_ops.p;
+    pa.nops = (int)ops.size();
+    pa.iters = iters;
+    pa.loop = loop ? 1 : 0;
+    pa.seed = seed;
+    pa.nrhs = nrhs;
+    pa.bar = (unsigned long long *)ctl;
+    pa.abort = (int *)(ctl + 8);
+    pa.ticks = c->prof ? (unsigned long long *)(ctl + 64) : nullptr;
+    pa.execs = c->prof ? (unsigned long long *)(ctl + 128) : nullptr;
+    HIPCHK(launch_persistent<T>(st, pa, grid, l));
+    unsigned char host[CTL];
+    HIPCHK(hipMemcpyAsync(host, c->ws_pctl.p, CTL, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int ab = 0;
+    std::memcpy(&ab, host + 8, sizeof(int));
+    if (ab) return set_error(S_ERR_HIP, "persistent launch: a grid barrier wait exceeded its bound");
+    if (c->prof) {
+        int khz = 0;
+        HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device));
+        unsigned long long tk[PERSIST_CLASSES], ex[PERSIST_CLASSES];
+        std::memcpy(tk, host + 64, sizeof(tk));
+        std::memcpy(ex, host + 128, sizeof(ex));
+        for (int k = 0; k < CL_COUNT && k < PERSIST_CLASSES; ++k) {
+            if (!ex[k]) continue;
+            c->srecs.push_back(Ctx::SRec{k, (long long)ex[k], khz > 0 ? (double)tk[k] / khz : 0.0,
+                                         cls_bytes ? cls_bytes[k] : 0.0});
+        }
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
 // the multi-shift solve
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -488,6 +681,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     const int max_outer = P.max_outer;
     const int max_steps = max_outer * l;
     c->bytes_acc = 0;
+    std::vector<POp> persist_ops1;   // operation table of the persistent first pass
     // algorithmic HBM bytes of one launch (each operand read or written once)
     const double cB = (double)cs, nd = (double)n, Vd = (double)V;
     auto ds_bytes = [&](int epi, int nr) {
@@ -679,127 +873,99 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     r2.gate = g_rel;
     const double ds64_plain = nrhs * 24 * 16.0 * Vd + 36 * 16.0 * Vd;
     const double ds64_sv = nrhs * 36 * 16.0 * Vd + 36 * 16.0 * Vd;
-    auto reliable_update = [&](VecArgs<T> &vv, Gate g, double2 *yacc, CoefRef yc, int nr) {
+    auto reliable_update = [&](Emit<T> &e, const VecArgs<T> &vv, Gate g, double2 *yacc, CoefRef yc, int nr) {
         DslashArgs<double> q1 = r1, q2 = r2;
         q1.gate = g;
         q2.gate = g;
-        {
-            Prof p(c, CL_STENCIL, ds64_plain * nr / std::max(nrhs, 1));
-            launch_dslash<double>(st, q1, nrhs, EPI_PLAIN, false);
-        }
-        {
-            Prof p(c, CL_STENCIL, ds64_sv * nr / std::max(nrhs, 1));
-            launch_dslash<double>(st, q2, nrhs, EPI_SV, false);
-        }
+        e.ds64(q1, nrhs, EPI_PLAIN, CL_STENCIL, ds64_plain * nr / std::max(nrhs, 1));
+        e.ds64(q2, nrhs, EPI_SV, CL_STENCIL, ds64_sv * nr / std::max(nrhs, 1));
         VecArgs<T> w = vv;
         w.gate = g;
-        {
-            Prof p(c, CL_SEED, nr * nd * (32.0 + cB + cB + (yacc ? 32.0 : 0.0)));
-            launch_rel_update<T>(st, w, b, v64, yacc, yc, nrhs, nbv);
+        e.rel_update(w, b, v64, yacc, yc, nrhs, nbv, CL_SEED, nr * nd * (32.0 + cB + cB + (yacc ? 32.0 : 0.0)));
+    };
+
+    // One outer iteration of the first pass: l BiCG steps, the MR step, the
+    // reliable update (mixed) and the convergence step.  nr_run and nsh_act
+    // (right-hand sides and shifts still iterating) only price the bytes.
+    auto emit_outer = [&](Emit<T> &e, int nr_run, double nsh_act) {
+        VecArgs<T> v = va;
+        ScalarArgs s = sa;
+        DslashArgs<T> e1 = d1, e2 = d2;
+        for (int j = 0; j < l; ++j) {
+            s.j = j;
+            s.nblk = (j == 0) ? nbv : nbd;
+            s.nblk2 = nbv;
+            e.scalar(OP_SC_BETA, s, nrhs);
+            v.gate = g_bicg;
+            e.seed_u(v, j, nrhs, nbv, CL_SEED, nr_run * 3.0 * (j + 1) * nd * cB);
+            // u_{j+1} = S u_j = a g5 D (g5 D u_j) + sigma0 u_j, <rt, u_{j+1}>
+            e1.in = Uv + (size_t)j * n;
+            e1.out = tmp;
+            e1.gate = g_bicg;
+            e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
+            e2.in = tmp;
+            e2.out = Uv + (size_t)(j + 1) * n;
+            e2.v = Uv + (size_t)j * n;
+            e2.gate = g_bicg;
+            e.ds(e2, nrhs, EPI_MV, CL_STENCIL, ds_bytes(EPI_MV, nr_run));
+            s.nblk = nbd;
+            e.scalar(OP_SC_ALPHA, s, nrhs);
+            v.partials = 1;
+            // seed: read r_i, u_{i+1}, write r_i; shift s: read u^s_0..j, x^s,
+            // write u^s_0..j+1, x^s
+            e.r_update(v, j, pass1, mixed, nrhs, nbv, pass1 ? CL_SHIFT : CL_SEED,
+                       nr_run * 3.0 * (j + 1) * nd * cB + (pass1 ? nsh_act * (2.0 * j + 5) * nd * cB : 0.0));
+            // r_{j+1} = S r_j, <rt, r_{j+1}>
+            e1.in = R + (size_t)j * n;
+            e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
+            e2.out = R + (size_t)(j + 1) * n;
+            e2.v = R + (size_t)j * n;
+            e.ds(e2, nrhs, EPI_MV, CL_STENCIL, ds_bytes(EPI_MV, nr_run));
         }
+        v.gate = g_run;
+        e.gram(v, nrhs, nbv, CL_SEED, nr_run * (l + 1.0) * nd * cB);
+        s.nblk = nbv;
+        e.scalar(OP_SC_MR, s, nrhs);
+        v.partials = 1;
+        // seed: read r_0..r_l, u_0..u_l, rt, write r_0, u_0; shift s: read
+        // u^s_0..u^s_l, x^s, write u^s_0, x^s
+        e.mr_update(v, pass1, mixed, nrhs, nbv, pass1 ? CL_SHIFT_MR : CL_SEED,
+                    nr_run * (2.0 * (l + 1) + 3) * nd * cB + (pass1 ? nsh_act * (l + 4.0) * nd * cB : 0.0));
+        if (mixed) {
+            e.scalar(OP_SC_REL, s, nrhs);
+            reliable_update(e, v, g_rel, nullptr, CoefRef{}, nr_run);
+        }
+        e.scalar(OP_SC_CONV, s, nrhs);
     };
 
     CHK(ensure_host(c, (size_t)nrhs * sizeof(SeedState)));
     SeedState *hseed = (SeedState *)c->host_pinned;
-    int nr_run = nrhs;                       // right-hand sides still iterating
-    double nsh_act = (double)nrhs * ns;      // active shifts over those
-    for (int m = 0; m < max_outer; ++m) {
-        for (int j = 0; j < l; ++j) {
-            sa.j = j;
-            sa.nblk = (j == 0) ? nbv : nbd;
-            sa.nblk2 = nbv;
-            {
-                Prof p(c, CL_SCALAR, 0);
-                launch_sc_beta(st, sa, nrhs);
+    if (P.persistent) {
+        // the whole first pass in one cooperative launch
+        Emit<T> er(c, Emit<T>::RECORD);
+        emit_outer(er, nrhs, (double)nrhs * ns);
+        std::vector<POp> ops = std::move(er.ops);
+        persist_ops1.swap(ops);
+        CHK(run_persistent<T>(c, persist_ops1, max_outer, true, l, seed, nrhs, nullptr));
+    } else {
+        int nr_run = nrhs;                       // right-hand sides still iterating
+        double nsh_act = (double)nrhs * ns;      // active shifts over those
+        Emit<T> el(c, Emit<T>::LAUNCH);
+        for (int m = 0; m < max_outer; ++m) {
+            emit_outer(el, nr_run, nsh_act);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(hseed, seed, nrhs * sizeof(SeedState), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            nr_run = 0;
+            nsh_act = 0;
+            for (int r = 0; r < nrhs; ++r) {
+                if (hseed[r].run) {
+                    nr_run += 1;
+                    nsh_act += hseed[r].nact;
+                }
             }
-            va.gate = g_bicg;
-            {
-                Prof p(c, CL_SEED, nr_run * 3.0 * (j + 1) * nd * cB);
-                launch_seed_u<T>(st, va, j, nrhs, nbv);
-            }
-            // u_{j+1} = S u_j = a g5 D (g5 D u_j) + sigma0 u_j, <rt, u_{j+1}>
-            d1.in = Uv + (size_t)j * n;
-            d1.out = tmp;
-            d1.gate = g_bicg;
-            {
-                Prof p(c, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
-                launch_dslash<T>(st, d1, nrhs, EPI_PLAIN, false);
-            }
-            d2.in = tmp;
-            d2.out = Uv + (size_t)(j + 1) * n;
-            d2.v = Uv + (size_t)j * n;
-            d2.gate = g_bicg;
-            {
-                Prof p(c, CL_STENCIL, ds_bytes(EPI_MV, nr_run));
-                launch_dslash<T>(st, d2, nrhs, EPI_MV, false);
-            }
-            sa.nblk = nbd;
-            {
-                Prof p(c, CL_SCALAR, 0);
-                launch_sc_alpha(st, sa, nrhs);
-            }
-            va.partials = 1;
-            {
-                // seed: read r_i, u_{i+1}, write r_i; shift s: read u^s_0..j, x^s,
-                // write u^s_0..j+1, x^s
-                Prof p(c, pass1 ? CL_SHIFT : CL_SEED,
-                       nr_run * 3.0 * (j + 1) * nd * cB + (pass1 ? nsh_act * (2.0 * j + 5) * nd * cB : 0.0));
-                launch_r_update<T>(st, va, j, pass1, mixed, nrhs, nbv);
-            }
-            // r_{j+1} = S r_j, <rt, r_{j+1}>
-            d1.in = R + (size_t)j * n;
-            {
-                Prof p(c, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
-                launch_dslash<T>(st, d1, nrhs, EPI_PLAIN, false);
-            }
-            d2.out = R + (size_t)(j + 1) * n;
-            d2.v = R + (size_t)j * n;
-            {
-                Prof p(c, CL_STENCIL, ds_bytes(EPI_MV, nr_run));
-                launch_dslash<T>(st, d2, nrhs, EPI_MV, false);
-            }
+            if (nr_run == 0) break;
         }
-        va.gate = g_run;
-        {
-            Prof p(c, CL_SEED, nr_run * (l + 1.0) * nd * cB);
-            launch_gram<T>(st, va, nrhs, nbv);
-        }
-        sa.nblk = nbv;
-        {
-            Prof p(c, CL_SCALAR, 0);
-            launch_sc_mr(st, sa, nrhs);
-        }
-        va.partials = 1;
-        {
-            // seed: read r_0..r_l, u_0..u_l, rt, write r_0, u_0; shift s: read
-            // u^s_0..u^s_l, x^s, write u^s_0, x^s
-            Prof p(c, pass1 ? CL_SHIFT_MR : CL_SEED,
-                   nr_run * (2.0 * (l + 1) + 3) * nd * cB + (pass1 ? nsh_act * (l + 4.0) * nd * cB : 0.0));
-            launch_mr_update<T>(st, va, pass1, mixed, nrhs, nbv);
-        }
-        if (mixed) {
-            {
-                Prof p(c, CL_SCALAR, 0);
-                launch_sc_rel(st, sa, nrhs);
-            }
-            reliable_update(va, g_rel, nullptr, CoefRef{}, nr_run);
-        }
-        {
-            Prof p(c, CL_SCALAR, 0);
-            launch_sc_conv(st, sa, nrhs);
-        }
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(hseed, seed, nrhs * sizeof(SeedState), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        nr_run = 0;
-        nsh_act = 0;
-        for (int r = 0; r < nrhs; ++r) {
-            if (hseed[r].run) {
-                nr_run += 1;
-                nsh_act += hseed[r].nact;
-            }
-        }
-        if (nr_run == 0) break;
     }
 
     // ---- results of pass 1
@@ -807,6 +973,30 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     std::vector<ShiftState> fsh((size_t)nrhs * NSMAX);
     HIPCHK(hipMemcpy(fs.data(), seed, nrhs * sizeof(SeedState), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(fsh.data(), sh, fsh.size() * sizeof(ShiftState), hipMemcpyDeviceToHost));
+
+    if (P.persistent) {
+        // byte model of the persistent first pass, priced per outer iteration
+        // with the right-hand sides and shifts that took part in it
+        int Mrun = 0;
+        for (int r = 0; r < nrhs; ++r) Mrun = std::max(Mrun, fs[r].m);
+        Emit<T> ec(c, Emit<T>::COUNT);
+        for (int m = 0; m < Mrun; ++m) {
+            int nr = 0;
+            double nsh = 0;
+            for (int r = 0; r < nrhs; ++r) {
+                if (fs[r].m <= m) continue;
+                nr += 1;
+                for (int s = 0; s < ns; ++s) nsh += (fsh[(size_t)r * NSMAX + s].iters > m) ? 1.0 : 0.0;
+            }
+            emit_outer(ec, nr, nsh);
+        }
+        if (c->prof) {
+            // attach the bytes to the stage times the kernel reported
+            for (Ctx::SRec &q : c->srecs)
+                if (q.bytes == 0.0 && q.cls >= 0 && q.cls < CL_COUNT && q.pending) q.bytes = ec.cls_bytes[q.cls];
+            for (Ctx::SRec &q : c->srecs) q.pending = false;
+        }
+    }
 
     rep->status = S_OK;
     rep->outer_max = 0;
@@ -898,6 +1088,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         e2.part = nullptr;
         e2.y = y;
         e2.y_rs = n;
+        Emit<T> e(c, P.persistent ? Emit<T>::RECORD : Emit<T>::LAUNCH, true);
         for (int m = 0; m < Mmax; ++m) {
             int nr_m = 0;      // right-hand sides whose replay reaches outer iteration m
             for (int r = 0; r < nrhs; ++r) nr_m += (fs[r].m > m) ? 1 : 0;
@@ -912,45 +1103,27 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 vb.beta = CoefRef{(const char *)&drs[idx].beta, rstride};
                 vb.alpha = CoefRef{(const char *)&drs[idx].alpha, rstride};
                 vb.gate = gu;
-                {
-                    Prof p(c, CL_SEED, nr_m * 3.0 * (j + 1) * nd * cB);
-                    launch_seed_u<T>(st, vb, j, nrhs, nbv);
-                }
+                e.seed_u(vb, j, nrhs, nbv, CL_SEED, nr_m * 3.0 * (j + 1) * nd * cB);
                 e1.in = Uv + (size_t)j * n;
                 e1.out = tmp;
                 e1.gate = gu;
-                {
-                    Prof p(c, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_m));
-                    launch_dslash<T>(st, e1, nrhs, EPI_PLAIN, false);
-                }
+                e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_m));
                 e2.in = tmp;
                 e2.out = Uv + (size_t)(j + 1) * n;
                 e2.v = Uv + (size_t)j * n;
                 e2.ycoef = CoefRef{(const char *)&drs[idx].cu, rstride};
                 e2.gate = gu;
-                {
-                    Prof p(c, CL_STENCIL, ds_bytes(EPI_MV_Y, nr_m));
-                    launch_dslash<T>(st, e2, nrhs, EPI_MV_Y, false);
-                }
+                e.ds(e2, nrhs, EPI_MV_Y, CL_STENCIL, ds_bytes(EPI_MV_Y, nr_m));
                 vb.gate = gr;
-                {
-                    Prof p(c, CL_SEED, nr_m * 3.0 * (j + 1) * nd * cB);
-                    launch_r_update<T>(st, vb, j, false, mixed, nrhs, nbv);
-                }
+                e.r_update(vb, j, false, mixed, nrhs, nbv, CL_SEED, nr_m * 3.0 * (j + 1) * nd * cB);
                 e1.in = R + (size_t)j * n;
                 e1.gate = gr;
-                {
-                    Prof p(c, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_m));
-                    launch_dslash<T>(st, e1, nrhs, EPI_PLAIN, false);
-                }
+                e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_m));
                 e2.out = R + (size_t)(j + 1) * n;
                 e2.v = R + (size_t)j * n;
                 e2.ycoef = CoefRef{(const char *)&drs[idx].cr, rstride};
                 e2.gate = gr;
-                {
-                    Prof p(c, CL_STENCIL, ds_bytes(EPI_MV_Y, nr_m));
-                    launch_dslash<T>(st, e2, nrhs, EPI_MV_Y, false);
-                }
+                e.ds(e2, nrhs, EPI_MV_Y, CL_STENCIL, ds_bytes(EPI_MV_Y, nr_m));
             }
             Gate gm;
             gm.flag = &dro[m].lm;
@@ -958,21 +1131,22 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             gm.need = 1;
             vb.gate = gm;
             vb.gam = CoefRef{(const char *)&dro[m].gam[0], (long)Mcap * (long)sizeof(ReplayOuter)};
-            {
-                Prof p(c, CL_SEED, nr_m * (2.0 * (l + 1) + 2) * nd * cB);
-                launch_mr_update<T>(st, vb, false, mixed, nrhs, nbv);
-            }
+            e.mr_update(vb, false, mixed, nrhs, nbv, CL_SEED, nr_m * (2.0 * (l + 1) + 2) * nd * cB);
             if (mixed) {
-                Gate gr;
-                gr.flag = &dro[m].rel;
-                gr.flag_stride = (long)Mcap * sizeof(ReplayOuter) / (long)sizeof(int);
-                gr.need = 1;
+                Gate grl;
+                grl.flag = &dro[m].rel;
+                grl.flag_stride = (long)Mcap * sizeof(ReplayOuter) / (long)sizeof(int);
+                grl.need = 1;
                 vb.partials = 1;   // the reliable update writes partials (unused in pass 2)
-                reliable_update(vb, gr, y, CoefRef{(const char *)&dro[m].crel, (long)Mcap * (long)sizeof(ReplayOuter)},
-                                nr_m);
+                reliable_update(e, vb, grl, y,
+                                CoefRef{(const char *)&dro[m].crel, (long)Mcap * (long)sizeof(ReplayOuter)}, nr_m);
                 vb.partials = 0;
             }
             HIPCHK(hipGetLastError());
+        }
+        if (P.persistent) {
+            CHK(run_persistent<T>(c, e.ops, 1, false, l, seed, nrhs, e.cls_bytes));
+            for (Ctx::SRec &q : c->srecs) q.pending = false;
         }
         rep->mv *= 2;
     }
