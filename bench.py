@@ -39,10 +39,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_variant(ctx, b, a, sig, w, l, tol, max_outer, pass_, mixed, profile=False):
+def solver_flags(mixed, persistent):
+    from paper_1010_2592_amd import msb
+    return (msb.MIXED if mixed else 0) | (msb.PERSISTENT if persistent else 0)
+
+
+def run_variant(ctx, b, a, sig, w, l, tol, max_outer, pass_, mixed, persistent=False, profile=False):
     import torch
     from paper_1010_2592_amd import msb
-    flags = msb.MIXED if mixed else 0
+    flags = solver_flags(mixed, persistent)
     if profile:
         ctx.profile_enable(True)
     torch.cuda.synchronize()
@@ -105,6 +110,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--pass", dest="pass_", type=int, default=2, choices=(1, 2))
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
+    ap.add_argument("--launch", default="stages", choices=("stages", "persistent"),
+                    help="one launch per stage, or the whole pass in one cooperative launch")
     ap.add_argument("--variants", default="all", choices=("all", "none"))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--max-outer", type=int, default=2000)
@@ -143,10 +150,11 @@ def main():
     a = 1.0 / (1.01 * rho)
     sig, w = msb.neuberger_pfe(wk.n_shift)
     mixed = args.precision == "mixed"
-    log(f"[bench] spectral radius {rho:.6f}; headline pass={args.pass_} {args.precision}")
+    persistent = args.launch == "persistent"
+    log(f"[bench] spectral radius {rho:.6f}; headline pass={args.pass_} {args.precision} {args.launch}")
 
     for i in range(args.warmup):
-        _, info, ms, _ = run_variant(ctx, b, a, sig, w, l, wk.tol, args.max_outer, args.pass_, mixed)
+        _, info, ms, _ = run_variant(ctx, b, a, sig, w, l, wk.tol, args.max_outer, args.pass_, mixed, persistent)
         log(f"[bench] warmup {i}: {ms:.1f} ms, M={info.outer_iters}, status {info.status}")
 
     # ---- timed steps (library timing hook on) ----
@@ -160,7 +168,7 @@ def main():
     y = None
     for k in range(args.steps):
         y, info, _ = ctx.mshift_bicgstabl(b, a, sig, w, l, wk.tol, args.max_outer, args.pass_,
-                                          flags=msb.MIXED if mixed else 0,
+                                          flags=solver_flags(mixed, persistent),
                                           allow=(msb.OK, msb.NOT_CONVERGED))
         infos.append(info)
     e1.record()
@@ -197,7 +205,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{WORKLOAD} Wilson-Dirac mu=0.05 m=-2, 12 point sources, "
                                f"Neuberger N_s={wk.n_shift}, BiCGstab(l={l}), tol {wk.tol}",
-                   "pass": args.pass_, "precision": args.precision, "rhs": nrhs,
+                   "pass": args.pass_, "precision": args.precision, "launch": args.launch, "rhs": nrhs,
                    "n_shift": wk.n_shift, "l": l, "outer_iters": info.outer_iters,
                    "mv_count": info.mv_count, "status": info.status,
                    "max_shift_resid": float(np.max(info.shift_resid))},
@@ -218,11 +226,12 @@ def main():
     if args.variants == "all":
         comps = {}
         ref = None
-        for (p, mx) in ((1, False), (2, False), (1, True), (2, True)):
-            name = f"{p}pass-{'mixed' if mx else 'fp64'}"
+        for (p, mx, pe) in ((1, False, False), (2, False, False), (1, True, False), (2, True, False),
+                            (1, False, True), (2, False, True), (1, True, True), (2, True, True)):
+            name = f"{p}pass-{'mixed' if mx else 'fp64'}-{'persistent' if pe else 'stages'}"
             try:
                 yv, iv, msv, pv = run_variant(ctx, b, a, sig, w, l, wk.tol, min(args.max_outer, 400), p,
-                                              mx, profile=True)
+                                              mx, pe, profile=True)
             except msb.MsbError as e:
                 comps[name] = {"error": str(e)}
                 continue

@@ -202,6 +202,19 @@ struct alignas(16) POp {
     alignas(16) unsigned char blob[POP_BLOB];
 };
 constexpr int PERSIST_CLASSES = 8;
+constexpr int PERSIST_GROUP = 32;      // blocks per first-level barrier group
+constexpr int PERSIST_MAX_GROUPS = 64; // per XCD
+// Barrier and timing state of a persistent launch (zeroed before it).
+struct PersistCtl {
+    unsigned long long bar;                              // XCD arrivals (8 per barrier)
+    int abort;                                           // set when a wait exceeds its bound
+    int pad;
+    unsigned long long ticks[PERSIST_CLASSES];           // wall-clock ticks per timing class
+    unsigned long long execs[PERSIST_CLASSES];           // operations executed per class
+    unsigned long long xbar[8], xrel[8];                 // per XCD: group arrivals, release
+    unsigned long long gbar[8 * PERSIST_MAX_GROUPS];     // per group: block arrivals
+    unsigned long long grel[8 * PERSIST_MAX_GROUPS];     // per group: release
+};
 struct PersistArgs {
     const POp *ops = nullptr;
     int nops = 0;                // operations per iteration of the table
@@ -209,10 +222,8 @@ struct PersistArgs {
     int loop = 0;                // 1: stop after a repetition when no seed runs
     const SeedState *seed = nullptr;
     int nrhs = 0;
-    unsigned long long *bar = nullptr;  // barrier counter, zero at launch
-    int *abort = nullptr;        // set when a barrier wait exceeds its bound
-    unsigned long long *ticks = nullptr;  // [PERSIST_CLASSES] wall-clock ticks per class, or null
-    unsigned long long *execs = nullptr;  // [PERSIST_CLASSES] operations executed per class
+    int timing = 0;              // record per-class stage times
+    PersistCtl *ctl = nullptr;
 };
 // Largest co-resident grid of the persistent kernel of MR degree l (a
 // multiple of 8; 0 when l is outside 1..PERSIST_LMAX).

@@ -10,15 +10,18 @@
 // first pass) until no right-hand side is still running, or runs once (the
 // double-pass replay, whose every outer iteration is known in advance).
 //
-// Grid barrier: a monotone counter in device memory.  Every work-item issues
-// an agent-scope release fence (its stores leave the CU and are written back
-// from its XCD's L2), the block's first work-item adds one to the counter and
-// waits until it reaches (barrier number) x (grid size), then an agent-scope
-// acquire fence invalidates the stale cache lines.  The launch is cooperative,
-// so every block is resident and each wait ends; a wait that still exceeds its
-// bound raises the abort flag, which every waiting block sees and leaves on,
-// so no wave can stay behind after a fault elsewhere.
-#pragma once
+// Grid barrier: a three-level tree of monotone counters.  Blocks are dealt
+// to XCDs round-robin (block b runs on XCD b % 8); inside an XCD they form
+// groups of PERSIST_GROUP.  Every work-item first waits for its own stores to
+// reach its XCD's L2; the last block of a group to arrive arrives at its XCD,
+// and the last group of an XCD writes that L2 back (agent-scope release) and
+// arrives at the global counter.  Release runs down the same tree, and every
+// block ends with an agent-scope acquire (invalidating stale lines), so
+// blocks on different XCDs see each other's results.  One L2 write-back per
+// XCD instead of one per block is what makes this barrier about 7x cheaper
+// than a flat one.  The launch is cooperative, so every block is resident and
+// each wait ends; a wait that still exceeds its bound raises the abort flag,
+// which every waiting block sees and leaves on, so no wave stays behind.
 #include "blas_dev.h"
 #include "scalar_dev.h"
 #include "stencil_dev.h"
@@ -31,28 +34,50 @@ using namespace dev;
 
 constexpr unsigned SPIN_LIMIT = 1u << 24;   // seconds of polling; a stage takes milliseconds
 
-__device__ __forceinline__ bool grid_barrier(const PersistArgs &pa, unsigned long long number) {
+__device__ __forceinline__ bool spin_until(unsigned long long *p, unsigned long long v, int *abortf) {
+    unsigned spins = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
+        if (__hip_atomic_load(abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        if (++spins > SPIN_LIMIT) {
+            __hip_atomic_store(abortf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool grid_barrier(PersistCtl *ctl, unsigned long long number) {
     __shared__ int ok_sh;
-    __threadfence();
+    // s_waitcnt vmcnt(0): this work-item's stores have reached the L2
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        __hip_atomic_fetch_add(pa.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long target = number * gridDim.x;
-        unsigned spins = 0;
-        while (__hip_atomic_load(pa.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(pa.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                ok = 0;
-                break;
+        const int x = blockIdx.x & 7;                       // XCD
+        const int k = blockIdx.x >> 3;                      // rank inside the XCD
+        const int nx = ((int)gridDim.x - x + 7) / 8;        // blocks on this XCD
+        const int g = k / PERSIST_GROUP, ng = (nx + PERSIST_GROUP - 1) / PERSIST_GROUP;
+        const int gsize = (g == ng - 1) ? nx - g * PERSIST_GROUP : PERSIST_GROUP;
+        const int gi = x * PERSIST_MAX_GROUPS + g;
+        const unsigned long long a =
+            __hip_atomic_fetch_add(&ctl->gbar[gi], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        if (a == number * (unsigned long long)gsize) {
+            const unsigned long long ax =
+                __hip_atomic_fetch_add(&ctl->xbar[x], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+            if (ax == number * (unsigned long long)ng) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // write this XCD's L2 back
+                __hip_atomic_fetch_add(&ctl->bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = spin_until(&ctl->bar, number * 8ull, &ctl->abort);
+                __hip_atomic_store(&ctl->xrel[x], number, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                ok = spin_until(&ctl->xrel[x], number, &ctl->abort);
             }
-            if (++spins > SPIN_LIMIT) {
-                __hip_atomic_store(pa.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
+            __hip_atomic_store(&ctl->grel[gi], number, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            ok = spin_until(&ctl->grel[gi], number, &ctl->abort);
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");       // drop stale lines
         ok_sh = ok;
     }
     __syncthreads();
@@ -185,17 +210,17 @@ __device__ __forceinline__ void exec_op(const POp &op) {
 template <typename T, int L>
 __global__ __launch_bounds__(BLOCK) void k_persistent(PersistArgs pa) {
     unsigned long long number = 0;
-    const bool timer = pa.ticks && blockIdx.x == 0 && threadIdx.x == 0;
+    const bool timer = pa.timing && blockIdx.x == 0 && threadIdx.x == 0;
     long long t0 = timer ? wall_clock64() : 0;
     for (int it = 0; it < pa.iters; ++it) {
         for (int k = 0; k < pa.nops; ++k) {
             const POp &op = pa.ops[k];
             exec_op<T, L>(op);
-            if (!grid_barrier(pa, ++number)) return;
+            if (!grid_barrier(pa.ctl, ++number)) return;
             if (timer) {
                 const long long t1 = wall_clock64();
-                pa.ticks[op.cls] += (unsigned long long)(t1 - t0);
-                pa.execs[op.cls] += 1;
+                pa.ctl->ticks[op.cls] += (unsigned long long)(t1 - t0);
+                pa.ctl->execs[op.cls] += 1;
                 t0 = t1;
             }
         }
@@ -220,7 +245,9 @@ int persistent_grid_l(int device) {
                                                      0) != hipSuccess)
         return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-    const long g = ((long)per_cu * ncu / 8) * 8;
+    long g = ((long)per_cu * ncu / 8) * 8;
+    const long cap = 8L * PERSIST_GROUP * PERSIST_MAX_GROUPS;   // what the barrier tree holds
+    if (g > cap) g = cap;
     return (int)g;
 }
 

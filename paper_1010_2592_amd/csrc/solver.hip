@@ -625,11 +625,9 @@ static int run_persistent(Ctx *c, const std::vector<POp> &ops, int iters, bool l
     if (grid == 0) grid = persistent_grid<T>(c->device, l);
     if (grid < 8) return set_error(S_ERR_HIP, "persistent launch: no co-resident grid for l = " + std::to_string(l));
     CHK(ensure(c->ws_ops, ops.size() * sizeof(POp)));
-    constexpr size_t CTL = 256;   // barrier counter, abort flag, ticks[8], execs[8]
-    CHK(ensure(c->ws_pctl, CTL));
+    CHK(ensure(c->ws_pctl, sizeof(PersistCtl)));
     HIPCHK(hipMemcpyAsync(c->ws_ops.p, ops.data(), ops.size() * sizeof(POp), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemsetAsync(c->ws_pctl.p, 0, CTL, st));
-    char *ctl = (char *)c->ws_pctl.p;
+    HIPCHK(hipMemsetAsync(c->ws_pctl.p, 0, sizeof(PersistCtl), st));
     PersistArgs pa;
     pa.ops = (const POp *)c->ws_ops.p;
     pa.nops = (int)ops.size();
@@ -637,23 +635,17 @@ static int run_persistent(Ctx *c, const std::vector<POp> &ops, int iters, bool l
     pa.loop = loop ? 1 : 0;
     pa.seed = seed;
     pa.nrhs = nrhs;
-    pa.bar = (unsigned long long *)ctl;
-    pa.abort = (int *)(ctl + 8);
-    pa.ticks = c->prof ? (unsigned long long *)(ctl + 64) : nullptr;
-    pa.execs = c->prof ? (unsigned long long *)(ctl + 128) : nullptr;
+    pa.timing = c->prof ? 1 : 0;
+    pa.ctl = (PersistCtl *)c->ws_pctl.p;
     HIPCHK(launch_persistent<T>(st, pa, grid, l));
-    unsigned char host[CTL];
-    HIPCHK(hipMemcpyAsync(host, c->ws_pctl.p, CTL, hipMemcpyDeviceToHost, st));
+    PersistCtl host;
+    HIPCHK(hipMemcpyAsync(&host, c->ws_pctl.p, sizeof(PersistCtl), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    int ab = 0;
-    std::memcpy(&ab, host + 8, sizeof(int));
-    if (ab) return set_error(S_ERR_HIP, "persistent launch: a grid barrier wait exceeded its bound");
+    if (host.abort) return set_error(S_ERR_HIP, "persistent launch: a grid barrier wait exceeded its bound");
     if (c->prof) {
         int khz = 0;
         HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device));
-        unsigned long long tk[PERSIST_CLASSES], ex[PERSIST_CLASSES];
-        std::memcpy(tk, host + 64, sizeof(tk));
-        std::memcpy(ex, host + 128, sizeof(ex));
+        const unsigned long long *tk = host.ticks, *ex = host.execs;
         for (int k = 0; k < CL_COUNT && k < PERSIST_CLASSES; ++k) {
             if (!ex[k]) continue;
             c->srecs.push_back(Ctx::SRec{k, (long long)ex[k], khz > 0 ? (double)tk[k] / khz : 0.0,
