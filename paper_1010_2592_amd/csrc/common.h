@@ -98,6 +98,21 @@ __device__ inline void block_reduce_store(double (&v)[NV], double *out, int stri
     }
 }
 
+// Reduce NV doubles over the 64 lanes of a wavefront (fixed shuffle tree, so
+// the same data always gives the same bits) and store them from lane 0 at
+// out[k * stride].
+template <int NV>
+__device__ inline void wave_reduce_store(double (&v)[NV], double *out, long stride) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) out[(size_t)k * stride] = x;
+    }
+}
+
 // Sum of p[0..n) by all BLOCK threads of one block, returned to every thread.
 __device__ inline double block_sum(const double *p, int n) {
     __shared__ double sh[BLOCK / 64];
@@ -226,9 +241,11 @@ __device__ inline bool gate_open(const Gate &g, int rhs) {
 
 // Row length of the reduction-partial buffer: one entry per block of the
 // widest reducing launch (the stencil uses one block per 256 sites).
+// Row stride of the partial-sum buffers: the stencil writes one partial per
+// 64-site chunk (one wavefront), the vector kernels at most NBMAX.
 inline long part_stride(const Geom &g) {
-    const long nsb = ((long)g.V + BLOCK - 1) / BLOCK;
-    return nsb > NBMAX ? nsb : NBMAX;
+    const long nch = ((long)g.V + 63) / 64;
+    return nch > NBMAX ? nch : NBMAX;
 }
 
 inline int nblocks_for(long n) {

@@ -34,6 +34,16 @@ __global__ __launch_bounds__(BLOCK) void dslash_kernel(DslashArgs<T> a) {
     dslash_body<T, EPI, G5IN>(a, blockIdx.x);
 }
 
+// wavefronts per block of the chunked stencil (measured on 16^3x32 and
+// 24^3x48 with 12 right-hand sides: 4 in FP64, where the 74 KB of staged links
+// allow two blocks per CU, and 12 in FP32)
+template <typename T> constexpr int chunk_waves() { return sizeof(T) == sizeof(double) ? 4 : 12; }
+
+template <typename T, int EPI, bool G5IN>
+__global__ __launch_bounds__(64 * chunk_waves<T>()) void dslash_chunk_kernel(DslashArgs<T> a) {
+    dslash_chunk<T, EPI, G5IN, chunk_waves<T>()>(a, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Link force: gradient of sum_pairs c Re <p, D(mu) q> with respect to the
 // links (the unconstrained complex gradient, dL/dRe + i dL/dIm).  U_nu(x)
@@ -142,6 +152,23 @@ __global__ __launch_bounds__(BLOCK) void link_force_kernel(LinkForceArgs a) {
 
 template <typename T>
 void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in) {
+    if (nrhs >= CHUNK_MIN_RHS) {
+        dim3 grid((unsigned)dslash_chunk_prepare(a, nrhs)), block(64 * chunk_waves<T>());
+#define MSB_DS(E, G5) hipLaunchKernelGGL((dslash_chunk_kernel<T, E, G5>), grid, block, 0, st, a)
+        if (g5in) {
+            if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, true);
+            else if (epi == EPI_MV) MSB_DS(EPI_MV, true);
+            else if (epi == EPI_SV) MSB_DS(EPI_SV, true);
+            else MSB_DS(EPI_MV_Y, true);
+        } else {
+            if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, false);
+            else if (epi == EPI_MV) MSB_DS(EPI_MV, false);
+            else if (epi == EPI_SV) MSB_DS(EPI_SV, false);
+            else MSB_DS(EPI_MV_Y, false);
+        }
+#undef MSB_DS
+        return;
+    }
     dim3 grid((unsigned)dslash_prepare(a, nrhs)), block(BLOCK);
 #define MSB_DS(E, G5) hipLaunchKernelGGL((dslash_kernel<T, E, G5>), grid, block, 0, st, a)
     if (g5in) {

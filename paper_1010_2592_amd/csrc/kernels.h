@@ -35,6 +35,9 @@ struct DslashArgs {
     int per = 0;               // blocks per XCD in the flattened grid (set by the launcher)
     int sstride = 0;           // site-loop stride (set by the launcher)
     int nrhs = 0;
+    int nch = 0;               // chunked stencil: 64-site chunks (set by the launcher)
+    int tsc = 0;               // chunked stencil: chunks per t-slice, 0 if not whole
+    int per_t = 0;             // chunked stencil: blocks per XCD (per rounded up to tsc)
     CoefRef ycoef;             // EPI_MV_Y: coefficient of the Mv output
     double2 *y = nullptr;      // EPI_MV_Y accumulator (always FP64)
     Gate gate{};
@@ -47,8 +50,9 @@ struct DslashArgs {
 template <typename T>
 void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in);
 
-// Launch geometry of the stencil: sets nsb, nrhs, per and sstride and returns
-// the number of (virtual) blocks, 8 per, so that block p runs on XCD p % 8.
+// Launch geometry of the site-block stencil: sets nsb, nrhs, per and sstride
+// and returns the number of (virtual) blocks, 8 per, so that block p runs on
+// XCD p % 8.
 template <typename T>
 inline long dslash_prepare(DslashArgs<T> &a, int nrhs) {
     a.nsb = (a.g.V + BLOCK - 1) / BLOCK;
@@ -57,6 +61,23 @@ inline long dslash_prepare(DslashArgs<T> &a, int nrhs) {
     a.per = (int)((G + 7) / 8);
     a.sstride = 1 << 30;
     return 8L * a.per;
+}
+
+// Batches of at least this many right-hand sides use the chunked stencil,
+// which stages the links of 64 sites in LDS once for all of them.
+constexpr int CHUNK_MIN_RHS = 4;
+constexpr int CHUNK = 64;
+// Launch geometry of the chunked stencil (blocks = 8 per_t).
+template <typename T>
+inline long dslash_chunk_prepare(DslashArgs<T> &a, int nrhs) {
+    a.nrhs = nrhs;
+    a.nch = (a.g.V + CHUNK - 1) / CHUNK;
+    a.per = (a.nch + 7) / 8;
+    const int sites_t = a.g.Lx * a.g.Ly * a.g.Lz;
+    a.tsc = (sites_t % CHUNK == 0) ? sites_t / CHUNK : 0;
+    a.per_t = a.tsc ? ((a.per + a.tsc - 1) / a.tsc) * a.tsc : a.per;
+    a.sstride = 1 << 30;
+    return 8L * a.per_t;
 }
 
 // link force: pairs (c, p, q), the gradient of sum c Re <p, D(mu) q>

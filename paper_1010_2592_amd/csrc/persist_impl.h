@@ -105,6 +105,12 @@ __device__ __noinline__ void call_sc_alpha(const ScalarArgs *a, int rhs) { sc_al
 __device__ __noinline__ void call_sc_mr(const ScalarArgs *a, int rhs) { sc_mr_body(*a, rhs); }
 __device__ __noinline__ void call_sc_rel(const ScalarArgs *a, int rhs) { sc_rel_body(*a, rhs); }
 __device__ __noinline__ void call_sc_conv(const ScalarArgs *a, int rhs) { sc_conv_body(*a, rhs); }
+// The stencil stages likewise: inlined next to the other stages the compiler
+// no longer keeps them at the register budget of their own kernels.
+template <typename T, int EPI>
+__device__ __noinline__ void call_dslash(const DslashArgs<T> *a, int vb) {
+    dslash_body<T, EPI, false>(*a, vb);
+}
 
 template <typename T, int L, bool XH, int J>
 __device__ __forceinline__ void exec_r_update_j(const POp &op, const VecArgs<T> &a) {
@@ -138,17 +144,17 @@ __device__ __forceinline__ void exec_op(const POp &op) {
     constexpr bool XH = sizeof(T) != sizeof(double);
     switch (op.kind) {
     case OP_DS: {
-        const DslashArgs<T> &a = *reinterpret_cast<const DslashArgs<T> *>(op.blob);
-        if (op.epi == EPI_PLAIN) VLOOP((dslash_body<T, EPI_PLAIN, false>(a, vb)))
-        else if (op.epi == EPI_MV) VLOOP((dslash_body<T, EPI_MV, false>(a, vb)))
-        else VLOOP((dslash_body<T, EPI_MV_Y, false>(a, vb)))
+        const DslashArgs<T> *a = reinterpret_cast<const DslashArgs<T> *>(op.blob);
+        if (op.epi == EPI_PLAIN) VLOOP((call_dslash<T, EPI_PLAIN>(a, vb)))
+        else if (op.epi == EPI_MV) VLOOP((call_dslash<T, EPI_MV>(a, vb)))
+        else VLOOP((call_dslash<T, EPI_MV_Y>(a, vb)))
         break;
     }
     case OP_DS64: {
         if constexpr (XH) {
-            const DslashArgs<double> &a = *reinterpret_cast<const DslashArgs<double> *>(op.blob);
-            if (op.epi == EPI_PLAIN) VLOOP((dslash_body<double, EPI_PLAIN, false>(a, vb)))
-            else VLOOP((dslash_body<double, EPI_SV, false>(a, vb)))
+            const DslashArgs<double> *a = reinterpret_cast<const DslashArgs<double> *>(op.blob);
+            if (op.epi == EPI_PLAIN) VLOOP((call_dslash<double, EPI_PLAIN>(a, vb)))
+            else VLOOP((call_dslash<double, EPI_SV>(a, vb)))
         }
         break;
     }
@@ -207,8 +213,10 @@ __device__ __forceinline__ void exec_op(const POp &op) {
     }
 }
 
+// Three wavefronts per SIMD (the stencil's own occupancy); the budget also
+// applies to the stages called out of line.
 template <typename T, int L>
-__global__ __launch_bounds__(BLOCK) void k_persistent(PersistArgs pa) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_persistent(PersistArgs pa) {
     unsigned long long number = 0;
     const bool timer = pa.timing && blockIdx.x == 0 && threadIdx.x == 0;
     long long t0 = timer ? wall_clock64() : 0;

@@ -666,7 +666,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     const long n = 12L * V;
     const int nrhs = P.nrhs, ns = P.n_shift, l = P.l;
     const bool pass1 = P.pass == 1;
-    const int nbd = (V + BLOCK - 1) / BLOCK;     // stencil partials: one per site block
+    const int nbd = (V + CHUNK - 1) / CHUNK;     // stencil partials: one per 64-site chunk
     const int nbv = nblocks_for(n);
     const long ps = part_stride(c->g);
     const size_t cs = sizeof(C<T>);

@@ -44,11 +44,12 @@ __device__ __forceinline__ void load_spin(const C<T> *__restrict__ in, int V, in
     }
 }
 
-// acc += f * (1 + SGN gamma_NU) Umat psi(sn), Umat = U_NU(sl) (DAG=false) or
-// U_NU(sl)^+ (DAG=true)
+// acc += f * (1 + SGN gamma_NU) Umat psi(sn), Umat = U (DAG=false) or U^+
+// (DAG=true), where entry (a, b) of U is Ub[(3 a + b) us]: the link in global
+// memory (us = V) or staged in LDS (us = CHUNK).
 template <typename T, int NU, int SGN, bool DAG, bool G5IN>
 __device__ __forceinline__ void hop(C<T> (&acc)[4][3], const C<T> *__restrict__ in,
-                                   const C<T> *__restrict__ U, int V, int sn, int sl, T f) {
+                                   const C<T> *__restrict__ Ub, int us, int V, int sn, T f) {
     using P = Proj<NU, SGN>;
     C<T> h[2][3];
     {
@@ -63,15 +64,14 @@ __device__ __forceinline__ void hop(C<T> (&acc)[4][3], const C<T> *__restrict__ 
             h[1][a] = cadd(p1[a], mulcode<P::C1>(q1[a]));
         }
     }
-    const C<T> *Un = U + (size_t)NU * 9 * V + sl;
     C<T> g[2][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         C<T> u0, u1, u2;
         if (!DAG) {
-            u0 = Un[(3 * a + 0) * V];
-            u1 = Un[(3 * a + 1) * V];
-            u2 = Un[(3 * a + 2) * V];
+            u0 = Ub[(3 * a + 0) * us];
+            u1 = Ub[(3 * a + 1) * us];
+            u2 = Ub[(3 * a + 2) * us];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 C<T> r = cmul(u0, h[i][0]);
@@ -81,9 +81,9 @@ __device__ __forceinline__ void hop(C<T> (&acc)[4][3], const C<T> *__restrict__ 
             }
         } else {
             // (U^+)_{ab} = conj(U_{ba})
-            u0 = Un[(0 * 3 + a) * V];
-            u1 = Un[(1 * 3 + a) * V];
-            u2 = Un[(2 * 3 + a) * V];
+            u0 = Ub[(0 * 3 + a) * us];
+            u1 = Ub[(1 * 3 + a) * us];
+            u2 = Ub[(2 * 3 + a) * us];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 C<T> r = cmulc(u0, h[i][0]);
@@ -102,103 +102,215 @@ __device__ __forceinline__ void hop(C<T> (&acc)[4][3], const C<T> *__restrict__ 
     }
 }
 
-// One block per (256-site block, right-hand side).  The flattened grid is
-// padded to a multiple of 8 and mapped XCD-aware: hardware block p runs on
-// XCD p % 8, which here owns the contiguous logical range
-// [(p % 8) per, (p % 8 + 1) per); inside it the right-hand side varies fastest,
-// so the 12 sources of one site block run back to back on one XCD and share
-// its L2 copy of the links and of the neighbouring planes.
+// Where a hop finds its link: in global memory ([4][3][3][V], entry stride V)
+// or staged in LDS for a 64-site chunk ([8 hops][9][CHUNK], stride CHUNK).
+template <typename T>
+struct GlobalLinks {
+    const C<T> *U;
+    int V;
+    __device__ __forceinline__ const C<T> *at(int nu, int bwd, int sl, int) const {
+        (void)bwd;
+        return U + (size_t)nu * 9 * V + sl;
+    }
+    __device__ __forceinline__ int stride() const { return V; }
+};
+template <typename T>
+struct LdsLinks {
+    const C<T> *L;
+    int base;   // first site of the chunk
+    __device__ __forceinline__ const C<T> *at(int nu, int bwd, int, int s) const {
+        return L + (2 * nu + bwd) * 9 * CHUNK + (s - base);
+    }
+    __device__ __forceinline__ int stride() const { return CHUNK; }
+};
+
+// The stencil and its epilogue for sites s0, s0 + sstride, ... < V of one
+// right-hand side.  sstride exceeds V, so the loop body runs at most once;
+// keeping it a loop with a run-time bound (and every address derived from s)
+// stops the compiler from hoisting the eight hops' loads all at once, which
+// needs more than 256 VGPRs and spills.
+template <typename T, int EPI, bool G5IN, typename LK>
+__device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &lk, const C<T> *__restrict__ in,
+                                             C<T> *__restrict__ out, const C<T> *__restrict__ v,
+                                             const C<T> *__restrict__ rt, double2 *__restrict__ y, C<T> yc,
+                                             T sig0, int s0, double (&part)[3]) {
+    const int V = a.g.V, Lx = a.g.Lx, Ly = a.g.Ly, Lz = a.g.Lz, Lt = a.g.Lt;
+    for (int s = s0; s < V; s += a.sstride) {
+    const int sxy = Lx * Ly, sxyz = Lx * Ly * Lz;
+    const int x = s % Lx;
+    const int r1 = s / Lx;
+    const int yy = r1 % Ly;
+    const int r2 = r1 / Ly;
+    const int z = r2 % Lz;
+    const int t = r2 / Lz;
+    const int us = lk.stride();
+    C<T> acc[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[i][c] = mk<T>(0, 0);
+
+    int sf, sb;
+    sf = (x == Lx - 1) ? s - (Lx - 1) : s + 1;
+    sb = (x == 0) ? s + (Lx - 1) : s - 1;
+    hop<T, 0, -1, false, G5IN>(acc, in, lk.at(0, 0, s, s), us, V, sf, (T)1);
+    hop<T, 0, +1, true, G5IN>(acc, in, lk.at(0, 1, sb, s), us, V, sb, (T)1);
+    sf = (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx;
+    sb = (yy == 0) ? s + (Ly - 1) * Lx : s - Lx;
+    hop<T, 1, -1, false, G5IN>(acc, in, lk.at(1, 0, s, s), us, V, sf, (T)1);
+    hop<T, 1, +1, true, G5IN>(acc, in, lk.at(1, 1, sb, s), us, V, sb, (T)1);
+    sf = (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy;
+    sb = (z == 0) ? s + (Lz - 1) * sxy : s - sxy;
+    hop<T, 2, -1, false, G5IN>(acc, in, lk.at(2, 0, s, s), us, V, sf, (T)1);
+    hop<T, 2, +1, true, G5IN>(acc, in, lk.at(2, 1, sb, s), us, V, sb, (T)1);
+    sf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
+    sb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
+    const T ff = (t == Lt - 1) ? a.ef * a.bc : a.ef;
+    const T fb = (t == 0) ? a.eb * a.bc : a.eb;
+    hop<T, 3, -1, false, G5IN>(acc, in, lk.at(3, 0, s, s), us, V, sf, ff);
+    hop<T, 3, +1, true, G5IN>(acc, in, lk.at(3, 1, sb, s), us, V, sb, fb);
+
+    // out = scale * [gamma5] ((4+m) psi(x) - acc / 2), formed in place
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+        C<T> ps[3];
+        load_spin<T, G5IN>(in, V, s, sp, ps);
+        const T sg = ((a.g5out && sp >= 2) ? (T)-1 : (T)1) * a.scale;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            acc[sp][c] = cscale(csub(cscale(ps[c], a.diag), cscale(acc[sp][c], (T)0.5)), sg);
+    }
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int k = 3 * sp + c;
+            C<T> o = acc[sp][c];
+            if (EPI != EPI_PLAIN) o = cadd(o, cscale(v[k * V + s], sig0));
+            out[k * V + s] = o;
+            if (EPI == EPI_MV) {
+                const C<T> r = rt[k * V + s];
+                part[0] += (double)r.x * o.x + (double)r.y * o.y;
+                part[1] += (double)r.x * o.y - (double)r.y * o.x;
+                part[2] += (double)o.x * o.x + (double)o.y * o.y;
+            }
+            if (EPI == EPI_MV_Y) {
+                double2 yv = y[k * V + s];
+                yv.x += (double)yc.x * o.x - (double)yc.y * o.y;
+                yv.y += (double)yc.x * o.y + (double)yc.y * o.x;
+                y[k * V + s] = yv;
+            }
+        }
+    }
+    }
+}
+
+// Operand pointers of right-hand side rhs.
+template <typename T>
+struct RhsOps {
+    const C<T> *in;
+    C<T> *out;
+    const C<T> *v, *rt;
+    double2 *y;
+    C<T> yc;
+    T sig0;
+};
+template <typename T, int EPI>
+__device__ __forceinline__ RhsOps<T> rhs_ops(const DslashArgs<T> &a, int rhs) {
+    const long nv = 12L * a.g.V;
+    RhsOps<T> o;
+    o.in = a.in + (size_t)rhs * (a.in_rs ? a.in_rs : nv);
+    o.out = a.out + (size_t)rhs * (a.out_rs ? a.out_rs : nv);
+    o.v = a.v ? a.v + (size_t)rhs * (a.v_rs ? a.v_rs : nv) : nullptr;
+    o.rt = a.rt ? a.rt + (size_t)rhs * (a.rt_rs ? a.rt_rs : nv) : nullptr;
+    o.y = a.y ? a.y + (size_t)rhs * (a.y_rs ? a.y_rs : nv) : nullptr;
+    o.yc = mk<T>(0, 0);
+    if (EPI == EPI_MV_Y) o.yc = to_c<T>(ld(a.ycoef, rhs));
+    o.sig0 = a.sigma0_rhs ? (T)a.sigma0_rhs[rhs] : a.sigma0;
+    return o;
+}
+
+// Site-block stencil: one block per (256-site block, right-hand side), links
+// read from global memory.  Partials: one per 64-site chunk (wavefront).
+template <typename T, int EPI, bool G5IN>
+__device__ __forceinline__ void dslash_site_block(const DslashArgs<T> &a, int sblk, int rhs) {
+    if (!gate_open(a.gate, rhs)) return;
+    const RhsOps<T> o = rhs_ops<T, EPI>(a, rhs);
+    const GlobalLinks<T> lk{a.U, a.g.V};
+    double part[3] = {0.0, 0.0, 0.0};
+    dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, sblk * BLOCK + threadIdx.x, part);
+    if (EPI == EPI_MV)
+        wave_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + sblk * (BLOCK / 64) + (threadIdx.x >> 6),
+                             a.ps);
+}
+
+// Block p of the flattened grid (8 per blocks) to (site block, rhs): hardware
+// block p runs on XCD p % 8, which owns the contiguous logical range
+// [(p % 8) per, (p % 8 + 1) per); inside it the right-hand side varies
+// fastest, so the sources of one site block run back to back on one XCD.
 template <typename T, int EPI, bool G5IN>
 __device__ __forceinline__ void dslash_body(const DslashArgs<T> &a, int p) {
     const int L = (p & 7) * a.per + (p >> 3);
     if (L >= a.nsb * a.nrhs) return;
     const int sblk = L / a.nrhs;
-    const int rhs = L - sblk * a.nrhs;
-    if (!gate_open(a.gate, rhs)) return;
-    const int V = a.g.V, Lx = a.g.Lx, Ly = a.g.Ly, Lz = a.g.Lz, Lt = a.g.Lt;
-    const long nv = 12L * V;
-    const C<T> *__restrict__ in = a.in + (size_t)rhs * (a.in_rs ? a.in_rs : nv);
-    C<T> *__restrict__ out = a.out + (size_t)rhs * (a.out_rs ? a.out_rs : nv);
-    const C<T> *__restrict__ U = a.U;
-    const C<T> *__restrict__ v = a.v ? a.v + (size_t)rhs * (a.v_rs ? a.v_rs : nv) : nullptr;
-    const C<T> *__restrict__ rt = a.rt ? a.rt + (size_t)rhs * (a.rt_rs ? a.rt_rs : nv) : nullptr;
-    double2 *__restrict__ y = a.y ? a.y + (size_t)rhs * (a.y_rs ? a.y_rs : nv) : nullptr;
-    C<T> yc = mk<T>(0, 0);
-    if (EPI == EPI_MV_Y) yc = to_c<T>(ld(a.ycoef, rhs));
-    const T sig0 = a.sigma0_rhs ? (T)a.sigma0_rhs[rhs] : a.sigma0;
-    double part[3] = {0.0, 0.0, 0.0};
-    // a.sstride exceeds V, so the loop body runs at most once; keeping it a
-    // loop with a run-time bound stops the compiler from hoisting every load
-    // of the eight hops at once (which needs more than 256 VGPRs and spills)
-    for (int s = sblk * BLOCK + threadIdx.x; s < V; s += a.sstride) {
-        const int sxy = Lx * Ly, sxyz = Lx * Ly * Lz;
-        const int x = s % Lx;
-        const int r1 = s / Lx;
-        const int yy = r1 % Ly;
-        const int r2 = r1 / Ly;
-        const int z = r2 % Lz;
-        const int t = r2 / Lz;
-        C<T> acc[4][3];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) acc[i][c] = mk<T>(0, 0);
+    dslash_site_block<T, EPI, G5IN>(a, sblk, L - sblk * a.nrhs);
+}
 
-        int sf, sb;
-        sf = (x == Lx - 1) ? s - (Lx - 1) : s + 1;
-        sb = (x == 0) ? s + (Lx - 1) : s - 1;
-        hop<T, 0, -1, false, G5IN>(acc, in, U, V, sf, s, (T)1);
-        hop<T, 0, +1, true, G5IN>(acc, in, U, V, sb, sb, (T)1);
-        sf = (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx;
-        sb = (yy == 0) ? s + (Ly - 1) * Lx : s - Lx;
-        hop<T, 1, -1, false, G5IN>(acc, in, U, V, sf, s, (T)1);
-        hop<T, 1, +1, true, G5IN>(acc, in, U, V, sb, sb, (T)1);
-        sf = (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy;
-        sb = (z == 0) ? s + (Lz - 1) * sxy : s - sxy;
-        hop<T, 2, -1, false, G5IN>(acc, in, U, V, sf, s, (T)1);
-        hop<T, 2, +1, true, G5IN>(acc, in, U, V, sb, sb, (T)1);
-        sf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
-        sb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
-        const T ff = (t == Lt - 1) ? a.ef * a.bc : a.ef;
-        const T fb = (t == 0) ? a.eb * a.bc : a.eb;
-        hop<T, 3, -1, false, G5IN>(acc, in, U, V, sf, s, ff);
-        hop<T, 3, +1, true, G5IN>(acc, in, U, V, sb, sb, fb);
-
-        // out = scale * [gamma5] ((4+m) psi(x) - acc / 2), formed in place
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp) {
-            C<T> ps[3];
-            load_spin<T, G5IN>(in, V, s, sp, ps);
-            const T sg = ((a.g5out && sp >= 2) ? (T)-1 : (T)1) * a.scale;
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                acc[sp][c] = cscale(csub(cscale(ps[c], a.diag), cscale(acc[sp][c], (T)0.5)), sg);
-        }
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int k = 3 * sp + c;
-                C<T> o = acc[sp][c];
-                if (EPI != EPI_PLAIN) o = cadd(o, cscale(v[k * V + s], sig0));
-                out[k * V + s] = o;
-                if (EPI == EPI_MV) {
-                    const C<T> r = rt[k * V + s];
-                    part[0] += (double)r.x * o.x + (double)r.y * o.y;
-                    part[1] += (double)r.x * o.y - (double)r.y * o.x;
-                    part[2] += (double)o.x * o.x + (double)o.y * o.y;
-                }
-                if (EPI == EPI_MV_Y) {
-                    double2 yv = y[k * V + s];
-                    yv.x += (double)yc.x * o.x - (double)yc.y * o.y;
-                    yv.y += (double)yc.x * o.y + (double)yc.y * o.x;
-                    y[k * V + s] = yv;
-                }
-            }
-        }
+// Chunked stencil for batches: one block of NW wavefronts per 64-site chunk.
+// The block first stages the chunk's eight links per site (forward U_nu(x)
+// and backward U_nu(x - nu)) in LDS, then its wavefronts take the right-hand
+// sides in turn, one site per lane, reading the links from LDS: the links
+// cross the memory fabric once per chunk instead of once per right-hand side
+// (which is what bounded the site-block stencil on batches).  Chunks are
+// dealt XCD-aware: XCD p % 8 owns a contiguous slab of chunks, walked with
+// the time coordinate varying fastest so that the t -/+ 1 neighbour planes
+// were read moments earlier by the same XCD.  Arithmetic, per site and per
+// partial, is the site-block stencil's, bit for bit.
+template <typename T, int EPI, bool G5IN, int NW>
+__device__ __forceinline__ void dslash_chunk(const DslashArgs<T> &a, int p) {
+    __shared__ C<T> Ls[8 * 9 * CHUNK];
+    const int x8 = p & 7, i = p >> 3;
+    const int s0 = x8 * a.per;
+    int n = a.nch - s0;
+    if (n > a.per) n = a.per;
+    int c = i;
+    if (a.tsc) {
+        const int ntl = a.per_t / a.tsc;
+        const int zc = i / ntl;
+        c = (i - zc * ntl) * a.tsc + zc;
     }
-    if (EPI == EPI_MV)
-        block_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + sblk, a.ps);
+    if (c >= n) return;
+    const int chunk = s0 + c;
+    const int V = a.g.V, Lx = a.g.Lx, Ly = a.g.Ly, Lz = a.g.Lz, Lt = a.g.Lt;
+    const int base = chunk * CHUNK;
+    for (int idx = threadIdx.x; idx < 8 * 9 * CHUNK; idx += 64 * NW) {
+        const int hp = idx / (9 * CHUNK), e = (idx / CHUNK) % 9;
+        const int s = base + idx % CHUNK;
+        C<T> u = mk<T>(0, 0);
+        if (s < V) {
+            const int nu = hp >> 1;
+            int sl = s;
+            if (hp & 1) {
+                const int x = s % Lx, q1 = s / Lx, yy = q1 % Ly, q2 = q1 / Ly, z = q2 % Lz, t = q2 / Lz;
+                if (nu == 0) sl = (x == 0) ? s + (Lx - 1) : s - 1;
+                else if (nu == 1) sl = (yy == 0) ? s + (Ly - 1) * Lx : s - Lx;
+                else if (nu == 2) sl = (z == 0) ? s + (Lz - 1) * Lx * Ly : s - Lx * Ly;
+                else sl = (t == 0) ? s + (Lt - 1) * Lx * Ly * Lz : s - Lx * Ly * Lz;
+            }
+            u = a.U[((size_t)nu * 9 + e) * V + sl];
+        }
+        Ls[idx] = u;
+    }
+    __syncthreads();
+    const LdsLinks<T> lk{Ls, base};
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int rhs = w; rhs < a.nrhs; rhs += NW) {
+        if (!gate_open(a.gate, rhs)) continue;
+        const RhsOps<T> o = rhs_ops<T, EPI>(a, rhs);
+        double part[3] = {0.0, 0.0, 0.0};
+        dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, base + lane, part);
+        if (EPI == EPI_MV) wave_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + chunk, a.ps);
+    }
 }
 
 }  // namespace dev
