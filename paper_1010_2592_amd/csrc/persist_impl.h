@@ -105,12 +105,104 @@ __device__ __noinline__ void call_sc_alpha(const ScalarArgs *a, int rhs) { sc_al
 __device__ __noinline__ void call_sc_mr(const ScalarArgs *a, int rhs) { sc_mr_body(*a, rhs); }
 __device__ __noinline__ void call_sc_rel(const ScalarArgs *a, int rhs) { sc_rel_body(*a, rhs); }
 __device__ __noinline__ void call_sc_conv(const ScalarArgs *a, int rhs) { sc_conv_body(*a, rhs); }
-// The stencil stages likewise: inlined next to the other stages the compiler
-// no longer keeps them at the register budget of their own kernels.
-template <typename T, int EPI>
-__device__ __noinline__ void call_dslash(const DslashArgs<T> *a, int vb) {
-    dslash_body<T, EPI, false>(*a, vb);
+// The site-block stencil in the form that keeps this kernel within the
+// stencil's own register budget (three wavefronts per SIMD): the same
+// arithmetic and per-wavefront partials as dslash_site_block and the chunked
+// stencil, with the one-trip site loop written out in the block function.
+template <typename T, int EPI, bool G5IN>
+__device__ __forceinline__ void dslash_persist_body(const DslashArgs<T> &a, int p) {
+    const int L = (p & 7) * a.per + (p >> 3);
+    if (L >= a.nsb * a.nrhs) return;
+    const int sblk = L / a.nrhs;
+    const int rhs = L - sblk * a.nrhs;
+    if (!gate_open(a.gate, rhs)) return;
+    const int V = a.g.V, Lx = a.g.Lx, Ly = a.g.Ly, Lz = a.g.Lz, Lt = a.g.Lt;
+    const long nv = 12L * V;
+    const C<T> *__restrict__ in = a.in + (size_t)rhs * (a.in_rs ? a.in_rs : nv);
+    C<T> *__restrict__ out = a.out + (size_t)rhs * (a.out_rs ? a.out_rs : nv);
+    const C<T> *__restrict__ U = a.U;
+    const C<T> *__restrict__ v = a.v ? a.v + (size_t)rhs * (a.v_rs ? a.v_rs : nv) : nullptr;
+    const C<T> *__restrict__ rt = a.rt ? a.rt + (size_t)rhs * (a.rt_rs ? a.rt_rs : nv) : nullptr;
+    double2 *__restrict__ y = a.y ? a.y + (size_t)rhs * (a.y_rs ? a.y_rs : nv) : nullptr;
+    C<T> yc = mk<T>(0, 0);
+    if (EPI == EPI_MV_Y) yc = to_c<T>(ld(a.ycoef, rhs));
+    const T sig0 = a.sigma0_rhs ? (T)a.sigma0_rhs[rhs] : a.sigma0;
+    double part[3] = {0.0, 0.0, 0.0};
+    // a.sstride exceeds V, so the loop body runs at most once; keeping it a
+    // loop with a run-time bound stops the compiler from hoisting every load
+    // of the eight hops at once (which needs more than 256 VGPRs and spills)
+    for (int s = sblk * BLOCK + threadIdx.x; s < V; s += a.sstride) {
+        const int sxy = Lx * Ly, sxyz = Lx * Ly * Lz;
+        const int x = s % Lx;
+        const int r1 = s / Lx;
+        const int yy = r1 % Ly;
+        const int r2 = r1 / Ly;
+        const int z = r2 % Lz;
+        const int t = r2 / Lz;
+        C<T> acc[4][3];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[i][c] = mk<T>(0, 0);
+
+        int sf, sb;
+        sf = (x == Lx - 1) ? s - (Lx - 1) : s + 1;
+        sb = (x == 0) ? s + (Lx - 1) : s - 1;
+        hop<T, 0, -1, false, G5IN>(acc, in, U + (size_t)0 * 9 * V + s, V, V, sf, (T)1);
+        hop<T, 0, +1, true, G5IN>(acc, in, U + (size_t)0 * 9 * V + sb, V, V, sb, (T)1);
+        sf = (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx;
+        sb = (yy == 0) ? s + (Ly - 1) * Lx : s - Lx;
+        hop<T, 1, -1, false, G5IN>(acc, in, U + (size_t)1 * 9 * V + s, V, V, sf, (T)1);
+        hop<T, 1, +1, true, G5IN>(acc, in, U + (size_t)1 * 9 * V + sb, V, V, sb, (T)1);
+        sf = (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy;
+        sb = (z == 0) ? s + (Lz - 1) * sxy : s - sxy;
+        hop<T, 2, -1, false, G5IN>(acc, in, U + (size_t)2 * 9 * V + s, V, V, sf, (T)1);
+        hop<T, 2, +1, true, G5IN>(acc, in, U + (size_t)2 * 9 * V + sb, V, V, sb, (T)1);
+        sf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
+        sb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
+        const T ff = (t == Lt - 1) ? a.ef * a.bc : a.ef;
+        const T fb = (t == 0) ? a.eb * a.bc : a.eb;
+        hop<T, 3, -1, false, G5IN>(acc, in, U + (size_t)3 * 9 * V + s, V, V, sf, ff);
+        hop<T, 3, +1, true, G5IN>(acc, in, U + (size_t)3 * 9 * V + sb, V, V, sb, fb);
+
+        // out = scale * [gamma5] ((4+m) psi(x) - acc / 2), formed in place
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            C<T> ps[3];
+            load_spin<T, G5IN>(in, V, s, sp, ps);
+            const T sg = ((a.g5out && sp >= 2) ? (T)-1 : (T)1) * a.scale;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                acc[sp][c] = cscale(csub(cscale(ps[c], a.diag), cscale(acc[sp][c], (T)0.5)), sg);
+        }
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int k = 3 * sp + c;
+                C<T> o = acc[sp][c];
+                if (EPI != EPI_PLAIN) o = cadd(o, cscale(v[k * V + s], sig0));
+                out[k * V + s] = o;
+                if (EPI == EPI_MV) {
+                    const C<T> r = rt[k * V + s];
+                    part[0] += (double)r.x * o.x + (double)r.y * o.y;
+                    part[1] += (double)r.x * o.y - (double)r.y * o.x;
+                    part[2] += (double)o.x * o.x + (double)o.y * o.y;
+                }
+                if (EPI == EPI_MV_Y) {
+                    double2 yv = y[k * V + s];
+                    yv.x += (double)yc.x * o.x - (double)yc.y * o.y;
+                    yv.y += (double)yc.x * o.y + (double)yc.y * o.x;
+                    y[k * V + s] = yv;
+                }
+            }
+        }
+    }
+    if (EPI == EPI_MV)
+        wave_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + sblk * (BLOCK / 64) + (threadIdx.x >> 6),
+                             a.ps);
 }
+
 
 template <typename T, int L, bool XH, int J>
 __device__ __forceinline__ void exec_r_update_j(const POp &op, const VecArgs<T> &a) {
@@ -145,16 +237,16 @@ __device__ __forceinline__ void exec_op(const POp &op) {
     switch (op.kind) {
     case OP_DS: {
         const DslashArgs<T> *a = reinterpret_cast<const DslashArgs<T> *>(op.blob);
-        if (op.epi == EPI_PLAIN) VLOOP((call_dslash<T, EPI_PLAIN>(a, vb)))
-        else if (op.epi == EPI_MV) VLOOP((call_dslash<T, EPI_MV>(a, vb)))
-        else VLOOP((call_dslash<T, EPI_MV_Y>(a, vb)))
+        if (op.epi == EPI_PLAIN) VLOOP((dslash_persist_body<T, EPI_PLAIN, false>(*a, vb)))
+        else if (op.epi == EPI_MV) VLOOP((dslash_persist_body<T, EPI_MV, false>(*a, vb)))
+        else VLOOP((dslash_persist_body<T, EPI_MV_Y, false>(*a, vb)))
         break;
     }
     case OP_DS64: {
         if constexpr (XH) {
             const DslashArgs<double> *a = reinterpret_cast<const DslashArgs<double> *>(op.blob);
-            if (op.epi == EPI_PLAIN) VLOOP((call_dslash<double, EPI_PLAIN>(a, vb)))
-            else VLOOP((call_dslash<double, EPI_SV>(a, vb)))
+            if (op.epi == EPI_PLAIN) VLOOP((dslash_persist_body<double, EPI_PLAIN, false>(*a, vb)))
+            else VLOOP((dslash_persist_body<double, EPI_SV, false>(*a, vb)))
         }
         break;
     }
@@ -213,10 +305,8 @@ __device__ __forceinline__ void exec_op(const POp &op) {
     }
 }
 
-// Three wavefronts per SIMD (the stencil's own occupancy); the budget also
-// applies to the stages called out of line.
 template <typename T, int L>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_persistent(PersistArgs pa) {
+__global__ __launch_bounds__(BLOCK) void k_persistent(PersistArgs pa) {
     unsigned long long number = 0;
     const bool timer = pa.timing && blockIdx.x == 0 && threadIdx.x == 0;
     long long t0 = timer ? wall_clock64() : 0;
