@@ -39,15 +39,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def solver_flags(mixed, persistent):
+def solver_flags(mixed, persistent, refine=False):
     from paper_1010_2592_amd import msb
-    return (msb.MIXED if mixed else 0) | (msb.PERSISTENT if persistent else 0)
+    return (msb.MIXED if mixed else 0) | (msb.PERSISTENT if persistent else 0) | (msb.REFINE if refine else 0)
 
 
-def run_variant(ctx, b, a, sig, w, l, tol, max_outer, pass_, mixed, persistent=False, profile=False):
+def run_variant(ctx, b, a, sig, w, l, tol, max_outer, pass_, mixed, persistent=False, profile=False,
+                refine=False):
     import torch
     from paper_1010_2592_amd import msb
-    flags = solver_flags(mixed, persistent)
+    flags = solver_flags(mixed, persistent, refine)
     if profile:
         ctx.profile_enable(True)
     torch.cuda.synchronize()
@@ -226,12 +227,14 @@ def main():
     if args.variants == "all":
         comps = {}
         ref = None
-        for (p, mx, pe) in ((1, False, False), (2, False, False), (1, True, False), (2, True, False),
-                            (1, False, True), (2, False, True), (1, True, True), (2, True, True)):
-            name = f"{p}pass-{'mixed' if mx else 'fp64'}-{'persistent' if pe else 'stages'}"
+        for (p, mx, pe, rf) in ((1, False, False, False), (2, False, False, False), (1, True, False, False),
+                                (2, True, False, False), (1, True, False, True),
+                                (1, False, True, False), (2, False, True, False), (1, True, True, False),
+                                (2, True, True, False)):
+            name = f"{p}pass-{'mixed' if mx else 'fp64'}{'-refine' if rf else ''}-{'persistent' if pe else 'stages'}"
             try:
                 yv, iv, msv, pv = run_variant(ctx, b, a, sig, w, l, wk.tol, min(args.max_outer, 400), p,
-                                              mx, pe, profile=True)
+                                              mx, pe, profile=True, refine=rf)
             except msb.MsbError as e:
                 comps[name] = {"error": str(e)}
                 continue
@@ -243,6 +246,9 @@ def main():
                            "GBps_model": round(iv.bytes_model / (msv / 1e3) / 1e9, 1),
                            "rel_diff_vs_1pass_fp64": err,
                            "max_shift_resid": float(np.max(iv.shift_resid)),
+                           "max_true_resid": (float(np.max(iv.shift_true_resid))
+                                              if iv.shift_true_resid is not None else None),
+                           "refined_shifts": iv.refined_shifts,
                            "shift_update_GBps": (round(pv["shift_update"]["bytes"] / (pv["shift_update"]["ms"] / 1e3) / 1e9, 1)
                                                  if pv["shift_update"]["ms"] > 0 else None),
                            "stencil_GBps": (round(pv["stencil"]["bytes"] / (pv["stencil"]["ms"] / 1e3) / 1e9, 1)

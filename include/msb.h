@@ -69,6 +69,10 @@ typedef enum {
 #define MSB_PERSISTENT 16   /* whole solve in one cooperative launch (batched)   */
 #define MSB_OVERLAP   32    /* pfe_sign_apply: out = b + gamma5 sign(H) b        */
 #define MSB_ADJOINT   64    /* solve with A^+ = A(-mu) (used by the backward)    */
+#define MSB_REFINE    128   /* pass 1: after the solve, the FP64 true residual of
+                               every shift; shifts above tol get refinement
+                               solves (A + sigma_s) d = r_s, x_s += d (<= 3
+                               rounds) -- what makes MSB_MIXED reach tol      */
 
 typedef struct msb_ctx msb_ctx;
 
@@ -95,6 +99,7 @@ typedef struct {
     double *shift_true_resid; /* out (pass 1 only): ||b-(A+sigma_s)x_s||/||b||   */
     const int *force_iters; /* in, test hook: freeze shift s after exactly
                                force_iters[...] outer iterations (no early exit) */
+    int refined_shifts;     /* out (MSB_REFINE): (rhs, shift) refinement solves   */
 } msb_solve_info;
 
 /* Create a context on the current HIP device.  links: device pointer to
@@ -145,7 +150,7 @@ int wilson_apply(msb_ctx *ctx, const void *in, void *out, int nrhs, int flags);
  *   l                degree of the MR polynomial, 1..8
  *   pass             1: single-pass (N_s (l+1) shift vectors);
  *                    2: double-pass (no shift vectors, 4 M l Mv)
- *   flags            MSB_MIXED, MSB_PERSISTENT, MSB_ADJOINT
+ *   flags            MSB_MIXED, MSB_PERSISTENT, MSB_ADJOINT, MSB_REFINE (pass 1)
  *   b                device [nrhs][12][V] complex128
  *   y                device [nrhs][12][V] complex128 (written)
  *   x_shifts         device [nrhs][n_shift][12][V] complex128 or NULL

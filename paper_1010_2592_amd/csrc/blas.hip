@@ -136,6 +136,20 @@ __global__ __launch_bounds__(BLOCK) void k_shift_dots(const double2 *eta, const 
     block_reduce_store<2>(p, out + (size_t)rs * 2 * gridDim.x + blockIdx.x, gridDim.x);
 }
 
+__global__ __launch_bounds__(BLOCK) void k_residual(double2 *R, const double2 *b, long b_rs, const double2 *t, long n,
+                                                    double *part, long ps) {
+    const int rhs = blockIdx.y;
+    const double2 *br = b + (size_t)rhs * b_rs, *tr = t + (size_t)rhs * n;
+    double2 *Rr = R + (size_t)rhs * n;
+    double p[1] = {0.0};
+    for (long e = (long)blockIdx.x * BLOCK + threadIdx.x; e < n; e += (long)gridDim.x * BLOCK) {
+        const double2 r = csub(br[e], tr[e]);
+        Rr[e] = r;
+        p[0] += r.x * r.x + r.y * r.y;
+    }
+    block_reduce_store<1>(p, part + (size_t)rhs * PMAX * ps + blockIdx.x, ps);
+}
+
 __global__ void k_yinit(double2 *y, const double2 *b, const double2 *c, long n) {
     const int rhs = blockIdx.y;
     const double2 cc = c[rhs];
@@ -260,6 +274,10 @@ void launch_diffnorm_partials(hipStream_t st, const C<T> *x, const C<T> *y, long
 }
 void launch_ysum(hipStream_t st, double2 *y, const double2 *X, const double *w, long n, int ns, int nrhs, int nblk) {
     hipLaunchKernelGGL(k_ysum, dim3(nblk, nrhs), dim3(BLOCK), 0, st, y, X, w, n, ns);
+}
+void launch_residual(hipStream_t st, double2 *R, const double2 *b, long b_rs, const double2 *t, long n,
+                     double *part, long ps, int nrhs, int nblk) {
+    hipLaunchKernelGGL(k_residual, dim3(nblk, nrhs), dim3(BLOCK), 0, st, R, b, b_rs, t, n, part, ps);
 }
 void launch_yinit(hipStream_t st, double2 *y, const double2 *b, const double2 *c, long n, int nrhs, int nblk) {
     hipLaunchKernelGGL(k_yinit, dim3(nblk, nrhs), dim3(BLOCK), 0, st, y, b, c, n);

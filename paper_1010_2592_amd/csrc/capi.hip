@@ -45,8 +45,10 @@ int make_params(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
     if (max_outer < 1 || (long)max_outer * l > (1L << 24)) return arg_error(w + ": max_outer out of range");
     if (pass != 1 && pass != 2) return arg_error(w + ": pass must be 1 or 2");
     if (nrhs < 1 || nrhs > 4096) return arg_error(w + ": nrhs must be in 1..4096");
-    if (flags & ~(MSB_MIXED | MSB_PERSISTENT | MSB_ADJOINT | MSB_OVERLAP))
+    if (flags & ~(MSB_MIXED | MSB_PERSISTENT | MSB_ADJOINT | MSB_OVERLAP | MSB_REFINE))
         return arg_error(w + ": unknown flag bits");
+    if ((flags & MSB_REFINE) && pass != 1)
+        return arg_error(w + ": MSB_REFINE needs pass = 1 (the double pass keeps no shift solutions)");
     if ((flags & MSB_PERSISTENT) && l > msb::PERSIST_LMAX)
         return arg_error(w + ": MSB_PERSISTENT needs l <= " + std::to_string(msb::PERSIST_LMAX));
     const long nsets = per_rhs ? nrhs : 1;
@@ -61,6 +63,7 @@ int make_params(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
     P->mixed = (flags & MSB_MIXED) != 0;
     P->neg_mu = (flags & MSB_ADJOINT) != 0;
     P->persistent = (flags & MSB_PERSISTENT) != 0;
+    P->refine = (flags & MSB_REFINE) != 0;
     P->nrhs = nrhs;
     P->shifts.resize((size_t)nrhs * n_shift);
     P->weights.resize((size_t)nrhs * n_shift);
@@ -84,6 +87,7 @@ void fill_info(msb_solve_info *info, const msb::SolveReport &R, int nrhs, int n_
     info->axpy_count = R.axpys;
     info->reliable_updates = R.reliable;
     info->bytes_model = R.bytes_model;
+    info->refined_shifts = R.refined;
     const size_t m = (size_t)nrhs * n_shift;
     if (info->shift_iters && R.shift_iters.size() == m)
         std::memcpy(info->shift_iters, R.shift_iters.data(), m * sizeof(int));

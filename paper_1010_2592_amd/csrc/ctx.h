@@ -27,7 +27,7 @@ struct Ctx {
     DevBuf ws_R, ws_U, ws_tmp, ws_W, ws_X, ws_rt, ws_b, ws_y, ws_part, ws_seed, ws_shift, ws_sc,
         ws_mc, ws_tape, ws_tape_gam, ws_tape_outer, ws_replay, ws_replay_outer, ws_wts, ws_sig0,
         ws_cb, ws_aux1, ws_aux2, ws_aux3, ws_aux4, ws_bX, ws_bZ, ws_by, ws_beta, ws_bA, ws_bB, ws_bdots,
-        ws_ops, ws_pctl;
+        ws_ops, ws_pctl, ws_rX, ws_rX2, ws_ry, ws_rB, ws_rR, ws_rt1, ws_rt2, ws_rsig, ws_rw;
     int pgrid[32] = {};        // co-resident grid of the persistent kernel, per (precision, l)
     void *host_pinned = nullptr;
     size_t host_pinned_bytes = 0;
@@ -79,11 +79,13 @@ struct SolveParams {
     std::vector<double> weights;   // [nrhs][n_shift]
     int l = 1;
     double tol = 1e-8;
+    std::vector<double> tol_rhs;       // optional per-rhs tolerance (overrides tol)
     int max_outer = 1000;
     int pass = 1;
     bool mixed = false;
     bool neg_mu = false;
     bool persistent = false;           // one cooperative launch per pass
+    bool refine = false;               // pass 1: refine shifts above tol (true residual)
     int nrhs = 1;
     const int *force_iters = nullptr;   // [nrhs][n_shift] or null
 };
@@ -98,6 +100,7 @@ struct SolveReport {
     std::vector<double> shift_resid;
     std::vector<double> shift_true_resid;
     std::vector<int> rhs_outer;
+    int refined = 0;                   // (rhs, shift) refinement solves
 };
 
 // status-returning helpers; on failure they record a message

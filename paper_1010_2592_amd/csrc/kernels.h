@@ -151,6 +151,10 @@ void launch_ysum(hipStream_t, double2 *y, const double2 *X, const double *w, lon
 // out[((rhs * ns + s) * 2 + k) * nblk + block]
 void launch_shift_dots(hipStream_t, const double2 *eta, const double2 *X, const double2 *Z, long n, int ns,
                        int nrhs, int nblk, double *out);
+// R[rhs] = b[rhs] - t[rhs] (b rows b_rs apart, t and R rows n apart),
+// partial slot 0 = ||R||^2
+void launch_residual(hipStream_t, double2 *R, const double2 *b, long b_rs, const double2 *t, long n,
+                     double *part, long ps, int nrhs, int nblk);
 // y[rhs] = c[rhs] * b[rhs]
 void launch_yinit(hipStream_t, double2 *y, const double2 *b, const double2 *c, long n, int nrhs,
                   int nblk);

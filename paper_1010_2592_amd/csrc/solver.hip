@@ -747,7 +747,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         sig0[r] = *std::min_element(sg, sg + ns);
         SeedState &S = hs[r];
         std::memset(&S, 0, sizeof(S));
-        S.tol = P.tol;
+        S.tol = P.tol_rhs.empty() ? P.tol : P.tol_rhs[r];
         S.nshift = ns;
         S.max_outer = max_outer;
         S.max_steps = max_steps;
@@ -1184,8 +1184,171 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Refinement of a single-pass solve (MSB_REFINE).  The collinear residual
+// estimate that freezes a shift is the iteration's recursive residual; in
+// FP32 arithmetic the true residual b - (A + sigma_s) x_s stalls near
+// eps_32 kappa(A + sigma_s) above it.  After the solve, every shift's true
+// residual is computed in FP64; each (rhs, shift) above tol gets a correction
+// solve (A + sigma_s) d = r_s, batched with one shift per batch member, to the
+// relative tolerance that brings it below tol with a factor 2 to spare, and
+// x_s += d in FP64.  At most three rounds; then y = sum_s w_s x_s again.
+// ---------------------------------------------------------------------------
+static int run_solve(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2 *xs, SolveReport *rep) {
+    if (P.mixed) return solve_impl<float>(c, P, b, y, xs, false, rep);
+    return solve_impl<double>(c, P, b, y, xs, false, rep);
+}
+
+static int solve_refined(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2 *x_shifts,
+                         SolveReport *rep) {
+    constexpr int KMAX = 48;        // correction solves per batch
+    constexpr int ROUNDS = 3;
+    const int V = c->g.V;
+    const long n = 12L * V;
+    const int nrhs = P.nrhs, ns = P.n_shift;
+    const int nbv = nblocks_for(n);
+    const long ps = part_stride(c->g);
+    hipStream_t st = c->stream;
+    double2 *X = x_shifts;
+    if (!X) {
+        CHK(ensure(c->ws_rX, (size_t)nrhs * ns * n * sizeof(double2)));
+        X = (double2 *)c->ws_rX.p;
+    }
+    SolveParams P0 = P;
+    P0.refine = false;
+    CHK(run_solve(c, P0, b, y, X, rep));
+    double bytes = rep->bytes_model;
+    if (rep->status == S_ERR_ARG) return 0;
+
+    CHK(ensure(c->ws_rt1, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c->ws_rt2, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c->ws_rR, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c->ws_rB, (size_t)KMAX * n * sizeof(double2)));
+    CHK(ensure(c->ws_rX2, (size_t)KMAX * n * sizeof(double2)));
+    CHK(ensure(c->ws_ry, (size_t)KMAX * n * sizeof(double2)));
+    CHK(ensure(c->ws_rsig, (size_t)nrhs * ns * sizeof(double)));
+    CHK(ensure(c->ws_rw, (size_t)nrhs * ns * sizeof(double)));
+    double2 *t1 = (double2 *)c->ws_rt1.p, *t2 = (double2 *)c->ws_rt2.p, *R = (double2 *)c->ws_rR.p;
+    double2 *RB = (double2 *)c->ws_rB.p, *DX = (double2 *)c->ws_rX2.p, *DY = (double2 *)c->ws_ry.p;
+    // shifts by shift then rhs (the per-rhs sigma of one residual launch)
+    std::vector<double> sig_sr((size_t)ns * nrhs);
+    for (int r = 0; r < nrhs; ++r)
+        for (int s = 0; s < ns; ++s) sig_sr[(size_t)s * nrhs + r] = P.shifts[(size_t)r * ns + s];
+    double *sig_dev = (double *)c->ws_rsig.p;
+    HIPCHK(hipMemcpyAsync(sig_dev, sig_sr.data(), sig_sr.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->ws_rw.p, P.weights.data(), (size_t)nrhs * ns * sizeof(double), hipMemcpyHostToDevice,
+                          st));
+
+    // ||b_r||
+    std::vector<double> bnorm(nrhs);
+    // ||.|| per rhs from partial slot `slot`: the nbv partials of every rhs in
+    // one strided copy
+    std::vector<double> rows((size_t)std::max(nrhs, KMAX) * nbv);
+    auto read_norms = [&](int nr, int slot, std::vector<double> &out) -> int {
+        out.assign(nr, 0.0);
+        HIPCHK(hipMemcpy2DAsync(rows.data(), nbv * sizeof(double),
+                                (double *)c->ws_part.p + (size_t)slot * ps, (size_t)PMAX * ps * sizeof(double),
+                                nbv * sizeof(double), nr, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int r = 0; r < nr; ++r) out[r] = std::sqrt(host_partial_sum(&rows[(size_t)r * nbv], nbv));
+        return 0;
+    };
+    CHK(ensure(c->ws_part, (size_t)std::max(nrhs, KMAX) * PMAX * ps * sizeof(double)));
+    double *part = (double *)c->ws_part.p;
+    launch_dot_partials<double>(st, b, b, n, part, ps, nrhs, nbv, Gate{});
+    CHK(read_norms(nrhs, 2, bnorm));
+
+    const double Vd = (double)V;
+    // R = b - (a H^2 + sigma_s) x_s for every rhs of shift s; returns ||R_r||
+    auto residuals = [&](int s, std::vector<double> &rn) -> int {
+        DslashArgs<double> d1 = ds_args<double>(c, P.neg_mu, true);
+        d1.in = X + (size_t)s * n;
+        d1.in_rs = (long)ns * n;
+        d1.out = t1;
+        launch_dslash<double>(st, d1, nrhs, EPI_PLAIN, false);
+        DslashArgs<double> d2 = ds_args<double>(c, P.neg_mu, true);
+        d2.in = t1;
+        d2.out = t2;
+        d2.v = X + (size_t)s * n;
+        d2.v_rs = (long)ns * n;
+        d2.scale = P.a_scale;
+        d2.sigma0_rhs = sig_dev + (size_t)s * nrhs;
+        launch_dslash<double>(st, d2, nrhs, EPI_SV, false);
+        launch_residual(st, R, b, n, t2, n, part, ps, nrhs, nbv);
+        HIPCHK(hipGetLastError());
+        bytes += nrhs * (24 + 36 + 48) * 16.0 * Vd + 2 * 36 * 16.0 * Vd;
+        rep->mv += nrhs;
+        return read_norms(nrhs, 0, rn);
+    };
+
+    struct Pair { int r, s; double rn; };
+    std::vector<Pair> batch;
+    auto flush = [&]() -> int {
+        if (batch.empty()) return 0;
+        const int K = (int)batch.size();
+        SolveParams Q = P0;
+        Q.nrhs = K;
+        Q.n_shift = 1;
+        Q.shifts.resize(K);
+        Q.weights.assign(K, 1.0);
+        Q.force_iters = nullptr;
+        Q.persistent = false;
+        // each correction to its own relative tolerance (factor 2 to spare)
+        Q.tol_rhs.resize(K);
+        for (int k = 0; k < K; ++k) {
+            Q.shifts[k] = P.shifts[(size_t)batch[k].r * ns + batch[k].s];
+            const double q = 0.5 * P.tol * bnorm[batch[k].r] / batch[k].rn;
+            Q.tol_rhs[k] = std::min(0.5, std::max(q, P.tol));
+        }
+        SolveReport r2;
+        CHK(run_solve(c, Q, RB, DY, DX, &r2));
+        bytes += r2.bytes_model;
+        rep->mv += r2.mv;
+        rep->dots += r2.dots;
+        rep->reliable += r2.reliable;
+        for (int k = 0; k < K; ++k)
+            launch_axpy_host(st, X + ((size_t)batch[k].r * ns + batch[k].s) * n, DX + (size_t)k * n, d2(1, 0), n,
+                             nbv);
+        HIPCHK(hipGetLastError());
+        rep->refined += K;
+        batch.clear();
+        return 0;
+    };
+
+    rep->shift_true_resid.assign((size_t)nrhs * ns, 0.0);
+    std::vector<double> rn;
+    for (int round = 0; round <= ROUNDS; ++round) {
+        int failing = 0;
+        for (int s = 0; s < ns; ++s) {
+            CHK(residuals(s, rn));
+            for (int r = 0; r < nrhs; ++r) {
+                const double rel = bnorm[r] > 0 ? rn[r] / bnorm[r] : 0.0;
+                rep->shift_true_resid[(size_t)r * ns + s] = rel;
+                if (!(rel <= P.tol)) {
+                    failing += 1;
+                    if (round == ROUNDS || !std::isfinite(rel)) continue;   // last round: report only
+                    HIPCHK(hipMemcpyAsync(RB + batch.size() * n, R + (size_t)r * n, n * sizeof(double2),
+                                          hipMemcpyDeviceToDevice, st));
+                    batch.push_back(Pair{r, s, rn[r]});
+                    if ((int)batch.size() == KMAX) CHK(flush());
+                }
+            }
+        }
+        CHK(flush());
+        if (failing == 0) break;
+        if (round == ROUNDS && rep->status == S_OK) rep->status = S_NOT_CONVERGED;
+    }
+    launch_ysum(st, y, X, (const double *)c->ws_rw.p, n, ns, nrhs, nbv);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    rep->bytes_model = bytes;
+    c->bytes_acc = bytes;
+    return 0;
+}
+
 int solve_mshift(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2 *x_shifts,
                  bool want_true_resid, SolveReport *rep) {
+    if (P.refine && P.pass == 1) return solve_refined(c, P, b, y, x_shifts, rep);
     if (P.mixed) return solve_impl<float>(c, P, b, y, x_shifts, want_true_resid, rep);
     return solve_impl<double>(c, P, b, y, x_shifts, want_true_resid, rep);
 }

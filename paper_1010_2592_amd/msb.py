@@ -23,12 +23,12 @@ __all__ = [
     "MsbError", "Lattice", "SolveInfo", "Context", "lib", "library_path",
     "neuberger_pfe", "wilson_apply", "mshift_bicgstabl", "pfe_sign_apply",
     "pfe_sign_backward", "spectral_radius",
-    "G5_LEFT", "NEG_MU", "DAGGER", "MIXED", "PERSISTENT", "OVERLAP", "ADJOINT",
+    "G5_LEFT", "NEG_MU", "DAGGER", "MIXED", "PERSISTENT", "OVERLAP", "ADJOINT", "REFINE",
     "OK", "ERR_ARG", "ERR_HIP", "ERR_OOM", "NOT_CONVERGED", "BREAKDOWN",
 ]
 
 OK, ERR_ARG, ERR_HIP, ERR_OOM, NOT_CONVERGED, BREAKDOWN = 0, 1, 2, 3, 4, 5
-G5_LEFT, NEG_MU, DAGGER, MIXED, PERSISTENT, OVERLAP, ADJOINT = 1, 2, 4, 8, 16, 32, 64
+G5_LEFT, NEG_MU, DAGGER, MIXED, PERSISTENT, OVERLAP, ADJOINT, REFINE = 1, 2, 4, 8, 16, 32, 64, 128
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -56,7 +56,8 @@ class _Info(ctypes.Structure):
                 ("shift_iters", ctypes.POINTER(ctypes.c_int)),
                 ("shift_resid", ctypes.POINTER(ctypes.c_double)),
                 ("shift_true_resid", ctypes.POINTER(ctypes.c_double)),
-                ("force_iters", ctypes.POINTER(ctypes.c_int))]
+                ("force_iters", ctypes.POINTER(ctypes.c_int)),
+                ("refined_shifts", ctypes.c_int)]
 
 
 _LIB = None
@@ -148,6 +149,7 @@ class SolveInfo:
     shift_iters: np.ndarray
     shift_resid: np.ndarray
     shift_true_resid: Optional[np.ndarray]
+    refined_shifts: int = 0
 
 
 def neuberger_pfe(n: int):
@@ -242,7 +244,7 @@ class Context:
         return SolveInfo(info.status, info.outer_iters, info.bicg_steps, info.mv_count,
                          info.dot_count, info.axpy_count, info.reliable_updates, info.bytes_model,
                          it.reshape(nrhs, ns).copy(), rs.reshape(nrhs, ns).copy(),
-                         None if tr is None else tr.reshape(nrhs, ns).copy())
+                         None if tr is None else tr.reshape(nrhs, ns).copy(), info.refined_shifts)
 
     def mshift_bicgstabl(self, b: torch.Tensor, a_scale: float, shifts, weights, l: int,
                          tol: float, max_outer: int, pass_: int = 1, flags: int = 0,
@@ -260,7 +262,7 @@ class Context:
         y = torch.empty_like(b)
         xs = torch.zeros((nrhs, ns, 12, self.V), dtype=torch.complex128, device=b.device) \
             if want_shifts else None
-        info, keep = self._info(nrhs, ns, force_iters, true_resid)
+        info, keep = self._info(nrhs, ns, force_iters, true_resid or bool(flags & REFINE))
         self._sync_stream()
         rc = lib().mshift_bicgstabl(self._h, float(a_scale), ns, _dptr(sh), _dptr(wt), per, int(l),
                                     float(tol), int(max_outer), int(pass_), int(flags), nrhs,

@@ -264,3 +264,42 @@ def test_production_lattice_fixed_iterations():
         y, info, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 2, wk.tol, 2, pass_, force_iters=force,
                                           allow=(msb.OK, msb.NOT_CONVERGED))
         assert rel(host(y)[0], ref) <= 1e-10, pass_
+
+
+@pytest.mark.parametrize("name", ["4x4x4x8", "8x8x8x8"])
+def test_mixed_precision_refined_meets_tolerance(name):
+    """Mixed single pass with MSB_REFINE: every shift's true residual
+    ||b - (A + sigma_s) x_s|| / ||b|| -- recomputed here with the oracle's
+    operator from the returned x_s -- is at most tol, and y agrees with the
+    FP64 oracle's f(A) b to the level the tolerance allows."""
+    from paper_1010_2592_amd import msb
+    wk, U, op, a, sig, w, b = problem(name)
+    l = wk.ells[0]
+    bb = wl.gaussian_source(wk.dims, 88, 3)
+    log(f"mixed + refine {name}")
+    ctx = ctx_for(wk, U)
+    y, info, xs = ctx.mshift_bicgstabl(cuda(bb), a, sig, w, l, wk.tol, 3000, 1, flags=msb.MIXED | msb.REFINE,
+                                       want_shifts=True)
+    xs = host(xs)
+    worst = 0.0
+    for r in range(3):
+        nb = np.linalg.norm(bb[r])
+        for s_ in range(len(sig)):
+            res = np.linalg.norm(bb[r] - op.a_op(xs[r, s_], a) - sig[s_] * xs[r, s_]) / nb
+            worst = max(worst, res)
+            assert res <= wk.tol * 1.05, (r, s_, res)
+            assert abs(res - info.shift_true_resid[r, s_]) <= 1e-3 * wk.tol + 1e-6 * res
+    y_ref = oracle_run(op, a, bb[0], sig, w, l, wk.tol * 1e-2, 3000, 1)[0]
+    err = rel(host(y)[0], y_ref)
+    log(f"  worst true residual {worst:.2e}, refined (rhs, shift) solves {info.refined_shifts}, "
+        f"y vs FP64 oracle (tol/100) {err:.2e}")
+    assert err <= 1e-6
+
+
+def test_refine_needs_single_pass():
+    from paper_1010_2592_amd import msb
+    wk, U, op, a, sig, w, b = problem("4x4x4x8")
+    ctx = ctx_for(wk, U)
+    with pytest.raises(msb.MsbError) as e:
+        ctx.mshift_bicgstabl(cuda(b), a, sig, w, 2, wk.tol, 100, 2, flags=msb.MIXED | msb.REFINE)
+    assert e.value.status == msb.ERR_ARG
