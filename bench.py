@@ -8,12 +8,16 @@ spin-colour point sources at the origin solved as one batch; tolerance 1e-8 on
 every shift's relative residual.
 
 One step = one f(A) b evaluation of the 12-source batch in the headline form
-(--pass, --precision).  ``value`` is f(A) b evaluations (one per source) per
-second over the K timed steps.  Every kernel launch inside the timed steps is
+(--pass, --precision, --refine).  The default is the single pass in mixed
+precision (FP32 stencil and vectors, FP64 reductions, accumulators and
+reliable updates) with per-shift refinement, so that every shift's FP64 true
+residual meets the tolerance.  ``value`` is f(A) b evaluations (one per
+source) per second over the K timed steps.  Every kernel launch inside the timed steps is
 bracketed by HIP events on its stream (the library's timing hook); the stencil
 kernel's algorithmic bytes over its summed event time give roofline.achieved.
-The other forms (single-pass / double-pass, FP64 / mixed) run once each
-afterwards for the comparison block.  The CPU oracle is timed on a bounded
+The other forms (single-pass / double-pass, FP64 / mixed, per-stage
+launches / one persistent launch) run once each afterwards for the
+comparison block.  The CPU oracle is timed on a bounded
 sample (one outer iteration of one source) and extrapolated.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -65,19 +69,23 @@ def run_variant(ctx, b, a, sig, w, l, tol, max_outer, pass_, mixed, persistent=F
     return y, info, e0.elapsed_time(e1), prof
 
 
-def measured_traffic(pass_, precision):
-    """HBM bytes per stencil launch from the committed rocprofv3 counter runs,
-    or None when the stencil source changed since they were taken or the
-    form differs from the one they were taken on."""
-    import hashlib
+def workload_key(pass_, precision, refine, persistent):
+    return (f"{WORKLOAD} 12 rhs {precision} pass {pass_}" + (" refine" if refine else "")
+            + (" persistent" if persistent else ""))
+
+
+def measured_traffic(key):
+    """HBM bytes per stencil launch from the committed rocprofv3 counter runs
+    (profiles/dslash_traffic.json), or None when the stencil sources changed
+    since they were taken or the form differs from the one they were taken on."""
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "dslash_traffic.json")))
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        from paper_1010_2592_amd.rocprof_summary import sources_hash
+        if sources_hash(rec["sources"]) != rec.get("sources_sha256_16"):
+            return None
     except (OSError, ValueError, KeyError):
         return None
-    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
-        return None
-    if rec.get("workload") != f"{WORKLOAD.replace('x', 'x')} 12 rhs {precision} pass {pass_}":
+    if rec.get("workload") != key:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -109,8 +117,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--pass", dest="pass_", type=int, default=2, choices=(1, 2))
-    ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
+    ap.add_argument("--pass", dest="pass_", type=int, default=1, choices=(1, 2))
+    ap.add_argument("--precision", default="mixed", choices=("fp64", "mixed"))
+    ap.add_argument("--refine", default="auto", choices=("auto", "on", "off"),
+                    help="per-shift FP64 true residual + refinement (pass 1); auto: on for pass 1")
     ap.add_argument("--launch", default="stages", choices=("stages", "persistent"),
                     help="one launch per stage, or the whole pass in one cooperative launch")
     ap.add_argument("--variants", default="all", choices=("all", "none"))
@@ -152,10 +162,12 @@ def main():
     sig, w = msb.neuberger_pfe(wk.n_shift)
     mixed = args.precision == "mixed"
     persistent = args.launch == "persistent"
+    refine = args.pass_ == 1 and (args.refine == "on" or (args.refine == "auto" and mixed))
     log(f"[bench] spectral radius {rho:.6f}; headline pass={args.pass_} {args.precision} {args.launch}")
 
     for i in range(args.warmup):
-        _, info, ms, _ = run_variant(ctx, b, a, sig, w, l, wk.tol, args.max_outer, args.pass_, mixed, persistent)
+        _, info, ms, _ = run_variant(ctx, b, a, sig, w, l, wk.tol, args.max_outer, args.pass_, mixed, persistent,
+                                     refine=refine)
         log(f"[bench] warmup {i}: {ms:.1f} ms, M={info.outer_iters}, status {info.status}")
 
     # ---- timed steps (library timing hook on) ----
@@ -169,7 +181,7 @@ def main():
     y = None
     for k in range(args.steps):
         y, info, _ = ctx.mshift_bicgstabl(b, a, sig, w, l, wk.tol, args.max_outer, args.pass_,
-                                          flags=solver_flags(mixed, persistent),
+                                          flags=solver_flags(mixed, persistent, refine),
                                           allow=(msb.OK, msb.NOT_CONVERGED))
         infos.append(info)
     e1.record()
@@ -202,18 +214,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if not mixed else "f32+f64",
+        "dtype": "f64" if not mixed else "f32+f64",   # mixed: FP32 stencil/vectors, FP64 reductions/accumulators
         "data": "synthetic",
         "config": {"workload": f"{WORKLOAD} Wilson-Dirac mu=0.05 m=-2, 12 point sources, "
                                f"Neuberger N_s={wk.n_shift}, BiCGstab(l={l}), tol {wk.tol}",
-                   "pass": args.pass_, "precision": args.precision, "launch": args.launch, "rhs": nrhs,
+                   "pass": args.pass_, "precision": args.precision, "refine": refine, "launch": args.launch,
+                   "rhs": nrhs,
                    "n_shift": wk.n_shift, "l": l, "outer_iters": info.outer_iters,
                    "mv_count": info.mv_count, "status": info.status,
-                   "max_shift_resid": float(np.max(info.shift_resid))},
+                   "max_shift_resid": float(np.max(info.shift_resid)),
+                   "max_true_resid": (float(np.max(info.shift_true_resid))
+                                      if info.shift_true_resid is not None else None),
+                   "refined_shifts": info.refined_shifts},
         "hbm_GBps_whole_call": round(info.bytes_model / (ms_step / 1e3) / 1e9, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.pass_, args.precision),
+                     "traffic": measured_traffic(workload_key(args.pass_, args.precision, refine, persistent)),
                      "kernel": "dslash (Wilson stencil, all epilogues)",
                      "launches": st["count"],
                      "avg_launch_us": round(st["ms"] * 1e3 / max(st["count"], 1), 2),

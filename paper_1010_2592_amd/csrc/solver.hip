@@ -639,8 +639,8 @@ static int run_persistent(Ctx *c, const std::vector<POp> &ops, int iters, bool l
     pa.ctl = (PersistCtl *)c->ws_pctl.p;
     HIPCHK(launch_persistent<T>(st, pa, grid, l));
     PersistCtl host;
-    HIPCHK(hipMemcpyAsync(&host, c->ws_pctl.p, sizeof(PersistCtl), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(&host, c->ws_pctl.p, sizeof(PersistCtl), hipMemcpyDeviceToHost));
     if (host.abort) return set_error(S_ERR_HIP, "persistent launch: a grid barrier wait exceeded its bound");
     if (c->prof) {
         int khz = 0;
@@ -1170,9 +1170,9 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             launch_diffnorm_partials<double>(st, b, t2, n, n, n, part, ps, nrhs, nbv);
             HIPCHK(hipGetLastError());
             for (int r = 0; r < nrhs; ++r) {
-                HIPCHK(hipMemcpyAsync(rowbuf.data(), part + (size_t)r * PMAX * ps, ps * sizeof(double),
-                                      hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));
+                HIPCHK(hipMemcpy(rowbuf.data(), part + (size_t)r * PMAX * ps, ps * sizeof(double),
+                                 hipMemcpyDeviceToHost));
                 const double d = std::sqrt(host_partial_sum(rowbuf.data(), nbv));
                 rep->shift_true_resid[(size_t)r * ns + s] = d / fs[r].bnorm;
             }
@@ -1242,13 +1242,15 @@ static int solve_refined(Ctx *c, const SolveParams &P, const double2 *b, double2
     // ||b_r||
     std::vector<double> bnorm(nrhs);
     // ||.|| per rhs from partial slot `slot`: the nbv partials of every rhs in
-    // one strided copy
-    std::vector<double> rows((size_t)std::max(nrhs, KMAX) * nbv);
+    // one strided copy into pinned host memory (a stream-ordered DMA; the
+    // synchronisation below then covers it)
     auto read_norms = [&](int nr, int slot, std::vector<double> &out) -> int {
         out.assign(nr, 0.0);
-        HIPCHK(hipMemcpy2DAsync(rows.data(), nbv * sizeof(double),
-                                (double *)c->ws_part.p + (size_t)slot * ps, (size_t)PMAX * ps * sizeof(double),
-                                nbv * sizeof(double), nr, hipMemcpyDeviceToHost, st));
+        CHK(ensure_host(c, (size_t)nr * nbv * sizeof(double)));
+        double *rows = (double *)c->host_pinned;
+        HIPCHK(hipMemcpy2DAsync(rows, nbv * sizeof(double), (double *)c->ws_part.p + (size_t)slot * ps,
+                                (size_t)PMAX * ps * sizeof(double), nbv * sizeof(double), nr,
+                                hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         for (int r = 0; r < nr; ++r) out[r] = std::sqrt(host_partial_sum(&rows[(size_t)r * nbv], nbv));
         return 0;
@@ -1322,7 +1324,9 @@ static int solve_refined(Ctx *c, const SolveParams &P, const double2 *b, double2
         for (int s = 0; s < ns; ++s) {
             CHK(residuals(s, rn));
             for (int r = 0; r < nrhs; ++r) {
-                const double rel = bnorm[r] > 0 ? rn[r] / bnorm[r] : 0.0;
+                // a zero right-hand side has x_s = 0 and a zero residual; any
+                // other residual of it counts as failing
+                const double rel = bnorm[r] > 0 ? rn[r] / bnorm[r] : (rn[r] > 0 ? INFINITY : 0.0);
                 rep->shift_true_resid[(size_t)r * ns + s] = rel;
                 if (!(rel <= P.tol)) {
                     failing += 1;
@@ -1425,7 +1429,8 @@ int sign_backward(Ctx *c, const SolveParams &P0, const double2 *b, const double2
     launch_shift_dots(st, etap, X, Z, n, ns, nrhs, nbv, (double *)c->ws_bdots.p);
     HIPCHK(hipGetLastError());
     std::vector<double> dots((size_t)nrhs * ns * 2 * nbv);
-    HIPCHK(hipMemcpyAsync(dots.data(), c->ws_bdots.p, dots.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(dots.data(), c->ws_bdots.p, dots.size() * sizeof(double), hipMemcpyDeviceToHost));
     HIPCHK(hipStreamSynchronize(st));
     for (int s = 0; s < ns; ++s) {
         double gw = 0.0, gs = 0.0;

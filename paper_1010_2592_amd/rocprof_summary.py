@@ -1,0 +1,148 @@
+"""Summaries of rocprofv3 runs of bench.py for profiles/.
+
+    python -m paper_1010_2592_amd.rocprof_summary --trace T.db --fetch F.db --write W.db \
+        --bench-json B.json --workload "16x16x16x32 12 rhs mixed pass 1 refine" \
+        --md profiles/X.md --json profiles/dslash_traffic.json --cmd-trace "..." --cmd-fetch "..." --cmd-write "..."
+
+Inputs are the rocpd databases rocprofv3 writes (-d DIR -o NAME gives
+DIR/NAME_results.db) of three runs of the same bench command: a kernel trace
+with --stats, a FETCH_SIZE counter run and a WRITE_SIZE counter run (each
+counter in a run of its own).  The counter runs include bench.py
+--calibrate-copy: three copies of a 1 GiB tensor, whose counter readings give
+the factor from counter units to bytes (1048576 KiB read and written).
+
+Outputs: a markdown summary (kernel table, stencil launch statistics, HBM
+bytes per stencil launch against the algorithmic bytes) and the JSON record
+bench.py reads for roofline.traffic, keyed by a hash of the stencil sources
+so that it lapses when the stencil changes.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sqlite3
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+STENCIL_SOURCES = ["paper_1010_2592_amd/csrc/stencil_dev.h", "paper_1010_2592_amd/csrc/dslash.hip"]
+COPY_KIB = 1048576.0
+
+
+def sources_hash(paths=STENCIL_SOURCES) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def is_stencil(name: str) -> bool:
+    return "dslash" in name and "link_force" not in name
+
+
+def short(name: str) -> str:
+    return name.replace("msb::(anonymous namespace)::", "").replace("msb::", "")
+
+
+def kernel_rows(db):
+    cur = sqlite3.connect(db).cursor()
+    return cur.execute("select name, count(*), avg(end - start), sum(end - start) from kernels "
+                       "group by name order by sum(end - start) desc").fetchall()
+
+
+def stencil_launches(db):
+    cur = sqlite3.connect(db).cursor()
+    return [(n, e - s) for n, s, e in cur.execute("select name, start, end from kernels").fetchall() if is_stencil(n)]
+
+
+def counter_values(db, counter):
+    cur = sqlite3.connect(db).cursor()
+    return cur.execute("select kernel_name, dispatch_id, value from counters_collection where counter_name = ? "
+                       "order by dispatch_id", (counter,)).fetchall()
+
+
+def scale(rows):
+    """Counter units per byte from the 1 GiB copies (the three largest copy dispatches)."""
+    copies = sorted((v for n, d, v in rows if "copyBuffer" in n), reverse=True)[:3]
+    if not copies:
+        return None
+    return COPY_KIB / (sum(copies) / len(copies))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--bench-json", required=True, help="bench.py output line of the trace run")
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--md", required=True)
+    ap.add_argument("--json", required=True)
+    ap.add_argument("--cmd-trace", required=True)
+    ap.add_argument("--cmd-fetch", required=True)
+    ap.add_argument("--cmd-write", required=True)
+    ap.add_argument("--top", type=int, default=18)
+    a = ap.parse_args()
+
+    bench = json.loads(open(a.bench_json).read().strip().splitlines()[-1])
+    rows = kernel_rows(a.trace)
+    tot = sum(r[3] for r in rows)
+    st = stencil_launches(a.trace)
+    st_avg_us = sum(d for _, d in st) / len(st) / 1e3
+    fr = counter_values(a.fetch, "FETCH_SIZE")
+    wr = counter_values(a.write, "WRITE_SIZE")
+    fs, ws = scale(fr), scale(wr)
+    f_st = [v for n, d, v in fr if is_stencil(n)]
+    w_st = [v for n, d, v in wr if is_stencil(n)]
+    fetch_b = sum(f_st) / len(f_st) * fs * 1024.0
+    write_b = sum(w_st) / len(w_st) * ws * 1024.0
+    traffic = fetch_b + write_b
+    roof = bench["roofline"]
+    alg = roof["bytes_per_launch"]
+
+    md = []
+    md.append(f"# Wilson stencil: {a.workload}\n")
+    md.append("Workload: bench.py headline (16^3x32, mu = 0.05, m = -2, Neuberger N_s = 30, "
+              "BiCGstab(l = 4), tol 1e-8, the 12 point sources in one batch); "
+              f"form: {bench['config'].get('pass')}-pass, {bench['config'].get('precision')}, "
+              f"refine {bench['config'].get('refine')}, {bench['config'].get('launch')} launches.\n")
+    md.append("## Kernel trace\n\nCommand (from the repository root on the MI355X box):\n")
+    md.append(f"    {a.cmd_trace}\n")
+    md.append("| kernel | calls | avg us | total ms | % |\n|---|---|---|---|---|")
+    for n, c, avg, s in rows[:a.top]:
+        md.append(f"| `{short(n)[:90]}` | {c} | {avg / 1e3:.2f} | {s / 1e6:.2f} | {100 * s / tot:.1f} |")
+    md.append("")
+    md.append(f"Stencil launches (all `dslash` kernels: site-block and chunked, every epilogue and "
+              f"precision; warm-up and timed steps): {len(st)} launches, average {st_avg_us:.1f} us.  "
+              f"bench.py's live HIP-event figure over its timed steps in the same run: "
+              f"{roof['avg_launch_us']:.1f} us over {roof['launches']} launches "
+              f"({100 * abs(roof['avg_launch_us'] - st_avg_us) / st_avg_us:.1f} % apart).\n")
+    md.append("## HBM traffic (rocprofv3 --pmc, one counter per run)\n\nCommands:\n")
+    md.append(f"    {a.cmd_fetch}\n    {a.cmd_write}\n")
+    md.append(f"Calibration (1 GiB copy, 1048576 KiB read and written): FETCH_SIZE x{fs:.3f}, "
+              f"WRITE_SIZE x{ws:.3f}.\n")
+    md.append("| per stencil launch | bytes |\n|---|---|")
+    md.append(f"| FETCH_SIZE (scaled) | {fetch_b / 1e6:.1f} MB |")
+    md.append(f"| WRITE_SIZE (scaled) | {write_b / 1e6:.1f} MB |")
+    md.append(f"| traffic | {traffic / 1e6:.1f} MB |")
+    md.append(f"| algorithmic (bench.py model) | {alg / 1e6:.1f} MB |")
+    md.append(f"| traffic / algorithmic | {traffic / alg:.2f} |\n")
+    md.append(f"Roofline of the timed steps: {roof['achieved']:.0f} GB/s algorithmic of {roof['peak']:.0f} "
+              f"GB/s ({100 * roof['frac']:.1f} %); {len(f_st)} / {len(w_st)} stencil dispatches counted.\n")
+    os.makedirs(os.path.dirname(os.path.abspath(a.md)), exist_ok=True)
+    with open(a.md, "w") as f:
+        f.write("\n".join(md))
+    rec = {"kernel": "Wilson stencil (dslash_kernel and dslash_chunk_kernel, all epilogues and precisions)",
+           "sources": STENCIL_SOURCES, "sources_sha256_16": sources_hash(),
+           "workload": a.workload, "traffic_bytes_per_launch": round(traffic),
+           "fetch_scale": fs, "write_scale": ws, "algorithmic_bytes_per_launch": alg,
+           "summary": os.path.relpath(os.path.abspath(a.md), ROOT)}
+    with open(a.json, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()
