@@ -43,16 +43,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def solver_flags(mixed, persistent, refine=False):
+def solver_flags(mixed, persistent, refine=False, deferred=False):
     from paper_1010_2592_amd import msb
-    return (msb.MIXED if mixed else 0) | (msb.PERSISTENT if persistent else 0) | (msb.REFINE if refine else 0)
+    return ((msb.MIXED if mixed else 0) | (msb.PERSISTENT if persistent else 0) | (msb.REFINE if refine else 0)
+            | (msb.DEFERRED if deferred else 0))
 
 
 def run_variant(ctx, b, a, sig, w, l, tol, max_outer, pass_, mixed, persistent=False, profile=False,
-                refine=False):
+                refine=False, deferred=False):
     import torch
     from paper_1010_2592_amd import msb
-    flags = solver_flags(mixed, persistent, refine)
+    flags = solver_flags(mixed, persistent, refine, deferred)
     if profile:
         ctx.profile_enable(True)
     torch.cuda.synchronize()
@@ -243,14 +244,17 @@ def main():
     if args.variants == "all":
         comps = {}
         ref = None
-        for (p, mx, pe, rf) in ((1, False, False, False), (2, False, False, False), (1, True, False, False),
-                                (2, True, False, False), (1, True, False, True),
-                                (1, False, True, False), (2, False, True, False), (1, True, True, False),
-                                (2, True, True, False)):
-            name = f"{p}pass-{'mixed' if mx else 'fp64'}{'-refine' if rf else ''}-{'persistent' if pe else 'stages'}"
+        forms = [(1, False, False, False, False), (2, False, False, False, False), (1, True, False, False, False),
+                 (2, True, False, False, False), (1, True, False, True, False),
+                 (1, False, False, False, True), (1, True, False, False, True), (1, True, False, True, True),
+                 (1, False, True, False, False), (2, False, True, False, False), (1, True, True, False, False),
+                 (2, True, True, False, False)]
+        for (p, mx, pe, rf, df) in forms:
+            name = (f"{p}pass-{'mixed' if mx else 'fp64'}{'-refine' if rf else ''}{'-deferred' if df else ''}"
+                    f"-{'persistent' if pe else 'stages'}")
             try:
                 yv, iv, msv, pv = run_variant(ctx, b, a, sig, w, l, wk.tol, min(args.max_outer, 400), p,
-                                              mx, pe, profile=True, refine=rf)
+                                              mx, pe, profile=True, refine=rf, deferred=df)
             except msb.MsbError as e:
                 comps[name] = {"error": str(e)}
                 continue

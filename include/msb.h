@@ -69,6 +69,9 @@ typedef enum {
 #define MSB_PERSISTENT 16   /* whole solve in one cooperative launch (batched)   */
 #define MSB_OVERLAP   32    /* pfe_sign_apply: out = b + gamma5 sign(H) b        */
 #define MSB_ADJOINT   64    /* solve with A^+ = A(-mu) (used by the backward)    */
+#define MSB_DEFERRED  256   /* pass 1: shift vectors updated once per outer
+                               iteration from its 2l+2 seed basis vectors (only
+                               u^s_0 and x^s kept per shift)                   */
 #define MSB_REFINE    128   /* pass 1: after the solve, the FP64 true residual of
                                every shift; shifts above tol get refinement
                                solves (A + sigma_s) d = r_s, x_s += d (<= 3
@@ -150,7 +153,8 @@ int wilson_apply(msb_ctx *ctx, const void *in, void *out, int nrhs, int flags);
  *   l                degree of the MR polynomial, 1..8
  *   pass             1: single-pass (N_s (l+1) shift vectors);
  *                    2: double-pass (no shift vectors, 4 M l Mv)
- *   flags            MSB_MIXED, MSB_PERSISTENT, MSB_ADJOINT, MSB_REFINE (pass 1)
+ *   flags            MSB_MIXED, MSB_PERSISTENT, MSB_ADJOINT, MSB_REFINE (pass 1),
+ *                    MSB_DEFERRED (pass 1, not with MSB_PERSISTENT)
  *   b                device [nrhs][12][V] complex128
  *   y                device [nrhs][12][V] complex128 (written)
  *   x_shifts         device [nrhs][n_shift][12][V] complex128 or NULL

@@ -54,6 +54,60 @@ __global__ __launch_bounds__(BLOCK) void k_rel_update(VecArgs<T> a, const double
 }
 
 // ---------------------------------------------------------------------------
+// Deferred single pass.
+// snapshot: B_0 <- r_0, B_1 <- u_0 at the start of an outer iteration.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_snapshot(VecArgs<T> a) {
+    const int rhs = blockIdx.y;
+    if (!gate_open(a.gate, rhs)) return;
+    const long n = a.n;
+    const C<T> *R = a.R + (size_t)rhs * (a.l + 1) * n;
+    const C<T> *U = a.U + (size_t)rhs * (a.l + 1) * n;
+    C<T> *B = a.Bm + (size_t)rhs * (2 * a.l + 2) * n;
+    for (long e = (long)blockIdx.x * BLOCK + threadIdx.x; e < n; e += (long)gridDim.x * BLOCK) {
+        B[e] = R[e];
+        B[n + e] = U[e];
+    }
+}
+
+// defer_update: per element, the 2L + 2 basis values are loaded once and every
+// active shift's u^s_0 (iteration precision) and x^s (FP64) are rewritten:
+// the shift vectors cross HBM twice per outer iteration instead of
+// (l + 1)(l + 4) times.
+template <typename T, int L>
+__global__ __launch_bounds__(BLOCK) void k_defer_update(VecArgs<T> a) {
+    const int rhs = blockIdx.y;
+    if (!gate_open(a.gate, rhs)) return;
+    constexpr int NB = 2 * L + 2;
+    const long n = a.n;
+    const int nact = a.seed[rhs].nact;
+    const C<T> *B = a.Bm + (size_t)rhs * NB * n;
+    const DeferCoef *dc = a.dc + (size_t)rhs * NSMAX;
+    for (long e = (long)blockIdx.x * BLOCK + threadIdx.x; e < n; e += (long)gridDim.x * BLOCK) {
+        C<T> b[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) b[k] = B[k * n + e];
+        for (int q = 0; q < nact; ++q) {
+            const DeferCoef &d = dc[q];
+            if (!d.live) continue;
+            C<T> *W = a.W0 + ((size_t)rhs * a.nshift + d.s) * n;
+            double2 *X = a.X + ((size_t)rhs * a.nshift + d.s) * n;
+            const C<T> u0 = W[e];
+            const double2 u0d = d2((double)u0.x, (double)u0.y);
+            C<T> un = cmul(cvt<T>(d.cu[NB]), u0);
+            double2 xn = cfma(d.cx[NB], u0d, X[e]);
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                un = cfma(cvt<T>(d.cu[k]), b[k], un);
+                xn = cfma(d.cx[k], d2((double)b[k].x, (double)b[k].y), xn);
+            }
+            W[e] = un;
+            X[e] = xn;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_convert_in(C<T> *dst, const double2 *src, long n, long ds, long ss) {
     const int rhs = blockIdx.y;
@@ -245,6 +299,21 @@ void launch_mr_update(hipStream_t st, const VecArgs<T> &a, bool shifts, bool xh,
 }
 
 template <typename T>
+void launch_snapshot(hipStream_t st, const VecArgs<T> &a, int nrhs, int nblk) {
+    hipLaunchKernelGGL((k_snapshot<T>), dim3(nblk, nrhs), dim3(BLOCK), 0, st, a);
+}
+
+template <typename T>
+void launch_defer_update(hipStream_t st, const VecArgs<T> &a, int nrhs, int nblk) {
+    dim3 g(nblk, nrhs), b(BLOCK);
+    switch (a.l) {
+#define C_(L) case L: hipLaunchKernelGGL((k_defer_update<T, L>), g, b, 0, st, a); break;
+        C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8)
+#undef C_
+    }
+}
+
+template <typename T>
 void launch_rel_update(hipStream_t st, const VecArgs<T> &a, const double2 *b, const double2 *v, double2 *y,
                        CoefRef yc, int nrhs, int nblk) {
     hipLaunchKernelGGL((k_rel_update<T>), dim3(nblk, nrhs), dim3(BLOCK), 0, st, a, b, v, y, yc);
@@ -299,6 +368,8 @@ void launch_axpy_host(hipStream_t st, double2 *y, const double2 *x, double2 a, l
     template void launch_seed_u<T>(hipStream_t, const VecArgs<T> &, int, int, int);              \
     template void launch_r_update<T>(hipStream_t, const VecArgs<T> &, int, bool, bool, int, int); \
     template void launch_gram<T>(hipStream_t, const VecArgs<T> &, int, int);                     \
+    template void launch_snapshot<T>(hipStream_t, const VecArgs<T> &, int, int);                 \
+    template void launch_defer_update<T>(hipStream_t, const VecArgs<T> &, int, int);             \
     template void launch_mr_update<T>(hipStream_t, const VecArgs<T> &, bool, bool, int, int);    \
     template void launch_rel_update<T>(hipStream_t, const VecArgs<T> &, const double2 *, const double2 *, double2 *, CoefRef, int, int); \
     template void launch_convert_in<T>(hipStream_t, C<T> *, const double2 *, long, long, long, int); \

@@ -45,8 +45,12 @@ int make_params(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
     if (max_outer < 1 || (long)max_outer * l > (1L << 24)) return arg_error(w + ": max_outer out of range");
     if (pass != 1 && pass != 2) return arg_error(w + ": pass must be 1 or 2");
     if (nrhs < 1 || nrhs > 4096) return arg_error(w + ": nrhs must be in 1..4096");
-    if (flags & ~(MSB_MIXED | MSB_PERSISTENT | MSB_ADJOINT | MSB_OVERLAP | MSB_REFINE))
+    if (flags & ~(MSB_MIXED | MSB_PERSISTENT | MSB_ADJOINT | MSB_OVERLAP | MSB_REFINE | MSB_DEFERRED))
         return arg_error(w + ": unknown flag bits");
+    if ((flags & MSB_DEFERRED) && pass != 1)
+        return arg_error(w + ": MSB_DEFERRED is a form of the single pass (pass = 1)");
+    if ((flags & MSB_DEFERRED) && (flags & MSB_PERSISTENT))
+        return arg_error(w + ": MSB_DEFERRED runs with one launch per stage, not MSB_PERSISTENT");
     if ((flags & MSB_REFINE) && pass != 1)
         return arg_error(w + ": MSB_REFINE needs pass = 1 (the double pass keeps no shift solutions)");
     if ((flags & MSB_PERSISTENT) && l > msb::PERSIST_LMAX)
@@ -64,6 +68,7 @@ int make_params(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
     P->neg_mu = (flags & MSB_ADJOINT) != 0;
     P->persistent = (flags & MSB_PERSISTENT) != 0;
     P->refine = (flags & MSB_REFINE) != 0;
+    P->deferred = (flags & MSB_DEFERRED) != 0;
     P->nrhs = nrhs;
     P->shifts.resize((size_t)nrhs * n_shift);
     P->weights.resize((size_t)nrhs * n_shift);

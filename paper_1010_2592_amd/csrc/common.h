@@ -159,6 +159,10 @@ struct SeedState {
     int rel;        // reliable update due at the end of this outer iteration
     double rmax;    // largest ||r_0|| since the last reliable update
     int act[NSMAX];
+    // this outer iteration's BiCG steps (deferred shift updates):
+    // flag 0 no step, 1 u-update and Mv only (gamma breakdown), 2 full step
+    double2 step_beta[LMAX], step_alpha[LMAX];
+    int step_flag[LMAX];
 };
 
 struct ShiftState {
@@ -177,6 +181,18 @@ struct StepCoef {   // one active shift, one BiCG step
 struct MRCoef {     // one active shift, one MR step
     double2 kc[LMAX];   // kappa * c_k
     double2 inv_q;
+    int s, live;
+};
+
+// Deferred single pass: one active shift's update over a whole outer
+// iteration as coefficients on the iteration's basis
+//   B = {r_0 at the start, u_0 at the start, S u_j and S r_j of step j = 0..l-1}
+// (index 0, 1, 2 + 2j, 3 + 2j) plus the shift's own u^s_0 at the start (index
+// 2l + 2):  u^s_0 <- sum_b cu[b] B_b + cu[2l+2] u^s_0,
+//           x^s   <- x^s + sum_b cx[b] B_b + cx[2l+2] u^s_0.
+constexpr int NDEF = 2 * LMAX + 3;
+struct DeferCoef {
+    double2 cu[NDEF], cx[NDEF];
     int s, live;
 };
 

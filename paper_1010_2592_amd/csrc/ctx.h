@@ -27,7 +27,8 @@ struct Ctx {
     DevBuf ws_R, ws_U, ws_tmp, ws_W, ws_X, ws_rt, ws_b, ws_y, ws_part, ws_seed, ws_shift, ws_sc,
         ws_mc, ws_tape, ws_tape_gam, ws_tape_outer, ws_replay, ws_replay_outer, ws_wts, ws_sig0,
         ws_cb, ws_aux1, ws_aux2, ws_aux3, ws_aux4, ws_bX, ws_bZ, ws_by, ws_beta, ws_bA, ws_bB, ws_bdots,
-        ws_ops, ws_pctl, ws_rX, ws_rX2, ws_ry, ws_rB, ws_rR, ws_rt1, ws_rt2, ws_rsig, ws_rw;
+        ws_ops, ws_pctl, ws_rX, ws_rX2, ws_ry, ws_rB, ws_rR, ws_rt1, ws_rt2, ws_rsig, ws_rw, ws_Bm, ws_schist,
+        ws_dc;
     int pgrid[32] = {};        // co-resident grid of the persistent kernel, per (precision, l)
     void *host_pinned = nullptr;
     size_t host_pinned_bytes = 0;
@@ -86,6 +87,7 @@ struct SolveParams {
     bool neg_mu = false;
     bool persistent = false;           // one cooperative launch per pass
     bool refine = false;               // pass 1: refine shifts above tol (true residual)
+    bool deferred = false;             // pass 1: shift vectors updated once per outer iteration
     int nrhs = 1;
     const int *force_iters = nullptr;   // [nrhs][n_shift] or null
 };

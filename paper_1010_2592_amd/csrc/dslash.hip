@@ -18,6 +18,8 @@
 //   EPI_MV_Y   as EPI_MV without partials, plus y += c * out (double-pass
 //              accumulation of the Mv outputs)
 //   EPI_SV     out = scale * gamma5 D in + sigma0 * v, nothing else
+//   EPI_MVB    as EPI_MV, and a second copy of out (the basis the deferred
+//              single pass updates its shift vectors from)
 // Which operands exist is a compile-time property of the mode: run-time null
 // checks inside the unrolled epilogue made the compiler keep every epilogue
 // load live at once and spill.
@@ -159,11 +161,13 @@ void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in
             if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, true);
             else if (epi == EPI_MV) MSB_DS(EPI_MV, true);
             else if (epi == EPI_SV) MSB_DS(EPI_SV, true);
+            else if (epi == EPI_MVB) MSB_DS(EPI_MVB, true);
             else MSB_DS(EPI_MV_Y, true);
         } else {
             if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, false);
             else if (epi == EPI_MV) MSB_DS(EPI_MV, false);
             else if (epi == EPI_SV) MSB_DS(EPI_SV, false);
+            else if (epi == EPI_MVB) MSB_DS(EPI_MVB, false);
             else MSB_DS(EPI_MV_Y, false);
         }
 #undef MSB_DS
@@ -175,11 +179,13 @@ void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in
         if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, true);
         else if (epi == EPI_MV) MSB_DS(EPI_MV, true);
         else if (epi == EPI_SV) MSB_DS(EPI_SV, true);
+        else if (epi == EPI_MVB) MSB_DS(EPI_MVB, true);
         else MSB_DS(EPI_MV_Y, true);
     } else {
         if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, false);
         else if (epi == EPI_MV) MSB_DS(EPI_MV, false);
         else if (epi == EPI_SV) MSB_DS(EPI_SV, false);
+        else if (epi == EPI_MVB) MSB_DS(EPI_MVB, false);
         else MSB_DS(EPI_MV_Y, false);
     }
 #undef MSB_DS

@@ -5,7 +5,7 @@
 
 namespace msb {
 
-enum { EPI_PLAIN = 0, EPI_MV = 1, EPI_MV_Y = 2, EPI_SV = 3 };
+enum { EPI_PLAIN = 0, EPI_MV = 1, EPI_MV_Y = 2, EPI_SV = 3, EPI_MVB = 4 };
 
 // A per-right-hand-side complex coefficient in device memory: the value for
 // rhs r is *(const double2 *)(p + r * stride).
@@ -40,6 +40,8 @@ struct DslashArgs {
     int per_t = 0;             // chunked stencil: blocks per XCD (per rounded up to tsc)
     CoefRef ycoef;             // EPI_MV_Y: coefficient of the Mv output
     double2 *y = nullptr;      // EPI_MV_Y accumulator (always FP64)
+    C<T> *out2 = nullptr;      // EPI_MVB: second copy of the output (the deferred basis)
+    long out2_rs = 0;
     Gate gate{};
     // element strides between right-hand sides (0: 12 V)
     long in_rs = 0, out_rs = 0, v_rs = 0, rt_rs = 0, y_rs = 0;
@@ -118,6 +120,10 @@ struct VecArgs {
     CoefRef gam;                // gamma_1 at gam, gamma_i at gam.p + (i-1)*16
     int partials = 1;
     Gate gate{};
+    // deferred single pass
+    C<T> *Bm = nullptr;         // [rhs][2l+2][n] the outer iteration's basis
+    C<T> *W0 = nullptr;         // [rhs][nshift][n] u^s_0 of every shift
+    const DeferCoef *dc = nullptr;  // [rhs][NSMAX]
 };
 
 template <typename T> void launch_seed_u(hipStream_t, const VecArgs<T> &, int j, int nrhs, int nblk);
@@ -128,6 +134,11 @@ template <typename T> void launch_mr_update(hipStream_t, const VecArgs<T> &, boo
 // (optionally y += c v with c from yc)
 template <typename T> void launch_rel_update(hipStream_t, const VecArgs<T> &, const double2 *b, const double2 *v,
                                              double2 *y, CoefRef yc, int nrhs, int nblk);
+
+// deferred single pass: B_0 <- r_0, B_1 <- u_0 at the start of an outer
+// iteration; once per iteration, u^s_0 and x^s of every active shift from B
+template <typename T> void launch_snapshot(hipStream_t, const VecArgs<T> &, int nrhs, int nblk);
+template <typename T> void launch_defer_update(hipStream_t, const VecArgs<T> &, int nrhs, int nblk);
 
 // small utility kernels
 template <typename T>
@@ -180,6 +191,8 @@ struct ScalarArgs {
     int l = 0;
     int j = 0;
     int record = 0;                 // record the tape (double-pass)
+    StepCoef *sc_hist = nullptr;    // deferred: [rhs][LMAX][NSMAX] every step's shift coefficients
+    DeferCoef *dc = nullptr;        // deferred: [rhs][NSMAX] the iteration's coefficients
 };
 
 void launch_sc_init(hipStream_t, const ScalarArgs &, int nrhs);
@@ -188,6 +201,7 @@ void launch_sc_alpha(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_mr(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_conv(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_rel(hipStream_t, const ScalarArgs &, int nrhs);
+void launch_sc_defer(hipStream_t, const ScalarArgs &, int nrhs);
 
 // ---- persistent execution --------------------------------------------------
 // The stages of a solve, recorded as a table of operations that one
@@ -209,6 +223,7 @@ enum OpKind : int {
     OP_SC_MR,
     OP_SC_REL,
     OP_SC_CONV,
+    OP_SC_DEFER,      // per-stage launches only (the deferred single pass)
 };
 constexpr int POP_BLOB = 512;
 struct alignas(16) POp {

@@ -34,6 +34,7 @@ __global__ __launch_bounds__(BLOCK) void sc_alpha(ScalarArgs a) { sc_alpha_body(
 __global__ __launch_bounds__(BLOCK) void sc_mr(ScalarArgs a) { sc_mr_body(a, blockIdx.x); }
 __global__ __launch_bounds__(BLOCK) void sc_rel(ScalarArgs a) { sc_rel_body(a, blockIdx.x); }
 __global__ __launch_bounds__(BLOCK) void sc_conv(ScalarArgs a) { sc_conv_body(a, blockIdx.x); }
+__global__ __launch_bounds__(BLOCK) void sc_defer(ScalarArgs a) { sc_defer_body(a, blockIdx.x); }
 
 }  // namespace
 
@@ -54,6 +55,9 @@ void launch_sc_rel(hipStream_t st, const ScalarArgs &a, int nrhs) {
 }
 void launch_sc_conv(hipStream_t st, const ScalarArgs &a, int nrhs) {
     hipLaunchKernelGGL(sc_conv, dim3(nrhs), dim3(BLOCK), 0, st, a);
+}
+void launch_sc_defer(hipStream_t st, const ScalarArgs &a, int nrhs) {
+    hipLaunchKernelGGL(sc_defer, dim3(nrhs), dim3(BLOCK), 0, st, a);
 }
 
 }  // namespace msb

@@ -45,6 +45,7 @@ __device__ __forceinline__ void sc_init_body(const ScalarArgs &a, int rhs) {
         S.mv = S.dots = S.axpys = S.reliable = 0;
         S.rel = 0;
         S.rmax = S.bnorm;
+        for (int i = 0; i < LMAX; ++i) S.step_flag[i] = 0;
         S.nact = 0;
         for (int s = 0; s < S.nshift; ++s) {
             if (a.sh[(size_t)rhs * NSMAX + s].active) S.act[S.nact++] = s;
@@ -106,6 +107,8 @@ __device__ __forceinline__ void sc_beta_body(const ScalarArgs &a, int rhs) {
     const double2 beta = cdiv(cmul(S.alpha, rho1), S.rho0);
     S.rho0 = rho1;
     S.beta = beta;
+    S.step_beta[j] = beta;
+    S.step_flag[j] = 1;
     if (a.record && S.n < S.max_steps) {
         TapeStep &t = a.tape[(size_t)rhs * S.max_steps + S.n];
         t.beta = beta;
@@ -140,6 +143,8 @@ __device__ __forceinline__ void sc_alpha_body(const ScalarArgs &a, int rhs) {
         } else {
             const double2 alpha = cdiv(S.rho0, gam);
             S.alpha = alpha;
+            S.step_alpha[j] = alpha;
+            S.step_flag[j] = 2;
             if (a.record && S.n < S.max_steps) {
                 TapeStep &t = a.tape[(size_t)rhs * S.max_steps + S.n];
                 t.alpha = alpha;
@@ -188,6 +193,12 @@ __device__ __forceinline__ void sc_alpha_body(const ScalarArgs &a, int rhs) {
         H.zeta_prev = z;
         H.zeta = z_next;
         H.pi_prev = pi_n;
+    }
+    if (a.sc_hist) {
+        // deferred single pass: keep every step's coefficients of the iteration
+        __syncthreads();
+        for (int q = threadIdx.x; q < nact; q += BLOCK)
+            a.sc_hist[((size_t)rhs * LMAX + j) * NSMAX + q] = a.sc[(size_t)rhs * NSMAX + q];
     }
     if (threadIdx.x == 0) {
         S.mv += 1;
@@ -398,6 +409,75 @@ __device__ __forceinline__ void sc_conv_body(const ScalarArgs &a, int rhs) {
         S.l_eff = 0;
         S.l_mr = 0;
         S.partial = 0;
+        for (int i = 0; i < LMAX; ++i) S.step_flag[i] = 0;
+    }
+}
+
+// Deferred single pass: every active shift's update over the outer iteration
+// that just ended, as coefficients on the iteration's basis (see DeferCoef).
+// One work-item per shift replays the iteration on coefficient vectors: the
+// seed's r_i, u_i exactly as the vector kernels updated them (the recorded
+// beta, alpha and step flags), and the shift's u^s_i and x^s increment by the
+// recurrences of the per-step form (the recorded step coefficients of every
+// step and the MR coefficients).  Vectors no step defined are zero, as the
+// per-step form multiplies their stale contents by zero coefficients.
+__device__ __forceinline__ void sc_defer_body(const ScalarArgs &a, int rhs) {
+    SeedState &S = a.seed[rhs];
+    if (!S.run) return;
+    const int l = a.l, nb = 2 * l + 2, self = nb;
+    for (int q = threadIdx.x; q < S.nact; q += BLOCK) {
+        DeferCoef &d = a.dc[(size_t)rhs * NSMAX + q];
+        d.s = S.act[q];
+        double2 R[LMAX + 1][NDEF], U[LMAX + 1][NDEF], w[LMAX + 1][NDEF], dx[NDEF];
+        for (int i = 0; i <= l; ++i)
+            for (int b = 0; b <= nb; ++b) R[i][b] = U[i][b] = w[i][b] = d2(0, 0);
+        for (int b = 0; b <= nb; ++b) dx[b] = d2(0, 0);
+        R[0][0] = d2(1, 0);
+        U[0][1] = d2(1, 0);
+        w[0][self] = d2(1, 0);
+        bool live = true;
+        for (int j = 0; j < l; ++j) {
+            const int flag = S.step_flag[j];
+            if (flag == 0) break;
+            const double2 beta = S.step_beta[j];
+            for (int i = 0; i <= j; ++i)
+                for (int b = 0; b <= nb; ++b) U[i][b] = csub(R[i][b], cmul(beta, U[i][b]));
+            for (int b = 0; b <= nb; ++b) U[j + 1][b] = d2(0, 0);
+            U[j + 1][2 + 2 * j] = d2(1, 0);
+            if (flag == 1) break;
+            const StepCoef c = a.sc_hist[((size_t)rhs * LMAX + j) * NSMAX + q];
+            if (live && c.live) {
+                for (int i = 0; i <= j; ++i)
+                    for (int b = 0; b <= nb; ++b) w[i][b] = csub(cmul(c.kap, R[i][b]), cmul(c.beta_s, w[i][b]));
+                for (int b = 0; b <= nb; ++b) dx[b] = cfma(c.alpha_s, w[0][b], dx[b]);
+                for (int b = 0; b <= nb; ++b)
+                    w[j + 1][b] = csub(cadd(cmul(c.a1, R[j][b]), cmul(c.a2, U[j + 1][b])), cscale(w[j][b], c.sp));
+            } else {
+                live = false;
+            }
+            const double2 alpha = S.step_alpha[j];
+            for (int i = 0; i <= j; ++i)
+                for (int b = 0; b <= nb; ++b) R[i][b] = csub(R[i][b], cmul(alpha, U[i + 1][b]));
+            for (int b = 0; b <= nb; ++b) R[j + 1][b] = d2(0, 0);
+            R[j + 1][3 + 2 * j] = d2(1, 0);
+        }
+        const MRCoef &m = a.mc[(size_t)rhs * NSMAX + q];
+        if (live && m.live) {
+            for (int k = 0; k < l; ++k)
+                for (int b = 0; b <= nb; ++b) dx[b] = cfma(m.kc[k], R[k][b], dx[b]);
+            for (int b = 0; b <= nb; ++b) {
+                double2 u0 = w[0][b];
+                for (int i = 1; i <= l; ++i) u0 = csub(u0, cmul(S.gam[i - 1], w[i][b]));
+                w[0][b] = cmul(u0, m.inv_q);
+            }
+        }
+        // a shift whose recurrences stopped this iteration keeps the part
+        // applied before: the per-step form updated it until then
+        for (int b = 0; b < NDEF; ++b) {
+            d.cu[b] = b <= nb ? w[0][b] : d2(0, 0);
+            d.cx[b] = b <= nb ? dx[b] : d2(0, 0);
+        }
+        d.live = 1;
     }
 }
 

@@ -594,6 +594,19 @@ struct Emit {
             record(o, a);
         }
     }
+    // deferred single pass (per-stage launches only)
+    void snapshot(const VecArgs<T> &a, int nrhs, int nblk, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_snapshot<T>(st, a, nrhs, nblk);
+        }
+    }
+    void defer_update(const VecArgs<T> &a, int nrhs, int nblk, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_defer_update<T>(st, a, nrhs, nblk);
+        }
+    }
     void scalar(int kind, const ScalarArgs &a, int nrhs) {
         if (launching(CL_SCALAR, 0.0)) {
             Prof p(c, CL_SCALAR, 0);
@@ -603,6 +616,7 @@ struct Emit {
             case OP_SC_MR: launch_sc_mr(st, a, nrhs); break;
             case OP_SC_REL: launch_sc_rel(st, a, nrhs); break;
             case OP_SC_CONV: launch_sc_conv(st, a, nrhs); break;
+            case OP_SC_DEFER: launch_sc_defer(st, a, nrhs); break;
             default: break;
             }
         } else if (mode == RECORD) {
@@ -679,6 +693,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     auto ds_bytes = [&](int epi, int nr) {
         double per = 24 * cB;                                  // in + out
         if (epi == EPI_MV) per = 48 * cB;                      // + v + rt
+        else if (epi == EPI_MVB) per = 60 * cB;                // + v + rt + the basis copy
         else if (epi == EPI_MV_Y) per = 36 * cB + 24 * 16.0;   // + v, y (FP64) read + write
         else if (epi == EPI_SV) per = 36 * cB;                 // + v
         return nr * per * Vd + 36 * cB * Vd;                   // links once per launch
@@ -720,8 +735,18 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         t64 = (double2 *)c->ws_aux2.p;
         v64 = (double2 *)c->ws_aux3.p;
     }
+    const bool deferred = pass1 && P.deferred;
+    const int nb = 2 * l + 2;            // deferred: basis vectors per outer iteration
+    C<T> *Bm = nullptr;
+    if (deferred) {
+        CHK(ensure(c->ws_Bm, (size_t)nrhs * nb * n * cs));
+        CHK(ensure(c->ws_schist, (size_t)nrhs * LMAX * NSMAX * sizeof(StepCoef)));
+        CHK(ensure(c->ws_dc, (size_t)nrhs * NSMAX * sizeof(DeferCoef)));
+        Bm = (C<T> *)c->ws_Bm.p;
+    }
+    const int wslots = deferred ? 1 : l + 1;   // shift vectors kept per shift
     if (pass1) {
-        CHK(ensure(c->ws_W, (size_t)nrhs * ns * (l + 1) * n * cs));
+        CHK(ensure(c->ws_W, (size_t)nrhs * ns * wslots * n * cs));
         W = (C<T> *)c->ws_W.p;
         if (xs_out) {
             X = xs_out;
@@ -774,13 +799,13 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
 
     // ---- initial vectors: r_0 = b, everything else zero
     {
-        Prof p(c, CL_OTHER, nrhs * nd * cB * (2.0 * (l + 1) + (pass1 ? ns * (l + 1.0) : 0.0)) +
+        Prof p(c, CL_OTHER, nrhs * nd * cB * (2.0 * (l + 1) + (pass1 ? ns * (double)wslots : 0.0)) +
                                 (pass1 ? nrhs * nd * ns * 16.0 : 0.0) + (mixed ? nrhs * nd * 16.0 : 0.0) +
                                 nrhs * nd * (16.0 + cB) + nrhs * nd * cB);
         launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
         launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
         if (pass1) {
-            launch_zero<T>(st, W, (long)nrhs * ns * (l + 1) * n, 0, 1);
+            launch_zero<T>(st, W, (long)nrhs * ns * wslots * n, 0, 1);
             launch_zero<double>(st, X, (long)nrhs * ns * n, 0, 1);
         }
         if (mixed) launch_zero<double>(st, XH, (long)nrhs * n, 0, 1);
@@ -800,6 +825,10 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     sa.l = l;
     sa.record = pass1 ? 0 : 1;
     sa.nblk = nbv;
+    if (deferred) {
+        sa.sc_hist = (StepCoef *)c->ws_schist.p;
+        sa.dc = (DeferCoef *)c->ws_dc.p;
+    }
     {
         Prof p(c, CL_SCALAR, 0);
         launch_sc_init(st, sa, nrhs);
@@ -826,6 +855,12 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     va.beta = CoefRef{(const char *)&seed[0].beta, (long)sizeof(SeedState)};
     va.alpha = CoefRef{(const char *)&seed[0].alpha, (long)sizeof(SeedState)};
     va.gam = CoefRef{(const char *)&seed[0].gam[0], (long)sizeof(SeedState)};
+    if (deferred) {
+        va.Bm = Bm;
+        va.W0 = W;
+        va.dc = (const DeferCoef *)c->ws_dc.p;
+    }
+    const bool shifts_step = pass1 && !deferred;   // shift vectors updated in every step
     Gate g_bicg;
     g_bicg.seed = seed;
     g_bicg.need_bicg = 1;
@@ -879,10 +914,17 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     // One outer iteration of the first pass: l BiCG steps, the MR step, the
     // reliable update (mixed) and the convergence step.  nr_run and nsh_act
     // (right-hand sides and shifts still iterating) only price the bytes.
+    const int mv_epi = deferred ? EPI_MVB : EPI_MV;
     auto emit_outer = [&](Emit<T> &e, int nr_run, double nsh_act) {
         VecArgs<T> v = va;
         ScalarArgs s = sa;
         DslashArgs<T> e1 = d1, e2 = d2;
+        if (deferred) {
+            // the iteration's basis starts with r_0 and u_0
+            v.gate = g_run;
+            e.snapshot(v, nrhs, nbv, CL_SHIFT, nr_run * 4.0 * nd * cB);
+            e2.out2_rs = (long)nb * n;
+        }
         for (int j = 0; j < l; ++j) {
             s.j = j;
             s.nblk = (j == 0) ? nbv : nbd;
@@ -899,20 +941,23 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             e2.out = Uv + (size_t)(j + 1) * n;
             e2.v = Uv + (size_t)j * n;
             e2.gate = g_bicg;
-            e.ds(e2, nrhs, EPI_MV, CL_STENCIL, ds_bytes(EPI_MV, nr_run));
+            if (deferred) e2.out2 = Bm + (size_t)(2 + 2 * j) * n;
+            e.ds(e2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
             s.nblk = nbd;
             e.scalar(OP_SC_ALPHA, s, nrhs);
             v.partials = 1;
-            // seed: read r_i, u_{i+1}, write r_i; shift s: read u^s_0..j, x^s,
-            // write u^s_0..j+1, x^s
-            e.r_update(v, j, pass1, mixed, nrhs, nbv, pass1 ? CL_SHIFT : CL_SEED,
-                       nr_run * 3.0 * (j + 1) * nd * cB + (pass1 ? nsh_act * (2.0 * j + 5) * nd * cB : 0.0));
+            // seed: read r_i, u_{i+1}, write r_i; shift s (per-step form): read
+            // u^s_0..j, x^s (FP64), write u^s_0..j+1, x^s
+            e.r_update(v, j, shifts_step, mixed, nrhs, nbv, shifts_step ? CL_SHIFT : CL_SEED,
+                       nr_run * (3.0 * (j + 1) * cB + (mixed ? 32.0 : 0.0)) * nd +
+                           (shifts_step ? nsh_act * ((2.0 * j + 3) * cB + 32.0) * nd : 0.0));
             // r_{j+1} = S r_j, <rt, r_{j+1}>
             e1.in = R + (size_t)j * n;
             e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
             e2.out = R + (size_t)(j + 1) * n;
             e2.v = R + (size_t)j * n;
-            e.ds(e2, nrhs, EPI_MV, CL_STENCIL, ds_bytes(EPI_MV, nr_run));
+            if (deferred) e2.out2 = Bm + (size_t)(3 + 2 * j) * n;
+            e.ds(e2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
         }
         v.gate = g_run;
         e.gram(v, nrhs, nbv, CL_SEED, nr_run * (l + 1.0) * nd * cB);
@@ -921,8 +966,17 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         v.partials = 1;
         // seed: read r_0..r_l, u_0..u_l, rt, write r_0, u_0; shift s: read
         // u^s_0..u^s_l, x^s, write u^s_0, x^s
-        e.mr_update(v, pass1, mixed, nrhs, nbv, pass1 ? CL_SHIFT_MR : CL_SEED,
-                    nr_run * (2.0 * (l + 1) + 3) * nd * cB + (pass1 ? nsh_act * (l + 4.0) * nd * cB : 0.0));
+        e.mr_update(v, shifts_step, mixed, nrhs, nbv, shifts_step ? CL_SHIFT_MR : CL_SEED,
+                    nr_run * ((2.0 * (l + 1) + 3) * cB + (mixed ? 32.0 : 0.0)) * nd +
+                        (shifts_step ? nsh_act * ((l + 2.0) * cB + 32.0) * nd : 0.0));
+        if (deferred) {
+            // every shift's update over the iteration, from the basis: read the
+            // 2l+2 basis vectors once, each active shift's u^s_0 and x^s (FP64)
+            // read and written
+            e.scalar(OP_SC_DEFER, s, nrhs);
+            v.gate = g_run;
+            e.defer_update(v, nrhs, nbv, CL_SHIFT_MR, nr_run * nb * nd * cB + nsh_act * (2.0 * cB + 32.0) * nd);
+        }
         if (mixed) {
             e.scalar(OP_SC_REL, s, nrhs);
             reliable_update(e, v, g_rel, nullptr, CoefRef{}, nr_run);

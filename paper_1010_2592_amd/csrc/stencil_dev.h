@@ -133,7 +133,7 @@ template <typename T, int EPI, bool G5IN, typename LK>
 __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &lk, const C<T> *__restrict__ in,
                                              C<T> *__restrict__ out, const C<T> *__restrict__ v,
                                              const C<T> *__restrict__ rt, double2 *__restrict__ y, C<T> yc,
-                                             T sig0, int s0, double (&part)[3]) {
+                                             T sig0, C<T> *__restrict__ out2, int s0, double (&part)[3]) {
     const int V = a.g.V, Lx = a.g.Lx, Ly = a.g.Ly, Lz = a.g.Lz, Lt = a.g.Lt;
     for (int s = s0; s < V; s += a.sstride) {
     const int sxy = Lx * Ly, sxyz = Lx * Ly * Lz;
@@ -188,7 +188,8 @@ __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &l
             C<T> o = acc[sp][c];
             if (EPI != EPI_PLAIN) o = cadd(o, cscale(v[k * V + s], sig0));
             out[k * V + s] = o;
-            if (EPI == EPI_MV) {
+            if (EPI == EPI_MVB) out2[k * V + s] = o;
+            if (EPI == EPI_MV || EPI == EPI_MVB) {
                 const C<T> r = rt[k * V + s];
                 part[0] += (double)r.x * o.x + (double)r.y * o.y;
                 part[1] += (double)r.x * o.y - (double)r.y * o.x;
@@ -214,6 +215,7 @@ struct RhsOps {
     double2 *y;
     C<T> yc;
     T sig0;
+    C<T> *out2;
 };
 template <typename T, int EPI>
 __device__ __forceinline__ RhsOps<T> rhs_ops(const DslashArgs<T> &a, int rhs) {
@@ -227,6 +229,7 @@ __device__ __forceinline__ RhsOps<T> rhs_ops(const DslashArgs<T> &a, int rhs) {
     o.yc = mk<T>(0, 0);
     if (EPI == EPI_MV_Y) o.yc = to_c<T>(ld(a.ycoef, rhs));
     o.sig0 = a.sigma0_rhs ? (T)a.sigma0_rhs[rhs] : a.sigma0;
+    o.out2 = a.out2 ? a.out2 + (size_t)rhs * (a.out2_rs ? a.out2_rs : nv) : nullptr;
     return o;
 }
 
@@ -238,8 +241,9 @@ __device__ __forceinline__ void dslash_site_block(const DslashArgs<T> &a, int sb
     const RhsOps<T> o = rhs_ops<T, EPI>(a, rhs);
     const GlobalLinks<T> lk{a.U, a.g.V};
     double part[3] = {0.0, 0.0, 0.0};
-    dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, sblk * BLOCK + threadIdx.x, part);
-    if (EPI == EPI_MV)
+    dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, o.out2, sblk * BLOCK + threadIdx.x,
+                              part);
+    if (EPI == EPI_MV || EPI == EPI_MVB)
         wave_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + sblk * (BLOCK / 64) + (threadIdx.x >> 6),
                              a.ps);
 }
@@ -308,8 +312,8 @@ __device__ __forceinline__ void dslash_chunk(const DslashArgs<T> &a, int p) {
         if (!gate_open(a.gate, rhs)) continue;
         const RhsOps<T> o = rhs_ops<T, EPI>(a, rhs);
         double part[3] = {0.0, 0.0, 0.0};
-        dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, base + lane, part);
-        if (EPI == EPI_MV) wave_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + chunk, a.ps);
+        dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, o.out2, base + lane, part);
+        if (EPI == EPI_MV || EPI == EPI_MVB) wave_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + chunk, a.ps);
     }
 }
 

@@ -23,12 +23,12 @@ __all__ = [
     "MsbError", "Lattice", "SolveInfo", "Context", "lib", "library_path",
     "neuberger_pfe", "wilson_apply", "mshift_bicgstabl", "pfe_sign_apply",
     "pfe_sign_backward", "spectral_radius",
-    "G5_LEFT", "NEG_MU", "DAGGER", "MIXED", "PERSISTENT", "OVERLAP", "ADJOINT", "REFINE",
+    "G5_LEFT", "NEG_MU", "DAGGER", "MIXED", "PERSISTENT", "OVERLAP", "ADJOINT", "REFINE", "DEFERRED",
     "OK", "ERR_ARG", "ERR_HIP", "ERR_OOM", "NOT_CONVERGED", "BREAKDOWN",
 ]
 
 OK, ERR_ARG, ERR_HIP, ERR_OOM, NOT_CONVERGED, BREAKDOWN = 0, 1, 2, 3, 4, 5
-G5_LEFT, NEG_MU, DAGGER, MIXED, PERSISTENT, OVERLAP, ADJOINT, REFINE = 1, 2, 4, 8, 16, 32, 64, 128
+G5_LEFT, NEG_MU, DAGGER, MIXED, PERSISTENT, OVERLAP, ADJOINT, REFINE, DEFERRED = 1, 2, 4, 8, 16, 32, 64, 128, 256
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
