@@ -8,10 +8,12 @@ spin-colour point sources at the origin solved as one batch; tolerance 1e-8 on
 every shift's relative residual.
 
 One step = one f(A) b evaluation of the 12-source batch in the headline form
-(--pass, --precision, --refine).  The default is the single pass in mixed
-precision (FP32 stencil and vectors, FP64 reductions, accumulators and
-reliable updates) with per-shift refinement, so that every shift's FP64 true
-residual meets the tolerance.  ``value`` is f(A) b evaluations (one per
+(--pass, --precision, --deferred, --refine).  The default is the fastest form
+that meets the tolerance on every shift: the single pass in FP64 with the
+shift vectors updated once per outer iteration from the iteration's seed
+basis (deferred).  The mixed-precision forms (FP32 stencil and vectors, FP64
+reductions, accumulators and reliable updates; with per-shift refinement to
+reach the tolerance) are in the comparison block with their errors.  ``value`` is f(A) b evaluations (one per
 source) per second over the K timed steps.  Every kernel launch inside the timed steps is
 bracketed by HIP events on its stream (the library's timing hook); the stencil
 kernel's algorithmic bytes over its summed event time give roofline.achieved.
@@ -70,9 +72,9 @@ def run_variant(ctx, b, a, sig, w, l, tol, max_outer, pass_, mixed, persistent=F
     return y, info, e0.elapsed_time(e1), prof
 
 
-def workload_key(pass_, precision, refine, persistent):
-    return (f"{WORKLOAD} 12 rhs {precision} pass {pass_}" + (" refine" if refine else "")
-            + (" persistent" if persistent else ""))
+def workload_key(pass_, precision, refine, persistent, deferred=False):
+    return (f"{WORKLOAD} 12 rhs {precision} pass {pass_}" + (" deferred" if deferred else "")
+            + (" refine" if refine else "") + (" persistent" if persistent else ""))
 
 
 def measured_traffic(key):
@@ -119,9 +121,11 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--pass", dest="pass_", type=int, default=1, choices=(1, 2))
-    ap.add_argument("--precision", default="mixed", choices=("fp64", "mixed"))
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
+    ap.add_argument("--deferred", default="auto", choices=("auto", "on", "off"),
+                    help="pass 1: shift vectors updated once per outer iteration; auto: on for pass 1")
     ap.add_argument("--refine", default="auto", choices=("auto", "on", "off"),
-                    help="per-shift FP64 true residual + refinement (pass 1); auto: on for pass 1")
+                    help="per-shift FP64 true residual + refinement (pass 1); auto: on for mixed pass 1")
     ap.add_argument("--launch", default="stages", choices=("stages", "persistent"),
                     help="one launch per stage, or the whole pass in one cooperative launch")
     ap.add_argument("--variants", default="all", choices=("all", "none"))
@@ -164,11 +168,12 @@ def main():
     mixed = args.precision == "mixed"
     persistent = args.launch == "persistent"
     refine = args.pass_ == 1 and (args.refine == "on" or (args.refine == "auto" and mixed))
+    deferred = args.pass_ == 1 and args.deferred != "off" and not persistent
     log(f"[bench] spectral radius {rho:.6f}; headline pass={args.pass_} {args.precision} {args.launch}")
 
     for i in range(args.warmup):
         _, info, ms, _ = run_variant(ctx, b, a, sig, w, l, wk.tol, args.max_outer, args.pass_, mixed, persistent,
-                                     refine=refine)
+                                     refine=refine, deferred=deferred)
         log(f"[bench] warmup {i}: {ms:.1f} ms, M={info.outer_iters}, status {info.status}")
 
     # ---- timed steps (library timing hook on) ----
@@ -182,7 +187,7 @@ def main():
     y = None
     for k in range(args.steps):
         y, info, _ = ctx.mshift_bicgstabl(b, a, sig, w, l, wk.tol, args.max_outer, args.pass_,
-                                          flags=solver_flags(mixed, persistent, refine),
+                                          flags=solver_flags(mixed, persistent, refine, deferred),
                                           allow=(msb.OK, msb.NOT_CONVERGED))
         infos.append(info)
     e1.record()
@@ -219,7 +224,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{WORKLOAD} Wilson-Dirac mu=0.05 m=-2, 12 point sources, "
                                f"Neuberger N_s={wk.n_shift}, BiCGstab(l={l}), tol {wk.tol}",
-                   "pass": args.pass_, "precision": args.precision, "refine": refine, "launch": args.launch,
+                   "pass": args.pass_, "precision": args.precision, "deferred": deferred, "refine": refine,
+                   "launch": args.launch,
                    "rhs": nrhs,
                    "n_shift": wk.n_shift, "l": l, "outer_iters": info.outer_iters,
                    "mv_count": info.mv_count, "status": info.status,
@@ -230,7 +236,8 @@ def main():
         "hbm_GBps_whole_call": round(info.bytes_model / (ms_step / 1e3) / 1e9, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(workload_key(args.pass_, args.precision, refine, persistent)),
+                     "traffic": measured_traffic(workload_key(args.pass_, args.precision, refine, persistent,
+                                                              deferred)),
                      "kernel": "dslash (Wilson stencil, all epilogues)",
                      "launches": st["count"],
                      "avg_launch_us": round(st["ms"] * 1e3 / max(st["count"], 1), 2),
