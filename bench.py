@@ -120,7 +120,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--pass", dest="pass_", type=int, default=1, choices=(1, 2))
+    ap.add_argument("--pass", dest="pass_", type=int, default=1, choices=(1, 2, 3),
+                    help="1 single pass, 2 double pass, 3 pseudo-double pass (Mv outputs stored)")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
     ap.add_argument("--deferred", default="auto", choices=("auto", "on", "off"),
                     help="pass 1: shift vectors updated once per outer iteration; auto: on for pass 1")
@@ -255,7 +256,7 @@ def main():
                  (2, True, False, False, False), (1, True, False, True, False),
                  (1, False, False, False, True), (1, True, False, False, True), (1, True, False, True, True),
                  (1, False, True, False, False), (2, False, True, False, False), (1, True, True, False, False),
-                 (2, True, True, False, False)]
+                 (2, True, True, False, False), (3, False, False, False, False), (3, True, False, False, False)]
         for (p, mx, pe, rf, df) in forms:
             name = (f"{p}pass-{'mixed' if mx else 'fp64'}{'-refine' if rf else ''}{'-deferred' if df else ''}"
                     f"-{'persistent' if pe else 'stages'}")

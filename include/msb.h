@@ -153,6 +153,13 @@ int wilson_apply(msb_ctx *ctx, const void *in, void *out, int nrhs, int flags);
  *   l                degree of the MR polynomial, 1..8
  *   pass             1: single-pass (N_s (l+1) shift vectors);
  *                    2: double-pass (no shift vectors, 4 M l Mv)
+ *                    3: pseudo-double-pass (Section 2, the second option
+ *                       after Eq. 2.2; Table 1): the first pass keeps all
+ *                       2 M l Mv outputs in device memory (2 M l vectors
+ *                       per right-hand side, plus M FP64 vectors with
+ *                       MSB_MIXED), and y is summed from them after the
+ *                       sweep: 2 M l Mv.  Not with MSB_PERSISTENT.  Fails
+ *                       with MSB_ERR_OOM when the vectors do not fit.
  *   flags            MSB_MIXED, MSB_PERSISTENT, MSB_ADJOINT, MSB_REFINE (pass 1),
  *                    MSB_DEFERRED (pass 1, not with MSB_PERSISTENT)
  *   b                device [nrhs][12][V] complex128

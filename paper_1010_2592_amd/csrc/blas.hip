@@ -107,6 +107,39 @@ __global__ __launch_bounds__(BLOCK) void k_defer_update(VecArgs<T> a) {
     }
 }
 
+// pseudo-double pass: the stored Mv outputs of one storage chunk, weighted
+// by the transposed sweep's coefficients, added to y (FP64)
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_pstore_sum(double2 *y, const C<T> *V, long v_rs, const double2 *rel,
+                                                      long rel_ms, const ReplayStep *rs, const ReplayOuter *ro,
+                                                      int Mcap, int l, int m0, int mc, long n) {
+    const int rhs = blockIdx.y;
+    const C<T> *Vr = V + (size_t)rhs * v_rs;
+    const double2 *relr = rel ? rel + (size_t)rhs * n : nullptr;
+    const ReplayStep *rsr = rs + (size_t)rhs * Mcap * l;
+    const ReplayOuter *ror = ro + (size_t)rhs * Mcap;
+    double2 *yr = y + (size_t)rhs * n;
+    for (long e = (long)blockIdx.x * BLOCK + threadIdx.x; e < n; e += (long)gridDim.x * BLOCK) {
+        double2 acc = yr[e];
+        for (int mm = 0; mm < mc; ++mm) {
+            const int m = m0 + mm;
+            for (int j = 0; j < l; ++j) {
+                const ReplayStep &q = rsr[(size_t)m * l + j];
+                if (q.flag >= 1) {
+                    const C<T> v = Vr[((size_t)mm * 2 * l + 2 * j) * n + e];
+                    acc = cfma(q.cu, d2((double)v.x, (double)v.y), acc);
+                }
+                if (q.flag >= 2) {
+                    const C<T> v = Vr[((size_t)mm * 2 * l + 2 * j + 1) * n + e];
+                    acc = cfma(q.cr, d2((double)v.x, (double)v.y), acc);
+                }
+            }
+            if (relr && ror[m].rel) acc = cfma(ror[m].crel, relr[(size_t)mm * rel_ms + e], acc);
+        }
+        yr[e] = acc;
+    }
+}
+
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_convert_in(C<T> *dst, const double2 *src, long n, long ds, long ss) {
@@ -314,6 +347,14 @@ void launch_defer_update(hipStream_t st, const VecArgs<T> &a, int nrhs, int nblk
 }
 
 template <typename T>
+void launch_pstore_sum(hipStream_t st, double2 *y, const C<T> *V, long v_rs, const double2 *rel, long rel_ms,
+                       const ReplayStep *rs, const ReplayOuter *ro, int Mcap, int l, int m0, int mc, long n,
+                       int nrhs, int nblk) {
+    hipLaunchKernelGGL((k_pstore_sum<T>), dim3(nblk, nrhs), dim3(BLOCK), 0, st, y, V, v_rs, rel, rel_ms, rs, ro,
+                       Mcap, l, m0, mc, n);
+}
+
+template <typename T>
 void launch_rel_update(hipStream_t st, const VecArgs<T> &a, const double2 *b, const double2 *v, double2 *y,
                        CoefRef yc, int nrhs, int nblk) {
     hipLaunchKernelGGL((k_rel_update<T>), dim3(nblk, nrhs), dim3(BLOCK), 0, st, a, b, v, y, yc);
@@ -369,6 +410,8 @@ void launch_axpy_host(hipStream_t st, double2 *y, const double2 *x, double2 a, l
     template void launch_r_update<T>(hipStream_t, const VecArgs<T> &, int, bool, bool, int, int); \
     template void launch_gram<T>(hipStream_t, const VecArgs<T> &, int, int);                     \
     template void launch_snapshot<T>(hipStream_t, const VecArgs<T> &, int, int);                 \
+    template void launch_pstore_sum<T>(hipStream_t, double2 *, const C<T> *, long, const double2 *, long, \
+                                       const ReplayStep *, const ReplayOuter *, int, int, int, int, long, int, int); \
     template void launch_defer_update<T>(hipStream_t, const VecArgs<T> &, int, int);             \
     template void launch_mr_update<T>(hipStream_t, const VecArgs<T> &, bool, bool, int, int);    \
     template void launch_rel_update<T>(hipStream_t, const VecArgs<T> &, const double2 *, const double2 *, double2 *, CoefRef, int, int); \

@@ -43,7 +43,9 @@ int make_params(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
     if (l < 1 || l > msb::LMAX) return arg_error(w + ": l must be in 1.." + std::to_string(msb::LMAX));
     if (!(tol > 0.0) || !std::isfinite(tol)) return arg_error(w + ": tol must be finite and > 0");
     if (max_outer < 1 || (long)max_outer * l > (1L << 24)) return arg_error(w + ": max_outer out of range");
-    if (pass != 1 && pass != 2) return arg_error(w + ": pass must be 1 or 2");
+    if (pass < 1 || pass > 3) return arg_error(w + ": pass must be 1, 2 or 3");
+    if (pass == 3 && (flags & MSB_PERSISTENT))
+        return arg_error(w + ": pass = 3 runs with one launch per stage, not MSB_PERSISTENT");
     if (nrhs < 1 || nrhs > 4096) return arg_error(w + ": nrhs must be in 1..4096");
     if (flags & ~(MSB_MIXED | MSB_PERSISTENT | MSB_ADJOINT | MSB_OVERLAP | MSB_REFINE | MSB_DEFERRED))
         return arg_error(w + ": unknown flag bits");

@@ -30,6 +30,10 @@ struct Ctx {
         ws_ops, ws_pctl, ws_rX, ws_rX2, ws_ry, ws_rB, ws_rR, ws_rt1, ws_rt2, ws_rsig, ws_rw, ws_Bm, ws_schist,
         ws_dc;
     int pgrid[32] = {};        // co-resident grid of the persistent kernel, per (precision, l)
+    // pseudo-double pass: stored Mv outputs (and reliable-update Mv outputs),
+    // in chunks of PSTORE_CHUNK outer iterations, kept for later calls
+    std::vector<DevBuf> pstore, prel;
+    DevBuf ws_ones;
     void *host_pinned = nullptr;
     size_t host_pinned_bytes = 0;
     // kernel timing (msb_profile_enable): HIP event pairs around launches

@@ -140,6 +140,16 @@ template <typename T> void launch_rel_update(hipStream_t, const VecArgs<T> &, co
 template <typename T> void launch_snapshot(hipStream_t, const VecArgs<T> &, int nrhs, int nblk);
 template <typename T> void launch_defer_update(hipStream_t, const VecArgs<T> &, int nrhs, int nblk);
 
+// pseudo-double pass: y += sum over outer iterations m0 .. m0+mc-1 of this
+// storage chunk of cu V^u_{m,j} + cr V^r_{m,j} (replay coefficients, step flags)
+// and, when rel is given, crel S x_m of the reliable updates.
+// V: [rhs][chunk slots][2l][n] (v_rs between rhs); rel: [chunk slots][rhs][n]
+// FP64 (rel_ms between slots).
+template <typename T>
+void launch_pstore_sum(hipStream_t, double2 *y, const C<T> *V, long v_rs, const double2 *rel, long rel_ms,
+                       const ReplayStep *rs, const ReplayOuter *ro, int Mcap, int l, int m0, int mc, long n,
+                       int nrhs, int nblk);
+
 // small utility kernels
 template <typename T>
 void launch_convert_in(hipStream_t, C<T> *dst, const double2 *src, long n, long dst_stride,

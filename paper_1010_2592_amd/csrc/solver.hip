@@ -199,9 +199,15 @@ void ctx_destroy(Ctx *c) {
                       &c->ws_tape, &c->ws_tape_gam, &c->ws_tape_outer, &c->ws_replay,
                       &c->ws_replay_outer, &c->ws_wts, &c->ws_sig0, &c->ws_cb, &c->ws_aux1,
                       &c->ws_aux2, &c->ws_aux3, &c->ws_aux4, &c->ws_bX, &c->ws_bZ, &c->ws_by,
-                      &c->ws_beta, &c->ws_bA, &c->ws_bB, &c->ws_bdots};
+                      &c->ws_beta, &c->ws_bA, &c->ws_bB, &c->ws_bdots, &c->ws_ops, &c->ws_pctl,
+                      &c->ws_rX, &c->ws_rX2, &c->ws_ry, &c->ws_rB, &c->ws_rR, &c->ws_rt1, &c->ws_rt2,
+                      &c->ws_rsig, &c->ws_rw, &c->ws_Bm, &c->ws_schist, &c->ws_dc, &c->ws_ones};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
+    for (DevBuf &b : c->pstore)
+        if (b.p) (void)hipFree(b.p);
+    for (DevBuf &b : c->prel)
+        if (b.p) (void)hipFree(b.p);
     if (c->U64) (void)hipFree(c->U64);
     if (c->U32) (void)hipFree(c->U32);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
@@ -680,6 +686,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     const long n = 12L * V;
     const int nrhs = P.nrhs, ns = P.n_shift, l = P.l;
     const bool pass1 = P.pass == 1;
+    const bool pass3 = P.pass == 3;          // pseudo-double pass: keep every Mv output
     const int nbd = (V + CHUNK - 1) / CHUNK;     // stencil partials: one per 64-site chunk
     const int nbv = nblocks_for(n);
     const long ps = part_stride(c->g);
@@ -823,7 +830,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     sa.part = part;
     sa.ps = ps;
     sa.l = l;
-    sa.record = pass1 ? 0 : 1;
+    sa.record = pass1 ? 0 : 1;            // the double and pseudo-double passes record the tape
     sa.nblk = nbv;
     if (deferred) {
         sa.sc_hist = (StepCoef *)c->ws_schist.p;
@@ -914,8 +921,30 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     // One outer iteration of the first pass: l BiCG steps, the MR step, the
     // reliable update (mixed) and the convergence step.  nr_run and nsh_act
     // (right-hand sides and shifts still iterating) only price the bytes.
-    const int mv_epi = deferred ? EPI_MVB : EPI_MV;
-    auto emit_outer = [&](Emit<T> &e, int nr_run, double nsh_act) {
+    // pseudo-double pass: every Mv output of outer iteration m goes to slot
+    // (m mod PSC) of storage chunk m / PSC, [rhs][PSC][2l][n]; with mixed
+    // precision also the FP64 S x of its reliable update, [PSC][rhs][n]
+    constexpr int PSC = 8;
+    const long ps_rs = (long)PSC * 2 * l * n;
+    auto pstore_chunk = [&](int k) -> int {
+        while ((int)c->pstore.size() <= k) c->pstore.push_back(DevBuf{});
+        CHK(ensure(c->pstore[k], (size_t)nrhs * ps_rs * cs));
+        if (mixed) {
+            while ((int)c->prel.size() <= k) c->prel.push_back(DevBuf{});
+            CHK(ensure(c->prel[k], (size_t)nrhs * PSC * n * sizeof(double2)));
+            launch_zero<double>(st, (double2 *)c->prel[k].p, (long)nrhs * PSC * n, 0, 1);
+        }
+        return 0;
+    };
+    if (pass3 && mixed) {
+        CHK(ensure(c->ws_ones, (size_t)nrhs * sizeof(double2)));
+        std::vector<double2> ones(nrhs, double2{1.0, 0.0});
+        HIPCHK(hipMemcpyAsync(c->ws_ones.p, ones.data(), nrhs * sizeof(double2), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+
+    const int mv_epi = (deferred || pass3) ? EPI_MVB : EPI_MV;
+    auto emit_outer = [&](Emit<T> &e, int nr_run, double nsh_act, int m) {
         VecArgs<T> v = va;
         ScalarArgs s = sa;
         DslashArgs<T> e1 = d1, e2 = d2;
@@ -942,6 +971,10 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             e2.v = Uv + (size_t)j * n;
             e2.gate = g_bicg;
             if (deferred) e2.out2 = Bm + (size_t)(2 + 2 * j) * n;
+            if (pass3) {
+                e2.out2 = (C<T> *)c->pstore[m / PSC].p + ((size_t)(m % PSC) * 2 * l + 2 * j) * n;
+                e2.out2_rs = ps_rs;
+            }
             e.ds(e2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
             s.nblk = nbd;
             e.scalar(OP_SC_ALPHA, s, nrhs);
@@ -957,6 +990,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             e2.out = R + (size_t)(j + 1) * n;
             e2.v = R + (size_t)j * n;
             if (deferred) e2.out2 = Bm + (size_t)(3 + 2 * j) * n;
+            if (pass3) e2.out2 = (C<T> *)c->pstore[m / PSC].p + ((size_t)(m % PSC) * 2 * l + 2 * j + 1) * n;
             e.ds(e2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
         }
         v.gate = g_run;
@@ -979,7 +1013,11 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         }
         if (mixed) {
             e.scalar(OP_SC_REL, s, nrhs);
-            reliable_update(e, v, g_rel, nullptr, CoefRef{}, nr_run);
+            if (pass3)   // keep S x of the update: slot += 1 * S x (the slot starts at zero)
+                reliable_update(e, v, g_rel, (double2 *)c->prel[m / PSC].p + (size_t)(m % PSC) * nrhs * n,
+                                CoefRef{(const char *)c->ws_ones.p, (long)sizeof(double2)}, nr_run);
+            else
+                reliable_update(e, v, g_rel, nullptr, CoefRef{}, nr_run);
         }
         e.scalar(OP_SC_CONV, s, nrhs);
     };
@@ -989,7 +1027,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     if (P.persistent) {
         // the whole first pass in one cooperative launch
         Emit<T> er(c, Emit<T>::RECORD);
-        emit_outer(er, nrhs, (double)nrhs * ns);
+        emit_outer(er, nrhs, (double)nrhs * ns, 0);
         std::vector<POp> ops = std::move(er.ops);
         persist_ops1.swap(ops);
         CHK(run_persistent<T>(c, persist_ops1, max_outer, true, l, seed, nrhs, nullptr));
@@ -998,7 +1036,8 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         double nsh_act = (double)nrhs * ns;      // active shifts over those
         Emit<T> el(c, Emit<T>::LAUNCH);
         for (int m = 0; m < max_outer; ++m) {
-            emit_outer(el, nr_run, nsh_act);
+            if (pass3 && m % PSC == 0) CHK(pstore_chunk(m / PSC));
+            emit_outer(el, nr_run, nsh_act, m);
             HIPCHK(hipGetLastError());
             HIPCHK(hipMemcpyAsync(hseed, seed, nrhs * sizeof(SeedState), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
@@ -1034,7 +1073,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 nr += 1;
                 for (int s = 0; s < ns; ++s) nsh += (fsh[(size_t)r * NSMAX + s].iters > m) ? 1.0 : 0.0;
             }
-            emit_outer(ec, nr, nsh);
+            emit_outer(ec, nr, nsh, m);
         }
         if (c->prof) {
             // attach the bytes to the stage times the kernel reported
@@ -1116,6 +1155,18 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         HIPCHK(hipMemcpyAsync(dro, router.data(), router.size() * sizeof(ReplayOuter), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(c->ws_cb.p, cb.data(), nrhs * sizeof(double2), hipMemcpyHostToDevice, st));
 
+        if (pass3) {
+            // pseudo-double pass: y = c_b b + sum_t c_t v_t over the stored Mv outputs
+            Prof p(c, CL_OTHER, nrhs * nd * (32.0 + 16.0 + (double)Mmax * (2.0 * l * cB + (mixed ? 16.0 : 0.0))));
+            launch_yinit(st, y, b, (const double2 *)c->ws_cb.p, n, nrhs, nbv);
+            for (int m0 = 0; m0 < Mmax; m0 += PSC) {
+                const int mc = std::min(PSC, Mmax - m0);
+                launch_pstore_sum<T>(st, y, (const C<T> *)c->pstore[m0 / PSC].p, ps_rs,
+                                     mixed ? (const double2 *)c->prel[m0 / PSC].p : nullptr, (long)nrhs * n, drs, dro,
+                                     Mcap, l, m0, mc, n, nrhs, nbv);
+            }
+            HIPCHK(hipGetLastError());
+        } else {
         // pass 2: regenerate the Mv outputs and accumulate y
         {
             Prof p(c, CL_OTHER, nrhs * nd * (2.0 * (l + 1) * cB + 16.0 + cB + 32.0));
@@ -1195,6 +1246,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             for (Ctx::SRec &q : c->srecs) q.pending = false;
         }
         rep->mv *= 2;
+        }
     }
 
     // ---- optional FP64 true residual of every shift (single-pass)

@@ -252,7 +252,10 @@ class Context:
                          allow=(OK,)):
         """y = sum_s w_s (A + sigma_s)^{-1} b; returns (y, info, x_shifts or None).
 
-        shifts/weights: (n_shift,) for one set, or (nrhs, n_shift) per rhs."""
+        shifts/weights: (n_shift,) for one set, or (nrhs, n_shift) per rhs.
+        pass_: 1 single pass, 2 double pass, 3 pseudo-double pass (the Mv
+        outputs of the first pass kept in device memory and summed after the
+        sweep)."""
         b = _spinors(b, self.V, "b")
         nrhs = b.shape[0]
         sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64))
