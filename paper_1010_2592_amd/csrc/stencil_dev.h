@@ -44,26 +44,14 @@ __device__ __forceinline__ void load_spin(const C<T> *__restrict__ in, int V, in
     }
 }
 
-// acc += f * (1 + SGN gamma_NU) Umat psi(sn), Umat = U (DAG=false) or U^+
-// (DAG=true), where entry (a, b) of U is Ub[(3 a + b) us]: the link in global
-// memory (us = V) or staged in LDS (us = CHUNK).
-template <typename T, int NU, int SGN, bool DAG, bool G5IN>
-__device__ __forceinline__ void hop(C<T> (&acc)[4][3], const C<T> *__restrict__ in,
-                                   const C<T> *__restrict__ Ub, int us, int V, int sn, T f) {
+// acc += f * [(1 + SGN gamma_NU) reconstruction of] Umat h for a projected
+// half-spinor h (h0, h1); Umat = U (DAG=false) or U^+ (DAG=true), where entry
+// (a, b) of U is Ub[(3 a + b) us]: the link in global memory (us = V) or
+// staged in LDS (us = CHUNK).
+template <typename T, int NU, int SGN, bool DAG>
+__device__ __forceinline__ void hop_h(C<T> (&acc)[4][3], const C<T> (&h)[2][3], const C<T> *__restrict__ Ub, int us,
+                                      T f) {
     using P = Proj<NU, SGN>;
-    C<T> h[2][3];
-    {
-        C<T> p0[3], p1[3], q0[3], q1[3];
-        load_spin<T, G5IN>(in, V, sn, 0, p0);
-        load_spin<T, G5IN>(in, V, sn, 1, p1);
-        load_spin<T, G5IN>(in, V, sn, P::P0, q0);
-        load_spin<T, G5IN>(in, V, sn, P::P1, q1);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            h[0][a] = cadd(p0[a], mulcode<P::C0>(q0[a]));
-            h[1][a] = cadd(p1[a], mulcode<P::C1>(q1[a]));
-        }
-    }
     C<T> g[2][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -102,10 +90,70 @@ __device__ __forceinline__ void hop(C<T> (&acc)[4][3], const C<T> *__restrict__ 
     }
 }
 
+// acc += f * (1 + SGN gamma_NU) Umat psi(sn), psi loaded here (one spin at a
+// time; used by the persistent kernel's stencil).
+template <typename T, int NU, int SGN, bool DAG, bool G5IN>
+__device__ __forceinline__ void hop(C<T> (&acc)[4][3], const C<T> *__restrict__ in,
+                                   const C<T> *__restrict__ Ub, int us, int V, int sn, T f) {
+    using P = Proj<NU, SGN>;
+    C<T> h[2][3];
+    {
+        C<T> p0[3], p1[3], q0[3], q1[3];
+        load_spin<T, G5IN>(in, V, sn, 0, p0);
+        load_spin<T, G5IN>(in, V, sn, 1, p1);
+        load_spin<T, G5IN>(in, V, sn, P::P0, q0);
+        load_spin<T, G5IN>(in, V, sn, P::P1, q1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            h[0][a] = cadd(p0[a], mulcode<P::C0>(q0[a]));
+            h[1][a] = cadd(p1[a], mulcode<P::C1>(q1[a]));
+        }
+    }
+    hop_h<T, NU, SGN, DAG>(acc, h, Ub, us, f);
+}
+
+// Element k (= 3 spin + colour) of site s: base in + k V is the same for the
+// whole wavefront and the site offset is a 32-bit unsigned index, so each
+// component load takes a scalar base and one vector offset per site.
+template <typename E>
+__device__ __forceinline__ E &elem(E *__restrict__ p, int k, int V, int s) {
+    return (p + (size_t)k * (unsigned)V)[(unsigned)s];
+}
+// UB = false: the plain signed index k V + s (the site-block kernel's form,
+// which the compiler schedules in fewer registers there)
+template <bool UB, typename E>
+__device__ __forceinline__ E &elem_at(E *__restrict__ p, int k, int V, int s) {
+    if constexpr (UB) return elem(p, k, V, s);
+    else return p[k * V + s];
+}
+
+// The 12 components of psi(s) ([gamma5] applied: lower spins negated).
+template <typename T, bool G5IN>
+__device__ __forceinline__ void load_site(const C<T> *__restrict__ in, int V, int s, C<T> (&b)[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        C<T> z = elem(in, k, V, s);
+        if (G5IN && k >= 6) z = cneg(z);
+        b[k] = z;
+    }
+}
+
+// h = the two independent spins of (1 + SGN gamma_NU) psi
+template <typename T, int NU, int SGN>
+__device__ __forceinline__ void project(const C<T> (&b)[12], C<T> (&h)[2][3]) {
+    using P = Proj<NU, SGN>;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        h[0][a] = cadd(b[a], mulcode<P::C0>(b[3 * P::P0 + a]));
+        h[1][a] = cadd(b[3 + a], mulcode<P::C1>(b[3 * P::P1 + a]));
+    }
+}
+
 // Where a hop finds its link: in global memory ([4][3][3][V], entry stride V)
 // or staged in LDS for a 64-site chunk ([8 hops][9][CHUNK], stride CHUNK).
 template <typename T>
 struct GlobalLinks {
+    static constexpr bool staged = false;
     const C<T> *U;
     int V;
     __device__ __forceinline__ const C<T> *at(int nu, int bwd, int sl, int) const {
@@ -116,6 +164,7 @@ struct GlobalLinks {
 };
 template <typename T>
 struct LdsLinks {
+    static constexpr bool staged = true;
     const C<T> *L;
     int base;   // first site of the chunk
     __device__ __forceinline__ const C<T> *at(int nu, int bwd, int, int s) const {
@@ -127,8 +176,12 @@ struct LdsLinks {
 // The stencil and its epilogue for sites s0, s0 + sstride, ... < V of one
 // right-hand side.  sstride exceeds V, so the loop body runs at most once;
 // keeping it a loop with a run-time bound (and every address derived from s)
-// stops the compiler from hoisting the eight hops' loads all at once, which
-// needs more than 256 VGPRs and spills.
+// stops the compiler from hoisting loads out of the caller's loop over
+// right-hand sides.  The neighbours are gathered two hops ahead: while hop k
+// is multiplied, the spinors of hops k + 1 and k + 2 are in flight (two
+// 12-component buffers; the centre site, needed by the epilogue, is the last
+// gather; with links in LDS only).  The hops are summed in the fixed order x-, x+, y-, y+, z-, z+,
+// t-, t+ whatever the form, so every stencil form gives the same bits.
 template <typename T, int EPI, bool G5IN, typename LK>
 __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &lk, const C<T> *__restrict__ in,
                                              C<T> *__restrict__ out, const C<T> *__restrict__ v,
@@ -150,35 +203,80 @@ __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &l
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[i][c] = mk<T>(0, 0);
 
-    int sf, sb;
-    sf = (x == Lx - 1) ? s - (Lx - 1) : s + 1;
-    sb = (x == 0) ? s + (Lx - 1) : s - 1;
-    hop<T, 0, -1, false, G5IN>(acc, in, lk.at(0, 0, s, s), us, V, sf, (T)1);
-    hop<T, 0, +1, true, G5IN>(acc, in, lk.at(0, 1, sb, s), us, V, sb, (T)1);
-    sf = (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx;
-    sb = (yy == 0) ? s + (Ly - 1) * Lx : s - Lx;
-    hop<T, 1, -1, false, G5IN>(acc, in, lk.at(1, 0, s, s), us, V, sf, (T)1);
-    hop<T, 1, +1, true, G5IN>(acc, in, lk.at(1, 1, sb, s), us, V, sb, (T)1);
-    sf = (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy;
-    sb = (z == 0) ? s + (Lz - 1) * sxy : s - sxy;
-    hop<T, 2, -1, false, G5IN>(acc, in, lk.at(2, 0, s, s), us, V, sf, (T)1);
-    hop<T, 2, +1, true, G5IN>(acc, in, lk.at(2, 1, sb, s), us, V, sb, (T)1);
-    sf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
-    sb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
     const T ff = (t == Lt - 1) ? a.ef * a.bc : a.ef;
     const T fb = (t == 0) ? a.eb * a.bc : a.eb;
-    hop<T, 3, -1, false, G5IN>(acc, in, lk.at(3, 0, s, s), us, V, sf, ff);
-    hop<T, 3, +1, true, G5IN>(acc, in, lk.at(3, 1, sb, s), us, V, sb, fb);
-
-    // out = scale * [gamma5] ((4+m) psi(x) - acc / 2), formed in place
+    if constexpr (!LK::staged) {
+        // links from global memory: one hop at a time (two gather buffers
+        // would cost the site-block kernel an occupancy step)
+        int sf, sb;
+        sf = (x == Lx - 1) ? s - (Lx - 1) : s + 1;
+        sb = (x == 0) ? s + (Lx - 1) : s - 1;
+        hop<T, 0, -1, false, G5IN>(acc, in, lk.at(0, 0, s, s), us, V, sf, (T)1);
+        hop<T, 0, +1, true, G5IN>(acc, in, lk.at(0, 1, sb, s), us, V, sb, (T)1);
+        sf = (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx;
+        sb = (yy == 0) ? s + (Ly - 1) * Lx : s - Lx;
+        hop<T, 1, -1, false, G5IN>(acc, in, lk.at(1, 0, s, s), us, V, sf, (T)1);
+        hop<T, 1, +1, true, G5IN>(acc, in, lk.at(1, 1, sb, s), us, V, sb, (T)1);
+        sf = (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy;
+        sb = (z == 0) ? s + (Lz - 1) * sxy : s - sxy;
+        hop<T, 2, -1, false, G5IN>(acc, in, lk.at(2, 0, s, s), us, V, sf, (T)1);
+        hop<T, 2, +1, true, G5IN>(acc, in, lk.at(2, 1, sb, s), us, V, sb, (T)1);
+        sf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
+        sb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
+        hop<T, 3, -1, false, G5IN>(acc, in, lk.at(3, 0, s, s), us, V, sf, ff);
+        hop<T, 3, +1, true, G5IN>(acc, in, lk.at(3, 1, sb, s), us, V, sb, fb);
+        // out = scale * [gamma5] ((4+m) psi(x) - acc / 2), one spin at a time
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            C<T> ps[3];
+            load_spin<T, G5IN>(in, V, s, sp, ps);
+            const T sg = ((a.g5out && sp >= 2) ? (T)-1 : (T)1) * a.scale;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                acc[sp][c] = cscale(csub(cscale(ps[c], a.diag), cscale(acc[sp][c], (T)0.5)), sg);
+        }
+    } else {
+    const int xf = (x == Lx - 1) ? s - (Lx - 1) : s + 1;
+    const int xb = (x == 0) ? s + (Lx - 1) : s - 1;
+    const int yf = (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx;
+    const int yb = (yy == 0) ? s + (Ly - 1) * Lx : s - Lx;
+    const int zf = (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy;
+    const int zb = (z == 0) ? s + (Lz - 1) * sxy : s - sxy;
+    const int tf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
+    const int tb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
+    C<T> bA[12], bB[12], h[2][3];
+    load_site<T, G5IN>(in, V, xf, bA);
+    load_site<T, G5IN>(in, V, xb, bB);
+    project<T, 0, -1>(bA, h);
+    load_site<T, G5IN>(in, V, yf, bA);
+    hop_h<T, 0, -1, false>(acc, h, lk.at(0, 0, s, s), us, (T)1);
+    project<T, 0, +1>(bB, h);
+    load_site<T, G5IN>(in, V, yb, bB);
+    hop_h<T, 0, +1, true>(acc, h, lk.at(0, 1, xb, s), us, (T)1);
+    project<T, 1, -1>(bA, h);
+    load_site<T, G5IN>(in, V, zf, bA);
+    hop_h<T, 1, -1, false>(acc, h, lk.at(1, 0, s, s), us, (T)1);
+    project<T, 1, +1>(bB, h);
+    load_site<T, G5IN>(in, V, zb, bB);
+    hop_h<T, 1, +1, true>(acc, h, lk.at(1, 1, yb, s), us, (T)1);
+    project<T, 2, -1>(bA, h);
+    load_site<T, G5IN>(in, V, tf, bA);
+    hop_h<T, 2, -1, false>(acc, h, lk.at(2, 0, s, s), us, (T)1);
+    project<T, 2, +1>(bB, h);
+    load_site<T, G5IN>(in, V, tb, bB);
+    hop_h<T, 2, +1, true>(acc, h, lk.at(2, 1, zb, s), us, (T)1);
+    project<T, 3, -1>(bA, h);
+    load_site<T, G5IN>(in, V, s, bA);    // the centre, for the diagonal term
+    hop_h<T, 3, -1, false>(acc, h, lk.at(3, 0, s, s), us, ff);
+    project<T, 3, +1>(bB, h);
+    hop_h<T, 3, +1, true>(acc, h, lk.at(3, 1, tb, s), us, fb);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp) {
-        C<T> ps[3];
-        load_spin<T, G5IN>(in, V, s, sp, ps);
         const T sg = ((a.g5out && sp >= 2) ? (T)-1 : (T)1) * a.scale;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            acc[sp][c] = cscale(csub(cscale(ps[c], a.diag), cscale(acc[sp][c], (T)0.5)), sg);
+            acc[sp][c] = cscale(csub(cscale(bA[3 * sp + c], a.diag), cscale(acc[sp][c], (T)0.5)), sg);
+    }
     }
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp) {
@@ -186,20 +284,21 @@ __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &l
         for (int c = 0; c < 3; ++c) {
             const int k = 3 * sp + c;
             C<T> o = acc[sp][c];
-            if (EPI != EPI_PLAIN) o = cadd(o, cscale(v[k * V + s], sig0));
-            out[k * V + s] = o;
-            if (EPI == EPI_MVB) out2[k * V + s] = o;
+            if (EPI != EPI_PLAIN) o = cadd(o, cscale(elem_at<LK::staged>(v, k, V, s), sig0));
+            elem_at<LK::staged>(out, k, V, s) = o;
+            if (EPI == EPI_MVB) elem_at<LK::staged>(out2, k, V, s) = o;
             if (EPI == EPI_MV || EPI == EPI_MVB) {
-                const C<T> r = rt[k * V + s];
+                const C<T> r = elem_at<LK::staged>(rt, k, V, s);
                 part[0] += (double)r.x * o.x + (double)r.y * o.y;
                 part[1] += (double)r.x * o.y - (double)r.y * o.x;
                 part[2] += (double)o.x * o.x + (double)o.y * o.y;
             }
             if (EPI == EPI_MV_Y) {
-                double2 yv = y[k * V + s];
+                double2 &yr = elem_at<LK::staged>(y, k, V, s);
+                double2 yv = yr;
                 yv.x += (double)yc.x * o.x - (double)yc.y * o.y;
                 yv.y += (double)yc.x * o.y + (double)yc.y * o.x;
-                y[k * V + s] = yv;
+                yr = yv;
             }
         }
     }
@@ -307,7 +406,8 @@ __device__ __forceinline__ void dslash_chunk(const DslashArgs<T> &a, int p) {
     }
     __syncthreads();
     const LdsLinks<T> lk{Ls, base};
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     for (int rhs = w; rhs < a.nrhs; rhs += NW) {
         if (!gate_open(a.gate, rhs)) continue;
         const RhsOps<T> o = rhs_ops<T, EPI>(a, rhs);
