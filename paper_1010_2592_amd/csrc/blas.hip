@@ -31,12 +31,14 @@ namespace {
 
 using namespace dev;
 
-template <typename T, int J>
-__global__ __launch_bounds__(BLOCK) void k_seed_u(VecArgs<T> a) { seed_u_body<T, J>(a, blockIdx.x, gridDim.x, blockIdx.y); }
+template <typename T, int J, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_seed_u(VecArgs<T> a) {
+    seed_u_body<T, J, MODE>(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
 
-template <typename T, int J, bool SHIFTS, bool XH>
+template <typename T, int J, bool SHIFTS, bool XH, bool FU>
 __global__ __launch_bounds__(BLOCK) void k_r_update(VecArgs<T> a) {
-    r_update_body<T, J, SHIFTS, XH>(a, blockIdx.x, gridDim.x, blockIdx.y);
+    r_update_body<T, J, SHIFTS, XH, FU>(a, blockIdx.x, gridDim.x, blockIdx.y);
 }
 
 template <typename T, int L>
@@ -269,35 +271,50 @@ __global__ void k_axpy_host(double2 *y, const double2 *x, double2 a, long n) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T>
-void launch_seed_u(hipStream_t st, const VecArgs<T> &a, int j, int nrhs, int nblk) {
-    dim3 g(nblk, nrhs), b(BLOCK);
+template <typename T, int MODE>
+static void seed_u_j(hipStream_t st, const VecArgs<T> &a, int j, dim3 g, dim3 b) {
     switch (j) {
-#define C_(J) case J: hipLaunchKernelGGL((k_seed_u<T, J>), g, b, 0, st, a); break;
+#define C_(J) case J: hipLaunchKernelGGL((k_seed_u<T, J, MODE>), g, b, 0, st, a); break;
         C_(0) C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7)
 #undef C_
     }
 }
 
-template <typename T, bool SH, bool XH>
+template <typename T>
+void launch_seed_u(hipStream_t st, const VecArgs<T> &a, int j, int nrhs, int nblk, int mode) {
+    dim3 g(nblk, nrhs), b(BLOCK);
+    if (mode == 1) seed_u_j<T, 1>(st, a, j, g, b);
+    else if (mode == 2) {
+        if (j >= 1) seed_u_j<T, 2>(st, a, j, g, b);
+    } else seed_u_j<T, 0>(st, a, j, g, b);
+}
+
+template <typename T, bool SH, bool XH, bool FU>
 static void r_update_j(hipStream_t st, const VecArgs<T> &a, int j, dim3 g, dim3 b) {
     switch (j) {
-#define C_(J) case J: hipLaunchKernelGGL((k_r_update<T, J, SH, XH>), g, b, 0, st, a); break;
+#define C_(J) case J: hipLaunchKernelGGL((k_r_update<T, J, SH, XH, FU>), g, b, 0, st, a); break;
         C_(0) C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7)
 #undef C_
     }
 }
 
-template <typename T>
-void launch_r_update(hipStream_t st, const VecArgs<T> &a, int j, bool shifts, bool xh, int nrhs, int nblk) {
-    dim3 g(nblk, nrhs), b(BLOCK);
+template <typename T, bool FU>
+static void r_update_f(hipStream_t st, const VecArgs<T> &a, int j, bool shifts, bool xh, dim3 g, dim3 b) {
     if (shifts) {
-        if (xh) r_update_j<T, true, true>(st, a, j, g, b);
-        else r_update_j<T, true, false>(st, a, j, g, b);
+        if (xh) r_update_j<T, true, true, FU>(st, a, j, g, b);
+        else r_update_j<T, true, false, FU>(st, a, j, g, b);
     } else {
-        if (xh) r_update_j<T, false, true>(st, a, j, g, b);
-        else r_update_j<T, false, false>(st, a, j, g, b);
+        if (xh) r_update_j<T, false, true, FU>(st, a, j, g, b);
+        else r_update_j<T, false, false, FU>(st, a, j, g, b);
     }
+}
+
+template <typename T>
+void launch_r_update(hipStream_t st, const VecArgs<T> &a, int j, bool shifts, bool xh, int nrhs, int nblk,
+                     bool fused) {
+    dim3 g(nblk, nrhs), b(BLOCK);
+    if (fused && j >= 1) r_update_f<T, true>(st, a, j, shifts, xh, g, b);
+    else r_update_f<T, false>(st, a, j, shifts, xh, g, b);
 }
 
 template <typename T>
@@ -406,8 +423,8 @@ void launch_axpy_host(hipStream_t st, double2 *y, const double2 *x, double2 a, l
 }
 
 #define INST(T)                                                                                  \
-    template void launch_seed_u<T>(hipStream_t, const VecArgs<T> &, int, int, int);              \
-    template void launch_r_update<T>(hipStream_t, const VecArgs<T> &, int, bool, bool, int, int); \
+    template void launch_seed_u<T>(hipStream_t, const VecArgs<T> &, int, int, int, int);                \
+    template void launch_r_update<T>(hipStream_t, const VecArgs<T> &, int, bool, bool, int, int, bool); \
     template void launch_gram<T>(hipStream_t, const VecArgs<T> &, int, int);                     \
     template void launch_snapshot<T>(hipStream_t, const VecArgs<T> &, int, int);                 \
     template void launch_pstore_sum<T>(hipStream_t, double2 *, const C<T> *, long, const double2 *, long, \

@@ -14,8 +14,14 @@ template <typename T>
 __device__ __forceinline__ C<T> cvt(double2 z) { return to_c<T>(z); }
 
 // ---------------------------------------------------------------------------
-template <typename T, int J>
+// u_i = r_i - beta u_i for i in [I0, I1]: MODE 0 all of 0..J (the BiCG step's
+// direction update), MODE 1 only u_J (the one the step's Mv needs; the others
+// then follow in the fused r-update), MODE 2 only u_0..u_{J-1} (completes a
+// step that ended after its Mv of u_J).
+template <typename T, int J, int MODE = 0>
 __device__ __forceinline__ void seed_u_body(const VecArgs<T> &a, int bx, int gx, int rhs) {
+    constexpr int I0 = (MODE == 1) ? J : 0;
+    constexpr int I1 = (MODE == 2) ? J - 1 : J;
     if (!gate_open(a.gate, rhs)) return;
     const long n = a.n;
     const C<T> beta = cvt<T>(ld(a.beta, rhs));
@@ -23,7 +29,7 @@ __device__ __forceinline__ void seed_u_body(const VecArgs<T> &a, int bx, int gx,
     C<T> *U = a.U + (size_t)rhs * (a.l + 1) * n;
     for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
 #pragma unroll
-        for (int i = 0; i <= J; ++i) {
+        for (int i = I0; i <= I1; ++i) {
             const C<T> r = R[i * n + e];
             const C<T> u = U[i * n + e];
             U[i * n + e] = csub(r, cmul(beta, u));
@@ -31,23 +37,41 @@ __device__ __forceinline__ void seed_u_body(const VecArgs<T> &a, int bx, int gx,
     }
 }
 
-template <typename T, int J, bool SHIFTS, bool XH>
+// r_i -= alpha u_{i+1}, i = 0..J.  FU (fused): the step's direction update of
+// u_0..u_{J-1} (u_i = r_i - beta u_i, deferred from before the Mv, which
+// needs only u_J) is done here on the same pass, with the same arithmetic:
+// u_0..u_{J-1} are read once, updated in registers and written back.
+template <typename T, int J, bool SHIFTS, bool XH, bool FU = false>
 __device__ __forceinline__ void r_update_body(const VecArgs<T> &a, int bx, int gx, int rhs) {
     if (!gate_open(a.gate, rhs)) return;
     const long n = a.n;
     const double2 alpha_d = ld(a.alpha, rhs);
     const C<T> alpha = cvt<T>(alpha_d);
     C<T> *R = a.R + (size_t)rhs * (a.l + 1) * n;
-    const C<T> *U = a.U + (size_t)rhs * (a.l + 1) * n;
+    C<T> *U = a.U + (size_t)rhs * (a.l + 1) * n;
+    const C<T> beta = FU ? cvt<T>(ld(a.beta, rhs)) : mk<T>(0, 0);
     const int nact = SHIFTS ? a.seed[rhs].nact : 0;
     const StepCoef *sc = SHIFTS ? a.sc + (size_t)rhs * NSMAX : nullptr;
     double part[1] = {0.0};
     for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
         C<T> r[J + 1], u1[J + 1];
+        C<T> u0n = mk<T>(0, 0);
 #pragma unroll
-        for (int i = 0; i <= J; ++i) {
-            r[i] = R[i * n + e];
-            u1[i] = U[(i + 1) * n + e];
+        for (int i = 0; i <= J; ++i) r[i] = R[i * n + e];
+        if (FU && J >= 1) {
+            // u_i (i < J) = r_i - beta u_i; u1[i] = u_{i+1}
+#pragma unroll
+            for (int i = 0; i < J; ++i) {
+                const C<T> un = csub(r[i], cmul(beta, U[i * n + e]));
+                U[i * n + e] = un;
+                if (i == 0) u0n = un;
+                else u1[i - 1] = un;
+            }
+            u1[J - 1] = U[J * n + e];
+            u1[J] = U[(J + 1) * n + e];
+        } else {
+#pragma unroll
+            for (int i = 0; i <= J; ++i) u1[i] = U[(i + 1) * n + e];
         }
         if (SHIFTS) {
             for (int q = 0; q < nact; ++q) {
@@ -70,7 +94,7 @@ __device__ __forceinline__ void r_update_body(const VecArgs<T> &a, int bx, int g
         }
         if (XH) {
             // seed solution x += alpha u_0, accumulated in FP64
-            const C<T> u0 = U[e];
+            const C<T> u0 = (FU && J >= 1) ? u0n : U[e];
             double2 *xh = a.XH + (size_t)rhs * n;
             xh[e] = cfma(alpha_d, d2((double)u0.x, (double)u0.y), xh[e]);
         }

@@ -235,7 +235,8 @@ namespace msb {
 
 // Launch gate: a kernel instance for right-hand side `rhs` does work only when
 // (seed == nullptr || seed[rhs].run && (!need_bicg || seed[rhs].bicg_on)) and
-// (flag == nullptr || flag[rhs * flag_stride] >= need).  The decision is
+// (flag == nullptr || flag[rhs * flag_stride] >= need, or == need with eq).
+// The decision is
 // uniform across a block (one block row per right-hand side).
 struct Gate {
     const SeedState *seed = nullptr;
@@ -243,6 +244,7 @@ struct Gate {
     const int *flag = nullptr;
     long flag_stride = 0;
     int need = 0;
+    int eq = 0;                // flag must equal need (not merely reach it)
 };
 
 __device__ inline bool gate_open(const Gate &g, int rhs) {
@@ -251,7 +253,10 @@ __device__ inline bool gate_open(const Gate &g, int rhs) {
         if (!s.run) return false;
         if (g.need_bicg && !s.bicg_on) return false;
     }
-    if (g.flag && g.flag[(long)rhs * g.flag_stride] < g.need) return false;
+    if (g.flag) {
+        const int f = g.flag[(long)rhs * g.flag_stride];
+        if (g.eq ? (f != g.need) : (f < g.need)) return false;
+    }
     return true;
 }
 

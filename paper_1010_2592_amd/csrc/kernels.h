@@ -126,8 +126,12 @@ struct VecArgs {
     const DeferCoef *dc = nullptr;  // [rhs][NSMAX]
 };
 
-template <typename T> void launch_seed_u(hipStream_t, const VecArgs<T> &, int j, int nrhs, int nblk);
-template <typename T> void launch_r_update(hipStream_t, const VecArgs<T> &, int j, bool shifts, bool xh, int nrhs, int nblk);
+// mode: 0 u_0..u_j, 1 u_j only, 2 u_0..u_{j-1} (see seed_u_body)
+template <typename T> void launch_seed_u(hipStream_t, const VecArgs<T> &, int j, int nrhs, int nblk, int mode = 0);
+// fused: the r-update also applies the step's deferred u_0..u_{j-1} update
+template <typename T>
+void launch_r_update(hipStream_t, const VecArgs<T> &, int j, bool shifts, bool xh, int nrhs, int nblk,
+                     bool fused = false);
 template <typename T> void launch_gram(hipStream_t, const VecArgs<T> &, int nrhs, int nblk);
 template <typename T> void launch_mr_update(hipStream_t, const VecArgs<T> &, bool shifts, bool xh, int nrhs, int nblk);
 // reliable update: r_0 = b - v (v = S x in FP64), partials <rt, r_0>, ||r_0||^2

@@ -541,10 +541,12 @@ struct Emit {
             record(o, a);
         }
     }
-    void seed_u(const VecArgs<T> &a, int j, int nrhs, int nblk, int cls, double bytes) {
+    // mode and fused (see launch_seed_u / launch_r_update) exist for the
+    // per-stage launches only; the persistent kernel runs the plain stages
+    void seed_u(const VecArgs<T> &a, int j, int nrhs, int nblk, int cls, double bytes, int umode = 0) {
         if (launching(cls, bytes)) {
             Prof p(c, cls, bytes);
-            launch_seed_u<T>(st, a, j, nrhs, nblk);
+            launch_seed_u<T>(st, a, j, nrhs, nblk, umode);
         } else if (mode == RECORD) {
             POp o = op(OP_SEED_U, cls, nblk * nrhs);
             o.j = j;
@@ -552,10 +554,11 @@ struct Emit {
             record(o, a);
         }
     }
-    void r_update(const VecArgs<T> &a, int j, bool shifts, bool xh, int nrhs, int nblk, int cls, double bytes) {
+    void r_update(const VecArgs<T> &a, int j, bool shifts, bool xh, int nrhs, int nblk, int cls, double bytes,
+                  bool fused = false) {
         if (launching(cls, bytes)) {
             Prof p(c, cls, bytes);
-            launch_r_update<T>(st, a, j, shifts, xh, nrhs, nblk);
+            launch_r_update<T>(st, a, j, shifts, xh, nrhs, nblk, fused);
         } else if (mode == RECORD) {
             POp o = op(OP_R_UPDATE, cls, nblk * nrhs);
             o.j = j;
@@ -944,6 +947,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     }
 
     const int mv_epi = (deferred || pass3) ? EPI_MVB : EPI_MV;
+    const bool fuse_seed = !P.persistent;   // fused direction updates (per-stage launches)
     auto emit_outer = [&](Emit<T> &e, int nr_run, double nsh_act, int m) {
         VecArgs<T> v = va;
         ScalarArgs s = sa;
@@ -960,7 +964,9 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             s.nblk2 = nbv;
             e.scalar(OP_SC_BETA, s, nrhs);
             v.gate = g_bicg;
-            e.seed_u(v, j, nrhs, nbv, CL_SEED, nr_run * 3.0 * (j + 1) * nd * cB);
+            // fused form: only u_j before its Mv; u_0..u_{j-1} in the r-update
+            const bool fu = fuse_seed && j >= 1;
+            e.seed_u(v, j, nrhs, nbv, CL_SEED, nr_run * (fu ? 3.0 : 3.0 * (j + 1)) * nd * cB, fu ? 1 : 0);
             // u_{j+1} = S u_j = a g5 D (g5 D u_j) + sigma0 u_j, <rt, u_{j+1}>
             e1.in = Uv + (size_t)j * n;
             e1.out = tmp;
@@ -982,8 +988,20 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             // seed: read r_i, u_{i+1}, write r_i; shift s (per-step form): read
             // u^s_0..j, x^s (FP64), write u^s_0..j+1, x^s
             e.r_update(v, j, shifts_step, mixed, nrhs, nbv, shifts_step ? CL_SHIFT : CL_SEED,
-                       nr_run * (3.0 * (j + 1) * cB + (mixed ? 32.0 : 0.0)) * nd +
-                           (shifts_step ? nsh_act * ((2.0 * j + 3) * cB + 32.0) * nd : 0.0));
+                       nr_run * ((fu ? 4.0 * j + 4 : 3.0 * (j + 1)) * cB + (mixed ? 32.0 : 0.0)) * nd +
+                           (shifts_step ? nsh_act * ((2.0 * j + 3) * cB + 32.0) * nd : 0.0),
+                       fu);
+            if (fu) {
+                // a step that ended after its u-Mv (alpha breakdown) still
+                // owes u_0..u_{j-1} their update, which the partial MR step reads
+                VecArgs<T> vc = v;
+                vc.gate = g_run;
+                vc.gate.flag = &seed[0].step_flag[j];
+                vc.gate.flag_stride = (long)sizeof(SeedState) / (long)sizeof(int);
+                vc.gate.need = 1;
+                vc.gate.eq = 1;
+                e.seed_u(vc, j, nrhs, nbv, CL_SEED, 0.0, 2);
+            }
             // r_{j+1} = S r_j, <rt, r_{j+1}>
             e1.in = R + (size_t)j * n;
             e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
@@ -1200,7 +1218,8 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 vb.beta = CoefRef{(const char *)&drs[idx].beta, rstride};
                 vb.alpha = CoefRef{(const char *)&drs[idx].alpha, rstride};
                 vb.gate = gu;
-                e.seed_u(vb, j, nrhs, nbv, CL_SEED, nr_m * 3.0 * (j + 1) * nd * cB);
+                const bool fu = !P.persistent && j >= 1;
+                e.seed_u(vb, j, nrhs, nbv, CL_SEED, nr_m * (fu ? 3.0 : 3.0 * (j + 1)) * nd * cB, fu ? 1 : 0);
                 e1.in = Uv + (size_t)j * n;
                 e1.out = tmp;
                 e1.gate = gu;
@@ -1212,7 +1231,15 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 e2.gate = gu;
                 e.ds(e2, nrhs, EPI_MV_Y, CL_STENCIL, ds_bytes(EPI_MV_Y, nr_m));
                 vb.gate = gr;
-                e.r_update(vb, j, false, mixed, nrhs, nbv, CL_SEED, nr_m * 3.0 * (j + 1) * nd * cB);
+                e.r_update(vb, j, false, mixed, nrhs, nbv, CL_SEED, nr_m * (fu ? 4.0 * j + 4 : 3.0 * (j + 1)) * nd * cB,
+                           fu);
+                if (fu) {
+                    // the step ended after its u-Mv: complete u_0..u_{j-1}
+                    VecArgs<T> vc = vb;
+                    vc.gate = gu;
+                    vc.gate.eq = 1;
+                    e.seed_u(vc, j, nrhs, nbv, CL_SEED, 0.0, 2);
+                }
                 e1.in = R + (size_t)j * n;
                 e1.gate = gr;
                 e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_m));

@@ -57,7 +57,9 @@ def test_persistent_bitwise_equals_launch_path(precision, pass_):
     assert np.array_equal(i0.shift_iters, i1.shift_iters)
     assert (i0.outer_iters, i0.mv_count, i0.dot_count, i0.reliable_updates) == \
         (i1.outer_iters, i1.mv_count, i1.dot_count, i1.reliable_updates)
-    assert i0.bytes_model == pytest.approx(i1.bytes_model, rel=1e-12)
+    # the per-stage path applies u_0..u_{j-1} of each BiCG step inside the
+    # r-update (same arithmetic, one pass fewer over them): fewer bytes
+    assert 0.8 * i1.bytes_model < i0.bytes_model < i1.bytes_model
 
 
 @pytest.mark.parametrize("l", [1, 2, 3, 4, 5, 6])
