@@ -9,11 +9,13 @@ every shift's relative residual.
 
 One step = one f(A) b evaluation of the 12-source batch in the headline form
 (--pass, --precision, --deferred, --refine).  The default is the fastest form
-that meets the tolerance on every shift: the single pass in FP64 with the
-shift vectors updated once per outer iteration from the iteration's seed
-basis (deferred).  The mixed-precision forms (FP32 stencil and vectors, FP64
-reductions, accumulators and reliable updates; with per-shift refinement to
-reach the tolerance) are in the comparison block with their errors.  ``value`` is f(A) b evaluations (one per
+that meets the tolerance on every shift: the pseudo-double pass in FP64 (the
+seed's 2 M l Mv outputs kept in HBM, y summed from them with the transposed
+sweep's coefficients; the same y as the single pass to rounding).  The
+single pass (per-step or deferred shift updates), the double pass and the
+mixed-precision forms (FP32 stencil and vectors, FP64 reductions,
+accumulators and reliable updates; with per-shift refinement to reach the
+tolerance) are in the comparison block with their errors.  ``value`` is f(A) b evaluations (one per
 source) per second over the K timed steps.  Every kernel launch inside the timed steps is
 bracketed by HIP events on its stream (the library's timing hook); the stencil
 kernel's algorithmic bytes over its summed event time give roofline.achieved.
@@ -120,7 +122,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--pass", dest="pass_", type=int, default=1, choices=(1, 2, 3),
+    ap.add_argument("--pass", dest="pass_", type=int, default=3, choices=(1, 2, 3),
                     help="1 single pass, 2 double pass, 3 pseudo-double pass (Mv outputs stored)")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
     ap.add_argument("--deferred", default="auto", choices=("auto", "on", "off"),
