@@ -7,8 +7,9 @@
  *     f(A) b  ~  y = sum_s w_s (A + sigma_s)^{-1} b,          (Eq. 1.2)
  *
  * for A = a (gamma5 D_w(mu))^2 with one Krylov space for all shifts
- * (shift invariance, Section 1), in the single-pass form and in the
- * double-pass form of Section 2 (option 1 after Eq. 2.2; Section 5), and
+ * (shift invariance, Section 1), in the single-pass form, the double-pass
+ * form of Section 2 (option 1 after Eq. 2.2; Section 5) and the
+ * pseudo-double-pass form (option 2 after Eq. 2.2), and
  * from it sign(H) b and the overlap operator D_ov = 1 + gamma5 sign(H)
  * (Eq. 1.1).  D_w(mu) is the Wilson-Dirac operator with the chemical
  * potential on the time links:

@@ -303,3 +303,25 @@ def test_refine_needs_single_pass():
     with pytest.raises(msb.MsbError) as e:
         ctx.mshift_bicgstabl(cuda(b), a, sig, w, 2, wk.tol, 100, 2, flags=msb.MIXED | msb.REFINE)
     assert e.value.status == msb.ERR_ARG
+
+
+def test_l8_every_form_matches_oracle():
+    """l = 8 (the largest MR degree): single (per step and deferred), double
+    and pseudo-double pass against the oracle's iteration, forced M_s."""
+    from paper_1010_2592_amd import msb
+    wk, U, op, a, sig, w, b = problem("4x4x4x8")
+    log("l = 8, every form, 4x4x4x8")
+    force = np.full(len(sig), 3)
+    y1, i1, _ = oracle_run(op, a, b[0], sig, w, 8, wk.tol, 3, 1, force=force)
+    y2, _ = oracle_run(op, a, b[0], sig, w, 8, wk.tol, 3, 2, force=force)
+    # l = 8 amplifies rounding: the oracle's own two passes differ by ~2e-10
+    bound = parity_bound(op, a, b[0], sig, w, 8, wk.tol, force, y1)
+    ctx = ctx_for(wk, U)
+    allow = (msb.OK, msb.NOT_CONVERGED)
+    for pass_, flags, ref in ((1, 0, y1), (1, msb.DEFERRED, y1), (2, 0, y2), (3, 0, y2)):
+        y, info, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 8, wk.tol, 3, pass_, flags=flags, force_iters=force,
+                                          allow=allow)
+        log(f"  pass {pass_} flags {flags}: rel err {rel(host(y)[0], ref):.2e} (bound {bound:.1e}), "
+            f"M {info.outer_iters}")
+        assert info.outer_iters == 3
+        assert rel(host(y)[0], ref) <= bound
