@@ -175,6 +175,27 @@ int mshift_bicgstabl(msb_ctx *ctx, double a_scale, int n_shift,
                      int pass, int flags, int nrhs, const void *b, void *y,
                      void *x_shifts, msb_solve_info *info);
 
+/* Multi-shift conjugate gradients for the same sum when A is Hermitian,
+ * i.e. the context has mu = 0 (then gamma5 D_w is Hermitian and
+ * A = a (gamma5 D_w)^2 >= 0): y = sum_s w_s (A + sigma_s)^{-1} b.  The CG
+ * setting of Neuberger's double pass, the model of Section 2, and of the
+ * pseudo-double pass the concluding section proposes for CG.
+ *   pass  1: single pass (per shift a direction and a solution vector);
+ *         2: double pass (scalars recorded, the seed residuals regenerated
+ *            and summed with coefficients from a backward recurrence:
+ *            2N - 1 Mv for N iterations);
+ *         3: pseudo-double pass (the N seed residuals kept in device memory;
+ *            N Mv; fails with MSB_ERR_OOM when they do not fit).
+ *   max_iter   CG iteration limit; shift s freezes at the first iteration k
+ *              with ||r_k|| / |zeta^s_k| <= tol ||b|| (info->shift_iters).
+ *   flags      must be 0 (FP64, one launch per stage).
+ *   Other arguments, layouts and returns as mshift_bicgstabl; info reports
+ *   outer_iters = bicg_steps = N.  Returns MSB_ERR_ARG when mu != 0. */
+int mshift_cg(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
+              const double *weights, int per_rhs_shift_sets, double tol, int max_iter,
+              int pass, int flags, int nrhs, const void *b, void *y, void *x_shifts,
+              msb_solve_info *info);
+
 /* out = sign(H) b = sqrt(a_scale) H y, y the PFE solve above (Section 1,
  * sign z = z / sqrt(z^2)); with MSB_OVERLAP out = b + gamma5 sign(H) b, the
  * overlap operator of Eq. 1.1.  Arguments as for mshift_bicgstabl. */

@@ -212,6 +212,23 @@ int mshift_bicgstabl(msb_ctx *ctx, double a_scale, int n_shift, const double *sh
     return finish(rc, R, info, nrhs, n_shift);
 }
 
+int mshift_cg(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts, const double *weights,
+              int per_rhs_shift_sets, double tol, int max_iter, int pass, int flags, int nrhs, const void *b,
+              void *y, void *x_shifts, msb_solve_info *info) {
+    msb::SolveParams P;
+    if (flags != 0) return arg_error("mshift_cg: no flags apply (FP64, one launch per stage)");
+    int rc = make_params(ctx, a_scale, n_shift, shifts, weights, per_rhs_shift_sets, 1, tol, max_iter, pass, 0,
+                         nrhs, "mshift_cg", &P);
+    if (rc) return rc;
+    if (ctx->c.mu != 0.0) return arg_error("mshift_cg: needs mu = 0 (A Hermitian); use mshift_bicgstabl");
+    if (!b || !y) return arg_error("mshift_cg: b and y are required");
+    if (x_shifts && pass != 1) return arg_error("mshift_cg: x_shifts needs pass = 1");
+    P.force_iters = info ? info->force_iters : nullptr;
+    msb::SolveReport R;
+    rc = msb::solve_cg(&ctx->c, P, (const double2 *)b, (double2 *)y, (double2 *)x_shifts, &R);
+    return finish(rc, R, info, nrhs, n_shift);
+}
+
 int pfe_sign_apply(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
                    const double *weights, int l, double tol, int max_outer, int pass, int flags,
                    int nrhs, const void *b, void *out, msb_solve_info *info) {

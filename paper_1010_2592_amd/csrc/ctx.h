@@ -28,10 +28,12 @@ struct Ctx {
         ws_mc, ws_tape, ws_tape_gam, ws_tape_outer, ws_replay, ws_replay_outer, ws_wts, ws_sig0,
         ws_cb, ws_aux1, ws_aux2, ws_aux3, ws_aux4, ws_bX, ws_bZ, ws_by, ws_beta, ws_bA, ws_bB, ws_bdots,
         ws_ops, ws_pctl, ws_rX, ws_rX2, ws_ry, ws_rB, ws_rR, ws_rt1, ws_rt2, ws_rsig, ws_rw, ws_Bm, ws_schist,
-        ws_dc;
+        ws_dc, ws_cg_r, ws_cg_p, ws_cg_w, ws_cg_P, ws_cg_seed, ws_cg_shift, ws_cg_coef, ws_cg_tape, ws_cg_c,
+        ws_cg_n;
     int pgrid[32] = {};        // co-resident grid of the persistent kernel, per (precision, l)
-    // pseudo-double pass: stored Mv outputs (and reliable-update Mv outputs),
-    // in chunks of PSTORE_CHUNK outer iterations, kept for later calls
+    // pseudo-double passes: stored Mv outputs (and reliable-update Mv
+    // outputs) of BiCGstab(l), or stored residuals of CG, in chunks, kept for
+    // later calls
     std::vector<DevBuf> pstore, prel;
     DevBuf ws_ones;
     void *host_pinned = nullptr;
@@ -122,6 +124,9 @@ int apply_wilson(Ctx *c, const double2 *in, double2 *out, int nrhs, int flags);
 int spectral_radius(Ctx *c, const double2 *start, int iters, double *rho);
 int solve_mshift(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2 *x_shifts,
                  bool want_true_resid, SolveReport *rep);
+// multi-shift CG (A Hermitian: mu = 0); P.max_outer is the iteration limit,
+// P.l is unused
+int solve_cg(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2 *x_shifts, SolveReport *rep);
 int sign_apply(Ctx *c, const SolveParams &P, const double2 *b, double2 *out, bool overlap,
                SolveReport *rep);
 int sign_backward(Ctx *c, const SolveParams &P, const double2 *b, const double2 *eta, int mode,

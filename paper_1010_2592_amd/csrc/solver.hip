@@ -201,7 +201,9 @@ void ctx_destroy(Ctx *c) {
                       &c->ws_aux2, &c->ws_aux3, &c->ws_aux4, &c->ws_bX, &c->ws_bZ, &c->ws_by,
                       &c->ws_beta, &c->ws_bA, &c->ws_bB, &c->ws_bdots, &c->ws_ops, &c->ws_pctl,
                       &c->ws_rX, &c->ws_rX2, &c->ws_ry, &c->ws_rB, &c->ws_rR, &c->ws_rt1, &c->ws_rt2,
-                      &c->ws_rsig, &c->ws_rw, &c->ws_Bm, &c->ws_schist, &c->ws_dc, &c->ws_ones};
+                      &c->ws_rsig, &c->ws_rw, &c->ws_Bm, &c->ws_schist, &c->ws_dc, &c->ws_ones,
+                      &c->ws_cg_r, &c->ws_cg_p, &c->ws_cg_w, &c->ws_cg_P, &c->ws_cg_seed, &c->ws_cg_shift,
+                      &c->ws_cg_coef, &c->ws_cg_tape, &c->ws_cg_c, &c->ws_cg_n};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (DevBuf &b : c->pstore)

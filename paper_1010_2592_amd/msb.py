@@ -86,6 +86,8 @@ def lib():
         L.wilson_apply.argtypes = [_P, _P, _P, _I, _I]
         L.mshift_bicgstabl.argtypes = [_P, _D, _I, _DP, _DP, _I, _I, _D, _I, _I, _I, _I,
                                        _P, _P, _P, ctypes.POINTER(_Info)]
+        L.mshift_cg.argtypes = [_P, _D, _I, _DP, _DP, _I, _D, _I, _I, _I, _I, _P, _P, _P,
+                                ctypes.POINTER(_Info)]
         L.pfe_sign_apply.argtypes = [_P, _D, _I, _DP, _DP, _I, _D, _I, _I, _I, _I, _P, _P,
                                      ctypes.POINTER(_Info)]
         L.pfe_sign_backward.argtypes = [_P, _D, _I, _DP, _DP, _I, _D, _I, _I, _I, _P, _P, _I,
@@ -94,7 +96,7 @@ def lib():
         L.msb_profile_read.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_longlong), _DP, _DP]
         for f in ("msb_create", "msb_set_stream", "msb_neuberger_pfe", "msb_spectral_radius",
                   "msb_profile_enable", "msb_profile_read",
-                  "wilson_apply", "mshift_bicgstabl", "pfe_sign_apply", "pfe_sign_backward"):
+                  "wilson_apply", "mshift_bicgstabl", "mshift_cg", "pfe_sign_apply", "pfe_sign_backward"):
             getattr(L, f).restype = _I
         _LIB = L
     return _LIB
@@ -274,6 +276,27 @@ class Context:
         _check(rc, allow)
         return y, self._pack_info(info, keep, nrhs, ns), xs
 
+    def mshift_cg(self, b: torch.Tensor, a_scale: float, shifts, weights, tol: float, max_iter: int,
+                  pass_: int = 1, want_shifts: bool = False, force_iters=None, allow=(OK,)):
+        """Multi-shift CG (the context must have mu = 0): y = sum_s w_s (A + sigma_s)^{-1} b;
+        returns (y, info, x_shifts or None).  pass_: 1 single, 2 double, 3 pseudo-double."""
+        b = _spinors(b, self.V, "b")
+        nrhs = b.shape[0]
+        sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64))
+        wt = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        per = 1 if sh.ndim == 2 else 0
+        ns = sh.shape[-1]
+        y = torch.empty_like(b)
+        xs = torch.zeros((nrhs, ns, 12, self.V), dtype=torch.complex128, device=b.device) \
+            if want_shifts else None
+        info, keep = self._info(nrhs, ns, force_iters, False)
+        self._sync_stream()
+        rc = lib().mshift_cg(self._h, float(a_scale), ns, _dptr(sh), _dptr(wt), per, float(tol), int(max_iter),
+                             int(pass_), 0, nrhs, _P(b.data_ptr()), _P(y.data_ptr()),
+                             _P(xs.data_ptr() if xs is not None else None), ctypes.byref(info))
+        _check(rc, allow)
+        return y, self._pack_info(info, keep, nrhs, ns), xs
+
     def pfe_sign_apply(self, b: torch.Tensor, a_scale: float, shifts, weights, l: int, tol: float,
                        max_outer: int, pass_: int = 1, flags: int = 0, force_iters=None,
                        allow=(OK,)):
@@ -330,6 +353,10 @@ def spectral_radius(ctx: Context, start, iters=100):
 
 def mshift_bicgstabl(ctx: Context, b, a_scale, shifts, weights, l, tol, max_outer, pass_=1, **kw):
     return ctx.mshift_bicgstabl(b, a_scale, shifts, weights, l, tol, max_outer, pass_, **kw)
+
+
+def mshift_cg(ctx: Context, b, a_scale, shifts, weights, tol, max_iter, pass_=1, **kw):
+    return ctx.mshift_cg(b, a_scale, shifts, weights, tol, max_iter, pass_, **kw)
 
 
 def pfe_sign_apply(ctx: Context, b, a_scale, shifts, weights, l, tol, max_outer, pass_=1, **kw):

@@ -29,7 +29,7 @@ def L():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for n in ("wilson_apply", "mshift_bicgstabl", "pfe_sign_apply", "pfe_sign_backward",
+    for n in ("wilson_apply", "mshift_bicgstabl", "mshift_cg", "pfe_sign_apply", "pfe_sign_backward",
               "msb_create", "msb_destroy", "msb_last_error"):
         assert n in names
 
@@ -71,7 +71,7 @@ def test_argument_errors_need_no_gpu(L):
 
 def test_python_binding_exposes_c_names():
     from paper_1010_2592_amd import msb
-    for n in ("wilson_apply", "mshift_bicgstabl", "pfe_sign_apply", "pfe_sign_backward"):
+    for n in ("wilson_apply", "mshift_bicgstabl", "mshift_cg", "pfe_sign_apply", "pfe_sign_backward"):
         assert callable(getattr(msb, n))
     s, w = msb.neuberger_pfe(10)
     assert s.shape == (10,) and np.all(s > 0)
