@@ -95,6 +95,48 @@ def measured_traffic(key):
     return rec["traffic_bytes_per_launch"]
 
 
+def mu0_block(wk, U, b, sig, w, l):
+    """The same lattice, links and 12 sources at mu = 0, where A is Hermitian:
+    multi-shift CG (single, double, pseudo-double pass) beside BiCGstab(l)
+    (pseudo-double pass and deferred single pass), one run each after a
+    warm-up, y compared with the CG single pass."""
+    import numpy as np
+    import torch
+    from paper_1010_2592_amd import msb
+    ctx = msb.Context(msb.Lattice(wk.dims, wk.mass, 0.0, wk.bc_t), U)
+    rho = ctx.spectral_radius(torch.from_numpy(wk.power_start()[None]).to(U.device), 100)
+    a0 = 1.0 / (1.01 * rho)
+    allow = (msb.OK, msb.NOT_CONVERGED)
+    forms = [("cg-1pass", "cg", 1, 0), ("cg-2pass", "cg", 2, 0), ("cg-3pass", "cg", 3, 0),
+             (f"bicgstab{l}-3pass", "bi", 3, 0), (f"bicgstab{l}-1pass-deferred", "bi", 1, msb.DEFERRED)]
+    out, ref = {}, None
+    for name, kind, pass_, flags in forms:
+        times, info, y = [], None, None
+        for rep in range(2):
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            if kind == "cg":
+                y, info, _ = ctx.mshift_cg(b, a0, sig, w, wk.tol, 20000, pass_, allow=allow)
+            else:
+                y, info, _ = ctx.mshift_bicgstabl(b, a0, sig, w, l, wk.tol, 4000, pass_, flags=flags, allow=allow)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        if ref is None:
+            ref = y
+        out[name] = {"ms": round(times[-1], 2), "iters": info.outer_iters, "mv": info.mv_count,
+                     "status": info.status, "max_shift_resid": float(np.max(info.shift_resid)),
+                     "rel_diff_vs_cg_1pass": float(torch.linalg.norm(y - ref) / torch.linalg.norm(ref))}
+        log(f"[bench] mu=0 {name}: {out[name]}")
+        del y
+        torch.cuda.empty_cache()
+    ctx.close()
+    torch.cuda.empty_cache()
+    return {"workload": "the headline lattice, links and sources at mu = 0 (A Hermitian)", "forms": out}
+
+
 def cpu_baseline(wk, a, sig, w, l, M_gpu):
     """The oracle's double-pass on one point source for one outer iteration
     (l BiCG steps, both passes), extrapolated linearly to the GPU's M."""
@@ -288,10 +330,14 @@ def main():
             torch.cuda.empty_cache()
         result["variants"] = comps
 
+    ctx.close()
+    torch.cuda.empty_cache()
+    if args.variants == "all":
+        result["mu0"] = mu0_block(wk, U, b, sig, w, l)
+
     if not args.no_cpu:
         log("[bench] CPU oracle sample ...")
         result["cpu_baseline"] = cpu_baseline(wk, a, sig, w, l, int(info.outer_iters))
-    ctx.close()
     print(json.dumps(result), flush=True)
 
 
