@@ -327,7 +327,7 @@ class _ShiftScalars:
 
 def mshift_bicgstabl(a_mv: Callable, b: np.ndarray, sigmas, weights, l: int,
                      tol: float, max_outer: int, pass_: int = 1,
-                     force_iters=None, monitor=None, keep_shifts=False):
+                     force_iters=None, monitor=None, keep_shifts=False, shadow=None):
     """f(A) b ~ sum_s w_s (A + sigma_s)^{-1} b by multi-shift BiCGstab(l).
 
     a_mv      callable v -> A v
@@ -339,6 +339,10 @@ def mshift_bicgstabl(a_mv: Callable, b: np.ndarray, sigmas, weights, l: int,
               exactly that many outer iterations instead of testing res_s)
     monitor   optional callback(m, r0, X, scal, active) after each outer
               iteration (single-pass only), for the collinearity checks.
+    shadow    optional shadow residual r~ (default r~ = b).  BiCGstab(l)
+              admits any r~ with <r~, r_0> != 0; a point source with
+              r~ = b meets a structural breakdown on D_w, whose hopping
+              term changes the site parity.
 
     Returns (y, info) for pass 2 and (y, info, xs) for pass 1 (xs the
     per-shift solutions in caller order).
@@ -360,7 +364,7 @@ def mshift_bicgstabl(a_mv: Callable, b: np.ndarray, sigmas, weights, l: int,
 
     r = [b.astype(np.complex128).copy()] + [np.zeros_like(b, dtype=np.complex128) for _ in range(l)]
     u = [np.zeros_like(r[0]) for _ in range(l + 1)]
-    rt = r[0].copy()
+    rt = r[0].copy() if shadow is None else np.asarray(shadow, dtype=np.complex128).copy()
     bn = norm(b)
     if vectors:
         X = [np.zeros_like(r[0]) for _ in range(N)]
