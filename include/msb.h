@@ -73,6 +73,15 @@ typedef enum {
 #define MSB_DEFERRED  256   /* pass 1: shift vectors updated once per outer
                                iteration from its 2l+2 seed basis vectors (only
                                u^s_0 and x^s kept per shift)                   */
+#define MSB_OP_WILSON 512   /* mshift_bicgstabl: A = a D_w(mu) (one stencil per
+                               Mv) instead of a (gamma5 D_w)^2.  Wilson masses
+                               differ by a shift, D_w(m + sigma) = D_w(m) +
+                               sigma, so with a = 1 and sigma_s = m_s - m (m the
+                               context's mass) the single pass's x_shifts are
+                               the propagators of every mass from one Krylov
+                               space.  Not with MSB_ADJOINT, pfe_sign_apply or
+                               pfe_sign_backward (which need the Hermitian
+                               kernel H = gamma5 D_w).                          */
 #define MSB_REFINE    128   /* pass 1: after the solve, the FP64 true residual of
                                every shift; shifts above tol get refinement
                                solves (A + sigma_s) d = r_s, x_s += d (<= 3
@@ -104,6 +113,12 @@ typedef struct {
     const int *force_iters; /* in, test hook: freeze shift s after exactly
                                force_iters[...] outer iterations (no early exit) */
     int refined_shifts;     /* out (MSB_REFINE): (rhs, shift) refinement solves   */
+    const void *shadow;     /* in, mshift_bicgstabl: DEVICE [nrhs][12][V]
+                               complex128 shadow residual r~ of BiCGstab(l)
+                               (any vector with <r~, b> != 0; NULL: r~ = b).
+                               A point source with r~ = b breaks down under
+                               MSB_OP_WILSON (D_w's hops change the site
+                               parity); a random r~ avoids it.               */
 } msb_solve_info;
 
 /* Create a context on the current HIP device.  links: device pointer to
@@ -162,7 +177,8 @@ int wilson_apply(msb_ctx *ctx, const void *in, void *out, int nrhs, int flags);
  *                       sweep: 2 M l Mv.  Not with MSB_PERSISTENT.  Fails
  *                       with MSB_ERR_OOM when the vectors do not fit.
  *   flags            MSB_MIXED, MSB_PERSISTENT, MSB_ADJOINT, MSB_REFINE (pass 1),
- *                    MSB_DEFERRED (pass 1, not with MSB_PERSISTENT)
+ *                    MSB_DEFERRED (pass 1, not with MSB_PERSISTENT),
+ *                    MSB_OP_WILSON (A = a D_w; not with MSB_ADJOINT)
  *   b                device [nrhs][12][V] complex128
  *   y                device [nrhs][12][V] complex128 (written)
  *   x_shifts         device [nrhs][n_shift][12][V] complex128 or NULL

@@ -47,8 +47,11 @@ int make_params(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
     if (pass == 3 && (flags & MSB_PERSISTENT))
         return arg_error(w + ": pass = 3 runs with one launch per stage, not MSB_PERSISTENT");
     if (nrhs < 1 || nrhs > 4096) return arg_error(w + ": nrhs must be in 1..4096");
-    if (flags & ~(MSB_MIXED | MSB_PERSISTENT | MSB_ADJOINT | MSB_OVERLAP | MSB_REFINE | MSB_DEFERRED))
+    if (flags & ~(MSB_MIXED | MSB_PERSISTENT | MSB_ADJOINT | MSB_OVERLAP | MSB_REFINE | MSB_DEFERRED |
+                  MSB_OP_WILSON))
         return arg_error(w + ": unknown flag bits");
+    if ((flags & MSB_OP_WILSON) && (flags & MSB_ADJOINT))
+        return arg_error(w + ": MSB_OP_WILSON (A = a D_w) has no MSB_ADJOINT form");
     if ((flags & MSB_DEFERRED) && pass != 1)
         return arg_error(w + ": MSB_DEFERRED is a form of the single pass (pass = 1)");
     if ((flags & MSB_DEFERRED) && (flags & MSB_PERSISTENT))
@@ -71,6 +74,7 @@ int make_params(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
     P->persistent = (flags & MSB_PERSISTENT) != 0;
     P->refine = (flags & MSB_REFINE) != 0;
     P->deferred = (flags & MSB_DEFERRED) != 0;
+    P->op_wilson = (flags & MSB_OP_WILSON) != 0;
     P->nrhs = nrhs;
     P->shifts.resize((size_t)nrhs * n_shift);
     P->weights.resize((size_t)nrhs * n_shift);
@@ -206,6 +210,7 @@ int mshift_bicgstabl(msb_ctx *ctx, double a_scale, int n_shift, const double *sh
     if (x_shifts && pass != 1) return arg_error("mshift_bicgstabl: x_shifts needs pass = 1");
     if (flags & MSB_OVERLAP) return arg_error("mshift_bicgstabl: MSB_OVERLAP applies to pfe_sign_apply");
     P.force_iters = info ? info->force_iters : nullptr;
+    P.shadow = info ? (const double2 *)info->shadow : nullptr;
     msb::SolveReport R;
     const bool want_true = info && info->shift_true_resid && pass == 1;
     rc = msb::solve_mshift(&ctx->c, P, (const double2 *)b, (double2 *)y, (double2 *)x_shifts, want_true, &R);
@@ -233,6 +238,7 @@ int pfe_sign_apply(msb_ctx *ctx, double a_scale, int n_shift, const double *shif
                    const double *weights, int l, double tol, int max_outer, int pass, int flags,
                    int nrhs, const void *b, void *out, msb_solve_info *info) {
     msb::SolveParams P;
+    if (flags & MSB_OP_WILSON) return arg_error("pfe_sign_apply: the sign function needs A = a H^2, not MSB_OP_WILSON");
     int rc = make_params(ctx, a_scale, n_shift, shifts, weights, 0, l, tol, max_outer, pass, flags, nrhs,
                          "pfe_sign_apply", &P);
     if (rc) return rc;
@@ -248,7 +254,8 @@ int pfe_sign_backward(msb_ctx *ctx, double a_scale, int n_shift, const double *s
                       const void *b, const void *eta, int mode, void *grad_b, double *grad_w,
                       double *grad_sigma, void *grad_links, msb_solve_info *info) {
     msb::SolveParams P;
-    if (flags & (MSB_OVERLAP | MSB_ADJOINT)) return arg_error("pfe_sign_backward: only MSB_MIXED applies");
+    if (flags & (MSB_OVERLAP | MSB_ADJOINT | MSB_OP_WILSON))
+        return arg_error("pfe_sign_backward: only MSB_MIXED applies");
     int rc = make_params(ctx, a_scale, n_shift, shifts, weights, 0, l, tol, max_outer, 1, flags, nrhs,
                          "pfe_sign_backward", &P);
     if (rc) return rc;

@@ -94,8 +94,10 @@ struct SolveParams {
     bool persistent = false;           // one cooperative launch per pass
     bool refine = false;               // pass 1: refine shifts above tol (true residual)
     bool deferred = false;             // pass 1: shift vectors updated once per outer iteration
+    bool op_wilson = false;            // A = a D_w(mu) instead of a (g5 D_w(mu))^2
     int nrhs = 1;
     const int *force_iters = nullptr;   // [nrhs][n_shift] or null
+    const double2 *shadow = nullptr;    // [nrhs][12V] shadow residual r~, or null (r~ = b)
 };
 
 struct SolveReport {

@@ -207,6 +207,7 @@ struct ScalarArgs {
     int record = 0;                 // record the tape (double-pass)
     StepCoef *sc_hist = nullptr;    // deferred: [rhs][LMAX][NSMAX] every step's shift coefficients
     DeferCoef *dc = nullptr;        // deferred: [rhs][NSMAX] the iteration's coefficients
+    int shadow = 0;                 // init: ||r~|| from partial row 5 (r~ other than b)
 };
 
 void launch_sc_init(hipStream_t, const ScalarArgs &, int nrhs);

@@ -25,10 +25,11 @@ __device__ __forceinline__ void sc_init_body(const ScalarArgs &a, int rhs) {
     const double re = block_sum(row, a.nblk);
     const double im = block_sum(row + a.ps, a.nblk);
     const double nb2 = block_sum(row + 2 * a.ps, a.nblk);
+    const double rt2 = a.shadow ? block_sum(row + 5 * a.ps, a.nblk) : nb2;
     if (threadIdx.x == 0) {
         S.rho1 = d2(re, im);
         S.bnorm = sqrt(nb2);
-        S.rtnorm = S.bnorm;
+        S.rtnorm = sqrt(rt2);
         S.rnorm0 = S.bnorm;
         S.rnorm_j = S.bnorm;
         S.rho0 = d2(1, 0);

@@ -728,10 +728,10 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     ShiftState *sh = (ShiftState *)c->ws_shift.p;
     const C<T> *rt;
     if (sizeof(T) == sizeof(double)) {
-        rt = (const C<T> *)b;
+        rt = (const C<T> *)(P.shadow ? P.shadow : b);
     } else {
         CHK(ensure(c->ws_rt, (size_t)nrhs * n * cs));
-        launch_convert_in<T>(st, (C<T> *)c->ws_rt.p, b, n, n, n, nrhs);
+        launch_convert_in<T>(st, (C<T> *)c->ws_rt.p, P.shadow ? P.shadow : b, n, n, n, nrhs);
         rt = (const C<T> *)c->ws_rt.p;
     }
     C<T> *W = nullptr;
@@ -822,7 +822,19 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         }
         if (mixed) launch_zero<double>(st, XH, (long)nrhs * n, 0, 1);
         launch_convert_in<T>(st, R, b, n, (long)(l + 1) * n, n, nrhs);
-        launch_dot_partials<T>(st, rt, rt, n, part, ps, nrhs, nbv, Gate{});
+        if (!P.shadow) {
+            // r~ = b: <r~, r_0> and ||b||^2 in one pass
+            launch_dot_partials<T>(st, rt, rt, n, part, ps, nrhs, nbv, Gate{});
+        } else {
+            // <r~, r_0> and ||b||^2 (rows 0..2), ||r~||^2 (row 5)
+            const C<T> *r0 = (const C<T> *)b;
+            if (sizeof(T) != sizeof(double)) {
+                launch_convert_in<T>(st, tmp, b, n, n, n, nrhs);
+                r0 = tmp;
+            }
+            launch_dot_partials<T>(st, rt, r0, n, part, ps, nrhs, nbv, Gate{});
+            launch_dot_partials<T>(st, rt, rt, n, part + 3 * ps, ps, nrhs, nbv, Gate{});
+        }
     }
     ScalarArgs sa;
     sa.seed = seed;
@@ -837,6 +849,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     sa.l = l;
     sa.record = pass1 ? 0 : 1;            // the double and pseudo-double passes record the tape
     sa.nblk = nbv;
+    sa.shadow = P.shadow ? 1 : 0;
     if (deferred) {
         sa.sc_hist = (StepCoef *)c->ws_schist.p;
         sa.dc = (DeferCoef *)c->ws_dc.p;
@@ -882,10 +895,14 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     DslashArgs<T> d1 = ds_args<T>(c, P.neg_mu, true);
     d1.in_rs = vs;
     d1.out_rs = n;
+    // A = a (g5 D)^2: two stencils per Mv (g5 D into tmp, then a g5 D tmp +
+    // sigma0 v); A = a D (MSB_OP_WILSON): one stencil straight from the vector
+    const bool opw = P.op_wilson;
     DslashArgs<T> d2 = d1;
     d2.scale = (T)P.a_scale;
     d2.sigma0_rhs = (const double *)c->ws_sig0.p;
-    d2.in_rs = n;
+    d2.in_rs = opw ? vs : n;
+    if (opw) d2.g5out = 0;
     d2.out_rs = vs;
     d2.v_rs = vs;
     d2.rt = rt;
@@ -903,8 +920,8 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     r1.in = XH;
     r1.out = t64;
     r1.gate = g_rel;
-    DslashArgs<double> r2 = ds_args<double>(c, P.neg_mu, true);
-    r2.in = t64;
+    DslashArgs<double> r2 = ds_args<double>(c, P.neg_mu, !opw);
+    r2.in = opw ? XH : t64;
     r2.out = v64;
     r2.v = XH;
     r2.scale = P.a_scale;
@@ -916,7 +933,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         DslashArgs<double> q1 = r1, q2 = r2;
         q1.gate = g;
         q2.gate = g;
-        e.ds64(q1, nrhs, EPI_PLAIN, CL_STENCIL, ds64_plain * nr / std::max(nrhs, 1));
+        if (!opw) e.ds64(q1, nrhs, EPI_PLAIN, CL_STENCIL, ds64_plain * nr / std::max(nrhs, 1));
         e.ds64(q2, nrhs, EPI_SV, CL_STENCIL, ds64_sv * nr / std::max(nrhs, 1));
         VecArgs<T> w = vv;
         w.gate = g;
@@ -973,8 +990,8 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             e1.in = Uv + (size_t)j * n;
             e1.out = tmp;
             e1.gate = g_bicg;
-            e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
-            e2.in = tmp;
+            if (!opw) e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
+            e2.in = opw ? Uv + (size_t)j * n : tmp;
             e2.out = Uv + (size_t)(j + 1) * n;
             e2.v = Uv + (size_t)j * n;
             e2.gate = g_bicg;
@@ -1006,7 +1023,8 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             }
             // r_{j+1} = S r_j, <rt, r_{j+1}>
             e1.in = R + (size_t)j * n;
-            e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
+            if (!opw) e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
+            else e2.in = R + (size_t)j * n;
             e2.out = R + (size_t)(j + 1) * n;
             e2.v = R + (size_t)j * n;
             if (deferred) e2.out2 = Bm + (size_t)(3 + 2 * j) * n;
@@ -1225,8 +1243,8 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 e1.in = Uv + (size_t)j * n;
                 e1.out = tmp;
                 e1.gate = gu;
-                e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_m));
-                e2.in = tmp;
+                if (!opw) e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_m));
+                e2.in = opw ? Uv + (size_t)j * n : tmp;
                 e2.out = Uv + (size_t)(j + 1) * n;
                 e2.v = Uv + (size_t)j * n;
                 e2.ycoef = CoefRef{(const char *)&drs[idx].cu, rstride};
@@ -1244,7 +1262,8 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 }
                 e1.in = R + (size_t)j * n;
                 e1.gate = gr;
-                e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_m));
+                if (!opw) e.ds(e1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_m));
+                else e2.in = R + (size_t)j * n;
                 e2.out = R + (size_t)(j + 1) * n;
                 e2.v = R + (size_t)j * n;
                 e2.ycoef = CoefRef{(const char *)&drs[idx].cr, rstride};
@@ -1292,10 +1311,10 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             DslashArgs<double> a1 = ds_args<double>(c, P.neg_mu, true);
             a1.in = xd;
             a1.out = t1;
-            launch_dslash<double>(st, a1, nrhs, EPI_PLAIN, false);
+            if (!P.op_wilson) launch_dslash<double>(st, a1, nrhs, EPI_PLAIN, false);
             for (int r = 0; r < nrhs; ++r) {
-                DslashArgs<double> a2 = ds_args<double>(c, P.neg_mu, true);
-                a2.in = t1 + (size_t)r * n;
+                DslashArgs<double> a2 = ds_args<double>(c, P.neg_mu, !P.op_wilson);
+                a2.in = (P.op_wilson ? xd : t1) + (size_t)r * n;
                 a2.out = t2 + (size_t)r * n;
                 a2.scale = P.a_scale;
                 a2.sigma0 = P.shifts[(size_t)r * ns + s];
@@ -1402,9 +1421,10 @@ static int solve_refined(Ctx *c, const SolveParams &P, const double2 *b, double2
         d1.in = X + (size_t)s * n;
         d1.in_rs = (long)ns * n;
         d1.out = t1;
-        launch_dslash<double>(st, d1, nrhs, EPI_PLAIN, false);
-        DslashArgs<double> d2 = ds_args<double>(c, P.neg_mu, true);
-        d2.in = t1;
+        if (!P.op_wilson) launch_dslash<double>(st, d1, nrhs, EPI_PLAIN, false);
+        DslashArgs<double> d2 = ds_args<double>(c, P.neg_mu, !P.op_wilson);
+        d2.in = P.op_wilson ? X + (size_t)s * n : t1;
+        if (P.op_wilson) d2.in_rs = (long)ns * n;
         d2.out = t2;
         d2.v = X + (size_t)s * n;
         d2.v_rs = (long)ns * n;
@@ -1429,6 +1449,7 @@ static int solve_refined(Ctx *c, const SolveParams &P, const double2 *b, double2
         Q.shifts.resize(K);
         Q.weights.assign(K, 1.0);
         Q.force_iters = nullptr;
+        Q.shadow = nullptr;                // the corrections' own right-hand sides
         Q.persistent = false;
         // each correction to its own relative tolerance (factor 2 to spare)
         Q.tol_rhs.resize(K);

@@ -21,14 +21,15 @@ import torch  # noqa: F401  -- loads torch's HIP runtime first; libmsb binds to 
 
 __all__ = [
     "MsbError", "Lattice", "SolveInfo", "Context", "lib", "library_path",
-    "neuberger_pfe", "wilson_apply", "mshift_bicgstabl", "pfe_sign_apply",
+    "neuberger_pfe", "wilson_apply", "mshift_bicgstabl", "mshift_cg", "pfe_sign_apply",
     "pfe_sign_backward", "spectral_radius",
-    "G5_LEFT", "NEG_MU", "DAGGER", "MIXED", "PERSISTENT", "OVERLAP", "ADJOINT", "REFINE", "DEFERRED",
+    "G5_LEFT", "NEG_MU", "DAGGER", "MIXED", "PERSISTENT", "OVERLAP", "ADJOINT", "REFINE", "DEFERRED", "OP_WILSON",
     "OK", "ERR_ARG", "ERR_HIP", "ERR_OOM", "NOT_CONVERGED", "BREAKDOWN",
 ]
 
 OK, ERR_ARG, ERR_HIP, ERR_OOM, NOT_CONVERGED, BREAKDOWN = 0, 1, 2, 3, 4, 5
 G5_LEFT, NEG_MU, DAGGER, MIXED, PERSISTENT, OVERLAP, ADJOINT, REFINE, DEFERRED = 1, 2, 4, 8, 16, 32, 64, 128, 256
+OP_WILSON = 512     # A = a D_w instead of a (gamma5 D_w)^2 (multi-mass propagators)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -57,7 +58,7 @@ class _Info(ctypes.Structure):
                 ("shift_resid", ctypes.POINTER(ctypes.c_double)),
                 ("shift_true_resid", ctypes.POINTER(ctypes.c_double)),
                 ("force_iters", ctypes.POINTER(ctypes.c_int)),
-                ("refined_shifts", ctypes.c_int)]
+                ("refined_shifts", ctypes.c_int), ("shadow", ctypes.c_void_p)]
 
 
 _LIB = None
@@ -251,13 +252,14 @@ class Context:
     def mshift_bicgstabl(self, b: torch.Tensor, a_scale: float, shifts, weights, l: int,
                          tol: float, max_outer: int, pass_: int = 1, flags: int = 0,
                          want_shifts: bool = False, force_iters=None, true_resid: bool = False,
-                         allow=(OK,)):
+                         allow=(OK,), shadow: Optional[torch.Tensor] = None):
         """y = sum_s w_s (A + sigma_s)^{-1} b; returns (y, info, x_shifts or None).
 
         shifts/weights: (n_shift,) for one set, or (nrhs, n_shift) per rhs.
         pass_: 1 single pass, 2 double pass, 3 pseudo-double pass (the Mv
         outputs of the first pass kept in device memory and summed after the
-        sweep)."""
+        sweep).  shadow: optional shadow residual r~ of BiCGstab(l) (default
+        b; a random r~ for point sources under OP_WILSON)."""
         b = _spinors(b, self.V, "b")
         nrhs = b.shape[0]
         sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64))
@@ -268,6 +270,11 @@ class Context:
         xs = torch.zeros((nrhs, ns, 12, self.V), dtype=torch.complex128, device=b.device) \
             if want_shifts else None
         info, keep = self._info(nrhs, ns, force_iters, true_resid or bool(flags & REFINE))
+        if shadow is not None:
+            shadow = _spinors(shadow, self.V, "shadow")
+            if shadow.shape != b.shape or shadow.device != b.device:
+                raise ValueError("shadow must have the shape and device of b")
+            info.shadow = shadow.data_ptr()     # shadow (a local) outlives the call
         self._sync_stream()
         rc = lib().mshift_bicgstabl(self._h, float(a_scale), ns, _dptr(sh), _dptr(wt), per, int(l),
                                     float(tol), int(max_outer), int(pass_), int(flags), nrhs,
