@@ -1,0 +1,75 @@
+"""The configuration bench.py times: 16^3x32, the 12 point sources in one
+batch (chunked stencil), N_s = 30, BiCGstab(4), tol 1e-8, FP64.
+
+  * fixed iterations: the pseudo-double pass and the deferred single pass,
+    forced to 2 outer iterations, against the oracle's iteration for two
+    sampled sources (the oracle cannot run all 12 at this size in seconds);
+  * to convergence: pass 3's y equals the single pass's y, whose every
+    shift solution (12 x 30) meets the tolerance in its true residual,
+    formed with wilson_apply (itself pinned to the oracle elementwise).
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import dirac as od
+from oracle import krylov as ok
+from tests.helpers import cuda, host, log, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def headline():
+    import torch
+    from paper_1010_2592_amd import msb
+    wk = wl.WORKLOADS["16x16x16x32"]
+    U = wk.links()
+    ctx = msb.Context(msb.Lattice(wk.dims, wk.mass, wk.mu, wk.bc_t), cuda(U))
+    rho = ctx.spectral_radius(cuda(wk.power_start()[None]), 100)
+    a = 1.0 / (1.01 * rho)
+    sig, w = msb.neuberger_pfe(wk.n_shift)
+    b = cuda(wl.point_sources(wk.dims))
+    yield wk, U, ctx, a, sig, w, b
+    ctx.close()
+    torch.cuda.empty_cache()
+
+
+def test_headline_forced_parity_sampled_sources(headline):
+    from paper_1010_2592_amd import msb
+    wk, U, ctx, a, sig, w, b = headline
+    force = np.full(len(sig), 2)
+    allow = (msb.OK, msb.NOT_CONVERGED)
+    log("headline batch, forced 2 outer iterations: pass 3 and deferred pass 1")
+    y3, i3, _ = ctx.mshift_bicgstabl(b, a, sig, w, 4, wk.tol, 2, 3, force_iters=force, allow=allow)
+    yd, idf, _ = ctx.mshift_bicgstabl(b, a, sig, w, 4, wk.tol, 2, 1, flags=msb.DEFERRED, force_iters=force,
+                                      allow=allow)
+    op = od.Dirac(U, wk.dims, wk.mass, wk.mu, wk.bc_t)
+    ps = wl.point_sources(wk.dims)
+    for k in (0, 7):
+        ref = ok.mshift_bicgstabl(lambda v: op.a_op(v, a), ps[k], sig, w, 4, wk.tol, 2, 1, force_iters=force)[0]
+        e3, ed = rel(host(y3)[k], ref), rel(host(yd)[k], ref)
+        log(f"  source {k}: pass 3 {e3:.2e}, deferred pass 1 {ed:.2e}")
+        assert e3 <= 1e-10 and ed <= 1e-10, k
+
+
+def test_headline_converged_properties(headline):
+    import torch
+    from paper_1010_2592_amd import msb
+    wk, U, ctx, a, sig, w, b = headline
+    log("headline batch to convergence: pass 3 vs single pass, true residuals")
+    y3, i3, _ = ctx.mshift_bicgstabl(b, a, sig, w, 4, wk.tol, 400, 3)
+    y1, i1, xs = ctx.mshift_bicgstabl(b, a, sig, w, 4, wk.tol, 400, 1, want_shifts=True)
+    d = float(torch.linalg.vector_norm(y3 - y1) / torch.linalg.vector_norm(y1))
+    assert np.array_equal(i3.shift_iters, i1.shift_iters)
+    assert d <= 1e-10
+    bn = torch.linalg.vector_norm(b.reshape(12, -1), dim=1)
+    worst = 0.0
+    for s in range(len(sig)):
+        x = xs[:, s].contiguous()
+        t = ctx.wilson_apply(ctx.wilson_apply(x, msb.G5_LEFT), msb.G5_LEFT)
+        r = b - a * t - sig[s] * x
+        worst = max(worst, float((torch.linalg.vector_norm(r.reshape(12, -1), dim=1) / bn).max()))
+        del x, t, r
+    log(f"  M = {i3.outer_iters}, pass 3 vs pass 1 {d:.2e}, worst true residual {worst:.2e}")
+    assert worst <= 1.05 * wk.tol
