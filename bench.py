@@ -95,7 +95,7 @@ def measured_traffic(key):
     return rec["traffic_bytes_per_launch"]
 
 
-def mu0_block(wk, U, b, sig, w, l):
+def mu0_block(wk, U, b, sig, w, l, with_cpu=True):
     """The same lattice, links and 12 sources at mu = 0, where A is Hermitian:
     multi-shift CG (single, double, pseudo-double pass) beside BiCGstab(l)
     (pseudo-double pass and deferred single pass), one run each after a
@@ -134,10 +134,28 @@ def mu0_block(wk, U, b, sig, w, l):
         torch.cuda.empty_cache()
     ctx.close()
     torch.cuda.empty_cache()
-    return {"workload": "the headline lattice, links and sources at mu = 0 (A Hermitian)", "forms": out}
+    res = {"workload": "the headline lattice, links and sources at mu = 0 (A Hermitian)", "forms": out}
+    if with_cpu:
+        # the CG oracle's pseudo-double pass: one point source, 8 iterations,
+        # extrapolated to the GPU run's N and to 12 sources
+        from oracle import cg as ocg
+        from oracle import dirac as od
+        import workloads as wl
+        op = od.Dirac(U.cpu().numpy(), wk.dims, wk.mass, 0.0, wk.bc_t)
+        b0 = wl.point_sources(wk.dims)[0]
+        t0 = time.perf_counter()
+        ocg.mshift_cg(lambda v: op.a_op(v, a0), b0, sig, w, wk.tol, 8, 3, force_iters=np.full(len(sig), 8))
+        t8 = time.perf_counter() - t0
+        N = out["cg-3pass"]["iters"]
+        res["cpu_baseline"] = {"value": 1.0 / (t8 * N / 8), "unit": "f(A)b/s", "cores": 1, "kind": "oracle",
+                               "sample": f"CG oracle pseudo-double pass, 1 point source, 8 forced iterations in "
+                                         f"{t8:.1f} s; extrapolated to N = {N}; NumPy single-threaded",
+                               "gpu_value": round(b.shape[0] / (out["cg-3pass"]["ms"] / 1e3), 2)}
+        log(f"[bench] mu=0 CPU oracle sample: {res['cpu_baseline']}")
+    return res
 
 
-def propagator_block(wk, U, b, l):
+def propagator_block(wk, U, b, l, with_cpu=True):
     """Multi-mass Wilson propagators of the 12 point sources on the headline
     lattice (mu = 0.05): D_w(m_s)^{-1} b for five masses from one Krylov space
     (A = D_w(m_0), sigma_s = m_s - m_0; a Gaussian shadow residual), single
@@ -183,8 +201,26 @@ def propagator_block(wk, U, b, l):
         torch.cuda.empty_cache()
     ctx.close()
     torch.cuda.empty_cache()
-    return {"workload": f"12 point sources, masses {masses.tolist()}, mu = {wk.mu}, tol {wk.tol}",
-            "forms": out}
+    res = {"workload": f"12 point sources, masses {masses.tolist()}, mu = {wk.mu}, tol {wk.tol}", "forms": out}
+    if with_cpu:
+        # the oracle's multi-shift solve with A = D_w: one point source, one
+        # forced outer iteration, extrapolated to the GPU run's M and 12 sources
+        from oracle import dirac as od
+        from oracle import krylov as ok
+        op = od.Dirac(U.cpu().numpy(), wk.dims, m0, wk.mu, wk.bc_t)
+        b0 = wl.point_sources(wk.dims)[0]
+        t0 = time.perf_counter()
+        ok.mshift_bicgstabl(op.dw, b0, sig, np.ones(len(sig)), l, wk.tol, 1, 1,
+                            force_iters=np.ones(len(sig), dtype=int), shadow=wl.gaussian_source(wk.dims, 5003)[0])
+        t1 = time.perf_counter() - t0
+        M = out["fp64-deferred"]["outer_iters"]
+        res["cpu_baseline"] = {"value": len(sig) / (t1 * M), "unit": "propagators/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"oracle single pass with A = D_w, 1 point source x {len(sig)} masses, "
+                                         f"1 forced outer iteration in {t1:.1f} s; extrapolated to M = {M}; "
+                                         f"NumPy single-threaded"}
+        log(f"[bench] propagators CPU oracle sample: {res['cpu_baseline']}")
+    return res
 
 
 def cpu_baseline(wk, a, sig, w, l, M_gpu):
@@ -383,8 +419,8 @@ def main():
     ctx.close()
     torch.cuda.empty_cache()
     if args.variants == "all":
-        result["mu0"] = mu0_block(wk, U, b, sig, w, l)
-        result["propagators"] = propagator_block(wk, U, b, l)
+        result["mu0"] = mu0_block(wk, U, b, sig, w, l, with_cpu=not args.no_cpu)
+        result["propagators"] = propagator_block(wk, U, b, l, with_cpu=not args.no_cpu)
 
     if not args.no_cpu:
         log("[bench] CPU oracle sample ...")
