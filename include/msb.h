@@ -212,6 +212,36 @@ int mshift_cg(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
               int pass, int flags, int nrhs, const void *b, void *y, void *x_shifts,
               msb_solve_info *info);
 
+/* Low modes of H = gamma5 D_w at mu = 0 (H Hermitian): the nev eigenpairs of
+ * smallest |lambda|, for deflation (the paper's overlap benchmarks deflate
+ * these modes; see the figure captions of Sections 3 and 4).  Chebyshev-
+ * filtered subspace iteration on H^2 with a block of nblock >= nev + 1
+ * vectors, Rayleigh-Ritz with H.
+ *   start   device [nblock][12][V] complex128 start block (the caller's
+ *           random vectors; read only)
+ *   tol     stop when ||H v - lambda v|| <= tol * ||H|| for every mode kept
+ *   degree  Chebyshev degree per iteration (2 stencils on the block each)
+ *   evals   host [nev], sorted by |lambda|; evecs device [nev][12][V]
+ *           (orthonormal); resid host [nev] or NULL; iters host or NULL.
+ * Returns MSB_ERR_ARG when mu != 0, MSB_NOT_CONVERGED after max_iter
+ * iterations (outputs filled), MSB_BREAKDOWN if the block loses rank. */
+int msb_low_modes(msb_ctx *ctx, int nev, int nblock, const void *start, double tol,
+                  int degree, int max_iter, double *evals, void *evecs, double *resid,
+                  int *iters);
+
+/* sign(H) b (or b + gamma5 sign(H) b with MSB_OVERLAP) at mu = 0 with nev
+ * orthonormal low modes deflated:
+ *   sign(H) b = sum_k sign(lambda_k) v_k <v_k, b> + sqrt(a) H f(a H^2) P b,
+ *   P b = b - sum_k v_k <v_k, b>,
+ * the partial-fraction expansion f (Eq. 1.2) solved as in mshift_bicgstabl.
+ * evals host [nev], evecs device [nev][12][V]; other arguments as
+ * pfe_sign_apply.  Returns MSB_ERR_ARG when mu != 0. */
+int pfe_sign_apply_deflated(msb_ctx *ctx, double a_scale, int n_shift,
+                            const double *shifts, const double *weights, int l, double tol,
+                            int max_outer, int pass, int flags, int nrhs, int nev,
+                            const double *evals, const void *evecs, const void *b, void *out,
+                            msb_solve_info *info);
+
 /* out = sign(H) b = sqrt(a_scale) H y, y the PFE solve above (Section 1,
  * sign z = z / sqrt(z^2)); with MSB_OVERLAP out = b + gamma5 sign(H) b, the
  * overlap operator of Eq. 1.1.  Arguments as for mshift_bicgstabl. */

@@ -234,6 +234,40 @@ int mshift_cg(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts, c
     return finish(rc, R, info, nrhs, n_shift);
 }
 
+int msb_low_modes(msb_ctx *ctx, int nev, int nblock, const void *start, double tol, int degree, int max_iter,
+                  double *evals, void *evecs, double *resid, int *iters) {
+    if (!ctx) return arg_error("msb_low_modes: null context");
+    if (ctx->c.mu != 0.0) return arg_error("msb_low_modes: needs mu = 0 (H Hermitian)");
+    if (nev < 1 || nblock < nev + 1 || nblock > 256)
+        return arg_error("msb_low_modes: need 1 <= nev < nblock <= 256");
+    if (!start || !evals || !evecs) return arg_error("msb_low_modes: start, evals and evecs are required");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return arg_error("msb_low_modes: tol must be finite and > 0");
+    if (degree < 1 || degree > 1000 || max_iter < 0) return arg_error("msb_low_modes: degree in 1..1000, max_iter >= 0");
+    return msb::low_modes(&ctx->c, nev, nblock, (const double2 *)start, tol, degree, max_iter, evals,
+                          (double2 *)evecs, resid, iters);
+}
+
+int pfe_sign_apply_deflated(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts, const double *weights,
+                            int l, double tol, int max_outer, int pass, int flags, int nrhs, int nev,
+                            const double *evals, const void *evecs, const void *b, void *out,
+                            msb_solve_info *info) {
+    if (flags & MSB_OP_WILSON) return arg_error("pfe_sign_apply_deflated: needs A = a H^2, not MSB_OP_WILSON");
+    msb::SolveParams P;
+    int rc = make_params(ctx, a_scale, n_shift, shifts, weights, 0, l, tol, max_outer, pass, flags, nrhs,
+                         "pfe_sign_apply_deflated", &P);
+    if (rc) return rc;
+    if (ctx->c.mu != 0.0) return arg_error("pfe_sign_apply_deflated: needs mu = 0 (orthonormal low modes of H)");
+    if (nev < 1 || !evals || !evecs) return arg_error("pfe_sign_apply_deflated: nev >= 1 with evals and evecs");
+    if (!finite_array(evals, nev)) return arg_error("pfe_sign_apply_deflated: evals must be finite");
+    if (!b || !out) return arg_error("pfe_sign_apply_deflated: b and out are required");
+    if (flags & MSB_ADJOINT) return arg_error("pfe_sign_apply_deflated: MSB_ADJOINT does not apply");
+    P.force_iters = info ? info->force_iters : nullptr;
+    msb::SolveReport R;
+    rc = msb::sign_apply_deflated(&ctx->c, P, nev, evals, (const double2 *)evecs, (const double2 *)b,
+                                  (double2 *)out, (flags & MSB_OVERLAP) != 0, &R);
+    return finish(rc, R, info, nrhs, n_shift);
+}
+
 int pfe_sign_apply(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
                    const double *weights, int l, double tol, int max_outer, int pass, int flags,
                    int nrhs, const void *b, void *out, msb_solve_info *info) {

@@ -29,7 +29,8 @@ struct Ctx {
         ws_cb, ws_aux1, ws_aux2, ws_aux3, ws_aux4, ws_bX, ws_bZ, ws_by, ws_beta, ws_bA, ws_bB, ws_bdots,
         ws_ops, ws_pctl, ws_rX, ws_rX2, ws_ry, ws_rB, ws_rR, ws_rt1, ws_rt2, ws_rsig, ws_rw, ws_Bm, ws_schist,
         ws_dc, ws_cg_r, ws_cg_p, ws_cg_w, ws_cg_P, ws_cg_seed, ws_cg_shift, ws_cg_coef, ws_cg_tape, ws_cg_c,
-        ws_cg_n;
+        ws_cg_n, ws_eY, ws_eW, ws_eZ, ws_eP, ws_eS;
+    void *blas = nullptr;      // rocBLAS handle of the eigensolver and deflation (created on first use)
     int pgrid[32] = {};        // co-resident grid of the persistent kernel, per (precision, l)
     // pseudo-double passes: stored Mv outputs (and reliable-update Mv
     // outputs) of BiCGstab(l), or stored residuals of CG, in chunks, kept for
@@ -129,6 +130,14 @@ int solve_mshift(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, dou
 // multi-shift CG (A Hermitian: mu = 0); P.max_outer is the iteration limit,
 // P.l is unused
 int solve_cg(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2 *x_shifts, SolveReport *rep);
+// low modes of H = gamma5 D_w (mu = 0) by Chebyshev-filtered subspace
+// iteration on H^2 with a block of m vectors from `start` ([m][12V])
+int low_modes(Ctx *c, int nev, int m, const double2 *start, double tol, int degree, int max_iter, double *evals,
+              double2 *evecs, double *resid, int *iters);
+// sign(H) b (or the overlap) with the given orthonormal low modes deflated
+int sign_apply_deflated(Ctx *c, const SolveParams &P, int nev, const double *evals, const double2 *evecs,
+                        const double2 *b, double2 *out, bool overlap, SolveReport *rep);
+void eig_release(Ctx *c);
 int sign_apply(Ctx *c, const SolveParams &P, const double2 *b, double2 *out, bool overlap,
                SolveReport *rep);
 int sign_backward(Ctx *c, const SolveParams &P, const double2 *b, const double2 *eta, int mode,

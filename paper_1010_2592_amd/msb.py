@@ -91,13 +91,17 @@ def lib():
                                 ctypes.POINTER(_Info)]
         L.pfe_sign_apply.argtypes = [_P, _D, _I, _DP, _DP, _I, _D, _I, _I, _I, _I, _P, _P,
                                      ctypes.POINTER(_Info)]
+        L.msb_low_modes.argtypes = [_P, _I, _I, _P, _D, _I, _I, _DP, _P, _DP, ctypes.POINTER(_I)]
+        L.pfe_sign_apply_deflated.argtypes = [_P, _D, _I, _DP, _DP, _I, _D, _I, _I, _I, _I, _I, _DP, _P,
+                                              _P, _P, ctypes.POINTER(_Info)]
         L.pfe_sign_backward.argtypes = [_P, _D, _I, _DP, _DP, _I, _D, _I, _I, _I, _P, _P, _I,
                                         _P, _DP, _DP, _P, ctypes.POINTER(_Info)]
         L.msb_profile_enable.argtypes = [_P, _I]
         L.msb_profile_read.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_longlong), _DP, _DP]
         for f in ("msb_create", "msb_set_stream", "msb_neuberger_pfe", "msb_spectral_radius",
                   "msb_profile_enable", "msb_profile_read",
-                  "wilson_apply", "mshift_bicgstabl", "mshift_cg", "pfe_sign_apply", "pfe_sign_backward"):
+                  "wilson_apply", "mshift_bicgstabl", "mshift_cg", "pfe_sign_apply", "pfe_sign_backward",
+                  "msb_low_modes", "pfe_sign_apply_deflated"):
             getattr(L, f).restype = _I
         _LIB = L
     return _LIB
@@ -303,6 +307,44 @@ class Context:
                              _P(xs.data_ptr() if xs is not None else None), ctypes.byref(info))
         _check(rc, allow)
         return y, self._pack_info(info, keep, nrhs, ns), xs
+
+    def low_modes(self, nev: int, start: torch.Tensor, tol: float = 1e-10, degree: int = 24,
+                  max_iter: int = 200, allow=(OK,)):
+        """Low modes of H = gamma5 D_w (mu = 0): (evals [nev] sorted by |lambda|,
+        evecs [nev][12][V], resid [nev], iterations).  start: [nblock][12][V]
+        complex128 start block, nblock > nev."""
+        start = _spinors(start, self.V, "start")
+        ev = np.zeros(nev)
+        rs = np.zeros(nev)
+        it = ctypes.c_int(0)
+        evecs = torch.empty((nev, 12, self.V), dtype=torch.complex128, device=start.device)
+        self._sync_stream()
+        rc = lib().msb_low_modes(self._h, int(nev), start.shape[0], _P(start.data_ptr()), float(tol), int(degree),
+                                 int(max_iter), _dptr(ev), _P(evecs.data_ptr()), _dptr(rs), ctypes.byref(it))
+        _check(rc, allow)
+        return ev, evecs, rs, it.value
+
+    def pfe_sign_apply_deflated(self, b: torch.Tensor, a_scale: float, shifts, weights, l: int, tol: float,
+                                max_outer: int, evals, evecs: torch.Tensor, pass_: int = 1, flags: int = 0,
+                                allow=(OK,)):
+        """sign(H) b (or the overlap with OVERLAP) with the low modes (evals,
+        evecs) deflated; mu = 0."""
+        b = _spinors(b, self.V, "b")
+        evecs = _spinors(evecs, self.V, "evecs")
+        nrhs = b.shape[0]
+        ev = np.ascontiguousarray(np.asarray(evals, dtype=np.float64))
+        sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64))
+        wt = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        ns = sh.shape[-1]
+        out = torch.empty_like(b)
+        info, keep = self._info(nrhs, ns, None, False)
+        self._sync_stream()
+        rc = lib().pfe_sign_apply_deflated(self._h, float(a_scale), ns, _dptr(sh), _dptr(wt), int(l), float(tol),
+                                           int(max_outer), int(pass_), int(flags), nrhs, len(ev), _dptr(ev),
+                                           _P(evecs.data_ptr()), _P(b.data_ptr()), _P(out.data_ptr()),
+                                           ctypes.byref(info))
+        _check(rc, allow)
+        return out, self._pack_info(info, keep, nrhs, ns)
 
     def pfe_sign_apply(self, b: torch.Tensor, a_scale: float, shifts, weights, l: int, tol: float,
                        max_outer: int, pass_: int = 1, flags: int = 0, force_iters=None,

@@ -30,6 +30,7 @@ def L():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("wilson_apply", "mshift_bicgstabl", "mshift_cg", "pfe_sign_apply", "pfe_sign_backward",
+              "msb_low_modes", "pfe_sign_apply_deflated",
               "msb_create", "msb_destroy", "msb_last_error"):
         assert n in names
 

@@ -1,0 +1,95 @@
+"""Low-mode deflation at mu = 0 on the GPU: the eigensolver (Chebyshev-
+filtered subspace iteration on H^2, Rayleigh-Ritz with H) against the dense
+eigendecomposition, and the deflated sign function / overlap against the
+oracle fed the oracle's own low modes.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import deflation as odf
+from oracle import dirac as od
+from oracle import pfe
+from tests.helpers import cuda, host, log, rel
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (4, 4, 4, 4)
+
+
+@pytest.fixture(scope="module")
+def mu0():
+    from paper_1010_2592_amd import msb
+    U = wl.gauge_links(DIMS, 0.6, 97)
+    op = od.Dirac(U, DIMS, -2.0, 0.0, -1)
+    H = odf.dense_h(op)
+    ev, Q = np.linalg.eigh(H)
+    order = np.argsort(np.abs(ev), kind="stable")
+    ctx = msb.Context(msb.Lattice(DIMS, -2.0, 0.0, -1), cuda(U))
+    yield U, op, ev, Q, order, ctx
+    ctx.close()
+
+
+def test_low_modes_match_dense_eigenpairs(mu0):
+    U, op, ev, Q, order, ctx = mu0
+    nev, nblock = 8, 16
+    absv = np.abs(ev[order])
+    assert absv[nev] - absv[nev - 1] > 1e-6 * absv[-1]     # the kept subspace is well separated
+    start = cuda(wl.gaussian_source(DIMS, 98, nblock))
+    from paper_1010_2592_amd import msb
+    lam, vecs, res, it = ctx.low_modes(nev, start, tol=1e-11, degree=24, max_iter=300,
+                                       allow=(msb.OK, msb.NOT_CONVERGED))
+    log(f"low modes 4^4: {it} iterations, |lambda| {np.abs(lam)} vs dense {absv[:nev]}, residuals {res}")
+    assert it < 300
+    hnorm = np.abs(ev).max()
+    assert np.max(np.abs(np.abs(lam) - absv[:nev])) <= 1e-9 * hnorm
+    assert np.max(np.abs(lam - ev[order[:nev]])) <= 1e-9 * hnorm
+    v = host(vecs)
+    M = v.reshape(nev, -1)
+    assert np.abs(M.conj() @ M.T - np.eye(nev)).max() <= 1e-10
+    for k in range(nev):
+        r = np.linalg.norm(op.h(v[k]) - lam[k] * v[k])
+        assert r <= 1e-9 * hnorm, (k, r)
+    # the same subspace as the dense eigenvectors
+    Qk = Q[:, order[:nev]]
+    proj = Qk.conj().T @ M.T
+    assert np.abs(np.linalg.svd(proj, compute_uv=False) - 1).max() <= 1e-9
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_deflated_sign_matches_oracle(mu0, overlap):
+    from paper_1010_2592_amd import msb
+    U, op, ev, Q, order, ctx = mu0
+    K = 16
+    lam = ev[order[:K]]
+    vecs = np.stack([Q[:, i].reshape(12, op.V) for i in order[:K]])
+    a = 1.0 / (1.01 * np.abs(ev).max() ** 2)
+    sig, w = pfe.neuberger(10)
+    bb = wl.gaussian_source(DIMS, 99, 3)
+    out, info = ctx.pfe_sign_apply_deflated(cuda(bb), a, sig, w, 2, 1e-11, 3000, lam, cuda(vecs),
+                                            flags=msb.OVERLAP if overlap else 0)
+    for r in range(3):
+        ref = odf.sign_apply_deflated(op, a, bb[r], lam, vecs, sig, w, 2, 1e-11, 3000)
+        if overlap:
+            ref = bb[r] + od.g5(ref)
+        d = rel(host(out)[r], ref)
+        log(f"deflated {'overlap' if overlap else 'sign'} rhs {r}: rel err vs oracle {d:.2e}")
+        assert d <= 1e-9, r
+
+
+def test_deflation_argument_checks(mu0):
+    from paper_1010_2592_amd import msb
+    U, op, ev, Q, order, ctx = mu0
+    start = cuda(wl.gaussian_source(DIMS, 100, 4))
+    with pytest.raises(msb.MsbError) as e:
+        ctx.low_modes(4, start)                       # nblock must exceed nev
+    assert e.value.status == msb.ERR_ARG
+    ctx_mu = msb.Context(msb.Lattice(DIMS, -2.0, 0.05, -1), cuda(U))
+    with pytest.raises(msb.MsbError) as e:
+        ctx_mu.low_modes(2, start)
+    assert e.value.status == msb.ERR_ARG
+    sig, w = pfe.neuberger(6)
+    with pytest.raises(msb.MsbError) as e:
+        ctx_mu.pfe_sign_apply_deflated(start[:1], 0.05, sig, w, 2, 1e-8, 10, np.ones(2), start[:2])
+    assert e.value.status == msb.ERR_ARG
+    ctx_mu.close()
