@@ -155,6 +155,108 @@ def mu0_block(wk, U, b, sig, w, l, with_cpu=True):
     return res
 
 
+def deflation_block(wk, U, b, sig, w, l, with_cpu=True):
+    """Low-mode deflation at mu = 0 on the headline lattice: the 12 eigenpairs
+    of H = gamma5 D_w of smallest |lambda| (block of 24, Chebyshev degree up to
+    200), then sign(H) b for the 12 point sources with and without those modes
+    deflated (pseudo-double pass).  Reports the eigensolver's time, iterations,
+    residuals and orthonormality, both sign applications, and the PFE error
+    bound over the interval each one sees."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1010_2592_amd import msb
+    dev = U.device
+    ctx = msb.Context(msb.Lattice(wk.dims, wk.mass, 0.0, wk.bc_t), U)
+    rho = ctx.spectral_radius(torch.from_numpy(wk.power_start()[None]).to(dev), 100)
+    a0 = 1.0 / (1.01 * rho)
+    nev, nblock, degree, tol_eig = 12, 24, 200, 1e-10
+    start = torch.from_numpy(wl.gaussian_source(wk.dims, 6003, nblock)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam, vecs, res, iters = ctx.low_modes(nev, start, tol=tol_eig, degree=degree, max_iter=60,
+                                          allow=(msb.OK, msb.NOT_CONVERGED))
+    torch.cuda.synchronize()
+    t_eig = (time.perf_counter() - t0) * 1e3
+    del start
+    vm = vecs.reshape(nev, -1)
+    orth = float((vm.conj() @ vm.T - torch.eye(nev, dtype=vm.dtype, device=dev)).abs().max())
+    eig = {"nev": nev, "block": nblock, "max_degree": degree, "tol": tol_eig, "ms": round(t_eig, 1),
+           "iterations": iters, "abs_lambda": [float(x) for x in np.abs(lam)], "max_resid": float(np.max(res)),
+           "orthonormality": orth}
+    log(f"[bench] deflation low modes: {eig}")
+    allow = (msb.OK, msb.NOT_CONVERGED)
+    forms, outs = {}, {}
+    for name in ("plain", "deflated"):
+        times = []
+        for rep in range(2):
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            if name == "plain":
+                o, info = ctx.pfe_sign_apply(b, a0, sig, w, l, wk.tol, 4000, 3, allow=allow)
+            else:
+                o, info = ctx.pfe_sign_apply_deflated(b, a0, sig, w, l, wk.tol, 4000, lam, vecs, 3, allow=allow)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        outs[name] = o
+        forms[name] = {"ms": round(times[-1], 2), "outer_iters": info.outer_iters, "status": info.status}
+        log(f"[bench] deflation sign {name}: {forms[name]}")
+    forms["rel_diff"] = float(torch.linalg.norm(outs["deflated"] - outs["plain"]) / torch.linalg.norm(outs["plain"]))
+    # PFE error of sign over the interval each form sees: [a lambda_0^2, 1]
+    # without deflation; the deflated source has no component below the
+    # largest deflated |lambda| (a lower bound of the first kept one)
+
+    def pfe_err(lo):
+        x = np.logspace(np.log10(lo), 0.0, 20001)
+        return float(np.max(np.abs(np.sqrt(x) * (w[None, :] / (x[:, None] + sig[None, :])).sum(axis=1) - 1.0)))
+    absl = np.abs(lam)
+    forms["pfe_error_bound_plain"] = pfe_err(a0 * absl.min() ** 2)
+    forms["pfe_error_bound_deflated"] = pfe_err(a0 * absl.max() ** 2)
+    log(f"[bench] deflation sign: rel diff {forms['rel_diff']:.2e}, PFE bounds "
+        f"{forms['pfe_error_bound_plain']:.2e} -> {forms['pfe_error_bound_deflated']:.2e}")
+    del outs, vecs, vm
+    ctx.close()
+    torch.cuda.empty_cache()
+    res_out = {"workload": "the headline lattice, links and 12 point sources at mu = 0", "low_modes": eig,
+               "sign": forms}
+    if with_cpu:
+        # the oracle's deflation (dense eigendecomposition for the low modes,
+        # then the deflated sign of one source) on a 4^4 lattice beside the
+        # library doing the same work there
+        from oracle import deflation as odf
+        from oracle import dirac as od
+        dims = (4, 4, 4, 4)
+        Us = wl.gauge_links(dims, wk.eps, wk.gauge_seed)
+        op = od.Dirac(Us, dims, wk.mass, 0.0, wk.bc_t)
+        b0 = wl.point_sources(dims)[:1]
+        t0 = time.perf_counter()
+        lam_o, vecs_o = odf.low_modes(op, nev)
+        odf.sign_apply_deflated(op, a0, b0[0], lam_o, vecs_o, sig, w, l, wk.tol, 4000, 3)
+        t_cpu = time.perf_counter() - t0
+        cs = msb.Context(msb.Lattice(dims, wk.mass, 0.0, wk.bc_t), torch.from_numpy(Us).to(dev))
+        st = torch.from_numpy(wl.gaussian_source(dims, 6003, nblock)).to(dev)
+        bt = torch.from_numpy(b0).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lg, vg, _, _ = cs.low_modes(nev, st, tol=tol_eig, degree=degree, max_iter=60, allow=allow)
+        cs.pfe_sign_apply_deflated(bt, a0, sig, w, l, wk.tol, 4000, lg, vg, 3, allow=allow)
+        torch.cuda.synchronize()
+        t_gpu = time.perf_counter() - t0
+        cs.close()
+        res_out["cpu_baseline"] = {"value": 1.0 / t_cpu, "unit": "deflated sign applications/s (4^4, 12 modes)",
+                                   "cores": 1, "kind": "oracle",
+                                   "sample": f"oracle on a 4^4 lattice: dense eigendecomposition for 12 low modes "
+                                             f"plus the deflated sign of one point source in {t_cpu:.1f} s; "
+                                             f"NumPy (dense eigensolver threaded by LAPACK)",
+                                   "gpu_value": round(1.0 / t_gpu, 2)}
+        log(f"[bench] deflation CPU oracle sample: {res_out['cpu_baseline']}")
+    return res_out
+
+
 def propagator_block(wk, U, b, l, with_cpu=True):
     """Multi-mass Wilson propagators of the 12 point sources on the headline
     lattice (mu = 0.05): D_w(m_s)^{-1} b for five masses from one Krylov space
@@ -421,6 +523,7 @@ def main():
     if args.variants == "all":
         result["mu0"] = mu0_block(wk, U, b, sig, w, l, with_cpu=not args.no_cpu)
         result["propagators"] = propagator_block(wk, U, b, l, with_cpu=not args.no_cpu)
+        result["deflation"] = deflation_block(wk, U, b, sig, w, l, with_cpu=not args.no_cpu)
 
     if not args.no_cpu:
         log("[bench] CPU oracle sample ...")

@@ -215,12 +215,16 @@ int mshift_cg(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
 /* Low modes of H = gamma5 D_w at mu = 0 (H Hermitian): the nev eigenpairs of
  * smallest |lambda|, for deflation (the paper's overlap benchmarks deflate
  * these modes; see the figure captions of Sections 3 and 4).  Chebyshev-
- * filtered subspace iteration on H^2 with a block of nblock >= nev + 1
- * vectors, Rayleigh-Ritz with H.
+ * filtered subspace iteration on H^2 with a block of nev + 1 <= nblock <= 128
+ * vectors: Cholesky-QR, Rayleigh-Ritz with H^2 on the block (its small Ritz
+ * values cannot be spurious), then with H on the leading nev Ritz vectors
+ * (the signed eigenvalues).
  *   start   device [nblock][12][V] complex128 start block (the caller's
  *           random vectors; read only)
  *   tol     stop when ||H v - lambda v|| <= tol * ||H|| for every mode kept
- *   degree  Chebyshev degree per iteration (2 stencils on the block each)
+ *   degree  largest Chebyshev degree per iteration (2 stencils on the block
+ *           each); lowered while the filter interval is wide, so that no
+ *           direction grows by more than 1e8 in one iteration
  *   evals   host [nev], sorted by |lambda|; evecs device [nev][12][V]
  *           (orthonormal); resid host [nev] or NULL; iters host or NULL.
  * Returns MSB_ERR_ARG when mu != 0, MSB_NOT_CONVERGED after max_iter

@@ -238,8 +238,8 @@ int msb_low_modes(msb_ctx *ctx, int nev, int nblock, const void *start, double t
                   double *evals, void *evecs, double *resid, int *iters) {
     if (!ctx) return arg_error("msb_low_modes: null context");
     if (ctx->c.mu != 0.0) return arg_error("msb_low_modes: needs mu = 0 (H Hermitian)");
-    if (nev < 1 || nblock < nev + 1 || nblock > 256)
-        return arg_error("msb_low_modes: need 1 <= nev < nblock <= 256");
+    if (nev < 1 || nblock < nev + 1 || nblock > 128)
+        return arg_error("msb_low_modes: need 1 <= nev < nblock <= 128");
     if (!start || !evals || !evecs) return arg_error("msb_low_modes: start, evals and evecs are required");
     if (!(tol > 0.0) || !std::isfinite(tol)) return arg_error("msb_low_modes: tol must be finite and > 0");
     if (degree < 1 || degree > 1000 || max_iter < 0) return arg_error("msb_low_modes: degree in 1..1000, max_iter >= 0");

@@ -204,8 +204,7 @@ void ctx_destroy(Ctx *c) {
                       &c->ws_rsig, &c->ws_rw, &c->ws_Bm, &c->ws_schist, &c->ws_dc, &c->ws_ones,
                       &c->ws_cg_r, &c->ws_cg_p, &c->ws_cg_w, &c->ws_cg_P, &c->ws_cg_seed, &c->ws_cg_shift,
                       &c->ws_cg_coef, &c->ws_cg_tape, &c->ws_cg_c, &c->ws_cg_n, &c->ws_eY, &c->ws_eW,
-                      &c->ws_eZ, &c->ws_eP, &c->ws_eS};
-    eig_release(c);
+                      &c->ws_eZ, &c->ws_eP, &c->ws_eS, &c->ws_eG};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (DevBuf &b : c->pstore)

@@ -30,16 +30,18 @@ def mu0():
     ctx.close()
 
 
-def test_low_modes_match_dense_eigenpairs(mu0):
+# (8, 16): one tile of the block kernels; (36, 44): the Gram and combine
+# products split into 32-vector tiles
+@pytest.mark.parametrize("nev,nblock", [(8, 16), (36, 44)])
+def test_low_modes_match_dense_eigenpairs(mu0, nev, nblock):
     U, op, ev, Q, order, ctx = mu0
-    nev, nblock = 8, 16
     absv = np.abs(ev[order])
     assert absv[nev] - absv[nev - 1] > 1e-6 * absv[-1]     # the kept subspace is well separated
     start = cuda(wl.gaussian_source(DIMS, 98, nblock))
     from paper_1010_2592_amd import msb
     lam, vecs, res, it = ctx.low_modes(nev, start, tol=1e-11, degree=24, max_iter=300,
                                        allow=(msb.OK, msb.NOT_CONVERGED))
-    log(f"low modes 4^4: {it} iterations, |lambda| {np.abs(lam)} vs dense {absv[:nev]}, residuals {res}")
+    log(f"low modes 4^4 nev {nev} block {nblock}: {it} iterations, |lambda| {np.abs(lam)} vs dense {absv[:nev]}, residuals {res}")
     assert it < 300
     hnorm = np.abs(ev).max()
     assert np.max(np.abs(np.abs(lam) - absv[:nev])) <= 1e-9 * hnorm
@@ -56,11 +58,10 @@ def test_low_modes_match_dense_eigenpairs(mu0):
     assert np.abs(np.linalg.svd(proj, compute_uv=False) - 1).max() <= 1e-9
 
 
-@pytest.mark.parametrize("overlap", [False, True])
-def test_deflated_sign_matches_oracle(mu0, overlap):
+@pytest.mark.parametrize("overlap,K", [(False, 16), (True, 16), (False, 40)])
+def test_deflated_sign_matches_oracle(mu0, overlap, K):
     from paper_1010_2592_amd import msb
     U, op, ev, Q, order, ctx = mu0
-    K = 16
     lam = ev[order[:K]]
     vecs = np.stack([Q[:, i].reshape(12, op.V) for i in order[:K]])
     a = 1.0 / (1.01 * np.abs(ev).max() ** 2)
@@ -73,7 +74,7 @@ def test_deflated_sign_matches_oracle(mu0, overlap):
         if overlap:
             ref = bb[r] + od.g5(ref)
         d = rel(host(out)[r], ref)
-        log(f"deflated {'overlap' if overlap else 'sign'} rhs {r}: rel err vs oracle {d:.2e}")
+        log(f"deflated {'overlap' if overlap else 'sign'} K {K} rhs {r}: rel err vs oracle {d:.2e}")
         assert d <= 1e-9, r
 
 
