@@ -72,9 +72,9 @@ def test_partial_deflation_within_pfe_bound():
     ref = odf.exact_sign(op, b)
     # PFE error of sign over the spectrum the projected source sees
     x = np.linspace(a * lam[-1] ** 2, a * lmax ** 2, 20001)
-    eps_k = np.max(np.abs(np.sqrt(x) * pfe.pfe_scalar(x[:, None], sig, w) - 1.0))
+    eps_k = np.max(np.abs(np.sqrt(x) * pfe.pfe_scalar(x, sig, w) - 1.0))
     x0 = np.linspace(a * np.abs(ev).min() ** 2, a * lmax ** 2, 20001)
-    eps_0 = np.max(np.abs(np.sqrt(x0) * pfe.pfe_scalar(x0[:, None], sig, w) - 1.0))
+    eps_0 = np.max(np.abs(np.sqrt(x0) * pfe.pfe_scalar(x0, sig, w) - 1.0))
     tol = 1e-11
     out = odf.sign_apply_deflated(op, a, b, lam, vecs, sig, w, 2, tol, 3000)
     _, pb = odf.project(vecs, b)
@@ -84,3 +84,13 @@ def test_partial_deflation_within_pfe_bound():
     err0 = np.linalg.norm(plain - ref)
     assert err0 <= 1.01 * eps_0 * np.linalg.norm(b) + 1e-8 * np.linalg.norm(b)
     assert err < err0 and eps_k < eps_0
+    # the error itself, from the dense eigendecomposition: the PFE sign
+    # sqrt(a) lambda f(a lambda^2) replaces sign(lambda) on every mode of the
+    # source the PFE sees (P b deflated, b plain); the low modes are exact
+    lam_all, Q = np.linalg.eigh(H)
+    pfe_sign = np.sqrt(a) * lam_all * pfe.pfe_scalar(a * lam_all ** 2, sig, w)
+    dsign = pfe_sign - np.sign(lam_all)
+    e_defl = Q @ (dsign * (Q.conj().T @ pb.reshape(-1)))
+    e_plain = Q @ (dsign * (Q.conj().T @ b.reshape(-1)))
+    assert np.linalg.norm((out - ref).reshape(-1) - e_defl) <= 1e-8 * np.linalg.norm(b)
+    assert np.linalg.norm((plain - ref).reshape(-1) - e_plain) <= 1e-8 * np.linalg.norm(b)
