@@ -364,6 +364,9 @@ def main():
     ap.add_argument("--variants", default="all", choices=("all", "none"))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--max-outer", type=int, default=2000)
+    ap.add_argument("--block", default=None, choices=("mu0", "propagators", "deflation"),
+                    help="run only this extra block on the headline inputs and print its JSON "
+                         "(for profiling it alone); the headline line is not printed")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 1 GiB tensor 3 times (reference kernel of known size "
                          "for the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -398,6 +401,16 @@ def main():
     rho = ctx.spectral_radius(torch.from_numpy(wk.power_start()[None]).to(dev), 100)
     a = 1.0 / (1.01 * rho)
     sig, w = msb.neuberger_pfe(wk.n_shift)
+    if args.block:
+        ctx.close()
+        if args.block == "mu0":
+            out = mu0_block(wk, U, b, sig, w, l, with_cpu=not args.no_cpu)
+        elif args.block == "propagators":
+            out = propagator_block(wk, U, b, l, with_cpu=not args.no_cpu)
+        else:
+            out = deflation_block(wk, U, b, sig, w, l, with_cpu=not args.no_cpu)
+        print(json.dumps({"block": args.block, "workload": WORKLOAD, "result": out}), flush=True)
+        return
     mixed = args.precision == "mixed"
     persistent = args.launch == "persistent"
     refine = args.pass_ == 1 and (args.refine == "on" or (args.refine == "auto" and mixed))

@@ -1,5 +1,11 @@
 """Summaries of rocprofv3 runs of bench.py for profiles/.
 
+    python -m paper_1010_2592_amd.rocprof_summary trace --trace T.db --title ... --workload ... \
+        --md profiles/X.md --cmd-trace "..." [--kernel-bytes NAME=BYTES ...]
+
+writes the kernel table of one kernel-trace run (any bench.py command).  The
+form below is the stencil's: trace, counters and the traffic record.
+
     python -m paper_1010_2592_amd.rocprof_summary --trace T.db --fetch F.db --write W.db \
         --bench-json B.json --workload "16x16x16x32 12 rhs mixed pass 1 refine" \
         --md profiles/X.md --json profiles/dslash_traffic.json --cmd-trace "..." --cmd-fetch "..." --cmd-write "..."
@@ -75,7 +81,49 @@ def scale(rows):
     return COPY_KIB / (sum(copies) / len(copies))
 
 
+def trace_main(argv):
+    """Kernel table of one --kernel-trace run, with the algorithmic bandwidth
+    of the kernels given as NAME=BYTES (bytes per launch; NAME matches a
+    substring of the kernel name)."""
+    ap = argparse.ArgumentParser(prog="rocprof_summary trace")
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--md", required=True)
+    ap.add_argument("--cmd-trace", required=True)
+    ap.add_argument("--kernel-bytes", action="append", default=[])
+    ap.add_argument("--top", type=int, default=18)
+    a = ap.parse_args(argv)
+    rows = kernel_rows(a.trace)
+    tot = sum(r[3] for r in rows)
+    md = [f"# {a.title}\n", f"Workload: {a.workload}\n",
+          "## Kernel trace\n\nCommand (from the repository root on the MI355X box):\n", f"    {a.cmd_trace}\n",
+          "| kernel | calls | avg us | total ms | % |\n|---|---|---|---|---|"]
+    for n, c, avg, s in rows[:a.top]:
+        md.append(f"| `{short(n)[:90]}` | {c} | {avg / 1e3:.2f} | {s / 1e6:.2f} | {100 * s / tot:.1f} |")
+    md.append("")
+    if a.kernel_bytes:
+        md.append("## Algorithmic bandwidth\n\n| kernel | bytes per launch | avg us | GB/s | of 8 TB/s |\n"
+                  "|---|---|---|---|---|")
+        for kb in a.kernel_bytes:
+            name, b = kb.split("=")
+            hit = [r for r in rows if name in r[0]]
+            if not hit:
+                continue
+            n, c, avg, s = hit[0]
+            gbs = float(b) / (avg / 1e9) / 1e9
+            md.append(f"| `{name}` | {float(b) / 1e6:.1f} MB | {avg / 1e3:.1f} | {gbs:.0f} | {100 * gbs / 8000:.0f} % |")
+        md.append("")
+    os.makedirs(os.path.dirname(os.path.abspath(a.md)), exist_ok=True)
+    with open(a.md, "w") as f:
+        f.write("\n".join(md))
+    print("\n".join(md))
+
+
 def main():
+    import sys
+    if len(sys.argv) > 1 and sys.argv[1] == "trace":
+        return trace_main(sys.argv[2:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch", required=True)
