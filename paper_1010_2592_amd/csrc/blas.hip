@@ -23,6 +23,8 @@
 // The seed vectors are loaded once per element and reused for every shift;
 // this is the paper's sum_s M_s l (0.5 l + 4.5) extra axpys (Section 2)
 // executed as one pass over the shift vectors per BiCG step and per MR step.
+#include <vector>
+
 #include "blas_dev.h"
 
 namespace msb {
@@ -420,6 +422,107 @@ void launch_shift_dots(hipStream_t st, const double2 *eta, const double2 *X, con
 
 void launch_axpy_host(hipStream_t st, double2 *y, const double2 *x, double2 a, long n, int nblk) {
     hipLaunchKernelGGL(k_axpy_host, dim3(nblk), dim3(BLOCK), 0, st, y, x, a, n);
+}
+
+// ---------------------------------------------------------------------------
+// Sparse shadow residual.  When every right-hand side's r~ has at most SPMAX
+// nonzero entries (a point source with r~ = b has one), the dots <r~, v> of
+// the Mv epilogue and of the MR update are taken from an index list instead
+// of a full read of r~.  One wavefront per (block range, rhs): count, then
+// write each nonzero at its rank in index order, so the list is the same on
+// every run.
+__global__ __launch_bounds__(64) void k_nnz_count(const double2 *__restrict__ v, long n, long rs, int *__restrict__ cnt,
+                                                  int nb) {
+    const int b = blockIdx.x, rhs = blockIdx.y, lane = threadIdx.x;
+    const long len = (n + nb - 1) / nb, e0 = (long)b * len;
+    const long e1 = e0 + len < n ? e0 + len : n;
+    const double2 *x = v + (size_t)rhs * rs;
+    int c = 0;
+    for (long e = e0; e < e1; e += 64) {
+        const long k = e + lane;
+        bool nz = false;
+        if (k < e1) {
+            const double2 z = x[k];
+            nz = z.x != 0.0 || z.y != 0.0;
+        }
+        c += __popcll(__ballot(nz));
+    }
+    if (lane == 0) cnt[(size_t)rhs * nb + b] = c;
+}
+
+__global__ __launch_bounds__(64) void k_nnz_collect(const double2 *__restrict__ v, long n, long rs,
+                                                    const int *__restrict__ off, int nb, long *__restrict__ idx,
+                                                    double2 *__restrict__ val, int spmax) {
+    const int b = blockIdx.x, rhs = blockIdx.y, lane = threadIdx.x;
+    const long len = (n + nb - 1) / nb, e0 = (long)b * len;
+    const long e1 = e0 + len < n ? e0 + len : n;
+    const double2 *x = v + (size_t)rhs * rs;
+    int c = off[(size_t)rhs * nb + b];
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (long e = e0; e < e1; e += 64) {
+        const long k = e + lane;
+        bool nz = false;
+        double2 z{0.0, 0.0};
+        if (k < e1) {
+            z = x[k];
+            nz = z.x != 0.0 || z.y != 0.0;
+        }
+        const unsigned long long m = __ballot(nz);
+        if (nz) {
+            const int pos = c + __popcll(m & below);
+            if (pos < spmax) {
+                idx[(size_t)rhs * spmax + pos] = k;
+                val[(size_t)rhs * spmax + pos] = z;
+            }
+        }
+        c += __popcll(m);
+    }
+}
+
+// <r~, x> of each open rhs from the list, written over column 0 of partial
+// slots 0 (re) and 1 (im); the kernel that produced x left those slots zero
+__global__ __launch_bounds__(64) void k_sparse_dot(SparseDotArgs a, int nrhs) {
+    const int rhs = blockIdx.x * 64 + threadIdx.x;
+    if (rhs >= nrhs || !gate_open(a.gate, rhs)) return;
+    const double2 *x = a.x + (size_t)rhs * a.x_rs;
+    double p0 = 0.0, p1 = 0.0;
+    const int nk = a.cnt[rhs];
+    for (int k = 0; k < nk; ++k) {
+        const double2 t = a.val[(size_t)rhs * a.spmax + k];
+        const double2 o = x[a.idx[(size_t)rhs * a.spmax + k]];
+        p0 += t.x * o.x + t.y * o.y;
+        p1 += t.x * o.y - t.y * o.x;
+    }
+    double *row = a.part + (size_t)rhs * PMAX * a.ps;
+    row[0] = p0;
+    row[a.ps] = p1;
+}
+
+int sparse_list(hipStream_t st, const double2 *v, long n, long rs, int nrhs, int spmax, long *idx, double2 *val,
+                int *cnt, int *work, int nb) {
+    hipLaunchKernelGGL(k_nnz_count, dim3(nb, nrhs), dim3(64), 0, st, v, n, rs, work, nb);
+    if (hipGetLastError() != hipSuccess) return -1;
+    std::vector<int> h((size_t)nrhs * nb), off((size_t)nrhs * nb), tot(nrhs, 0);
+    if (hipStreamSynchronize(st) != hipSuccess) return -1;
+    if (hipMemcpy(h.data(), work, h.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    int worst = 0;
+    for (int r = 0; r < nrhs; ++r) {
+        for (int b = 0; b < nb; ++b) {
+            off[(size_t)r * nb + b] = tot[r];
+            tot[r] += h[(size_t)r * nb + b];
+        }
+        worst = tot[r] > worst ? tot[r] : worst;
+    }
+    if (worst > spmax) return worst;
+    if (hipMemcpy(work, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return -1;
+    if (hipMemcpy(cnt, tot.data(), nrhs * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return -1;
+    hipLaunchKernelGGL(k_nnz_collect, dim3(nb, nrhs), dim3(64), 0, st, v, n, rs, work, nb, idx, val, spmax);
+    if (hipGetLastError() != hipSuccess) return -1;
+    return worst;
+}
+
+void launch_sparse_dot(hipStream_t st, const SparseDotArgs &a, int nrhs) {
+    hipLaunchKernelGGL(k_sparse_dot, dim3((nrhs + 63) / 64), dim3(64), 0, st, a, nrhs);
 }
 
 #define INST(T)                                                                                  \

@@ -29,7 +29,7 @@ struct Ctx {
         ws_cb, ws_aux1, ws_aux2, ws_aux3, ws_aux4, ws_bX, ws_bZ, ws_by, ws_beta, ws_bA, ws_bB, ws_bdots,
         ws_ops, ws_pctl, ws_rX, ws_rX2, ws_ry, ws_rB, ws_rR, ws_rt1, ws_rt2, ws_rsig, ws_rw, ws_Bm, ws_schist,
         ws_dc, ws_cg_r, ws_cg_p, ws_cg_w, ws_cg_P, ws_cg_seed, ws_cg_shift, ws_cg_coef, ws_cg_tape, ws_cg_c,
-        ws_cg_n, ws_eY, ws_eW, ws_eZ, ws_eP, ws_eS, ws_eG;
+        ws_cg_n, ws_eY, ws_eW, ws_eZ, ws_eP, ws_eS, ws_eG, ws_sp;
     int pgrid[32] = {};        // co-resident grid of the persistent kernel, per (precision, l)
     // pseudo-double passes: stored Mv outputs (and reliable-update Mv
     // outputs) of BiCGstab(l), or stored residuals of CG, in chunks, kept for

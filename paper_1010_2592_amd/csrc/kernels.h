@@ -5,7 +5,12 @@
 
 namespace msb {
 
-enum { EPI_PLAIN = 0, EPI_MV = 1, EPI_MV_Y = 2, EPI_SV = 3, EPI_MVB = 4 };
+enum { EPI_PLAIN = 0, EPI_MV = 1, EPI_MV_Y = 2, EPI_SV = 3, EPI_MVB = 4, EPI_MVN = 5, EPI_MVBN = 6 };
+// epilogues that write partials (EPI_MVN / EPI_MVBN: EPI_MV / EPI_MVB without
+// the <r~, out> term, which a sparse list supplies)
+__host__ __device__ constexpr bool epi_dots(int e) {
+    return e == EPI_MV || e == EPI_MVB || e == EPI_MVN || e == EPI_MVBN;
+}
 
 // A per-right-hand-side complex coefficient in device memory: the value for
 // rhs r is *(const double2 *)(p + r * stride).
@@ -163,6 +168,25 @@ void launch_convert_out(hipStream_t, double2 *dst, const C<T> *src, long n, long
                         long src_stride, int nrhs);
 template <typename T>
 void launch_zero(hipStream_t, C<T> *dst, long n, long stride, int nrhs);
+
+// sparse shadow residual: index list of the nonzero entries of v ([nrhs] rows
+// of n at stride rs), at most spmax per row, in index order.  Returns the
+// largest row count (the list is written only when it is <= spmax), or -1 on
+// a HIP error.  work: nrhs * nb ints.  Synchronises the stream.
+int sparse_list(hipStream_t, const double2 *v, long n, long rs, int nrhs, int spmax, long *idx, double2 *val,
+                int *cnt, int *work, int nb);
+struct SparseDotArgs {
+    const long *idx = nullptr;      // [nrhs][spmax]
+    const double2 *val = nullptr;   // [nrhs][spmax]
+    const int *cnt = nullptr;       // [nrhs]
+    int spmax = 0;
+    const double2 *x = nullptr;     // the vector dotted with r~, rhs stride x_rs
+    long x_rs = 0;
+    double *part = nullptr;
+    long ps = 0;
+    Gate gate{};
+};
+void launch_sparse_dot(hipStream_t, const SparseDotArgs &, int nrhs);
 template <typename T>
 void launch_dot_partials(hipStream_t, const C<T> *x, const C<T> *y, long n, double *part, long ps,
                          int nrhs, int nblk, Gate gate);

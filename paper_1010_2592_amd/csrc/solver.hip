@@ -204,7 +204,7 @@ void ctx_destroy(Ctx *c) {
                       &c->ws_rsig, &c->ws_rw, &c->ws_Bm, &c->ws_schist, &c->ws_dc, &c->ws_ones,
                       &c->ws_cg_r, &c->ws_cg_p, &c->ws_cg_w, &c->ws_cg_P, &c->ws_cg_seed, &c->ws_cg_shift,
                       &c->ws_cg_coef, &c->ws_cg_tape, &c->ws_cg_c, &c->ws_cg_n, &c->ws_eY, &c->ws_eW,
-                      &c->ws_eZ, &c->ws_eP, &c->ws_eS, &c->ws_eG};
+                      &c->ws_eZ, &c->ws_eP, &c->ws_eS, &c->ws_eG, &c->ws_sp};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (DevBuf &b : c->pstore)
@@ -591,6 +591,14 @@ struct Emit {
             record(o, a);
         }
     }
+    // <r~, x> from the sparse list of r~ (per-stage launches only; the
+    // solver turns the sparse form off for the persistent launch)
+    void sparse_dot(const SparseDotArgs &a, int nrhs, double bytes) {
+        if (launching(CL_SCALAR, bytes)) {
+            Prof p(c, CL_SCALAR, bytes);
+            launch_sparse_dot(st, a, nrhs);
+        }
+    }
     void rel_update(const VecArgs<T> &a, const double2 *bb, const double2 *v, double2 *yy, CoefRef yc, int nrhs,
                     int nblk, int cls, double bytes) {
         if (launching(cls, bytes)) {
@@ -703,10 +711,13 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     std::vector<POp> persist_ops1;   // operation table of the persistent first pass
     // algorithmic HBM bytes of one launch (each operand read or written once)
     const double cB = (double)cs, nd = (double)n, Vd = (double)V;
+    bool sparse_rt = false;   // r~ read from its sparse list (see below)
     auto ds_bytes = [&](int epi, int nr) {
         double per = 24 * cB;                                  // in + out
         if (epi == EPI_MV) per = 48 * cB;                      // + v + rt
         else if (epi == EPI_MVB) per = 60 * cB;                // + v + rt + the basis copy
+        else if (epi == EPI_MVN) per = 36 * cB;               // EPI_MV without rt
+        else if (epi == EPI_MVBN) per = 48 * cB;              // EPI_MVB without rt
         else if (epi == EPI_MV_Y) per = 36 * cB + 24 * 16.0;   // + v, y (FP64) read + write
         else if (epi == EPI_SV) per = 36 * cB;                 // + v
         return nr * per * Vd + 36 * cB * Vd;                   // links once per launch
@@ -837,6 +848,29 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             launch_dot_partials<T>(st, rt, rt, n, part + 3 * ps, ps, nrhs, nbv, Gate{});
         }
     }
+    // A shadow residual with few nonzero entries (r~ = b for a point source
+    // has one per right-hand side): the Mv epilogue and the MR update skip
+    // their full read of r~ and <r~, .> is summed from an index list in a
+    // one-wavefront kernel after them.  FP64 per-stage launches only.
+    constexpr int SPMAX = 16;
+    SparseDotArgs spa;
+    if (!mixed && !P.persistent) {
+        constexpr int NBL = 256;
+        CHK(ensure(c->ws_sp, (size_t)nrhs * (SPMAX * (sizeof(long) + sizeof(double2)) + (1 + NBL) * sizeof(int)) + 256));
+        long *spi = (long *)c->ws_sp.p;
+        double2 *spv = (double2 *)(spi + (size_t)nrhs * SPMAX);
+        int *spc = (int *)(spv + (size_t)nrhs * SPMAX);
+        int *spw = spc + nrhs;
+        const int worst = sparse_list(st, (const double2 *)rt, n, n, nrhs, SPMAX, spi, spv, spc, spw, NBL);
+        if (worst < 0) return set_error(S_ERR_HIP, "scan of the shadow residual for nonzero entries failed");
+        sparse_rt = worst <= SPMAX;
+        spa.idx = spi;
+        spa.val = spv;
+        spa.cnt = spc;
+        spa.spmax = SPMAX;
+        spa.part = part;
+        spa.ps = ps;
+    }
     ScalarArgs sa;
     sa.seed = seed;
     sa.sh = sh;
@@ -872,7 +906,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     va.W = W;
     va.X = X;
     va.XH = XH;
-    va.rt = rt;
+    va.rt = sparse_rt ? nullptr : rt;
     va.part = part;
     va.ps = ps;
     va.seed = seed;
@@ -906,7 +940,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     if (opw) d2.g5out = 0;
     d2.out_rs = vs;
     d2.v_rs = vs;
-    d2.rt = rt;
+    d2.rt = sparse_rt ? nullptr : rt;
     d2.rt_rs = n;
     d2.part = part;
     d2.ps = ps;
@@ -966,7 +1000,16 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         HIPCHK(hipStreamSynchronize(st));
     }
 
-    const int mv_epi = (deferred || pass3) ? EPI_MVB : EPI_MV;
+    // <r~, x> for x = [rhs] rows at the seed-vector stride, into the partial
+    // slots the preceding kernel left at zero
+    auto sparse_dot_of = [&](Emit<T> &e, const double2 *x, const Gate &g, int nr_run) {
+        SparseDotArgs a = spa;
+        a.x = x;
+        a.x_rs = vs;
+        a.gate = g;
+        e.sparse_dot(a, nrhs, nr_run * SPMAX * (8.0 + 16.0 + 16.0));
+    };
+    const int mv_epi = (deferred || pass3) ? (sparse_rt ? EPI_MVBN : EPI_MVB) : (sparse_rt ? EPI_MVN : EPI_MV);
     const bool fuse_seed = !P.persistent;   // fused direction updates (per-stage launches)
     auto emit_outer = [&](Emit<T> &e, int nr_run, double nsh_act, int m) {
         VecArgs<T> v = va;
@@ -1002,6 +1045,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 e2.out2_rs = ps_rs;
             }
             e.ds(e2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
+            if (sparse_rt) sparse_dot_of(e, (const double2 *)e2.out, e2.gate, nr_run);
             s.nblk = nbd;
             e.scalar(OP_SC_ALPHA, s, nrhs);
             v.partials = 1;
@@ -1031,6 +1075,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             if (deferred) e2.out2 = Bm + (size_t)(3 + 2 * j) * n;
             if (pass3) e2.out2 = (C<T> *)c->pstore[m / PSC].p + ((size_t)(m % PSC) * 2 * l + 2 * j + 1) * n;
             e.ds(e2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
+            if (sparse_rt) sparse_dot_of(e, (const double2 *)e2.out, e2.gate, nr_run);
         }
         v.gate = g_run;
         e.gram(v, nrhs, nbv, CL_SEED, nr_run * (l + 1.0) * nd * cB);
@@ -1040,8 +1085,9 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         // seed: read r_0..r_l, u_0..u_l, rt, write r_0, u_0; shift s: read
         // u^s_0..u^s_l, x^s, write u^s_0, x^s
         e.mr_update(v, shifts_step, mixed, nrhs, nbv, shifts_step ? CL_SHIFT_MR : CL_SEED,
-                    nr_run * ((2.0 * (l + 1) + 3) * cB + (mixed ? 32.0 : 0.0)) * nd +
+                    nr_run * ((2.0 * (l + 1) + (sparse_rt ? 2 : 3)) * cB + (mixed ? 32.0 : 0.0)) * nd +
                         (shifts_step ? nsh_act * ((l + 2.0) * cB + 32.0) * nd : 0.0));
+        if (sparse_rt) sparse_dot_of(e, (const double2 *)R, v.gate, nr_run);
         if (deferred) {
             // every shift's update over the iteration, from the basis: read the
             // 2l+2 basis vectors once, each active shift's u^s_0 and x^s (FP64)

@@ -286,13 +286,14 @@ __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &l
             C<T> o = acc[sp][c];
             if (EPI != EPI_PLAIN) o = cadd(o, cscale(elem_at<LK::staged>(v, k, V, s), sig0));
             elem_at<LK::staged>(out, k, V, s) = o;
-            if (EPI == EPI_MVB) elem_at<LK::staged>(out2, k, V, s) = o;
+            if (EPI == EPI_MVB || EPI == EPI_MVBN) elem_at<LK::staged>(out2, k, V, s) = o;
             if (EPI == EPI_MV || EPI == EPI_MVB) {
                 const C<T> r = elem_at<LK::staged>(rt, k, V, s);
                 part[0] += (double)r.x * o.x + (double)r.y * o.y;
                 part[1] += (double)r.x * o.y - (double)r.y * o.x;
-                part[2] += (double)o.x * o.x + (double)o.y * o.y;
             }
+            // EPI_MVN / EPI_MVBN: no r~ here, its dot comes from a sparse list
+            if (epi_dots(EPI)) part[2] += (double)o.x * o.x + (double)o.y * o.y;
             if (EPI == EPI_MV_Y) {
                 double2 &yr = elem_at<LK::staged>(y, k, V, s);
                 double2 yv = yr;
@@ -342,7 +343,7 @@ __device__ __forceinline__ void dslash_site_block(const DslashArgs<T> &a, int sb
     double part[3] = {0.0, 0.0, 0.0};
     dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, o.out2, sblk * BLOCK + threadIdx.x,
                               part);
-    if (EPI == EPI_MV || EPI == EPI_MVB)
+    if (epi_dots(EPI))
         wave_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + sblk * (BLOCK / 64) + (threadIdx.x >> 6),
                              a.ps);
 }
@@ -413,7 +414,7 @@ __device__ __forceinline__ void dslash_chunk(const DslashArgs<T> &a, int p) {
         const RhsOps<T> o = rhs_ops<T, EPI>(a, rhs);
         double part[3] = {0.0, 0.0, 0.0};
         dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, o.out2, base + lane, part);
-        if (EPI == EPI_MV || EPI == EPI_MVB) wave_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + chunk, a.ps);
+        if (epi_dots(EPI)) wave_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + chunk, a.ps);
     }
 }
 
