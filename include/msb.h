@@ -11,8 +11,8 @@
  * form of Section 2 (option 1 after Eq. 2.2; Section 5) and the
  * pseudo-double-pass form (option 2 after Eq. 2.2), and
  * from it sign(H) b and the overlap operator D_ov = 1 + gamma5 sign(H)
- * (Eq. 1.1).  D_w(mu) is the Wilson-Dirac operator with the chemical
- * potential on the time links:
+ * (Eq. 1.1).  D_w(mu): the Wilson stencil, mu entering as e^{+-mu} on the
+ * time links:
  *
  *   (D psi)(x) = (4+m) psi(x)
  *     - 1/2 sum_nu b_nu(x)   (1-gamma_nu) e^{+mu d_nu4} U_nu(x)     psi(x+nu)

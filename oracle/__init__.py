@@ -11,8 +11,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 (``paper_1010_2592_amd``) never does.
 
 Modules
-  dirac     gamma matrices, the Wilson-Dirac operator with chemical potential
-            D_w(mu), H = gamma5 D_w, A = a H^2 (Section 1, Eq. (1.1) and the
+  dirac     gamma matrices, the Wilson stencil D_w(mu) (mu as e^{+-mu} on
+            the time links), H = gamma5 D_w, A = a H^2 (Section 1, Eq. (1.1) and the
             text after Eq. (1.2)), spectral-radius estimate, dense builders.
   pfe       Neuberger partial-fraction coefficients (Eq. (1.2), Fig. 1).
   krylov    seed BiCGstab(l), multi-shift single-pass, double-pass
