@@ -29,41 +29,38 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--dims", type=int, nargs=4, default=[12, 12, 12, 24])
-    ap.add_argument("--ml", type=int, default=256)
-    ap.add_argument("--ls", type=int, nargs="+", default=[1, 2, 4, 8])
-    ap.add_argument("--ns", type=int, nargs="+", default=[2, 4, 8, 16, 32, 64])
-    ap.add_argument("--reps", type=int, default=3)
-    ap.add_argument("--json", default=None)
-    args = ap.parse_args()
+FORMS = (("1-pass", 1, "plain"), ("1-pass deferred", 1, "deferred"), ("2-pass", 2, "plain"),
+         ("3-pass", 3, "plain"))
 
+
+def sweep(dims, ml, ls, ns_list, reps, log=print):
+    """The measurement: one row per (l, N_s, form) with the median time of
+    `reps` runs after a warm-up, the Mv count and the outer iterations."""
     import numpy as np
     import torch
 
     import workloads as wl
     from paper_1010_2592_amd import msb
 
-    dims = tuple(args.dims)
+    dims = tuple(dims)
     U = torch.as_tensor(wl.gauge_links(dims, 0.5, 1006)).cuda()
     b = torch.as_tensor(wl.gaussian_source(dims, 2006, 1)).cuda()
     ctx = msb.Context(msb.Lattice(dims, -2.0, 0.05, -1), U)
     rho = ctx.spectral_radius(torch.as_tensor(wl.start_vector(dims, 4006)[None]).cuda(), 100)
     a = 1.0 / (1.01 * rho)
-    forms = [("1-pass", 1, 0), ("1-pass deferred", 1, msb.DEFERRED), ("2-pass", 2, 0), ("3-pass", 3, 0)]
     allow = (msb.OK, msb.NOT_CONVERGED, msb.BREAKDOWN)
     vec_mb = 12 * wl.volume(dims) * 16 / 1e6
-    print(f"[fig2] {dims}, vector {vec_mb:.1f} MB (FP64), Ml = {args.ml}, rho = {rho:.6f}", flush=True)
+    log(f"[fig2] {dims}, vector {vec_mb:.1f} MB (FP64), Ml = {ml}, rho = {rho:.6f}")
     rows = []
-    for l in args.ls:
-        M = max(args.ml // l, 1)
-        for ns in args.ns:
+    for l in ls:
+        M = max(ml // l, 1)
+        for ns in ns_list:
             sig, w = msb.neuberger_pfe(ns)
             force = np.full(ns, M, dtype=np.int32)
-            for name, pass_, flags in forms:
+            for name, pass_, kind in FORMS:
+                flags = msb.DEFERRED if kind == "deferred" else 0
                 times = []
-                for r in range(args.reps + 1):
+                for r in range(reps + 1):
                     torch.cuda.synchronize()
                     e0 = torch.cuda.Event(enable_timing=True)
                     e1 = torch.cuda.Event(enable_timing=True)
@@ -76,23 +73,40 @@ def main():
                         times.append(e0.elapsed_time(e1))
                     del y
                 ms = statistics.median(times)
-                rows.append({"l": l, "M": M, "n_shift": ns, "form": name, "ms": ms, "mv": info.mv_count,
-                             "outer": info.outer_iters, "status": info.status,
+                rows.append({"l": l, "M": M, "n_shift": ns, "form": name, "pass": pass_, "ms": ms,
+                             "mv": info.mv_count, "outer": info.outer_iters, "status": info.status,
                              "shift_vectors_GB": (ns * (l + 1) * vec_mb / 1e3) if pass_ == 1 else 0.0})
-                print(f"[fig2] l={l} M={M} N_s={ns:3d} {name:16s} {ms:9.2f} ms  Mv {info.mv_count}", flush=True)
+                log(f"[fig2] l={l} M={M} N_s={ns:3d} {name:16s} {ms:9.2f} ms  Mv {info.mv_count}")
             torch.cuda.empty_cache()
     ctx.close()
+    return rho, rows
 
-    print("\n| l | N_s | " + " | ".join(f[0] for f in forms) + " |")
-    print("|---|---|" + "---|" * len(forms))
-    for l in args.ls:
-        for ns in args.ns:
+
+def table(rows, ls, ns_list):
+    """Markdown table: one row per (l, N_s), one column per form (ms)."""
+    out = ["| l | N_s | " + " | ".join(f[0] for f in FORMS) + " |", "|---|---|" + "---|" * len(FORMS)]
+    for l in ls:
+        for ns in ns_list:
             ms = [next(r["ms"] for r in rows if r["l"] == l and r["n_shift"] == ns and r["form"] == f[0])
-                  for f in forms]
-            print(f"| {l} | {ns} | " + " | ".join(f"{m:.1f}" for m in ms) + " |")
+                  for f in FORMS]
+            out.append(f"| {l} | {ns} | " + " | ".join(f"{m:.1f}" for m in ms) + " |")
+    return "\n".join(out)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--dims", type=int, nargs=4, default=[12, 12, 12, 24])
+    ap.add_argument("--ml", type=int, default=256)
+    ap.add_argument("--ls", type=int, nargs="+", default=[1, 2, 4, 8])
+    ap.add_argument("--ns", type=int, nargs="+", default=[2, 4, 8, 16, 32, 64])
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--json", default=None)
+    args = ap.parse_args()
+    rho, rows = sweep(args.dims, args.ml, args.ls, args.ns, args.reps, log=lambda m: print(m, flush=True))
+    print("\n" + table(rows, args.ls, args.ns))
     if args.json:
         with open(args.json, "w") as f:
-            json.dump({"dims": dims, "ml": args.ml, "rho": rho, "rows": rows}, f, indent=1)
+            json.dump({"dims": list(args.dims), "ml": args.ml, "rho": rho, "rows": rows}, f, indent=1)
 
 
 if __name__ == "__main__":
