@@ -257,6 +257,59 @@ def deflation_block(wk, U, b, sig, w, l, with_cpu=True):
     return res_out
 
 
+def config4_block():
+    """The 24^3x48 configuration (one Gaussian source, N_s = 58, tol 1e-8,
+    mu = 0.05): every FP64 form for l = 2 and 6, each in a context of its own
+    (one warm-up, then one timed solve), with the vectors each form holds."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1010_2592_amd import msb
+    wk = wl.WORKLOADS["24x24x24x48"]
+    dev = torch.device("cuda:0")
+    log("[bench] cfg4: building 24x24x24x48 inputs")
+    U = torch.from_numpy(wk.links()).to(dev)
+    b = torch.from_numpy(wk.sources()).to(dev)
+    vec_gb = 12 * wk.volume * 16 / 1e9
+    sig, w = msb.neuberger_pfe(wk.n_shift)
+    ctx = msb.Context(msb.Lattice(wk.dims, wk.mass, wk.mu, wk.bc_t), U)
+    rho = ctx.spectral_radius(torch.from_numpy(wk.power_start()[None]).to(dev), 100)
+    ctx.close()
+    a = 1.0 / (1.01 * rho)
+    out, ref = {}, {}
+    for l in wk.ells:
+        for name, pass_, flags in (("1pass", 1, 0), ("1pass-deferred", 1, msb.DEFERRED), ("2pass", 2, 0),
+                                   ("3pass", 3, 0)):
+            ctx = msb.Context(msb.Lattice(wk.dims, wk.mass, wk.mu, wk.bc_t), U)
+            times = []
+            for rep in range(2):
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                y, info, _ = ctx.mshift_bicgstabl(b, a, sig, w, l, wk.tol, 3000, pass_, flags=flags)
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            M = info.outer_iters
+            held = {"1pass": wk.n_shift * (l + 1), "1pass-deferred": wk.n_shift + 2 * l + 2, "2pass": 0,
+                    "3pass": 2 * M * l}[name]
+            key = f"l{l}-{name}"
+            if l not in ref:
+                ref[l] = y
+            out[key] = {"ms": round(times[-1], 1), "outer_iters": M, "mv": info.mv_count, "status": info.status,
+                        "max_shift_resid": float(np.max(info.shift_resid)),
+                        "extra_vectors_GB": round(held * vec_gb, 1),
+                        "rel_diff_vs_1pass": float(torch.linalg.vector_norm(y - ref[l]) /
+                                                   torch.linalg.vector_norm(ref[l]))}
+            log(f"[bench] cfg4 {key}: {out[key]}")
+            del y
+            ctx.close()
+            torch.cuda.empty_cache()
+    return {"workload": "24x24x24x48, 1 Gaussian source, N_s = 58, tol 1e-8, mu = 0.05, FP64", "forms": out}
+
+
 def propagator_block(wk, U, b, l, with_cpu=True):
     """Multi-mass Wilson propagators of the 12 point sources on the headline
     lattice (mu = 0.05): D_w(m_s)^{-1} b for five masses from one Krylov space
@@ -429,7 +482,7 @@ def main():
     ap.add_argument("--variants", default="all", choices=("all", "none"))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--max-outer", type=int, default=2000)
-    ap.add_argument("--block", default=None, choices=("mu0", "propagators", "deflation"),
+    ap.add_argument("--block", default=None, choices=("mu0", "propagators", "deflation", "cfg4"),
                     help="run only this extra block on the headline inputs and print its JSON "
                          "(for profiling it alone); the headline line is not printed")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -472,6 +525,10 @@ def main():
             out = mu0_block(wk, U, b, sig, w, l, with_cpu=not args.no_cpu)
         elif args.block == "propagators":
             out = propagator_block(wk, U, b, l, with_cpu=not args.no_cpu)
+        elif args.block == "cfg4":
+            del U, b
+            torch.cuda.empty_cache()
+            out = config4_block()
         else:
             out = deflation_block(wk, U, b, sig, w, l, with_cpu=not args.no_cpu)
         print(json.dumps({"block": args.block, "workload": WORKLOAD, "result": out}), flush=True)
