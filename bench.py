@@ -468,8 +468,8 @@ def cpu_baseline(wk, a, sig, w, l, M_gpu, nproc=12):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--pass", dest="pass_", type=int, default=3, choices=(1, 2, 3),
                     help="1 single pass, 2 double pass, 3 pseudo-double pass (Mv outputs stored)")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
