@@ -20,6 +20,8 @@
 //   EPI_SV     out = scale * gamma5 D in + sigma0 * v, nothing else
 //   EPI_MVB    as EPI_MV, and a second copy of out (the basis the deferred
 //              single pass updates its shift vectors from)
+//   EPI_SV2    as EPI_SV minus w (the Chebyshev three-term step of the
+//              low-mode eigensolver: out = scale gamma5 D in + sigma0 v - w)
 //   EPI_MVN, EPI_MVBN  as EPI_MV, EPI_MVB without reading rt (partials of
 //              <rt, out> left zero; the solver adds them from a sparse list
 //              of rt's nonzero entries)
@@ -164,6 +166,7 @@ void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in
             if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, true);
             else if (epi == EPI_MV) MSB_DS(EPI_MV, true);
             else if (epi == EPI_SV) MSB_DS(EPI_SV, true);
+            else if (epi == EPI_SV2) MSB_DS(EPI_SV2, true);
             else if (epi == EPI_MVB) MSB_DS(EPI_MVB, true);
             else if (epi == EPI_MVN) MSB_DS(EPI_MVN, true);
             else if (epi == EPI_MVBN) MSB_DS(EPI_MVBN, true);
@@ -172,6 +175,7 @@ void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in
             if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, false);
             else if (epi == EPI_MV) MSB_DS(EPI_MV, false);
             else if (epi == EPI_SV) MSB_DS(EPI_SV, false);
+            else if (epi == EPI_SV2) MSB_DS(EPI_SV2, false);
             else if (epi == EPI_MVB) MSB_DS(EPI_MVB, false);
             else if (epi == EPI_MVN) MSB_DS(EPI_MVN, false);
             else if (epi == EPI_MVBN) MSB_DS(EPI_MVBN, false);
@@ -186,6 +190,7 @@ void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in
         if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, true);
         else if (epi == EPI_MV) MSB_DS(EPI_MV, true);
         else if (epi == EPI_SV) MSB_DS(EPI_SV, true);
+        else if (epi == EPI_SV2) MSB_DS(EPI_SV2, true);
         else if (epi == EPI_MVB) MSB_DS(EPI_MVB, true);
         else if (epi == EPI_MVN) MSB_DS(EPI_MVN, true);
         else if (epi == EPI_MVBN) MSB_DS(EPI_MVBN, true);
@@ -194,6 +199,7 @@ void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in
         if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, false);
         else if (epi == EPI_MV) MSB_DS(EPI_MV, false);
         else if (epi == EPI_SV) MSB_DS(EPI_SV, false);
+        else if (epi == EPI_SV2) MSB_DS(EPI_SV2, false);
         else if (epi == EPI_MVB) MSB_DS(EPI_MVB, false);
         else if (epi == EPI_MVN) MSB_DS(EPI_MVN, false);
         else if (epi == EPI_MVBN) MSB_DS(EPI_MVBN, false);

@@ -172,12 +172,6 @@ __global__ __launch_bounds__(BLOCK) void k_combine(const double2 *__restrict__ X
     }
 }
 
-// z -= y over n complex (Chebyshev three-term step)
-__global__ __launch_bounds__(BLOCK) void k_sub(double2 *z, const double2 *y, long n) {
-    for (long e = (long)blockIdx.x * BLOCK + threadIdx.x; e < n; e += (long)gridDim.x * BLOCK)
-        z[e] = csub(z[e], y[e]);
-}
-
 // partial sums of ||W_i - theta_i Y_i||^2, one row of nblk per vector i
 __global__ __launch_bounds__(BLOCK) void k_resid(const double2 *W, const double2 *Y, const double *theta, long n,
                                                  double *part, int nblk) {
@@ -408,8 +402,8 @@ int low_modes(Ctx *c, int nev, int m, const double2 *start, double tol, int degr
             a2.v = Yc;
             a2.scale = (d == 1 ? 1.0 : 2.0) / hw;
             a2.sigma0 = -(d == 1 ? 1.0 : 2.0) * e / hw;
-            launch_dslash<double>(st, a2, m, EPI_SV, false);
-            if (d > 1) hipLaunchKernelGGL(k_sub, dim3(nbv), dim3(BLOCK), 0, st, Yn, Yp, (long)m * n);
+            if (d > 1) a2.w = Yp;                             // the subtraction in the epilogue
+            launch_dslash<double>(st, a2, m, d > 1 ? EPI_SV2 : EPI_SV, false);
             E_HIPCHK(hipGetLastError());
             double2 *t = Yp;
             Yp = Yc;

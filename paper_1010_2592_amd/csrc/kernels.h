@@ -5,7 +5,7 @@
 
 namespace msb {
 
-enum { EPI_PLAIN = 0, EPI_MV = 1, EPI_MV_Y = 2, EPI_SV = 3, EPI_MVB = 4, EPI_MVN = 5, EPI_MVBN = 6 };
+enum { EPI_PLAIN = 0, EPI_MV = 1, EPI_MV_Y = 2, EPI_SV = 3, EPI_MVB = 4, EPI_MVN = 5, EPI_MVBN = 6, EPI_SV2 = 7 };
 // epilogues that write partials (EPI_MVN / EPI_MVBN: EPI_MV / EPI_MVB without
 // the <r~, out> term, which a sparse list supplies)
 __host__ __device__ constexpr bool epi_dots(int e) {
@@ -47,6 +47,8 @@ struct DslashArgs {
     double2 *y = nullptr;      // EPI_MV_Y accumulator (always FP64)
     C<T> *out2 = nullptr;      // EPI_MVB: second copy of the output (the deferred basis)
     long out2_rs = 0;
+    const C<T> *w = nullptr;   // EPI_SV2: subtracted from the output
+    long w_rs = 0;
     Gate gate{};
     // element strides between right-hand sides (0: 12 V)
     long in_rs = 0, out_rs = 0, v_rs = 0, rt_rs = 0, y_rs = 0;

@@ -186,7 +186,8 @@ template <typename T, int EPI, bool G5IN, typename LK>
 __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &lk, const C<T> *__restrict__ in,
                                              C<T> *__restrict__ out, const C<T> *__restrict__ v,
                                              const C<T> *__restrict__ rt, double2 *__restrict__ y, C<T> yc,
-                                             T sig0, C<T> *__restrict__ out2, int s0, double (&part)[3]) {
+                                             T sig0, C<T> *__restrict__ out2, const C<T> *__restrict__ wsub,
+                                             int s0, double (&part)[3]) {
     const int V = a.g.V, Lx = a.g.Lx, Ly = a.g.Ly, Lz = a.g.Lz, Lt = a.g.Lt;
     for (int s = s0; s < V; s += a.sstride) {
     const int sxy = Lx * Ly, sxyz = Lx * Ly * Lz;
@@ -285,6 +286,7 @@ __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &l
             const int k = 3 * sp + c;
             C<T> o = acc[sp][c];
             if (EPI != EPI_PLAIN) o = cadd(o, cscale(elem_at<LK::staged>(v, k, V, s), sig0));
+            if (EPI == EPI_SV2) o = csub(o, elem_at<LK::staged>(wsub, k, V, s));
             elem_at<LK::staged>(out, k, V, s) = o;
             if (EPI == EPI_MVB || EPI == EPI_MVBN) elem_at<LK::staged>(out2, k, V, s) = o;
             if (EPI == EPI_MV || EPI == EPI_MVB) {
@@ -316,6 +318,7 @@ struct RhsOps {
     C<T> yc;
     T sig0;
     C<T> *out2;
+    const C<T> *w;
 };
 template <typename T, int EPI>
 __device__ __forceinline__ RhsOps<T> rhs_ops(const DslashArgs<T> &a, int rhs) {
@@ -330,6 +333,7 @@ __device__ __forceinline__ RhsOps<T> rhs_ops(const DslashArgs<T> &a, int rhs) {
     if (EPI == EPI_MV_Y) o.yc = to_c<T>(ld(a.ycoef, rhs));
     o.sig0 = a.sigma0_rhs ? (T)a.sigma0_rhs[rhs] : a.sigma0;
     o.out2 = a.out2 ? a.out2 + (size_t)rhs * (a.out2_rs ? a.out2_rs : nv) : nullptr;
+    o.w = a.w ? a.w + (size_t)rhs * (a.w_rs ? a.w_rs : nv) : nullptr;
     return o;
 }
 
@@ -341,7 +345,7 @@ __device__ __forceinline__ void dslash_site_block(const DslashArgs<T> &a, int sb
     const RhsOps<T> o = rhs_ops<T, EPI>(a, rhs);
     const GlobalLinks<T> lk{a.U, a.g.V};
     double part[3] = {0.0, 0.0, 0.0};
-    dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, o.out2, sblk * BLOCK + threadIdx.x,
+    dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, o.out2, o.w, sblk * BLOCK + threadIdx.x,
                               part);
     if (epi_dots(EPI))
         wave_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + sblk * (BLOCK / 64) + (threadIdx.x >> 6),
@@ -413,7 +417,7 @@ __device__ __forceinline__ void dslash_chunk(const DslashArgs<T> &a, int p) {
         if (!gate_open(a.gate, rhs)) continue;
         const RhsOps<T> o = rhs_ops<T, EPI>(a, rhs);
         double part[3] = {0.0, 0.0, 0.0};
-        dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, o.out2, base + lane, part);
+        dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, o.out2, o.w, base + lane, part);
         if (epi_dots(EPI)) wave_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + chunk, a.ps);
     }
 }
