@@ -452,7 +452,7 @@ __global__ __launch_bounds__(64) void k_nnz_count(const double2 *__restrict__ v,
 
 __global__ __launch_bounds__(64) void k_nnz_collect(const double2 *__restrict__ v, long n, long rs,
                                                     const int *__restrict__ off, int nb, long *__restrict__ idx,
-                                                    double2 *__restrict__ val, int spmax) {
+                                                    double2 *__restrict__ val, int spmax, int fp32) {
     const int b = blockIdx.x, rhs = blockIdx.y, lane = threadIdx.x;
     const long len = (n + nb - 1) / nb, e0 = (long)b * len;
     const long e1 = e0 + len < n ? e0 + len : n;
@@ -472,7 +472,8 @@ __global__ __launch_bounds__(64) void k_nnz_collect(const double2 *__restrict__ 
             const int pos = c + __popcll(m & below);
             if (pos < spmax) {
                 idx[(size_t)rhs * spmax + pos] = k;
-                val[(size_t)rhs * spmax + pos] = z;
+                // mixed precision: the value of the FP32 copy of r~ the dense path reads
+                val[(size_t)rhs * spmax + pos] = fp32 ? double2{(double)(float)z.x, (double)(float)z.y} : z;
             }
         }
         c += __popcll(m);
@@ -480,16 +481,26 @@ __global__ __launch_bounds__(64) void k_nnz_collect(const double2 *__restrict__ 
 }
 
 // <r~, x> of each open rhs from the list, written over column 0 of partial
-// slots 0 (re) and 1 (im); the kernel that produced x left those slots zero
+// slots 0 (re) and 1 (im); the kernel that produced x left those slots zero.
+// X: the element type of x (double2, or float2 for mixed precision, each
+// product formed in FP64 as the dense epilogues do).  With DIFF, x = b - v
+// for FP64 b and v (the reliable update's residual before its rounding).
+template <typename X, bool DIFF>
 __global__ __launch_bounds__(64) void k_sparse_dot(SparseDotArgs a, int nrhs) {
     const int rhs = blockIdx.x * 64 + threadIdx.x;
     if (rhs >= nrhs || !gate_open(a.gate, rhs)) return;
-    const double2 *x = a.x + (size_t)rhs * a.x_rs;
     double p0 = 0.0, p1 = 0.0;
     const int nk = a.cnt[rhs];
     for (int k = 0; k < nk; ++k) {
         const double2 t = a.val[(size_t)rhs * a.spmax + k];
-        const double2 o = x[a.idx[(size_t)rhs * a.spmax + k]];
+        const long e = a.idx[(size_t)rhs * a.spmax + k];
+        double2 o;
+        if (DIFF) {
+            o = csub(a.b[(size_t)rhs * a.x_rs + e], a.v[(size_t)rhs * a.x_rs + e]);
+        } else {
+            const X z = reinterpret_cast<const X *>(a.x)[(size_t)rhs * a.x_rs + e];
+            o = double2{(double)z.x, (double)z.y};
+        }
         p0 += t.x * o.x + t.y * o.y;
         p1 += t.x * o.y - t.y * o.x;
     }
@@ -499,7 +510,7 @@ __global__ __launch_bounds__(64) void k_sparse_dot(SparseDotArgs a, int nrhs) {
 }
 
 int sparse_list(hipStream_t st, const double2 *v, long n, long rs, int nrhs, int spmax, long *idx, double2 *val,
-                int *cnt, int *work, int nb) {
+                int *cnt, int *work, int nb, bool fp32) {
     hipLaunchKernelGGL(k_nnz_count, dim3(nb, nrhs), dim3(64), 0, st, v, n, rs, work, nb);
     if (hipGetLastError() != hipSuccess) return -1;
     std::vector<int> h((size_t)nrhs * nb), off((size_t)nrhs * nb), tot(nrhs, 0);
@@ -516,13 +527,17 @@ int sparse_list(hipStream_t st, const double2 *v, long n, long rs, int nrhs, int
     if (worst > spmax) return worst;
     if (hipMemcpy(work, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return -1;
     if (hipMemcpy(cnt, tot.data(), nrhs * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return -1;
-    hipLaunchKernelGGL(k_nnz_collect, dim3(nb, nrhs), dim3(64), 0, st, v, n, rs, work, nb, idx, val, spmax);
+    hipLaunchKernelGGL(k_nnz_collect, dim3(nb, nrhs), dim3(64), 0, st, v, n, rs, work, nb, idx, val, spmax,
+                       fp32 ? 1 : 0);
     if (hipGetLastError() != hipSuccess) return -1;
     return worst;
 }
 
 void launch_sparse_dot(hipStream_t st, const SparseDotArgs &a, int nrhs) {
-    hipLaunchKernelGGL(k_sparse_dot, dim3((nrhs + 63) / 64), dim3(64), 0, st, a, nrhs);
+    const dim3 g((nrhs + 63) / 64), b(64);
+    if (a.b) hipLaunchKernelGGL((k_sparse_dot<double2, true>), g, b, 0, st, a, nrhs);
+    else if (a.fp32) hipLaunchKernelGGL((k_sparse_dot<float2, false>), g, b, 0, st, a, nrhs);
+    else hipLaunchKernelGGL((k_sparse_dot<double2, false>), g, b, 0, st, a, nrhs);
 }
 
 #define INST(T)                                                                                  \

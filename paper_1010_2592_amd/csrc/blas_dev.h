@@ -211,7 +211,7 @@ __device__ __forceinline__ void rel_update_body(const VecArgs<T> &a, const doubl
     if (!gate_open(a.gate, rhs)) return;
     const long n = a.n;
     C<T> *R = a.R + (size_t)rhs * (a.l + 1) * n;
-    const C<T> *rt = a.rt + (size_t)rhs * n;
+    const C<T> *rt = a.rt ? a.rt + (size_t)rhs * n : nullptr;   // null: sparse r~, dot taken afterwards
     const double2 *br = b + (size_t)rhs * n, *vr = v + (size_t)rhs * n;
     double2 *yr = y ? y + (size_t)rhs * n : nullptr;
     const double2 c = y ? ld(yc, rhs) : d2(0, 0);
@@ -221,9 +221,11 @@ __device__ __forceinline__ void rel_update_body(const VecArgs<T> &a, const doubl
         const double2 r0 = csub(br[e], ve);
         R[e] = to_c<T>(r0);
         if (yr) yr[e] = cfma(c, ve, yr[e]);
-        const C<T> t = rt[e];
-        p[0] += (double)t.x * r0.x + (double)t.y * r0.y;
-        p[1] += (double)t.x * r0.y - (double)t.y * r0.x;
+        if (rt) {
+            const C<T> t = rt[e];
+            p[0] += (double)t.x * r0.x + (double)t.y * r0.y;
+            p[1] += (double)t.x * r0.y - (double)t.y * r0.x;
+        }
         p[2] += r0.x * r0.x + r0.y * r0.y;
     }
     block_reduce_store<3>(p, a.part + (size_t)rhs * PMAX * a.ps + bx, a.ps);

@@ -176,14 +176,17 @@ void launch_zero(hipStream_t, C<T> *dst, long n, long stride, int nrhs);
 // largest row count (the list is written only when it is <= spmax), or -1 on
 // a HIP error.  work: nrhs * nb ints.  Synchronises the stream.
 int sparse_list(hipStream_t, const double2 *v, long n, long rs, int nrhs, int spmax, long *idx, double2 *val,
-                int *cnt, int *work, int nb);
+                int *cnt, int *work, int nb, bool fp32 = false);
 struct SparseDotArgs {
     const long *idx = nullptr;      // [nrhs][spmax]
     const double2 *val = nullptr;   // [nrhs][spmax]
     const int *cnt = nullptr;       // [nrhs]
     int spmax = 0;
-    const double2 *x = nullptr;     // the vector dotted with r~, rhs stride x_rs
+    const void *x = nullptr;        // the vector dotted with r~, rhs stride x_rs (elements)
     long x_rs = 0;
+    int fp32 = 0;                   // x holds float2 (mixed precision)
+    const double2 *b = nullptr;     // set: dot with b - v instead (FP64, rhs stride x_rs)
+    const double2 *v = nullptr;
     double *part = nullptr;
     long ps = 0;
     Gate gate{};

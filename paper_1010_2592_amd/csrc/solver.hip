@@ -854,14 +854,16 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     // one-wavefront kernel after them.  FP64 per-stage launches only.
     constexpr int SPMAX = 16;
     SparseDotArgs spa;
-    if (!mixed && !P.persistent) {
+    if (!P.persistent) {
         constexpr int NBL = 256;
         CHK(ensure(c->ws_sp, (size_t)nrhs * (SPMAX * (sizeof(long) + sizeof(double2)) + (1 + NBL) * sizeof(int)) + 256));
         long *spi = (long *)c->ws_sp.p;
         double2 *spv = (double2 *)(spi + (size_t)nrhs * SPMAX);
         int *spc = (int *)(spv + (size_t)nrhs * SPMAX);
         int *spw = spc + nrhs;
-        const int worst = sparse_list(st, (const double2 *)rt, n, n, nrhs, SPMAX, spi, spv, spc, spw, NBL);
+        // from the FP64 r~ (mixed precision: values rounded as in its FP32 copy)
+        const int worst = sparse_list(st, P.shadow ? P.shadow : b, n, n, nrhs, SPMAX, spi, spv, spc, spw, NBL,
+                                      mixed);
         if (worst < 0) return set_error(S_ERR_HIP, "scan of the shadow residual for nonzero entries failed");
         sparse_rt = worst <= SPMAX;
         spa.idx = spi;
@@ -870,6 +872,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         spa.spmax = SPMAX;
         spa.part = part;
         spa.ps = ps;
+        spa.fp32 = mixed ? 1 : 0;
     }
     ScalarArgs sa;
     sa.seed = seed;
@@ -972,7 +975,16 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         e.ds64(q2, nrhs, EPI_SV, CL_STENCIL, ds64_sv * nr / std::max(nrhs, 1));
         VecArgs<T> w = vv;
         w.gate = g;
-        e.rel_update(w, b, v64, yacc, yc, nrhs, nbv, CL_SEED, nr * nd * (32.0 + cB + cB + (yacc ? 32.0 : 0.0)));
+        e.rel_update(w, b, v64, yacc, yc, nrhs, nbv, CL_SEED,
+                     nr * nd * (32.0 + (sparse_rt ? 0.0 : cB) + cB + (yacc ? 32.0 : 0.0)));
+        if (sparse_rt) {   // <r~, b - S x> from the list, as the update would have formed it
+            SparseDotArgs a = spa;
+            a.b = b;
+            a.v = v64;
+            a.x_rs = n;
+            a.gate = g;
+            e.sparse_dot(a, nrhs, nr * SPMAX * (8.0 + 16.0 + 32.0));
+        }
     };
 
     // One outer iteration of the first pass: l BiCG steps, the MR step, the
@@ -1002,7 +1014,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
 
     // <r~, x> for x = [rhs] rows at the seed-vector stride, into the partial
     // slots the preceding kernel left at zero
-    auto sparse_dot_of = [&](Emit<T> &e, const double2 *x, const Gate &g, int nr_run) {
+    auto sparse_dot_of = [&](Emit<T> &e, const void *x, const Gate &g, int nr_run) {
         SparseDotArgs a = spa;
         a.x = x;
         a.x_rs = vs;
@@ -1045,7 +1057,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 e2.out2_rs = ps_rs;
             }
             e.ds(e2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
-            if (sparse_rt) sparse_dot_of(e, (const double2 *)e2.out, e2.gate, nr_run);
+            if (sparse_rt) sparse_dot_of(e, e2.out, e2.gate, nr_run);
             s.nblk = nbd;
             e.scalar(OP_SC_ALPHA, s, nrhs);
             v.partials = 1;
@@ -1075,7 +1087,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             if (deferred) e2.out2 = Bm + (size_t)(3 + 2 * j) * n;
             if (pass3) e2.out2 = (C<T> *)c->pstore[m / PSC].p + ((size_t)(m % PSC) * 2 * l + 2 * j + 1) * n;
             e.ds(e2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
-            if (sparse_rt) sparse_dot_of(e, (const double2 *)e2.out, e2.gate, nr_run);
+            if (sparse_rt) sparse_dot_of(e, e2.out, e2.gate, nr_run);
         }
         v.gate = g_run;
         e.gram(v, nrhs, nbv, CL_SEED, nr_run * (l + 1.0) * nd * cB);
@@ -1087,7 +1099,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         e.mr_update(v, shifts_step, mixed, nrhs, nbv, shifts_step ? CL_SHIFT_MR : CL_SEED,
                     nr_run * ((2.0 * (l + 1) + (sparse_rt ? 2 : 3)) * cB + (mixed ? 32.0 : 0.0)) * nd +
                         (shifts_step ? nsh_act * ((l + 2.0) * cB + 32.0) * nd : 0.0));
-        if (sparse_rt) sparse_dot_of(e, (const double2 *)R, v.gate, nr_run);
+        if (sparse_rt) sparse_dot_of(e, R, v.gate, nr_run);
         if (deferred) {
             // every shift's update over the iteration, from the basis: read the
             // 2l+2 basis vectors once, each active shift's u^s_0 and x^s (FP64)
