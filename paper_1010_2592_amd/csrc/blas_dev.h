@@ -13,6 +13,18 @@ namespace dev {
 template <typename T>
 __device__ __forceinline__ C<T> cvt(double2 z) { return to_c<T>(z); }
 
+// Where seed vector r_i / u_i of right-hand side rhs is read: its row of R / U
+// (base already offset to the right-hand side), or the store of the
+// pseudo-double pass for the one vector named by r_src_i / u_src_i.
+template <typename T>
+__device__ __forceinline__ const C<T> *rsrc(const VecArgs<T> &a, const C<T> *R, int i, int rhs, long n) {
+    return i == a.r_src_i ? a.r_src + (size_t)rhs * a.r_src_rs : R + (size_t)i * n;
+}
+template <typename T>
+__device__ __forceinline__ const C<T> *usrc(const VecArgs<T> &a, const C<T> *U, int i, int rhs, long n) {
+    return i == a.u_src_i ? a.u_src + (size_t)rhs * a.u_src_rs : U + (size_t)i * n;
+}
+
 // ---------------------------------------------------------------------------
 // u_i = r_i - beta u_i for i in [I0, I1]: MODE 0 all of 0..J (the BiCG step's
 // direction update), MODE 1 only u_J (the one the step's Mv needs; the others
@@ -30,8 +42,8 @@ __device__ __forceinline__ void seed_u_body(const VecArgs<T> &a, int bx, int gx,
     for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
 #pragma unroll
         for (int i = I0; i <= I1; ++i) {
-            const C<T> r = R[i * n + e];
-            const C<T> u = U[i * n + e];
+            const C<T> r = rsrc(a, R, i, rhs, n)[e];
+            const C<T> u = usrc(a, U, i, rhs, n)[e];
             U[i * n + e] = csub(r, cmul(beta, u));
         }
     }
@@ -57,21 +69,21 @@ __device__ __forceinline__ void r_update_body(const VecArgs<T> &a, int bx, int g
         C<T> r[J + 1], u1[J + 1];
         C<T> u0n = mk<T>(0, 0);
 #pragma unroll
-        for (int i = 0; i <= J; ++i) r[i] = R[i * n + e];
+        for (int i = 0; i <= J; ++i) r[i] = rsrc(a, R, i, rhs, n)[e];
         if (FU && J >= 1) {
             // u_i (i < J) = r_i - beta u_i; u1[i] = u_{i+1}
 #pragma unroll
             for (int i = 0; i < J; ++i) {
-                const C<T> un = csub(r[i], cmul(beta, U[i * n + e]));
+                const C<T> un = csub(r[i], cmul(beta, usrc(a, U, i, rhs, n)[e]));
                 U[i * n + e] = un;
                 if (i == 0) u0n = un;
                 else u1[i - 1] = un;
             }
-            u1[J - 1] = U[J * n + e];
-            u1[J] = U[(J + 1) * n + e];
+            u1[J - 1] = usrc(a, U, J, rhs, n)[e];
+            u1[J] = usrc(a, U, J + 1, rhs, n)[e];
         } else {
 #pragma unroll
-            for (int i = 0; i <= J; ++i) u1[i] = U[(i + 1) * n + e];
+            for (int i = 0; i <= J; ++i) u1[i] = usrc(a, U, i + 1, rhs, n)[e];
         }
         if (SHIFTS) {
             for (int q = 0; q < nact; ++q) {
@@ -94,7 +106,7 @@ __device__ __forceinline__ void r_update_body(const VecArgs<T> &a, int bx, int g
         }
         if (XH) {
             // seed solution x += alpha u_0, accumulated in FP64
-            const C<T> u0 = (FU && J >= 1) ? u0n : U[e];
+            const C<T> u0 = (FU && J >= 1) ? u0n : usrc(a, U, 0, rhs, n)[e];
             double2 *xh = a.XH + (size_t)rhs * n;
             xh[e] = cfma(alpha_d, d2((double)u0.x, (double)u0.y), xh[e]);
         }
@@ -121,7 +133,7 @@ __device__ __forceinline__ void gram_body(const VecArgs<T> &a, int bx, int gx, i
     for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
         C<T> r[L + 1];
 #pragma unroll
-        for (int i = 0; i <= L; ++i) r[i] = R[i * n + e];
+        for (int i = 0; i <= L; ++i) r[i] = rsrc(a, R, i, rhs, n)[e];
         int p = 0;
 #pragma unroll
         for (int i = 0; i <= L; ++i)
@@ -158,7 +170,7 @@ __device__ __forceinline__ void mr_update_body(const VecArgs<T> &a, int bx, int 
     for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
         C<T> r[L + 1];
 #pragma unroll
-        for (int i = 0; i <= L; ++i) r[i] = R[i * n + e];
+        for (int i = 0; i <= L; ++i) r[i] = rsrc(a, R, i, rhs, n)[e];
         if (SHIFTS) {
             for (int q = 0; q < nact; ++q) {
                 const MRCoef &c = mc[q];
@@ -187,9 +199,9 @@ __device__ __forceinline__ void mr_update_body(const VecArgs<T> &a, int bx, int 
 #pragma unroll
         for (int i = 1; i <= L; ++i) r0 = csub(r0, cmul(g[i], r[i]));
         R[e] = r0;
-        C<T> u0 = U[e];
+        C<T> u0 = usrc(a, U, 0, rhs, n)[e];
 #pragma unroll
-        for (int i = 1; i <= L; ++i) u0 = csub(u0, cmul(g[i], U[i * n + e]));
+        for (int i = 1; i <= L; ++i) u0 = csub(u0, cmul(g[i], usrc(a, U, i, rhs, n)[e]));
         U[e] = u0;
         if (a.partials) {
             if (rt) {

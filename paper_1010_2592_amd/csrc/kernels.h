@@ -131,6 +131,14 @@ struct VecArgs {
     C<T> *Bm = nullptr;         // [rhs][2l+2][n] the outer iteration's basis
     C<T> *W0 = nullptr;         // [rhs][nshift][n] u^s_0 of every shift
     const DeferCoef *dc = nullptr;  // [rhs][NSMAX]
+    // pseudo-double pass: an Mv output is written to the store only, and is
+    // read from there (not from R / U) until its first update; index -1: none
+    const C<T> *r_src = nullptr;
+    long r_src_rs = 0;
+    int r_src_i = -1;
+    const C<T> *u_src = nullptr;
+    long u_src_rs = 0;
+    int u_src_i = -1;
 };
 
 // mode: 0 u_0..u_j, 1 u_j only, 2 u_0..u_{j-1} (see seed_u_body)

@@ -1014,14 +1014,17 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
 
     // <r~, x> for x = [rhs] rows at the seed-vector stride, into the partial
     // slots the preceding kernel left at zero
-    auto sparse_dot_of = [&](Emit<T> &e, const void *x, const Gate &g, int nr_run) {
+    auto sparse_dot_of = [&](Emit<T> &e, const void *x, const Gate &g, int nr_run, long x_rs) {
         SparseDotArgs a = spa;
         a.x = x;
-        a.x_rs = vs;
+        a.x_rs = x_rs;
         a.gate = g;
         e.sparse_dot(a, nrhs, nr_run * SPMAX * (8.0 + 16.0 + 16.0));
     };
-    const int mv_epi = (deferred || pass3) ? (sparse_rt ? EPI_MVBN : EPI_MVB) : (sparse_rt ? EPI_MVN : EPI_MV);
+    // pass 3 writes each Mv output to its store slot only (the seed kernels
+    // read it from there until its first update); the deferred single pass
+    // writes it to R / U and a copy to its basis
+    const int mv_epi = deferred ? (sparse_rt ? EPI_MVBN : EPI_MVB) : (sparse_rt ? EPI_MVN : EPI_MV);
     const bool fuse_seed = !P.persistent;   // fused direction updates (per-stage launches)
     auto emit_outer = [&](Emit<T> &e, int nr_run, double nsh_act, int m) {
         VecArgs<T> v = va;
@@ -1033,12 +1036,22 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             e.snapshot(v, nrhs, nbv, CL_SHIFT, nr_run * 4.0 * nd * cB);
             e2.out2_rs = (long)nb * n;
         }
+        // pass 3: store slot t of this outer iteration (t = 2j: u_{j+1}, 2j + 1: r_{j+1})
+        auto slot = [&](int t) { return (C<T> *)c->pstore[m / PSC].p + ((size_t)(m % PSC) * 2 * l + t) * n; };
+        auto from_store = [&](VecArgs<T> &x, int ri, int ui) {
+            x.r_src_i = (pass3 && ri >= 1) ? ri : -1;
+            x.u_src_i = (pass3 && ui >= 1) ? ui : -1;
+            if (x.r_src_i >= 1) x.r_src = slot(2 * (ri - 1) + 1);
+            if (x.u_src_i >= 1) x.u_src = slot(2 * (ui - 1));
+            x.r_src_rs = x.u_src_rs = ps_rs;
+        };
         for (int j = 0; j < l; ++j) {
             s.j = j;
             s.nblk = (j == 0) ? nbv : nbd;
             s.nblk2 = nbv;
             e.scalar(OP_SC_BETA, s, nrhs);
             v.gate = g_bicg;
+            from_store(v, j, j);     // r_j and u_j: this step's first update of both
             // fused form: only u_j before its Mv; u_0..u_{j-1} in the r-update
             const bool fu = fuse_seed && j >= 1;
             e.seed_u(v, j, nrhs, nbv, CL_SEED, nr_run * (fu ? 3.0 : 3.0 * (j + 1)) * nd * cB, fu ? 1 : 0);
@@ -1053,14 +1066,15 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             e2.gate = g_bicg;
             if (deferred) e2.out2 = Bm + (size_t)(2 + 2 * j) * n;
             if (pass3) {
-                e2.out2 = (C<T> *)c->pstore[m / PSC].p + ((size_t)(m % PSC) * 2 * l + 2 * j) * n;
-                e2.out2_rs = ps_rs;
+                e2.out = slot(2 * j);
+                e2.out_rs = ps_rs;
             }
             e.ds(e2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
-            if (sparse_rt) sparse_dot_of(e, e2.out, e2.gate, nr_run);
+            if (sparse_rt) sparse_dot_of(e, e2.out, e2.gate, nr_run, pass3 ? ps_rs : vs);
             s.nblk = nbd;
             e.scalar(OP_SC_ALPHA, s, nrhs);
             v.partials = 1;
+            from_store(v, j, j + 1);     // r_j (first update) and u_{j+1} (read only)
             // seed: read r_i, u_{i+1}, write r_i; shift s (per-step form): read
             // u^s_0..j, x^s (FP64), write u^s_0..j+1, x^s
             e.r_update(v, j, shifts_step, mixed, nrhs, nbv, shifts_step ? CL_SHIFT : CL_SEED,
@@ -1085,11 +1099,12 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             e2.out = R + (size_t)(j + 1) * n;
             e2.v = R + (size_t)j * n;
             if (deferred) e2.out2 = Bm + (size_t)(3 + 2 * j) * n;
-            if (pass3) e2.out2 = (C<T> *)c->pstore[m / PSC].p + ((size_t)(m % PSC) * 2 * l + 2 * j + 1) * n;
+            if (pass3) e2.out = slot(2 * j + 1);
             e.ds(e2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
-            if (sparse_rt) sparse_dot_of(e, e2.out, e2.gate, nr_run);
+            if (sparse_rt) sparse_dot_of(e, e2.out, e2.gate, nr_run, pass3 ? ps_rs : vs);
         }
         v.gate = g_run;
+        from_store(v, l, l);         // r_l and u_l: read by the MR step only
         e.gram(v, nrhs, nbv, CL_SEED, nr_run * (l + 1.0) * nd * cB);
         s.nblk = nbv;
         e.scalar(OP_SC_MR, s, nrhs);
@@ -1099,7 +1114,8 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         e.mr_update(v, shifts_step, mixed, nrhs, nbv, shifts_step ? CL_SHIFT_MR : CL_SEED,
                     nr_run * ((2.0 * (l + 1) + (sparse_rt ? 2 : 3)) * cB + (mixed ? 32.0 : 0.0)) * nd +
                         (shifts_step ? nsh_act * ((l + 2.0) * cB + 32.0) * nd : 0.0));
-        if (sparse_rt) sparse_dot_of(e, R, v.gate, nr_run);
+        if (sparse_rt) sparse_dot_of(e, R, v.gate, nr_run, vs);
+        from_store(v, -1, -1);
         if (deferred) {
             // every shift's update over the iteration, from the basis: read the
             // 2l+2 basis vectors once, each active shift's u^s_0 and x^s (FP64)
