@@ -81,12 +81,13 @@ def workload_key(pass_, precision, refine, persistent, deferred=False):
 
 def measured_traffic(key):
     """HBM bytes per stencil launch from the committed rocprofv3 counter runs
-    (profiles/dslash_traffic.json), or None when the stencil sources changed
-    since they were taken or the form differs from the one they were taken on."""
+    (profiles/dslash_traffic.json), or None when the stencil or solver sources
+    changed since they were taken or the form differs from the one they were
+    taken on."""
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "dslash_traffic.json")))
-        from paper_1010_2592_amd.rocprof_summary import sources_hash
-        if sources_hash(rec["sources"]) != rec.get("sources_sha256_16"):
+        from paper_1010_2592_amd.rocprof_summary import STENCIL_SOURCES, sources_hash
+        if rec.get("sources") != STENCIL_SOURCES or sources_hash() != rec.get("sources_sha256_16"):
             return None
     except (OSError, ValueError, KeyError):
         return None
