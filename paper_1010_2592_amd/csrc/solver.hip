@@ -1021,10 +1021,10 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         a.gate = g;
         e.sparse_dot(a, nrhs, nr_run * SPMAX * (8.0 + 16.0 + 16.0));
     };
-    // pass 3 writes each Mv output to its store slot only (the seed kernels
-    // read it from there until its first update); the deferred single pass
-    // writes it to R / U and a copy to its basis
-    const int mv_epi = deferred ? (sparse_rt ? EPI_MVBN : EPI_MVB) : (sparse_rt ? EPI_MVN : EPI_MV);
+    // pass 3 and the deferred single pass write each Mv output to their store
+    // (or basis) slot only; the seed kernels read it from there until its
+    // first update
+    const int mv_epi = sparse_rt ? EPI_MVN : EPI_MV;
     const bool fuse_seed = !P.persistent;   // fused direction updates (per-stage launches)
     auto emit_outer = [&](Emit<T> &e, int nr_run, double nsh_act, int m) {
         VecArgs<T> v = va;
@@ -1034,16 +1034,22 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             // the iteration's basis starts with r_0 and u_0
             v.gate = g_run;
             e.snapshot(v, nrhs, nbv, CL_SHIFT, nr_run * 4.0 * nd * cB);
-            e2.out2_rs = (long)nb * n;
         }
-        // pass 3: store slot t of this outer iteration (t = 2j: u_{j+1}, 2j + 1: r_{j+1})
-        auto slot = [&](int t) { return (C<T> *)c->pstore[m / PSC].p + ((size_t)(m % PSC) * 2 * l + t) * n; };
+        // Mv output t of this outer iteration (t = 2j: u_{j+1}, 2j + 1:
+        // r_{j+1}): its slot in the pass-3 store, or in the deferred single
+        // pass's basis (after B_0 = r_0, B_1 = u_0)
+        const bool stored = pass3 || deferred;
+        const long store_rs = pass3 ? ps_rs : (long)nb * n;
+        auto slot = [&](int t) {
+            return pass3 ? (C<T> *)c->pstore[m / PSC].p + ((size_t)(m % PSC) * 2 * l + t) * n
+                         : Bm + (size_t)(2 + t) * n;
+        };
         auto from_store = [&](VecArgs<T> &x, int ri, int ui) {
-            x.r_src_i = (pass3 && ri >= 1) ? ri : -1;
-            x.u_src_i = (pass3 && ui >= 1) ? ui : -1;
+            x.r_src_i = (stored && ri >= 1) ? ri : -1;
+            x.u_src_i = (stored && ui >= 1) ? ui : -1;
             if (x.r_src_i >= 1) x.r_src = slot(2 * (ri - 1) + 1);
             if (x.u_src_i >= 1) x.u_src = slot(2 * (ui - 1));
-            x.r_src_rs = x.u_src_rs = ps_rs;
+            x.r_src_rs = x.u_src_rs = store_rs;
         };
         for (int j = 0; j < l; ++j) {
             s.j = j;
@@ -1064,13 +1070,12 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             e2.out = Uv + (size_t)(j + 1) * n;
             e2.v = Uv + (size_t)j * n;
             e2.gate = g_bicg;
-            if (deferred) e2.out2 = Bm + (size_t)(2 + 2 * j) * n;
-            if (pass3) {
+            if (stored) {
                 e2.out = slot(2 * j);
-                e2.out_rs = ps_rs;
+                e2.out_rs = store_rs;
             }
             e.ds(e2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
-            if (sparse_rt) sparse_dot_of(e, e2.out, e2.gate, nr_run, pass3 ? ps_rs : vs);
+            if (sparse_rt) sparse_dot_of(e, e2.out, e2.gate, nr_run, stored ? store_rs : vs);
             s.nblk = nbd;
             e.scalar(OP_SC_ALPHA, s, nrhs);
             v.partials = 1;
@@ -1098,10 +1103,9 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             else e2.in = R + (size_t)j * n;
             e2.out = R + (size_t)(j + 1) * n;
             e2.v = R + (size_t)j * n;
-            if (deferred) e2.out2 = Bm + (size_t)(3 + 2 * j) * n;
-            if (pass3) e2.out = slot(2 * j + 1);
+            if (stored) e2.out = slot(2 * j + 1);
             e.ds(e2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
-            if (sparse_rt) sparse_dot_of(e, e2.out, e2.gate, nr_run, pass3 ? ps_rs : vs);
+            if (sparse_rt) sparse_dot_of(e, e2.out, e2.gate, nr_run, stored ? store_rs : vs);
         }
         v.gate = g_run;
         from_store(v, l, l);         // r_l and u_l: read by the MR step only
