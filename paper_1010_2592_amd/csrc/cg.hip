@@ -188,6 +188,8 @@ struct CGVec {
     int nshift = 0;
     double2 *store = nullptr;             // pseudo-double pass: slot for r_{k+1} ([rhs] stride store_rs)
     long store_rs = 0;
+    const double2 *rk = nullptr;          // pseudo-double pass: where r_k is read ([rhs] stride rk_rs;
+    long rk_rs = 0;                       // null: r), r_{k+1} then going to the store slot only
     double *part = nullptr;
     long ps = 0;
     long n = 0;
@@ -195,7 +197,8 @@ struct CGVec {
 
 // r_{k+1} = r_k - alpha_k w and ||r_{k+1}||^2; with SHIFTS every active shift's
 // p^s_k = r_k / zeta_k + beta^s_{k-1} p^s_{k-1} (p^s_0 = r_0) and
-// x^s += alpha^s_k p^s_k; with STORE r_{k+1} also goes to the store slot.
+// x^s += alpha^s_k p^s_k; with STORE r_{k+1} goes to the store slot instead of
+// r (r_k read from rk when set: the previous slot).
 template <bool SHIFTS, bool STORE>
 __global__ __launch_bounds__(BLOCK) void k_cg_r(CGVec a) {
     const int rhs = blockIdx.y;
@@ -204,15 +207,16 @@ __global__ __launch_bounds__(BLOCK) void k_cg_r(CGVec a) {
     const long n = a.n;
     const double alpha = S.alpha;
     double2 *r = a.r + (size_t)rhs * n;
+    const double2 *rin = (STORE && a.rk) ? a.rk + (size_t)rhs * a.rk_rs : r;
     const double2 *w = a.w + (size_t)rhs * n;
     const int nact = SHIFTS ? S.nact : 0;
     const CGCoef *cf = a.coef + (size_t)rhs * NSMAX;
     double part[1] = {0.0};
     for (long e = (long)blockIdx.x * BLOCK + threadIdx.x; e < n; e += (long)gridDim.x * BLOCK) {
-        const double2 ro = r[e];
+        const double2 ro = rin[e];
         const double2 rn = csub(ro, cscale(w[e], alpha));
-        r[e] = rn;
         if (STORE) a.store[(size_t)rhs * a.store_rs + e] = rn;
+        else r[e] = rn;
         part[0] += rn.x * rn.x + rn.y * rn.y;
         if (SHIFTS) {
             for (int q = 0; q < nact; ++q) {
@@ -235,7 +239,7 @@ __global__ __launch_bounds__(BLOCK) void k_cg_p(CGVec a) {
     const long n = a.n;
     const double beta = S.beta;
     double2 *p = a.p + (size_t)rhs * n;
-    const double2 *r = a.r + (size_t)rhs * n;
+    const double2 *r = a.rk ? a.rk + (size_t)rhs * a.rk_rs : a.r + (size_t)rhs * n;   // rk: r_{k+1}'s slot
     for (long e = (long)blockIdx.x * BLOCK + threadIdx.x; e < n; e += (long)gridDim.x * BLOCK)
         p[e] = cadd(r[e], cscale(p[e], beta));
 }
@@ -475,6 +479,7 @@ int solve_cg(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2
 
     const long store_rs = (long)CG_CHUNK * n;
     for (int k = 0; k < max_iter; ++k) {
+        CGVec vp = vv;   // the p-update's arguments (pass 3: r_{k+1} from its slot)
         {
             Prof pr(c, CL_STENCIL, ds_plain);
             launch_dslash<double>(st, d1, nrhs, EPI_PLAIN, false);
@@ -490,16 +495,24 @@ int solve_cg(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2
         {
             CGVec v1 = vv;
             if (pass3) {
+                // r_{k+1} is written to its slot only; r_k is read from slot k
+                // (r_0 = b from r)
                 const int slot = k + 1;
                 const int ch = slot / CG_CHUNK;
                 while ((int)c->pstore.size() <= ch) c->pstore.push_back(DevBuf{});
                 CG_CHK(ensure(c->pstore[ch], (size_t)nrhs * store_rs * sizeof(double2)));
                 v1.store = (double2 *)c->pstore[ch].p + (size_t)(slot % CG_CHUNK) * n;
                 v1.store_rs = store_rs;
+                if (k >= 1) {
+                    v1.rk = (const double2 *)c->pstore[k / CG_CHUNK].p + (size_t)(k % CG_CHUNK) * n;
+                    v1.rk_rs = store_rs;
+                }
+                vp.rk = v1.store;
+                vp.rk_rs = store_rs;
             }
             // upper bound: every shift active (the byte model of the solve)
             Prof pr(c, pass1 ? CL_SHIFT : CL_SEED,
-                    nrhs * nd * (3.0 * cB + (pass3 ? cB : 0.0) + (pass1 ? ns * 4.0 * cB : 0.0)));
+                    nrhs * nd * (3.0 * cB + (pass1 ? ns * 4.0 * cB : 0.0)));
             dim3 g(nbv, nrhs);
             if (pass1) hipLaunchKernelGGL((k_cg_r<true, false>), g, dim3(BLOCK), 0, st, v1);
             else if (pass3) hipLaunchKernelGGL((k_cg_r<false, true>), g, dim3(BLOCK), 0, st, v1);
@@ -511,7 +524,7 @@ int solve_cg(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2
         }
         {
             Prof pr(c, CL_SEED, nrhs * nd * 3.0 * cB);
-            hipLaunchKernelGGL(k_cg_p, dim3(nbv, nrhs), dim3(BLOCK), 0, st, vv);
+            hipLaunchKernelGGL(k_cg_p, dim3(nbv, nrhs), dim3(BLOCK), 0, st, vp);
         }
         CG_HIPCHK(hipGetLastError());
         if ((k + 1) % CG_SYNC == 0 || k + 1 == max_iter) {
