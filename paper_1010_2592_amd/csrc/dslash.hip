@@ -18,11 +18,9 @@
 //   EPI_MV_Y   as EPI_MV without partials, plus y += c * out (double-pass
 //              accumulation of the Mv outputs)
 //   EPI_SV     out = scale * gamma5 D in + sigma0 * v, nothing else
-//   EPI_MVB    as EPI_MV, and a second copy of out (the basis the deferred
-//              single pass updates its shift vectors from)
 //   EPI_SV2    as EPI_SV minus w (the Chebyshev three-term step of the
 //              low-mode eigensolver: out = scale gamma5 D in + sigma0 v - w)
-//   EPI_MVN, EPI_MVBN  as EPI_MV, EPI_MVB without reading rt (partials of
+//   EPI_MVN    as EPI_MV without reading rt (partials of
 //              <rt, out> left zero; the solver adds them from a sparse list
 //              of rt's nonzero entries)
 // Which operands exist is a compile-time property of the mode: run-time null
@@ -167,18 +165,14 @@ void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in
             else if (epi == EPI_MV) MSB_DS(EPI_MV, true);
             else if (epi == EPI_SV) MSB_DS(EPI_SV, true);
             else if (epi == EPI_SV2) MSB_DS(EPI_SV2, true);
-            else if (epi == EPI_MVB) MSB_DS(EPI_MVB, true);
             else if (epi == EPI_MVN) MSB_DS(EPI_MVN, true);
-            else if (epi == EPI_MVBN) MSB_DS(EPI_MVBN, true);
             else MSB_DS(EPI_MV_Y, true);
         } else {
             if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, false);
             else if (epi == EPI_MV) MSB_DS(EPI_MV, false);
             else if (epi == EPI_SV) MSB_DS(EPI_SV, false);
             else if (epi == EPI_SV2) MSB_DS(EPI_SV2, false);
-            else if (epi == EPI_MVB) MSB_DS(EPI_MVB, false);
             else if (epi == EPI_MVN) MSB_DS(EPI_MVN, false);
-            else if (epi == EPI_MVBN) MSB_DS(EPI_MVBN, false);
             else MSB_DS(EPI_MV_Y, false);
         }
 #undef MSB_DS
@@ -191,18 +185,14 @@ void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in
         else if (epi == EPI_MV) MSB_DS(EPI_MV, true);
         else if (epi == EPI_SV) MSB_DS(EPI_SV, true);
         else if (epi == EPI_SV2) MSB_DS(EPI_SV2, true);
-        else if (epi == EPI_MVB) MSB_DS(EPI_MVB, true);
         else if (epi == EPI_MVN) MSB_DS(EPI_MVN, true);
-        else if (epi == EPI_MVBN) MSB_DS(EPI_MVBN, true);
         else MSB_DS(EPI_MV_Y, true);
     } else {
         if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, false);
         else if (epi == EPI_MV) MSB_DS(EPI_MV, false);
         else if (epi == EPI_SV) MSB_DS(EPI_SV, false);
         else if (epi == EPI_SV2) MSB_DS(EPI_SV2, false);
-        else if (epi == EPI_MVB) MSB_DS(EPI_MVB, false);
         else if (epi == EPI_MVN) MSB_DS(EPI_MVN, false);
-        else if (epi == EPI_MVBN) MSB_DS(EPI_MVBN, false);
         else MSB_DS(EPI_MV_Y, false);
     }
 #undef MSB_DS

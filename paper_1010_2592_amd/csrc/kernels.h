@@ -5,12 +5,10 @@
 
 namespace msb {
 
-enum { EPI_PLAIN = 0, EPI_MV = 1, EPI_MV_Y = 2, EPI_SV = 3, EPI_MVB = 4, EPI_MVN = 5, EPI_MVBN = 6, EPI_SV2 = 7 };
-// epilogues that write partials (EPI_MVN / EPI_MVBN: EPI_MV / EPI_MVB without
-// the <r~, out> term, which a sparse list supplies)
-__host__ __device__ constexpr bool epi_dots(int e) {
-    return e == EPI_MV || e == EPI_MVB || e == EPI_MVN || e == EPI_MVBN;
-}
+enum { EPI_PLAIN = 0, EPI_MV = 1, EPI_MV_Y = 2, EPI_SV = 3, EPI_MVN = 5, EPI_SV2 = 7 };
+// epilogues that write partials (EPI_MVN: EPI_MV without the <r~, out> term,
+// which a sparse list supplies)
+__host__ __device__ constexpr bool epi_dots(int e) { return e == EPI_MV || e == EPI_MVN; }
 
 // A per-right-hand-side complex coefficient in device memory: the value for
 // rhs r is *(const double2 *)(p + r * stride).
@@ -45,8 +43,6 @@ struct DslashArgs {
     int per_t = 0;             // chunked stencil: blocks per XCD (per rounded up to tsc)
     CoefRef ycoef;             // EPI_MV_Y: coefficient of the Mv output
     double2 *y = nullptr;      // EPI_MV_Y accumulator (always FP64)
-    C<T> *out2 = nullptr;      // EPI_MVB: second copy of the output (the deferred basis)
-    long out2_rs = 0;
     const C<T> *w = nullptr;   // EPI_SV2: subtracted from the output
     long w_rs = 0;
     Gate gate{};

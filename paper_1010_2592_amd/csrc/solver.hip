@@ -715,9 +715,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     auto ds_bytes = [&](int epi, int nr) {
         double per = 24 * cB;                                  // in + out
         if (epi == EPI_MV) per = 48 * cB;                      // + v + rt
-        else if (epi == EPI_MVB) per = 60 * cB;                // + v + rt + the basis copy
         else if (epi == EPI_MVN) per = 36 * cB;               // EPI_MV without rt
-        else if (epi == EPI_MVBN) per = 48 * cB;              // EPI_MVB without rt
         else if (epi == EPI_MV_Y) per = 36 * cB + 24 * 16.0;   // + v, y (FP64) read + write
         else if (epi == EPI_SV) per = 36 * cB;                 // + v
         return nr * per * Vd + 36 * cB * Vd;                   // links once per launch

@@ -186,7 +186,7 @@ template <typename T, int EPI, bool G5IN, typename LK>
 __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &lk, const C<T> *__restrict__ in,
                                              C<T> *__restrict__ out, const C<T> *__restrict__ v,
                                              const C<T> *__restrict__ rt, double2 *__restrict__ y, C<T> yc,
-                                             T sig0, C<T> *__restrict__ out2, const C<T> *__restrict__ wsub,
+                                             T sig0, const C<T> *__restrict__ wsub,
                                              int s0, double (&part)[3]) {
     const int V = a.g.V, Lx = a.g.Lx, Ly = a.g.Ly, Lz = a.g.Lz, Lt = a.g.Lt;
     for (int s = s0; s < V; s += a.sstride) {
@@ -288,13 +288,12 @@ __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &l
             if (EPI != EPI_PLAIN) o = cadd(o, cscale(elem_at<LK::staged>(v, k, V, s), sig0));
             if (EPI == EPI_SV2) o = csub(o, elem_at<LK::staged>(wsub, k, V, s));
             elem_at<LK::staged>(out, k, V, s) = o;
-            if (EPI == EPI_MVB || EPI == EPI_MVBN) elem_at<LK::staged>(out2, k, V, s) = o;
-            if (EPI == EPI_MV || EPI == EPI_MVB) {
+            if (EPI == EPI_MV) {
                 const C<T> r = elem_at<LK::staged>(rt, k, V, s);
                 part[0] += (double)r.x * o.x + (double)r.y * o.y;
                 part[1] += (double)r.x * o.y - (double)r.y * o.x;
             }
-            // EPI_MVN / EPI_MVBN: no r~ here, its dot comes from a sparse list
+            // EPI_MVN: no r~ here, its dot comes from a sparse list
             if (epi_dots(EPI)) part[2] += (double)o.x * o.x + (double)o.y * o.y;
             if (EPI == EPI_MV_Y) {
                 double2 &yr = elem_at<LK::staged>(y, k, V, s);
@@ -317,7 +316,6 @@ struct RhsOps {
     double2 *y;
     C<T> yc;
     T sig0;
-    C<T> *out2;
     const C<T> *w;
 };
 template <typename T, int EPI>
@@ -332,7 +330,6 @@ __device__ __forceinline__ RhsOps<T> rhs_ops(const DslashArgs<T> &a, int rhs) {
     o.yc = mk<T>(0, 0);
     if (EPI == EPI_MV_Y) o.yc = to_c<T>(ld(a.ycoef, rhs));
     o.sig0 = a.sigma0_rhs ? (T)a.sigma0_rhs[rhs] : a.sigma0;
-    o.out2 = a.out2 ? a.out2 + (size_t)rhs * (a.out2_rs ? a.out2_rs : nv) : nullptr;
     o.w = a.w ? a.w + (size_t)rhs * (a.w_rs ? a.w_rs : nv) : nullptr;
     return o;
 }
@@ -345,7 +342,7 @@ __device__ __forceinline__ void dslash_site_block(const DslashArgs<T> &a, int sb
     const RhsOps<T> o = rhs_ops<T, EPI>(a, rhs);
     const GlobalLinks<T> lk{a.U, a.g.V};
     double part[3] = {0.0, 0.0, 0.0};
-    dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, o.out2, o.w, sblk * BLOCK + threadIdx.x,
+    dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, o.w, sblk * BLOCK + threadIdx.x,
                               part);
     if (epi_dots(EPI))
         wave_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + sblk * (BLOCK / 64) + (threadIdx.x >> 6),
@@ -417,7 +414,7 @@ __device__ __forceinline__ void dslash_chunk(const DslashArgs<T> &a, int p) {
         if (!gate_open(a.gate, rhs)) continue;
         const RhsOps<T> o = rhs_ops<T, EPI>(a, rhs);
         double part[3] = {0.0, 0.0, 0.0};
-        dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, o.out2, o.w, base + lane, part);
+        dslash_sites<T, EPI, G5IN>(a, lk, o.in, o.out, o.v, o.rt, o.y, o.yc, o.sig0, o.w, base + lane, part);
         if (epi_dots(EPI)) wave_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + chunk, a.ps);
     }
 }
