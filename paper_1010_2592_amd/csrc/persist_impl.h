@@ -144,36 +144,69 @@ __device__ __forceinline__ void dslash_persist_body(const DslashArgs<T> &a, int 
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[i][c] = mk<T>(0, 0);
-
-        int sf, sb;
-        sf = (x == Lx - 1) ? s - (Lx - 1) : s + 1;
-        sb = (x == 0) ? s + (Lx - 1) : s - 1;
-        hop<T, 0, -1, false, G5IN>(acc, in, U + (size_t)0 * 9 * V + s, V, V, sf, (T)1);
-        hop<T, 0, +1, true, G5IN>(acc, in, U + (size_t)0 * 9 * V + sb, V, V, sb, (T)1);
-        sf = (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx;
-        sb = (yy == 0) ? s + (Ly - 1) * Lx : s - Lx;
-        hop<T, 1, -1, false, G5IN>(acc, in, U + (size_t)1 * 9 * V + s, V, V, sf, (T)1);
-        hop<T, 1, +1, true, G5IN>(acc, in, U + (size_t)1 * 9 * V + sb, V, V, sb, (T)1);
-        sf = (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy;
-        sb = (z == 0) ? s + (Lz - 1) * sxy : s - sxy;
-        hop<T, 2, -1, false, G5IN>(acc, in, U + (size_t)2 * 9 * V + s, V, V, sf, (T)1);
-        hop<T, 2, +1, true, G5IN>(acc, in, U + (size_t)2 * 9 * V + sb, V, V, sb, (T)1);
-        sf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
-        sb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
+        // the hop order of wilson_site_global (by the parity of z + t),
+        // written out here: through that function the kernel's allocation
+        // needs more than 256 VGPRs and spills
         const T ff = (t == Lt - 1) ? a.ef * a.bc : a.ef;
         const T fb = (t == 0) ? a.eb * a.bc : a.eb;
-        hop<T, 3, -1, false, G5IN>(acc, in, U + (size_t)3 * 9 * V + s, V, V, sf, ff);
-        hop<T, 3, +1, true, G5IN>(acc, in, U + (size_t)3 * 9 * V + sb, V, V, sb, fb);
-
-        // out = scale * [gamma5] ((4+m) psi(x) - acc / 2), formed in place
+        if ((z + t) & 1) {
+            int sf, sb;
+            sf = (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy;
+            sb = (z == 0) ? s + (Lz - 1) * sxy : s - sxy;
+            hop<T, 2, -1, false, G5IN>(acc, in, U + (size_t)2 * 9 * V + s, V, V, sf, (T)1);
+            hop<T, 2, +1, true, G5IN>(acc, in, U + (size_t)2 * 9 * V + sb, V, V, sb, (T)1);
+            sf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
+            sb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
+            hop<T, 3, -1, false, G5IN>(acc, in, U + (size_t)3 * 9 * V + s, V, V, sf, ff);
+            hop<T, 3, +1, true, G5IN>(acc, in, U + (size_t)3 * 9 * V + sb, V, V, sb, fb);
+            sf = (x == Lx - 1) ? s - (Lx - 1) : s + 1;
+            sb = (x == 0) ? s + (Lx - 1) : s - 1;
+            hop<T, 0, -1, false, G5IN>(acc, in, U + (size_t)0 * 9 * V + s, V, V, sf, (T)1);
+            hop<T, 0, +1, true, G5IN>(acc, in, U + (size_t)0 * 9 * V + sb, V, V, sb, (T)1);
+            sf = (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx;
+            sb = (yy == 0) ? s + (Ly - 1) * Lx : s - Lx;
+            hop<T, 1, -1, false, G5IN>(acc, in, U + (size_t)1 * 9 * V + s, V, V, sf, (T)1);
+            hop<T, 1, +1, true, G5IN>(acc, in, U + (size_t)1 * 9 * V + sb, V, V, sb, (T)1);
 #pragma unroll
-        for (int sp = 0; sp < 4; ++sp) {
-            C<T> ps[3];
-            load_spin<T, G5IN>(in, V, s, sp, ps);
-            const T sg = ((a.g5out && sp >= 2) ? (T)-1 : (T)1) * a.scale;
+            for (int sp = 0; sp < 4; ++sp) {
+                C<T> ps[3];
+                load_spin<T, G5IN>(in, V, s, sp, ps);
+                const T sg = ((a.g5out && sp >= 2) ? (T)-1 : (T)1) * a.scale;
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                acc[sp][c] = cscale(csub(cscale(ps[c], a.diag), cscale(acc[sp][c], (T)0.5)), sg);
+                for (int c = 0; c < 3; ++c)
+                    acc[sp][c] = cscale(csub(cscale(ps[c], a.diag), cscale(acc[sp][c], (T)0.5)), sg);
+            }
+        } else {
+            const T m2d = (T)-2 * a.diag;
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) {
+                C<T> ps[3];
+                load_spin<T, G5IN>(in, V, s, sp, ps);
+                diag_start_spin<T>(acc[sp], ps, m2d);
+            }
+            int sf, sb;
+            sf = (x == Lx - 1) ? s - (Lx - 1) : s + 1;
+            sb = (x == 0) ? s + (Lx - 1) : s - 1;
+            hop<T, 0, -1, false, G5IN>(acc, in, U + (size_t)0 * 9 * V + s, V, V, sf, (T)1);
+            hop<T, 0, +1, true, G5IN>(acc, in, U + (size_t)0 * 9 * V + sb, V, V, sb, (T)1);
+            sf = (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx;
+            sb = (yy == 0) ? s + (Ly - 1) * Lx : s - Lx;
+            hop<T, 1, -1, false, G5IN>(acc, in, U + (size_t)1 * 9 * V + s, V, V, sf, (T)1);
+            hop<T, 1, +1, true, G5IN>(acc, in, U + (size_t)1 * 9 * V + sb, V, V, sb, (T)1);
+            sf = (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy;
+            sb = (z == 0) ? s + (Lz - 1) * sxy : s - sxy;
+            hop<T, 2, -1, false, G5IN>(acc, in, U + (size_t)2 * 9 * V + s, V, V, sf, (T)1);
+            hop<T, 2, +1, true, G5IN>(acc, in, U + (size_t)2 * 9 * V + sb, V, V, sb, (T)1);
+            sf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
+            sb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
+            hop<T, 3, -1, false, G5IN>(acc, in, U + (size_t)3 * 9 * V + s, V, V, sf, ff);
+            hop<T, 3, +1, true, G5IN>(acc, in, U + (size_t)3 * 9 * V + sb, V, V, sb, fb);
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) {
+                const T f = ((a.g5out && sp >= 2) ? (T)0.5 : (T)-0.5) * a.scale;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[sp][c] = cscale(acc[sp][c], f);
+            }
         }
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp) {

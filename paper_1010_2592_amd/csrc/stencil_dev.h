@@ -173,23 +173,138 @@ struct LdsLinks {
     __device__ __forceinline__ int stride() const { return CHUNK; }
 };
 
+// Order of the hop sum, chosen by the parity of z + t (uniform over a 64-site
+// chunk and a 256-site block whenever Lx Ly is a multiple of them).  Even
+// sites start from the diagonal term, -2 (4+m) psi(x), add the hops x-, x+,
+// y-, y+, z-, z+, t-, t+ and scale the sum by -scale/2; odd sites add z-, z+,
+// t-, t+, x-, x+, y-, y+ and form scale ((4+m) psi(x) - sum/2) at the end.
+// A chunk's spinors are read by the chunk itself (its x and y hops and its
+// centre) and by the z and t neighbour chunks, which have the other parity:
+// an even chunk reads its own data first and then its neighbours', an odd
+// chunk its neighbours' first and then its own, so co-resident chunks that
+// sweep a right-hand side together read each line within a short stretch of
+// the sweep, while it is still in the XCD's L2.  Every stencil form uses the
+// same per-site order, so all of them give the same bits.
+
+// m2d = -2 (4+m): acc = m2d psi(x).  No multiply-add may absorb this product
+// (the forms must round it alike wherever it is inlined).
+template <typename T>
+__device__ __forceinline__ void diag_start_spin(C<T> (&acc)[3], const C<T> (&b)[3], T m2d) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = mk<T>(b[c].x * m2d, b[c].y * m2d);
+}
+template <typename T>
+__device__ __forceinline__ void diag_start(C<T> (&acc)[4][3], const C<T> (&b)[12], T m2d) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+        const C<T> bs[3] = {b[3 * sp], b[3 * sp + 1], b[3 * sp + 2]};
+        diag_start_spin<T>(acc[sp], bs, m2d);
+    }
+}
+// even sites: out = (-scale/2 [gamma5]) acc
+template <typename T>
+__device__ __forceinline__ void even_finish(C<T> (&acc)[4][3], T scale, int g5out) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+        const T f = ((g5out && sp >= 2) ? (T)0.5 : (T)-0.5) * scale;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[sp][c] = cscale(acc[sp][c], f);
+    }
+}
+// odd sites: out = scale [gamma5] ((4+m) psi(x) - acc / 2)
+template <typename T>
+__device__ __forceinline__ void odd_finish_spin(C<T> (&acc)[3], const C<T> (&b)[3], T diag, T sg) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = cscale(csub(cscale(b[c], diag), cscale(acc[c], (T)0.5)), sg);
+}
+template <typename T>
+__device__ __forceinline__ void odd_finish(C<T> (&acc)[4][3], const C<T> (&b)[12], T diag, T scale, int g5out) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+        const C<T> bs[3] = {b[3 * sp], b[3 * sp + 1], b[3 * sp + 2]};
+        odd_finish_spin<T>(acc[sp], bs, diag, ((g5out && sp >= 2) ? (T)-1 : (T)1) * scale);
+    }
+}
+
+// The Wilson operator at site s with the links read from global memory
+// ([4][3][3][V]; the site-block and persistent forms): one hop at a time,
+// since two gather buffers would cost the site-block kernel an occupancy
+// step.  Leaves scale [gamma5] D [gamma5] psi(s) in acc.
+template <typename T, bool G5IN>
+__device__ __forceinline__ void wilson_site_global(const DslashArgs<T> &a, const C<T> *__restrict__ U,
+                                                   const C<T> *__restrict__ in, int s, C<T> (&acc)[4][3]) {
+    const int V = a.g.V, Lx = a.g.Lx, Ly = a.g.Ly, Lz = a.g.Lz, Lt = a.g.Lt;
+    const int sxy = Lx * Ly, sxyz = Lx * Ly * Lz;
+    const int x = s % Lx;
+    const int r1 = s / Lx;
+    const int yy = r1 % Ly;
+    const int r2 = r1 / Ly;
+    const int z = r2 % Lz;
+    const int t = r2 / Lz;
+    const T ff = (t == Lt - 1) ? a.ef * a.bc : a.ef;
+    const T fb = (t == 0) ? a.eb * a.bc : a.eb;
+    auto hx = [&]() __attribute__((always_inline)) {
+        const int sf = (x == Lx - 1) ? s - (Lx - 1) : s + 1;
+        const int sb = (x == 0) ? s + (Lx - 1) : s - 1;
+        hop<T, 0, -1, false, G5IN>(acc, in, U + s, V, V, sf, (T)1);
+        hop<T, 0, +1, true, G5IN>(acc, in, U + sb, V, V, sb, (T)1);
+    };
+    auto hy = [&]() __attribute__((always_inline)) {
+        const int sf = (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx;
+        const int sb = (yy == 0) ? s + (Ly - 1) * Lx : s - Lx;
+        hop<T, 1, -1, false, G5IN>(acc, in, U + (size_t)9 * V + s, V, V, sf, (T)1);
+        hop<T, 1, +1, true, G5IN>(acc, in, U + (size_t)9 * V + sb, V, V, sb, (T)1);
+    };
+    auto hz = [&]() __attribute__((always_inline)) {
+        const int sf = (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy;
+        const int sb = (z == 0) ? s + (Lz - 1) * sxy : s - sxy;
+        hop<T, 2, -1, false, G5IN>(acc, in, U + (size_t)18 * V + s, V, V, sf, (T)1);
+        hop<T, 2, +1, true, G5IN>(acc, in, U + (size_t)18 * V + sb, V, V, sb, (T)1);
+    };
+    auto ht = [&]() __attribute__((always_inline)) {
+        const int sf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
+        const int sb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
+        hop<T, 3, -1, false, G5IN>(acc, in, U + (size_t)27 * V + s, V, V, sf, ff);
+        hop<T, 3, +1, true, G5IN>(acc, in, U + (size_t)27 * V + sb, V, V, sb, fb);
+    };
+    C<T> b[12];
+    if ((z + t) & 1) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[i][c] = mk<T>(0, 0);
+        hz(); ht(); hx(); hy();
+        load_site<T, G5IN>(in, V, s, b);
+        odd_finish<T>(acc, b, a.diag, a.scale, a.g5out);
+    } else {
+        load_site<T, G5IN>(in, V, s, b);
+        diag_start<T>(acc, b, (T)-2 * a.diag);
+        hx(); hy(); hz(); ht();
+        even_finish<T>(acc, a.scale, a.g5out);
+    }
+}
+
 // The stencil and its epilogue for sites s0, s0 + sstride, ... < V of one
 // right-hand side.  sstride exceeds V, so the loop body runs at most once;
 // keeping it a loop with a run-time bound (and every address derived from s)
 // stops the compiler from hoisting loads out of the caller's loop over
-// right-hand sides.  The neighbours are gathered two hops ahead: while hop k
-// is multiplied, the spinors of hops k + 1 and k + 2 are in flight (two
-// 12-component buffers; the centre site, needed by the epilogue, is the last
-// gather; with links in LDS only).  The hops are summed in the fixed order x-, x+, y-, y+, z-, z+,
-// t-, t+ whatever the form, so every stencil form gives the same bits.
+// right-hand sides.  With links in LDS the neighbours are gathered two hops
+// ahead: while hop k is multiplied, the spinors of hops k + 1 and k + 2 are
+// in flight (two 12-component buffers), in the parity order above.
 template <typename T, int EPI, bool G5IN, typename LK>
 __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &lk, const C<T> *__restrict__ in,
                                              C<T> *__restrict__ out, const C<T> *__restrict__ v,
                                              const C<T> *__restrict__ rt, double2 *__restrict__ y, C<T> yc,
                                              T sig0, const C<T> *__restrict__ wsub,
                                              int s0, double (&part)[3]) {
-    const int V = a.g.V, Lx = a.g.Lx, Ly = a.g.Ly, Lz = a.g.Lz, Lt = a.g.Lt;
+    const int V = a.g.V;
     for (int s = s0; s < V; s += a.sstride) {
+    C<T> acc[4][3];
+    if constexpr (!LK::staged) {
+        wilson_site_global<T, G5IN>(a, lk.U, in, s, acc);
+    } else {
+    const int Lx = a.g.Lx, Ly = a.g.Ly, Lz = a.g.Lz, Lt = a.g.Lt;
     const int sxy = Lx * Ly, sxyz = Lx * Ly * Lz;
     const int x = s % Lx;
     const int r1 = s / Lx;
@@ -198,45 +313,8 @@ __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &l
     const int z = r2 % Lz;
     const int t = r2 / Lz;
     const int us = lk.stride();
-    C<T> acc[4][3];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc[i][c] = mk<T>(0, 0);
-
     const T ff = (t == Lt - 1) ? a.ef * a.bc : a.ef;
     const T fb = (t == 0) ? a.eb * a.bc : a.eb;
-    if constexpr (!LK::staged) {
-        // links from global memory: one hop at a time (two gather buffers
-        // would cost the site-block kernel an occupancy step)
-        int sf, sb;
-        sf = (x == Lx - 1) ? s - (Lx - 1) : s + 1;
-        sb = (x == 0) ? s + (Lx - 1) : s - 1;
-        hop<T, 0, -1, false, G5IN>(acc, in, lk.at(0, 0, s, s), us, V, sf, (T)1);
-        hop<T, 0, +1, true, G5IN>(acc, in, lk.at(0, 1, sb, s), us, V, sb, (T)1);
-        sf = (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx;
-        sb = (yy == 0) ? s + (Ly - 1) * Lx : s - Lx;
-        hop<T, 1, -1, false, G5IN>(acc, in, lk.at(1, 0, s, s), us, V, sf, (T)1);
-        hop<T, 1, +1, true, G5IN>(acc, in, lk.at(1, 1, sb, s), us, V, sb, (T)1);
-        sf = (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy;
-        sb = (z == 0) ? s + (Lz - 1) * sxy : s - sxy;
-        hop<T, 2, -1, false, G5IN>(acc, in, lk.at(2, 0, s, s), us, V, sf, (T)1);
-        hop<T, 2, +1, true, G5IN>(acc, in, lk.at(2, 1, sb, s), us, V, sb, (T)1);
-        sf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
-        sb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
-        hop<T, 3, -1, false, G5IN>(acc, in, lk.at(3, 0, s, s), us, V, sf, ff);
-        hop<T, 3, +1, true, G5IN>(acc, in, lk.at(3, 1, sb, s), us, V, sb, fb);
-        // out = scale * [gamma5] ((4+m) psi(x) - acc / 2), one spin at a time
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp) {
-            C<T> ps[3];
-            load_spin<T, G5IN>(in, V, s, sp, ps);
-            const T sg = ((a.g5out && sp >= 2) ? (T)-1 : (T)1) * a.scale;
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                acc[sp][c] = cscale(csub(cscale(ps[c], a.diag), cscale(acc[sp][c], (T)0.5)), sg);
-        }
-    } else {
     const int xf = (x == Lx - 1) ? s - (Lx - 1) : s + 1;
     const int xb = (x == 0) ? s + (Lx - 1) : s - 1;
     const int yf = (yy == Ly - 1) ? s - (Ly - 1) * Lx : s + Lx;
@@ -246,37 +324,70 @@ __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &l
     const int tf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
     const int tb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
     C<T> bA[12], bB[12], h[2][3];
-    load_site<T, G5IN>(in, V, xf, bA);
-    load_site<T, G5IN>(in, V, xb, bB);
-    project<T, 0, -1>(bA, h);
-    load_site<T, G5IN>(in, V, yf, bA);
-    hop_h<T, 0, -1, false>(acc, h, lk.at(0, 0, s, s), us, (T)1);
-    project<T, 0, +1>(bB, h);
-    load_site<T, G5IN>(in, V, yb, bB);
-    hop_h<T, 0, +1, true>(acc, h, lk.at(0, 1, xb, s), us, (T)1);
-    project<T, 1, -1>(bA, h);
-    load_site<T, G5IN>(in, V, zf, bA);
-    hop_h<T, 1, -1, false>(acc, h, lk.at(1, 0, s, s), us, (T)1);
-    project<T, 1, +1>(bB, h);
-    load_site<T, G5IN>(in, V, zb, bB);
-    hop_h<T, 1, +1, true>(acc, h, lk.at(1, 1, yb, s), us, (T)1);
-    project<T, 2, -1>(bA, h);
-    load_site<T, G5IN>(in, V, tf, bA);
-    hop_h<T, 2, -1, false>(acc, h, lk.at(2, 0, s, s), us, (T)1);
-    project<T, 2, +1>(bB, h);
-    load_site<T, G5IN>(in, V, tb, bB);
-    hop_h<T, 2, +1, true>(acc, h, lk.at(2, 1, zb, s), us, (T)1);
-    project<T, 3, -1>(bA, h);
-    load_site<T, G5IN>(in, V, s, bA);    // the centre, for the diagonal term
-    hop_h<T, 3, -1, false>(acc, h, lk.at(3, 0, s, s), us, ff);
-    project<T, 3, +1>(bB, h);
-    hop_h<T, 3, +1, true>(acc, h, lk.at(3, 1, tb, s), us, fb);
+    if ((z + t) & 1) {
+        // odd: z, t, x, y, then the centre
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp) {
-        const T sg = ((a.g5out && sp >= 2) ? (T)-1 : (T)1) * a.scale;
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            acc[sp][c] = cscale(csub(cscale(bA[3 * sp + c], a.diag), cscale(acc[sp][c], (T)0.5)), sg);
+            for (int c = 0; c < 3; ++c) acc[i][c] = mk<T>(0, 0);
+        load_site<T, G5IN>(in, V, zf, bA);
+        load_site<T, G5IN>(in, V, zb, bB);
+        project<T, 2, -1>(bA, h);
+        load_site<T, G5IN>(in, V, tf, bA);
+        hop_h<T, 2, -1, false>(acc, h, lk.at(2, 0, s, s), us, (T)1);
+        project<T, 2, +1>(bB, h);
+        load_site<T, G5IN>(in, V, tb, bB);
+        hop_h<T, 2, +1, true>(acc, h, lk.at(2, 1, zb, s), us, (T)1);
+        project<T, 3, -1>(bA, h);
+        load_site<T, G5IN>(in, V, xf, bA);
+        hop_h<T, 3, -1, false>(acc, h, lk.at(3, 0, s, s), us, ff);
+        project<T, 3, +1>(bB, h);
+        load_site<T, G5IN>(in, V, xb, bB);
+        hop_h<T, 3, +1, true>(acc, h, lk.at(3, 1, tb, s), us, fb);
+        project<T, 0, -1>(bA, h);
+        load_site<T, G5IN>(in, V, yf, bA);
+        hop_h<T, 0, -1, false>(acc, h, lk.at(0, 0, s, s), us, (T)1);
+        project<T, 0, +1>(bB, h);
+        load_site<T, G5IN>(in, V, yb, bB);
+        hop_h<T, 0, +1, true>(acc, h, lk.at(0, 1, xb, s), us, (T)1);
+        project<T, 1, -1>(bA, h);
+        load_site<T, G5IN>(in, V, s, bA);    // the centre, for the diagonal term
+        hop_h<T, 1, -1, false>(acc, h, lk.at(1, 0, s, s), us, (T)1);
+        project<T, 1, +1>(bB, h);
+        hop_h<T, 1, +1, true>(acc, h, lk.at(1, 1, yb, s), us, (T)1);
+        odd_finish<T>(acc, bA, a.diag, a.scale, a.g5out);
+    } else {
+        // even: the centre, x, y, z, t
+        {
+            C<T> cc[12];
+            load_site<T, G5IN>(in, V, s, cc);
+            load_site<T, G5IN>(in, V, xf, bA);
+            load_site<T, G5IN>(in, V, xb, bB);
+            diag_start<T>(acc, cc, (T)-2 * a.diag);
+        }
+        project<T, 0, -1>(bA, h);
+        load_site<T, G5IN>(in, V, yf, bA);
+        hop_h<T, 0, -1, false>(acc, h, lk.at(0, 0, s, s), us, (T)1);
+        project<T, 0, +1>(bB, h);
+        load_site<T, G5IN>(in, V, yb, bB);
+        hop_h<T, 0, +1, true>(acc, h, lk.at(0, 1, xb, s), us, (T)1);
+        project<T, 1, -1>(bA, h);
+        load_site<T, G5IN>(in, V, zf, bA);
+        hop_h<T, 1, -1, false>(acc, h, lk.at(1, 0, s, s), us, (T)1);
+        project<T, 1, +1>(bB, h);
+        load_site<T, G5IN>(in, V, zb, bB);
+        hop_h<T, 1, +1, true>(acc, h, lk.at(1, 1, yb, s), us, (T)1);
+        project<T, 2, -1>(bA, h);
+        load_site<T, G5IN>(in, V, tf, bA);
+        hop_h<T, 2, -1, false>(acc, h, lk.at(2, 0, s, s), us, (T)1);
+        project<T, 2, +1>(bB, h);
+        load_site<T, G5IN>(in, V, tb, bB);
+        hop_h<T, 2, +1, true>(acc, h, lk.at(2, 1, zb, s), us, (T)1);
+        project<T, 3, -1>(bA, h);
+        hop_h<T, 3, -1, false>(acc, h, lk.at(3, 0, s, s), us, ff);
+        project<T, 3, +1>(bB, h);
+        hop_h<T, 3, +1, true>(acc, h, lk.at(3, 1, tb, s), us, fb);
+        even_finish<T>(acc, a.scale, a.g5out);
     }
     }
 #pragma unroll
