@@ -149,7 +149,7 @@ __device__ __forceinline__ void dslash_persist_body(const DslashArgs<T> &a, int 
         // needs more than 256 VGPRs and spills
         const T ff = (t == Lt - 1) ? a.ef * a.bc : a.ef;
         const T fb = (t == 0) ? a.eb * a.bc : a.eb;
-        if ((z + t) & 1) {
+        if (order_parity(a.g, s)) {
             int sf, sb;
             sf = (z == Lz - 1) ? s - (Lz - 1) * sxy : s + sxy;
             sb = (z == 0) ? s + (Lz - 1) * sxy : s - sxy;

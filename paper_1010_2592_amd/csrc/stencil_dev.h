@@ -173,8 +173,8 @@ struct LdsLinks {
     __device__ __forceinline__ int stride() const { return CHUNK; }
 };
 
-// Order of the hop sum, chosen by the parity of z + t (uniform over a 64-site
-// chunk and a 256-site block whenever Lx Ly is a multiple of them).  Even
+// Order of the hop sum, chosen by the parity of z + t at the first site of
+// the site's aligned 64-site group (order_parity below).  Even
 // sites start from the diagonal term, -2 (4+m) psi(x), add the hops x-, x+,
 // y-, y+, z-, z+, t-, t+ and scale the sum by -scale/2; odd sites add z-, z+,
 // t-, t+, x-, x+, y-, y+ and form scale ((4+m) psi(x) - sum/2) at the end.
@@ -185,6 +185,18 @@ struct LdsLinks {
 // sweep a right-hand side together read each line within a short stretch of
 // the sweep, while it is still in the XCD's L2.  Every stencil form uses the
 // same per-site order, so all of them give the same bits.
+
+// The parity that picks a site's order: that of z + t at the first site of
+// its aligned 64-site group.  Every form runs its wavefronts over such groups
+// (chunks, and the four wavefronts of a 256-site block), so the choice is
+// uniform over a wavefront and the branch on it is a scalar one: a per-lane
+// choice made the waves that straddle a z-t plane (Lx Ly not a multiple of
+// 64) run both orders.  Where Lx Ly is a multiple of 64 this is the site's
+// own parity.
+__device__ __forceinline__ int order_parity(const Geom &g, int s) {
+    const int zt = (s & ~63) / (g.Lx * g.Ly);
+    return __builtin_amdgcn_readfirstlane((zt % g.Lz + zt / g.Lz) & 1);
+}
 
 // m2d = -2 (4+m): acc = m2d psi(x).  No multiply-add may absorb this product
 // (the forms must round it alike wherever it is inlined).
@@ -269,7 +281,7 @@ __device__ __forceinline__ void wilson_site_global(const DslashArgs<T> &a, const
         hop<T, 3, +1, true, G5IN>(acc, in, U + (size_t)27 * V + sb, V, V, sb, fb);
     };
     C<T> b[12];
-    if ((z + t) & 1) {
+    if (order_parity(a.g, s)) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -324,7 +336,7 @@ __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &l
     const int tf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
     const int tb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
     C<T> bA[12], bB[12], h[2][3];
-    if ((z + t) & 1) {
+    if (order_parity(a.g, s)) {
         // odd: z, t, x, y, then the centre
 #pragma unroll
         for (int i = 0; i < 4; ++i)
