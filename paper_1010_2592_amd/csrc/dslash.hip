@@ -39,10 +39,12 @@ __global__ __launch_bounds__(BLOCK) void dslash_kernel(DslashArgs<T> a) {
     dslash_body<T, EPI, G5IN>(a, blockIdx.x);
 }
 
-// wavefronts per block of the chunked stencil (measured on 16^3x32 and
-// 24^3x48 with 12 right-hand sides: 4 in FP64, where the 74 KB of staged links
-// allow two blocks per CU, and 12 in FP32)
-template <typename T> constexpr int chunk_waves() { return sizeof(T) == sizeof(double) ? 4 : 12; }
+// wavefronts per block of the chunked stencil: 4 (FP64: two blocks per CU by
+// the 74 KB of staged links and by registers; FP32: three, 96 chunks resident
+// per XCD, whose z-t checkerboard reads overlap in L2 better than those of
+// one 12-wavefront block per CU, 2863 against 2690 GB/s on 16^3x32 with 12
+// right-hand sides)
+template <typename T> constexpr int chunk_waves() { return 4; }
 
 template <typename T, int EPI, bool G5IN>
 __global__ __launch_bounds__(64 * chunk_waves<T>()) void dslash_chunk_kernel(DslashArgs<T> a) {
