@@ -127,6 +127,21 @@ __device__ __forceinline__ E &elem_at(E *__restrict__ p, int k, int V, int s) {
     else return p[k * V + s];
 }
 
+// An operand read once per sweep (v, w, r~, y): with UB (the chunked form) streamed
+// past L2, like the output, so that it does not evict neighbour spinors.
+template <bool UB, typename E>
+__device__ __forceinline__ E ld_stream(const E *__restrict__ p, int k, int V, int s) {
+    if constexpr (UB) {
+        const E &q = elem(p, k, V, s);
+        E r;
+        r.x = __builtin_nontemporal_load(&q.x);
+        r.y = __builtin_nontemporal_load(&q.y);
+        return r;
+    } else {
+        return p[k * V + s];
+    }
+}
+
 // The 12 components of psi(s) ([gamma5] applied: lower spins negated).
 template <typename T, bool G5IN>
 __device__ __forceinline__ void load_site(const C<T> *__restrict__ in, int V, int s, C<T> (&b)[12]) {
@@ -408,11 +423,19 @@ __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &l
         for (int c = 0; c < 3; ++c) {
             const int k = 3 * sp + c;
             C<T> o = acc[sp][c];
-            if (EPI != EPI_PLAIN) o = cadd(o, cscale(elem_at<LK::staged>(v, k, V, s), sig0));
-            if (EPI == EPI_SV2) o = csub(o, elem_at<LK::staged>(wsub, k, V, s));
-            elem_at<LK::staged>(out, k, V, s) = o;
+            if (EPI != EPI_PLAIN) o = cadd(o, cscale(ld_stream<LK::staged>(v, k, V, s), sig0));
+            if (EPI == EPI_SV2) o = csub(o, ld_stream<LK::staged>(wsub, k, V, s));
+            if constexpr (LK::staged) {
+                // streamed past L2: the output is not read again by this
+                // sweep, and its lines would evict neighbour spinors
+                C<T> &d = elem_at<true>(out, k, V, s);
+                __builtin_nontemporal_store(o.x, &d.x);
+                __builtin_nontemporal_store(o.y, &d.y);
+            } else {
+                elem_at<false>(out, k, V, s) = o;
+            }
             if (EPI == EPI_MV) {
-                const C<T> r = elem_at<LK::staged>(rt, k, V, s);
+                const C<T> r = ld_stream<LK::staged>(rt, k, V, s);
                 part[0] += (double)r.x * o.x + (double)r.y * o.y;
                 part[1] += (double)r.x * o.y - (double)r.y * o.x;
             }
@@ -420,10 +443,15 @@ __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &l
             if (epi_dots(EPI)) part[2] += (double)o.x * o.x + (double)o.y * o.y;
             if (EPI == EPI_MV_Y) {
                 double2 &yr = elem_at<LK::staged>(y, k, V, s);
-                double2 yv = yr;
+                double2 yv = ld_stream<LK::staged>(y, k, V, s);
                 yv.x += (double)yc.x * o.x - (double)yc.y * o.y;
                 yv.y += (double)yc.x * o.y + (double)yc.y * o.x;
-                yr = yv;
+                if constexpr (LK::staged) {
+                    __builtin_nontemporal_store(yv.x, &yr.x);
+                    __builtin_nontemporal_store(yv.y, &yr.y);
+                } else {
+                    yr = yv;
+                }
             }
         }
     }
