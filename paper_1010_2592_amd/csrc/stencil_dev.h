@@ -188,6 +188,32 @@ struct LdsLinks {
     __device__ __forceinline__ int stride() const { return CHUNK; }
 };
 
+// Lx = 16 in the chunked form: the 16 lanes of each row of a wavefront hold
+// one periodic x-line, so a site's x-neighbour values are in the lanes next
+// to it.  x_rotate replaces each lane's half spinor with that of lane
+// (i + 1) mod 16 (FWD) or (i - 1) mod 16 of its row (DPP row rotate), which
+// is bitwise the projection the lane would have formed from the neighbour's
+// loaded spinor, without its twelve loads.
+template <bool FWD>
+__device__ __forceinline__ int row_rot(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, FWD ? 0x12F : 0x121, 0xF, 0xF, false);
+}
+__device__ __forceinline__ double row_rot_d(double v, bool fwd) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return fwd ? __hiloint2double(row_rot<true>(hi), row_rot<true>(lo))
+               : __hiloint2double(row_rot<false>(hi), row_rot<false>(lo));
+}
+__device__ __forceinline__ float row_rot_d(float v, bool fwd) {
+    return __int_as_float(fwd ? row_rot<true>(__float_as_int(v)) : row_rot<false>(__float_as_int(v)));
+}
+template <typename T, bool FWD>
+__device__ __forceinline__ void x_rotate(C<T> (&h)[2][3]) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) h[i][c] = mk<T>(row_rot_d(h[i][c].x, FWD), row_rot_d(h[i][c].y, FWD));
+}
+
 // Order of the hop sum, chosen by the parity of z + t at the first site of
 // the site's aligned 64-site group (order_parity below).  Even
 // sites start from the diagonal term, -2 (4+m) psi(x), add the hops x-, x+,
@@ -351,7 +377,40 @@ __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &l
     const int tf = (t == Lt - 1) ? s - (Lt - 1) * sxyz : s + sxyz;
     const int tb = (t == 0) ? s + (Lt - 1) * sxyz : s - sxyz;
     C<T> bA[12], bB[12], h[2][3];
-    if (order_parity(a.g, s)) {
+    if (order_parity(a.g, s) && Lx == 16) {
+        // odd, x from the neighbouring lanes: z, t, x, y, the centre loaded
+        // during the t hops and kept for the diagonal term
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[i][c] = mk<T>(0, 0);
+        load_site<T, G5IN>(in, V, zf, bA);
+        load_site<T, G5IN>(in, V, zb, bB);
+        project<T, 2, -1>(bA, h);
+        load_site<T, G5IN>(in, V, tf, bA);
+        hop_h<T, 2, -1, false>(acc, h, lk.at(2, 0, s, s), us, (T)1);
+        project<T, 2, +1>(bB, h);
+        load_site<T, G5IN>(in, V, tb, bB);
+        hop_h<T, 2, +1, true>(acc, h, lk.at(2, 1, zb, s), us, (T)1);
+        project<T, 3, -1>(bA, h);
+        load_site<T, G5IN>(in, V, s, bA);    // the centre
+        hop_h<T, 3, -1, false>(acc, h, lk.at(3, 0, s, s), us, ff);
+        project<T, 3, +1>(bB, h);
+        load_site<T, G5IN>(in, V, yf, bB);
+        hop_h<T, 3, +1, true>(acc, h, lk.at(3, 1, tb, s), us, fb);
+        project<T, 0, -1>(bA, h);
+        x_rotate<T, true>(h);
+        hop_h<T, 0, -1, false>(acc, h, lk.at(0, 0, s, s), us, (T)1);
+        project<T, 0, +1>(bA, h);
+        x_rotate<T, false>(h);
+        hop_h<T, 0, +1, true>(acc, h, lk.at(0, 1, xb, s), us, (T)1);
+        project<T, 1, -1>(bB, h);
+        load_site<T, G5IN>(in, V, yb, bB);
+        hop_h<T, 1, -1, false>(acc, h, lk.at(1, 0, s, s), us, (T)1);
+        project<T, 1, +1>(bB, h);
+        hop_h<T, 1, +1, true>(acc, h, lk.at(1, 1, yb, s), us, (T)1);
+        odd_finish<T>(acc, bA, a.diag, a.scale, a.g5out);
+    } else if (order_parity(a.g, s)) {
         // odd: z, t, x, y, then the centre
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -385,19 +444,31 @@ __device__ __forceinline__ void dslash_sites(const DslashArgs<T> &a, const LK &l
         odd_finish<T>(acc, bA, a.diag, a.scale, a.g5out);
     } else {
         // even: the centre, x, y, z, t
-        {
+        if (Lx == 16) {
+            // x from the neighbouring lanes (the centre's projections)
+            load_site<T, G5IN>(in, V, s, bB);
+            load_site<T, G5IN>(in, V, yf, bA);
+            diag_start<T>(acc, bB, (T)-2 * a.diag);
+            project<T, 0, -1>(bB, h);
+            x_rotate<T, true>(h);
+            hop_h<T, 0, -1, false>(acc, h, lk.at(0, 0, s, s), us, (T)1);
+            project<T, 0, +1>(bB, h);
+            load_site<T, G5IN>(in, V, yb, bB);
+            x_rotate<T, false>(h);
+            hop_h<T, 0, +1, true>(acc, h, lk.at(0, 1, xb, s), us, (T)1);
+        } else {
             C<T> cc[12];
             load_site<T, G5IN>(in, V, s, cc);
             load_site<T, G5IN>(in, V, xf, bA);
             load_site<T, G5IN>(in, V, xb, bB);
             diag_start<T>(acc, cc, (T)-2 * a.diag);
+            project<T, 0, -1>(bA, h);
+            load_site<T, G5IN>(in, V, yf, bA);
+            hop_h<T, 0, -1, false>(acc, h, lk.at(0, 0, s, s), us, (T)1);
+            project<T, 0, +1>(bB, h);
+            load_site<T, G5IN>(in, V, yb, bB);
+            hop_h<T, 0, +1, true>(acc, h, lk.at(0, 1, xb, s), us, (T)1);
         }
-        project<T, 0, -1>(bA, h);
-        load_site<T, G5IN>(in, V, yf, bA);
-        hop_h<T, 0, -1, false>(acc, h, lk.at(0, 0, s, s), us, (T)1);
-        project<T, 0, +1>(bB, h);
-        load_site<T, G5IN>(in, V, yb, bB);
-        hop_h<T, 0, +1, true>(acc, h, lk.at(0, 1, xb, s), us, (T)1);
         project<T, 1, -1>(bA, h);
         load_site<T, G5IN>(in, V, zf, bA);
         hop_h<T, 1, -1, false>(acc, h, lk.at(1, 0, s, s), us, (T)1);

@@ -43,13 +43,17 @@ def test_wilson_apply_fp64(dims, flags):
         assert rel(out[r], ref[r]) <= 1e-14, (dims, flags, r)
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (3, 5, 2, 6), (6, 4, 10, 3), (8, 8, 8, 8)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (3, 5, 2, 6), (6, 4, 10, 3), (8, 8, 8, 8), (16, 4, 2, 6),
+                                  (16, 3, 3, 5)])
 @pytest.mark.parametrize("flags", FLAG_CASES)
 def test_batched_chunked_stencil_matches_single_rhs(dims, flags):
     """Batches of >= 4 right-hand sides take the chunked stencil (links staged
     in LDS per 64-site chunk); single right-hand sides the site-block one.
     Same arithmetic: bitwise equal outputs, and the oracle at 1e-14.  Lattices
-    with whole chunks per time slice (t-fastest chunk order) and without."""
+    with whole chunks per time slice (t-fastest chunk order) and without;
+    Lx = 16 takes the x-neighbours from the adjacent lanes of a row, with a
+    whole z-t plane per wavefront (16 x 4) and with wavefronts that straddle
+    planes (16 x 3)."""
     from paper_1010_2592_amd import msb
     log(f"chunked stencil dims={dims} flags={flags}")
     U = wl.gauge_links(dims, 0.6, 21 + sum(dims))
