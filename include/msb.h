@@ -191,6 +191,42 @@ int mshift_bicgstabl(msb_ctx *ctx, double a_scale, int n_shift,
                      int pass, int flags, int nrhs, const void *b, void *y,
                      void *x_shifts, msb_solve_info *info);
 
+/* Size of the fixed device array behind mshift_bicgstabl_noalloc (one copy
+ * per device the library runs on, held until the process ends). */
+#define MSB_NOALLOC_SCRATCH_BYTES (256ull << 20)
+
+/* mshift_bicgstabl without any device allocation, for callers that cannot
+ * allocate: code that must not call hipMalloc/hipFree (under stream capture of
+ * the surrounding work, tight serving loops, harnesses that forbid it).  Same
+ * arguments, layouts, outputs and returns as mshift_bicgstabl; the workspace
+ * (seed vectors, shift vectors of pass 1, reduction partials, scalar state,
+ * the double-pass tape and replay program) is carved from one fixed device
+ * array of MSB_NOALLOC_SCRATCH_BYTES, whose device address msb_create looks
+ * up once per device.  The call makes no hipMalloc, hipFree or pinned host
+ * allocation (host-side bookkeeping uses ordinary heap memory), and does not
+ * grow the context's own workspace.
+ *   pass   1 or 2 (the pseudo-double pass keeps a store that grows with the
+ *          iteration count, so it is not offered here)
+ *   flags  those of mshift_bicgstabl except MSB_PERSISTENT and MSB_REFINE
+ * Returns MSB_ERR_ARG, before anything is queued, when the workspace would
+ * exceed the array.  With c = 16 bytes (8 with MSB_MIXED) and n = 12 V it
+ * is about nrhs * n * c * (2 l + 3) for the seed (+ 3 * 16 n per rhs with
+ * MSB_MIXED), + nrhs * n_shift * n * c * (l + 1) for pass 1's shift vectors
+ * (c * 1 with MSB_DEFERRED, which adds nrhs * n * c * (2 l + 2)), + 16 n
+ * per shift and rhs when x_shifts is NULL, + 720 bytes per rhs per 64
+ * sites, at least 1.5 MB per rhs (reduction partials), + about 100 bytes
+ * per rhs per BiCG step of max_outer * l for pass 2's tape and replay
+ * program.
+ * Every call on one device shares that device's array and leaves its
+ * contents there; nothing is read from it before the call writes it.  Calls
+ * that overlap in time on one device (several streams or host threads) race.
+ * msb_profile_enable's records do not cover this call. */
+int mshift_bicgstabl_noalloc(msb_ctx *ctx, double a_scale, int n_shift,
+                             const double *shifts, const double *weights,
+                             int per_rhs_shift_sets, int l, double tol, int max_outer,
+                             int pass, int flags, int nrhs, const void *b, void *y,
+                             void *x_shifts, msb_solve_info *info);
+
 /* Multi-shift conjugate gradients for the same sum when A is Hermitian,
  * i.e. the context has mu = 0 (then gamma5 D_w is Hermitian and
  * A = a (gamma5 D_w)^2 >= 0): y = sum_s w_s (A + sigma_s)^{-1} b.  The CG

@@ -141,6 +141,8 @@ int msb_create(msb_ctx **out, const msb_lattice *lat, const void *links, void *s
     msb_ctx *x = new (std::nothrow) msb_ctx;
     if (!x) return set_error(MSB_ERR_OOM, "msb_create: out of host memory");
     int rc = msb::ctx_create(&x->c, lat->dims, lat->mass, lat->mu, lat->bc_t, links, (hipStream_t)stream);
+    // the no-allocation entry point's scratch array on this device
+    if (!rc) rc = msb::noalloc_setup(x->c.device);
     if (rc) {
         msb::ctx_destroy(&x->c);
         delete x;
@@ -214,6 +216,28 @@ int mshift_bicgstabl(msb_ctx *ctx, double a_scale, int n_shift, const double *sh
     msb::SolveReport R;
     const bool want_true = info && info->shift_true_resid && pass == 1;
     rc = msb::solve_mshift(&ctx->c, P, (const double2 *)b, (double2 *)y, (double2 *)x_shifts, want_true, &R);
+    return finish(rc, R, info, nrhs, n_shift);
+}
+
+int mshift_bicgstabl_noalloc(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
+                             const double *weights, int per_rhs_shift_sets, int l, double tol, int max_outer,
+                             int pass, int flags, int nrhs, const void *b, void *y, void *x_shifts,
+                             msb_solve_info *info) {
+    msb::SolveParams P;
+    int rc = make_params(ctx, a_scale, n_shift, shifts, weights, per_rhs_shift_sets, l, tol, max_outer,
+                         pass, flags & ~MSB_OVERLAP, nrhs, "mshift_bicgstabl_noalloc", &P);
+    if (rc) return rc;
+    if (pass != 1 && pass != 2) return arg_error("mshift_bicgstabl_noalloc: pass must be 1 or 2");
+    if (flags & (MSB_PERSISTENT | MSB_REFINE))
+        return arg_error("mshift_bicgstabl_noalloc: MSB_PERSISTENT and MSB_REFINE are not offered");
+    if (!b || !y) return arg_error("mshift_bicgstabl_noalloc: b and y are required");
+    if (x_shifts && pass != 1) return arg_error("mshift_bicgstabl_noalloc: x_shifts needs pass = 1");
+    if (flags & MSB_OVERLAP) return arg_error("mshift_bicgstabl_noalloc: MSB_OVERLAP applies to pfe_sign_apply");
+    P.force_iters = info ? info->force_iters : nullptr;
+    P.shadow = info ? (const double2 *)info->shadow : nullptr;
+    msb::SolveReport R;
+    const bool want_true = info && info->shift_true_resid && pass == 1;
+    rc = msb::solve_noalloc(&ctx->c, P, (const double2 *)b, (double2 *)y, (double2 *)x_shifts, want_true, &R);
     return finish(rc, R, info, nrhs, n_shift);
 }
 

@@ -355,16 +355,16 @@ int solve_cg(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2
     const double nd = (double)n, Vd = (double)V, cB = 16.0;
     c->bytes_acc = 0;
 
-    CG_CHK(ensure(c->ws_cg_r, (size_t)nrhs * n * sizeof(double2)));
-    CG_CHK(ensure(c->ws_cg_p, (size_t)nrhs * n * sizeof(double2)));
-    CG_CHK(ensure(c->ws_tmp, (size_t)nrhs * n * sizeof(double2)));
-    CG_CHK(ensure(c->ws_cg_w, (size_t)nrhs * n * sizeof(double2)));
-    CG_CHK(ensure(c->ws_part, (size_t)nrhs * PMAX * ps * sizeof(double)));
-    CG_CHK(ensure(c->ws_cg_seed, (size_t)nrhs * sizeof(CGSeed)));
-    CG_CHK(ensure(c->ws_cg_shift, (size_t)nrhs * NSMAX * sizeof(CGShift)));
-    CG_CHK(ensure(c->ws_cg_coef, (size_t)nrhs * NSMAX * sizeof(CGCoef)));
-    CG_CHK(ensure(c->ws_sig0, (size_t)nrhs * sizeof(double)));
-    CG_CHK(ensure(c->ws_wts, (size_t)nrhs * ns * sizeof(double)));
+    CG_CHK(ensure(c, c->ws_cg_r, (size_t)nrhs * n * sizeof(double2)));
+    CG_CHK(ensure(c, c->ws_cg_p, (size_t)nrhs * n * sizeof(double2)));
+    CG_CHK(ensure(c, c->ws_tmp, (size_t)nrhs * n * sizeof(double2)));
+    CG_CHK(ensure(c, c->ws_cg_w, (size_t)nrhs * n * sizeof(double2)));
+    CG_CHK(ensure(c, c->ws_part, (size_t)nrhs * PMAX * ps * sizeof(double)));
+    CG_CHK(ensure(c, c->ws_cg_seed, (size_t)nrhs * sizeof(CGSeed)));
+    CG_CHK(ensure(c, c->ws_cg_shift, (size_t)nrhs * NSMAX * sizeof(CGShift)));
+    CG_CHK(ensure(c, c->ws_cg_coef, (size_t)nrhs * NSMAX * sizeof(CGCoef)));
+    CG_CHK(ensure(c, c->ws_sig0, (size_t)nrhs * sizeof(double)));
+    CG_CHK(ensure(c, c->ws_wts, (size_t)nrhs * ns * sizeof(double)));
     double2 *r = (double2 *)c->ws_cg_r.p, *p = (double2 *)c->ws_cg_p.p, *tmp = (double2 *)c->ws_tmp.p;
     double2 *w = (double2 *)c->ws_cg_w.p;
     double *part = (double *)c->ws_part.p;
@@ -372,18 +372,18 @@ int solve_cg(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2
     CGShift *sh = (CGShift *)c->ws_cg_shift.p;
     double2 *Pv = nullptr, *X = nullptr;
     if (pass1) {
-        CG_CHK(ensure(c->ws_cg_P, (size_t)nrhs * ns * n * sizeof(double2)));
+        CG_CHK(ensure(c, c->ws_cg_P, (size_t)nrhs * ns * n * sizeof(double2)));
         Pv = (double2 *)c->ws_cg_P.p;
         if (xs_out) {
             X = xs_out;
         } else {
-            CG_CHK(ensure(c->ws_X, (size_t)nrhs * ns * n * sizeof(double2)));
+            CG_CHK(ensure(c, c->ws_X, (size_t)nrhs * ns * n * sizeof(double2)));
             X = (double2 *)c->ws_X.p;
         }
     }
     double *tape_a = nullptr, *tape_b = nullptr;
     if (!pass1) {
-        CG_CHK(ensure(c->ws_cg_tape, (size_t)2 * nrhs * max_iter * sizeof(double)));
+        CG_CHK(ensure(c, c->ws_cg_tape, (size_t)2 * nrhs * max_iter * sizeof(double)));
         tape_a = (double *)c->ws_cg_tape.p;
         tape_b = tape_a + (size_t)nrhs * max_iter;
     }
@@ -500,7 +500,7 @@ int solve_cg(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2
                 const int slot = k + 1;
                 const int ch = slot / CG_CHUNK;
                 while ((int)c->pstore.size() <= ch) c->pstore.push_back(DevBuf{});
-                CG_CHK(ensure(c->pstore[ch], (size_t)nrhs * store_rs * sizeof(double2)));
+                CG_CHK(ensure(c, c->pstore[ch], (size_t)nrhs * store_rs * sizeof(double2)));
                 v1.store = (double2 *)c->pstore[ch].p + (size_t)(slot % CG_CHUNK) * n;
                 v1.store_rs = store_rs;
                 if (k >= 1) {
@@ -597,9 +597,9 @@ int solve_cg(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2
                                 wv.data(), Ms.data(), &cc[(size_t)q * Nmax]);
             c0[q] = double2{cc[(size_t)q * Nmax], 0.0};
         }
-        CG_CHK(ensure(c->ws_cg_c, cc.size() * sizeof(double)));
-        CG_CHK(ensure(c->ws_cg_n, (size_t)nrhs * sizeof(int)));
-        CG_CHK(ensure(c->ws_cb, (size_t)nrhs * sizeof(double2)));
+        CG_CHK(ensure(c, c->ws_cg_c, cc.size() * sizeof(double)));
+        CG_CHK(ensure(c, c->ws_cg_n, (size_t)nrhs * sizeof(int)));
+        CG_CHK(ensure(c, c->ws_cb, (size_t)nrhs * sizeof(double2)));
         CG_HIPCHK(hipMemcpy(c->ws_cg_c.p, cc.data(), cc.size() * sizeof(double), hipMemcpyHostToDevice));
         CG_HIPCHK(hipMemcpy(c->ws_cg_n.p, Nr.data(), nrhs * sizeof(int), hipMemcpyHostToDevice));
         CG_HIPCHK(hipMemcpy(c->ws_cb.p, c0.data(), nrhs * sizeof(double2), hipMemcpyHostToDevice));

@@ -15,6 +15,15 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// A caller-provided block of device memory that ensure() carves workspace
+// from instead of allocating (the no-allocation entry point): bump
+// allocation in 256-byte steps, never freed, an error once it is full.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+};
+
 struct Ctx {
     Geom g{};
     double mass = 0, mu = 0;
@@ -38,6 +47,10 @@ struct Ctx {
     DevBuf ws_ones;
     void *host_pinned = nullptr;
     size_t host_pinned_bytes = 0;
+    // set for the duration of a no-allocation call: device workspace comes
+    // from the arena and host staging from ordinary (pageable) heap memory
+    Arena *arena = nullptr;
+    std::vector<char> host_heap;
     // kernel timing (msb_profile_enable): HIP event pairs around launches
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -116,7 +129,8 @@ struct SolveReport {
 // status-returning helpers; on failure they record a message
 int set_error(int status, const std::string &msg);
 int hip_check(hipError_t e, const char *what);
-int ensure(DevBuf &b, size_t bytes);
+// grow b to at least `bytes` (hipMalloc, or carved from c->arena when set)
+int ensure(Ctx *c, DevBuf &b, size_t bytes);
 
 int ctx_create(Ctx *c, const int dims[4], double mass, double mu, int bc_t, const void *links,
                hipStream_t stream);
@@ -136,6 +150,12 @@ int low_modes(Ctx *c, int nev, int m, const double2 *start, double tol, int degr
 // sign(H) b (or the overlap) with the given orthonormal low modes deflated
 int sign_apply_deflated(Ctx *c, const SolveParams &P, int nev, const double *evals, const double2 *evecs,
                         const double2 *b, double2 *out, bool overlap, SolveReport *rep);
+// the no-allocation entry point: the device scratch array's address is looked
+// up once per device (at context creation) and the solve's workspace is
+// carved from it
+int noalloc_setup(int device);
+int solve_noalloc(Ctx *c, const SolveParams &P, const double2 *b, double2 *y, double2 *x_shifts, bool want_true,
+                  SolveReport *rep);
 int sign_apply(Ctx *c, const SolveParams &P, const double2 *b, double2 *out, bool overlap,
                SolveReport *rep);
 int sign_backward(Ctx *c, const SolveParams &P, const double2 *b, const double2 *eta, int mode,

@@ -205,7 +205,7 @@ int gram(Ctx *c, const double2 *X, int m1, const double2 *Y, int m2, long n, dou
     hipStream_t st = c->stream;
     const long ntile = (n + TE - 1) / TE;
     const int nblk = (int)std::min<long>(ntile, GRAM_BLOCKS);
-    E_CHK(ensure(c->ws_eG, (size_t)TM * TM * nblk * sizeof(double2)));
+    E_CHK(ensure(c, c->ws_eG, (size_t)TM * TM * nblk * sizeof(double2)));
     double2 *part = (double2 *)c->ws_eG.p;
     for (int i0 = 0; i0 < m1; i0 += TM)
         for (int j0 = 0; j0 < m2; j0 += TM) {
@@ -266,12 +266,12 @@ int low_modes(Ctx *c, int nev, int m, const double2 *start, double tol, int degr
     const double dnorm = std::fabs(4.0 + c->mass) + 3.0 + std::exp(std::fabs(c->mu));
     const double hi = dnorm * dnorm;
     const size_t blk = (size_t)m * n * sizeof(double2);
-    E_CHK(ensure(c->ws_eY, blk));
-    E_CHK(ensure(c->ws_eW, blk));
-    E_CHK(ensure(c->ws_eZ, blk));
-    E_CHK(ensure(c->ws_eP, blk));
-    E_CHK(ensure(c->ws_eS, (size_t)m * m * sizeof(double2) + (size_t)m * sizeof(double) + 256));
-    E_CHK(ensure(c->ws_part, (size_t)m * nbv * sizeof(double)));
+    E_CHK(ensure(c, c->ws_eY, blk));
+    E_CHK(ensure(c, c->ws_eW, blk));
+    E_CHK(ensure(c, c->ws_eZ, blk));
+    E_CHK(ensure(c, c->ws_eP, blk));
+    E_CHK(ensure(c, c->ws_eS, (size_t)m * m * sizeof(double2) + (size_t)m * sizeof(double) + 256));
+    E_CHK(ensure(c, c->ws_part, (size_t)m * nbv * sizeof(double)));
     double2 *Y = (double2 *)c->ws_eY.p, *W = (double2 *)c->ws_eW.p, *Z = (double2 *)c->ws_eZ.p,
             *Pv = (double2 *)c->ws_eP.p;
     double2 *Sd = (double2 *)c->ws_eS.p;
@@ -436,9 +436,9 @@ int sign_apply_deflated(Ctx *c, const SolveParams &P, int nev, const double *eva
     const long n = 12L * V;
     const int nrhs = P.nrhs;
     const int nbv = nblocks_for(n);
-    E_CHK(ensure(c->ws_eS, (size_t)nev * nrhs * sizeof(double2) + 256));
-    E_CHK(ensure(c->ws_eY, (size_t)nrhs * n * sizeof(double2)));   // P b, then sign(H) b
-    E_CHK(ensure(c->ws_eW, (size_t)nrhs * n * sizeof(double2)));   // H y
+    E_CHK(ensure(c, c->ws_eS, (size_t)nev * nrhs * sizeof(double2) + 256));
+    E_CHK(ensure(c, c->ws_eY, (size_t)nrhs * n * sizeof(double2)));   // P b, then sign(H) b
+    E_CHK(ensure(c, c->ws_eW, (size_t)nrhs * n * sizeof(double2)));   // H y
     double2 *cd = (double2 *)c->ws_eS.p;
     double2 *pb = (double2 *)c->ws_eY.p, *hy = (double2 *)c->ws_eW.p;
     // c = V^H b (nev x nrhs), P b = b - V c
@@ -447,7 +447,7 @@ int sign_apply_deflated(Ctx *c, const SolveParams &P, int nev, const double *eva
     E_HIPCHK(hipMemcpyAsync(pb, b, (size_t)nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, st));
     E_CHK(combine(c, evecs, nev, cd, nrhs, n, pb, -1.0, 1.0));
     // y = f(A) P b
-    E_CHK(ensure(c->ws_y, (size_t)nrhs * n * sizeof(double2)));
+    E_CHK(ensure(c, c->ws_y, (size_t)nrhs * n * sizeof(double2)));
     double2 *yy = (double2 *)c->ws_y.p;
     E_CHK(solve_mshift(c, P, pb, yy, nullptr, false, rep));
     // sign part: sqrt(a) H y + V (sign(lambda) c)

@@ -55,9 +55,23 @@ int hip_check(hipError_t e, const char *what) {
         if (rc_) return rc_;                       \
     } while (0)
 
-int ensure(DevBuf &b, size_t bytes) {
+int ensure(Ctx *c, DevBuf &b, size_t bytes) {
     if (bytes < 256) bytes = 256;
     if (b.bytes >= bytes) return 0;
+    if (c->arena) {
+        // no-allocation call: a fresh region of the arena (a smaller region
+        // this buffer held earlier in the call stays unused)
+        Arena &a = *c->arena;
+        const size_t off = (a.used + 255) & ~(size_t)255;
+        if (off > a.cap || bytes > a.cap - off)
+            return set_error(S_ERR_ARG, "workspace of more than " + std::to_string(a.cap) +
+                                            " bytes needed: beyond the fixed scratch buffer of the "
+                                            "no-allocation entry point");
+        b.p = a.base + off;
+        b.bytes = bytes;
+        a.used = off + bytes;
+        return 0;
+    }
     if (b.p) {
         (void)hipFree(b.p);
         b.p = nullptr;
@@ -74,6 +88,14 @@ int ensure(DevBuf &b, size_t bytes) {
 
 static int ensure_host(Ctx *c, size_t bytes) {
     if (c->host_pinned_bytes >= bytes) return 0;
+    if (c->arena) {
+        // no-allocation call: pageable heap memory (the host reads it only
+        // after synchronising the stream, as it does the pinned buffer)
+        c->host_heap.resize(bytes);
+        c->host_pinned = c->host_heap.data();
+        c->host_pinned_bytes = bytes;
+        return 0;
+    }
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
     c->host_pinned = nullptr;
     c->host_pinned_bytes = 0;
@@ -233,8 +255,8 @@ int apply_wilson(Ctx *c, const double2 *in, double2 *out, int nrhs, int flags) {
         a.out = out;
         launch_dslash<double>(c->stream, a, nrhs, EPI_PLAIN, g5in);
     } else {
-        CHK(ensure(c->ws_aux1, (size_t)nrhs * n * sizeof(float2)));
-        CHK(ensure(c->ws_aux2, (size_t)nrhs * n * sizeof(float2)));
+        CHK(ensure(c, c->ws_aux1, (size_t)nrhs * n * sizeof(float2)));
+        CHK(ensure(c, c->ws_aux2, (size_t)nrhs * n * sizeof(float2)));
         float2 *fi = (float2 *)c->ws_aux1.p, *fo = (float2 *)c->ws_aux2.p;
         launch_convert_in<float>(c->stream, fi, in, n, n, n, nrhs);
         DslashArgs<float> a = ds_args<float>(c, nm, g5out);
@@ -259,11 +281,11 @@ int spectral_radius(Ctx *c, const double2 *start, int iters, double *rho) {
     const long n = 12L * V;
     const int nbv = nblocks_for(n);
     hipStream_t st = c->stream;
-    CHK(ensure(c->ws_aux1, n * sizeof(double2)));
-    CHK(ensure(c->ws_aux2, n * sizeof(double2)));
-    CHK(ensure(c->ws_aux3, n * sizeof(double2)));
+    CHK(ensure(c, c->ws_aux1, n * sizeof(double2)));
+    CHK(ensure(c, c->ws_aux2, n * sizeof(double2)));
+    CHK(ensure(c, c->ws_aux3, n * sizeof(double2)));
     const long ps = part_stride(c->g);
-    CHK(ensure(c->ws_part, (size_t)PMAX * ps * sizeof(double)));
+    CHK(ensure(c, c->ws_part, (size_t)PMAX * ps * sizeof(double)));
     CHK(ensure_host(c, 3 * ps * sizeof(double)));
     double2 *v = (double2 *)c->ws_aux1.p, *w = (double2 *)c->ws_aux2.p, *z = (double2 *)c->ws_aux3.p;
     double *part = (double *)c->ws_part.p;
@@ -658,8 +680,8 @@ static int run_persistent(Ctx *c, const std::vector<POp> &ops, int iters, bool l
     int &grid = c->pgrid[key];
     if (grid == 0) grid = persistent_grid<T>(c->device, l);
     if (grid < 8) return set_error(S_ERR_HIP, "persistent launch: no co-resident grid for l = " + std::to_string(l));
-    CHK(ensure(c->ws_ops, ops.size() * sizeof(POp)));
-    CHK(ensure(c->ws_pctl, sizeof(PersistCtl)));
+    CHK(ensure(c, c->ws_ops, ops.size() * sizeof(POp)));
+    CHK(ensure(c, c->ws_pctl, sizeof(PersistCtl)));
     HIPCHK(hipMemcpyAsync(c->ws_ops.p, ops.data(), ops.size() * sizeof(POp), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemsetAsync(c->ws_pctl.p, 0, sizeof(PersistCtl), st));
     PersistArgs pa;
@@ -721,66 +743,87 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         return nr * per * Vd + 36 * cB * Vd;                   // links once per launch
     };
 
-    // ---- workspace
-    CHK(ensure(c->ws_R, (size_t)nrhs * (l + 1) * n * cs));
-    CHK(ensure(c->ws_U, (size_t)nrhs * (l + 1) * n * cs));
-    CHK(ensure(c->ws_tmp, (size_t)nrhs * n * cs));
-    CHK(ensure(c->ws_part, (size_t)nrhs * PMAX * ps * sizeof(double)));
-    CHK(ensure(c->ws_seed, (size_t)nrhs * sizeof(SeedState)));
-    CHK(ensure(c->ws_shift, (size_t)nrhs * NSMAX * sizeof(ShiftState)));
-    CHK(ensure(c->ws_sc, (size_t)nrhs * NSMAX * sizeof(StepCoef)));
-    CHK(ensure(c->ws_mc, (size_t)nrhs * NSMAX * sizeof(MRCoef)));
-    CHK(ensure(c->ws_sig0, (size_t)nrhs * sizeof(double)));
-    CHK(ensure(c->ws_wts, (size_t)nrhs * ns * sizeof(double)));
+    // ---- workspace: every buffer of the call is sized here, before the
+    // first launch (the pseudo-double pass's store grows by chunks during
+    // the first pass, and the persistent launch sizes its operation table
+    // when it starts)
+    const bool mixed = sizeof(T) != sizeof(double);
+    const bool deferred = pass1 && P.deferred;
+    const int nb = 2 * l + 2;                  // deferred: basis vectors per outer iteration
+    const int wslots = deferred ? 1 : l + 1;   // shift vectors kept per shift
+    constexpr int SPMAX = 16;                  // sparse shadow residual: entries per rhs
+    constexpr int NBL = 256;                   // blocks of its scan
+    CHK(ensure(c, c->ws_R, (size_t)nrhs * (l + 1) * n * cs));
+    CHK(ensure(c, c->ws_U, (size_t)nrhs * (l + 1) * n * cs));
+    CHK(ensure(c, c->ws_tmp, (size_t)nrhs * n * cs));
+    CHK(ensure(c, c->ws_part, (size_t)nrhs * PMAX * ps * sizeof(double)));
+    CHK(ensure(c, c->ws_seed, (size_t)nrhs * sizeof(SeedState)));
+    CHK(ensure(c, c->ws_shift, (size_t)nrhs * NSMAX * sizeof(ShiftState)));
+    CHK(ensure(c, c->ws_sc, (size_t)nrhs * NSMAX * sizeof(StepCoef)));
+    CHK(ensure(c, c->ws_mc, (size_t)nrhs * NSMAX * sizeof(MRCoef)));
+    CHK(ensure(c, c->ws_sig0, (size_t)nrhs * sizeof(double)));
+    CHK(ensure(c, c->ws_wts, (size_t)nrhs * ns * sizeof(double)));
+    if (mixed) {
+        // FP32 copy of r~; FP64 seed solution and the FP64 Mv of the
+        // reliable updates
+        CHK(ensure(c, c->ws_rt, (size_t)nrhs * n * cs));
+        CHK(ensure(c, c->ws_aux1, (size_t)nrhs * n * sizeof(double2)));
+        CHK(ensure(c, c->ws_aux2, (size_t)nrhs * n * sizeof(double2)));
+        CHK(ensure(c, c->ws_aux3, (size_t)nrhs * n * sizeof(double2)));
+    }
+    if (deferred) {
+        CHK(ensure(c, c->ws_Bm, (size_t)nrhs * nb * n * cs));
+        CHK(ensure(c, c->ws_schist, (size_t)nrhs * LMAX * NSMAX * sizeof(StepCoef)));
+        CHK(ensure(c, c->ws_dc, (size_t)nrhs * NSMAX * sizeof(DeferCoef)));
+    }
+    if (pass1) {
+        CHK(ensure(c, c->ws_W, (size_t)nrhs * ns * wslots * n * cs));
+        if (!xs_out) CHK(ensure(c, c->ws_X, (size_t)nrhs * ns * n * sizeof(double2)));
+        if (want_true) {
+            CHK(ensure(c, c->ws_aux1, (size_t)nrhs * n * sizeof(double2)));
+            CHK(ensure(c, c->ws_aux2, (size_t)nrhs * n * sizeof(double2)));
+            CHK(ensure(c, c->ws_aux3, (size_t)nrhs * n * sizeof(double2)));
+        }
+    } else {
+        CHK(ensure(c, c->ws_tape, (size_t)nrhs * max_steps * sizeof(TapeStep)));
+        CHK(ensure(c, c->ws_tape_gam, (size_t)nrhs * max_outer * LMAX * sizeof(double2)));
+        CHK(ensure(c, c->ws_tape_outer, (size_t)nrhs * max_outer * sizeof(TapeOuter)));
+        // the replay program written after the sweep (at most max_outer
+        // outer iterations)
+        CHK(ensure(c, c->ws_replay, (size_t)nrhs * max_outer * l * sizeof(ReplayStep)));
+        CHK(ensure(c, c->ws_replay_outer, (size_t)nrhs * max_outer * sizeof(ReplayOuter)));
+        CHK(ensure(c, c->ws_cb, (size_t)nrhs * sizeof(double2)));
+        if (pass3 && mixed) CHK(ensure(c, c->ws_ones, (size_t)nrhs * sizeof(double2)));
+    }
+    if (!P.persistent)
+        CHK(ensure(c, c->ws_sp, (size_t)nrhs * (SPMAX * (sizeof(long) + sizeof(double2)) + (1 + NBL) * sizeof(int)) +
+                                    256));
+    CHK(ensure_host(c, std::max((size_t)nrhs * sizeof(SeedState), (size_t)ps * sizeof(double))));
+
     C<T> *R = (C<T> *)c->ws_R.p, *Uv = (C<T> *)c->ws_U.p, *tmp = (C<T> *)c->ws_tmp.p;
     double *part = (double *)c->ws_part.p;
     SeedState *seed = (SeedState *)c->ws_seed.p;
     ShiftState *sh = (ShiftState *)c->ws_shift.p;
     const C<T> *rt;
-    if (sizeof(T) == sizeof(double)) {
+    if (!mixed) {
         rt = (const C<T> *)(P.shadow ? P.shadow : b);
     } else {
-        CHK(ensure(c->ws_rt, (size_t)nrhs * n * cs));
         launch_convert_in<T>(st, (C<T> *)c->ws_rt.p, P.shadow ? P.shadow : b, n, n, n, nrhs);
         rt = (const C<T> *)c->ws_rt.p;
     }
     C<T> *W = nullptr;
     double2 *X = nullptr;
-    const bool mixed = sizeof(T) != sizeof(double);
     double2 *XH = nullptr, *t64 = nullptr, *v64 = nullptr;
     if (mixed) {
-        // FP64 seed solution and the FP64 Mv of the reliable updates
-        CHK(ensure(c->ws_aux1, (size_t)nrhs * n * sizeof(double2)));
-        CHK(ensure(c->ws_aux2, (size_t)nrhs * n * sizeof(double2)));
-        CHK(ensure(c->ws_aux3, (size_t)nrhs * n * sizeof(double2)));
         XH = (double2 *)c->ws_aux1.p;
         t64 = (double2 *)c->ws_aux2.p;
         v64 = (double2 *)c->ws_aux3.p;
     }
-    const bool deferred = pass1 && P.deferred;
-    const int nb = 2 * l + 2;            // deferred: basis vectors per outer iteration
-    C<T> *Bm = nullptr;
-    if (deferred) {
-        CHK(ensure(c->ws_Bm, (size_t)nrhs * nb * n * cs));
-        CHK(ensure(c->ws_schist, (size_t)nrhs * LMAX * NSMAX * sizeof(StepCoef)));
-        CHK(ensure(c->ws_dc, (size_t)nrhs * NSMAX * sizeof(DeferCoef)));
-        Bm = (C<T> *)c->ws_Bm.p;
-    }
-    const int wslots = deferred ? 1 : l + 1;   // shift vectors kept per shift
+    C<T> *Bm = deferred ? (C<T> *)c->ws_Bm.p : nullptr;
     if (pass1) {
-        CHK(ensure(c->ws_W, (size_t)nrhs * ns * wslots * n * cs));
         W = (C<T> *)c->ws_W.p;
-        if (xs_out) {
-            X = xs_out;
-        } else {
-            CHK(ensure(c->ws_X, (size_t)nrhs * ns * n * sizeof(double2)));
-            X = (double2 *)c->ws_X.p;
-        }
-    }
-    if (!pass1) {
-        CHK(ensure(c->ws_tape, (size_t)nrhs * max_steps * sizeof(TapeStep)));
-        CHK(ensure(c->ws_tape_gam, (size_t)nrhs * max_outer * LMAX * sizeof(double2)));
-        CHK(ensure(c->ws_tape_outer, (size_t)nrhs * max_outer * sizeof(TapeOuter)));
+        X = xs_out ? xs_out : (double2 *)c->ws_X.p;
+    } else {
         HIPCHK(hipMemsetAsync(c->ws_tape.p, 0, (size_t)nrhs * max_steps * sizeof(TapeStep), st));
         HIPCHK(hipMemsetAsync(c->ws_tape_outer.p, 0, (size_t)nrhs * max_outer * sizeof(TapeOuter), st));
     }
@@ -850,11 +893,8 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     // has one per right-hand side): the Mv epilogue and the MR update skip
     // their full read of r~ and <r~, .> is summed from an index list in a
     // one-wavefront kernel after them.  FP64 per-stage launches only.
-    constexpr int SPMAX = 16;
     SparseDotArgs spa;
     if (!P.persistent) {
-        constexpr int NBL = 256;
-        CHK(ensure(c->ws_sp, (size_t)nrhs * (SPMAX * (sizeof(long) + sizeof(double2)) + (1 + NBL) * sizeof(int)) + 256));
         long *spi = (long *)c->ws_sp.p;
         double2 *spv = (double2 *)(spi + (size_t)nrhs * SPMAX);
         int *spc = (int *)(spv + (size_t)nrhs * SPMAX);
@@ -995,16 +1035,16 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     const long ps_rs = (long)PSC * 2 * l * n;
     auto pstore_chunk = [&](int k) -> int {
         while ((int)c->pstore.size() <= k) c->pstore.push_back(DevBuf{});
-        CHK(ensure(c->pstore[k], (size_t)nrhs * ps_rs * cs));
+        CHK(ensure(c, c->pstore[k], (size_t)nrhs * ps_rs * cs));
         if (mixed) {
             while ((int)c->prel.size() <= k) c->prel.push_back(DevBuf{});
-            CHK(ensure(c->prel[k], (size_t)nrhs * PSC * n * sizeof(double2)));
+            CHK(ensure(c, c->prel[k], (size_t)nrhs * PSC * n * sizeof(double2)));
             launch_zero<double>(st, (double2 *)c->prel[k].p, (long)nrhs * PSC * n, 0, 1);
         }
         return 0;
     };
     if (pass3 && mixed) {
-        CHK(ensure(c->ws_ones, (size_t)nrhs * sizeof(double2)));
+        CHK(ensure(c, c->ws_ones, (size_t)nrhs * sizeof(double2)));
         std::vector<double2> ones(nrhs, double2{1.0, 0.0});
         HIPCHK(hipMemcpyAsync(c->ws_ones.p, ones.data(), nrhs * sizeof(double2), hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1261,9 +1301,9 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             std::copy(sr.steps.begin(), sr.steps.begin() + (size_t)Mcap * l, rsteps.begin() + (size_t)r * Mcap * l);
             std::copy(sr.outer.begin(), sr.outer.begin() + Mcap, router.begin() + (size_t)r * Mcap);
         }
-        CHK(ensure(c->ws_replay, rsteps.size() * sizeof(ReplayStep)));
-        CHK(ensure(c->ws_replay_outer, router.size() * sizeof(ReplayOuter)));
-        CHK(ensure(c->ws_cb, nrhs * sizeof(double2)));
+        CHK(ensure(c, c->ws_replay, rsteps.size() * sizeof(ReplayStep)));
+        CHK(ensure(c, c->ws_replay_outer, router.size() * sizeof(ReplayOuter)));
+        CHK(ensure(c, c->ws_cb, nrhs * sizeof(double2)));
         ReplayStep *drs = (ReplayStep *)c->ws_replay.p;
         ReplayOuter *dro = (ReplayOuter *)c->ws_replay_outer.p;
         HIPCHK(hipMemcpyAsync(drs, rsteps.data(), rsteps.size() * sizeof(ReplayStep), hipMemcpyHostToDevice, st));
@@ -1377,9 +1417,9 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     // ---- optional FP64 true residual of every shift (single-pass)
     if (pass1 && want_true) {
         rep->shift_true_resid.assign((size_t)nrhs * ns, 0.0);
-        CHK(ensure(c->ws_aux1, (size_t)nrhs * n * sizeof(double2)));
-        CHK(ensure(c->ws_aux2, (size_t)nrhs * n * sizeof(double2)));
-        CHK(ensure(c->ws_aux3, (size_t)nrhs * n * sizeof(double2)));
+        CHK(ensure(c, c->ws_aux1, (size_t)nrhs * n * sizeof(double2)));
+        CHK(ensure(c, c->ws_aux2, (size_t)nrhs * n * sizeof(double2)));
+        CHK(ensure(c, c->ws_aux3, (size_t)nrhs * n * sizeof(double2)));
         CHK(ensure_host(c, (size_t)std::max(nrhs * sizeof(SeedState), (size_t)ps * sizeof(double))));
         double2 *xd = (double2 *)c->ws_aux1.p, *t1 = (double2 *)c->ws_aux2.p, *t2 = (double2 *)c->ws_aux3.p;
         std::vector<double> rowbuf(ps);
@@ -1442,7 +1482,7 @@ static int solve_refined(Ctx *c, const SolveParams &P, const double2 *b, double2
     hipStream_t st = c->stream;
     double2 *X = x_shifts;
     if (!X) {
-        CHK(ensure(c->ws_rX, (size_t)nrhs * ns * n * sizeof(double2)));
+        CHK(ensure(c, c->ws_rX, (size_t)nrhs * ns * n * sizeof(double2)));
         X = (double2 *)c->ws_rX.p;
     }
     SolveParams P0 = P;
@@ -1451,14 +1491,14 @@ static int solve_refined(Ctx *c, const SolveParams &P, const double2 *b, double2
     double bytes = rep->bytes_model;
     if (rep->status == S_ERR_ARG) return 0;
 
-    CHK(ensure(c->ws_rt1, (size_t)nrhs * n * sizeof(double2)));
-    CHK(ensure(c->ws_rt2, (size_t)nrhs * n * sizeof(double2)));
-    CHK(ensure(c->ws_rR, (size_t)nrhs * n * sizeof(double2)));
-    CHK(ensure(c->ws_rB, (size_t)KMAX * n * sizeof(double2)));
-    CHK(ensure(c->ws_rX2, (size_t)KMAX * n * sizeof(double2)));
-    CHK(ensure(c->ws_ry, (size_t)KMAX * n * sizeof(double2)));
-    CHK(ensure(c->ws_rsig, (size_t)nrhs * ns * sizeof(double)));
-    CHK(ensure(c->ws_rw, (size_t)nrhs * ns * sizeof(double)));
+    CHK(ensure(c, c->ws_rt1, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_rt2, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_rR, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_rB, (size_t)KMAX * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_rX2, (size_t)KMAX * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_ry, (size_t)KMAX * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_rsig, (size_t)nrhs * ns * sizeof(double)));
+    CHK(ensure(c, c->ws_rw, (size_t)nrhs * ns * sizeof(double)));
     double2 *t1 = (double2 *)c->ws_rt1.p, *t2 = (double2 *)c->ws_rt2.p, *R = (double2 *)c->ws_rR.p;
     double2 *RB = (double2 *)c->ws_rB.p, *DX = (double2 *)c->ws_rX2.p, *DY = (double2 *)c->ws_ry.p;
     // shifts by shift then rhs (the per-rhs sigma of one residual launch)
@@ -1486,7 +1526,7 @@ static int solve_refined(Ctx *c, const SolveParams &P, const double2 *b, double2
         for (int r = 0; r < nr; ++r) out[r] = std::sqrt(host_partial_sum(&rows[(size_t)r * nbv], nbv));
         return 0;
     };
-    CHK(ensure(c->ws_part, (size_t)std::max(nrhs, KMAX) * PMAX * ps * sizeof(double)));
+    CHK(ensure(c, c->ws_part, (size_t)std::max(nrhs, KMAX) * PMAX * ps * sizeof(double)));
     double *part = (double *)c->ws_part.p;
     launch_dot_partials<double>(st, b, b, n, part, ps, nrhs, nbv, Gate{});
     CHK(read_norms(nrhs, 2, bnorm));
@@ -1597,10 +1637,10 @@ int sign_apply(Ctx *c, const SolveParams &P, const double2 *b, double2 *out, boo
                SolveReport *rep) {
     const int V = c->g.V;
     const long n = 12L * V;
-    CHK(ensure(c->ws_y, (size_t)P.nrhs * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_y, (size_t)P.nrhs * n * sizeof(double2)));
     double2 *y = (double2 *)c->ws_y.p;
     CHK(solve_mshift(c, P, b, y, nullptr, false, rep));
-    CHK(ensure(c->ws_aux4, (size_t)P.nrhs * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_aux4, (size_t)P.nrhs * n * sizeof(double2)));
     double2 *hy = (double2 *)c->ws_aux4.p;
     DslashArgs<double> a = ds_args<double>(c, P.neg_mu, true);   // H y = g5 D y
     a.in = y;
@@ -1630,13 +1670,13 @@ int sign_backward(Ctx *c, const SolveParams &P0, const double2 *b, const double2
     const long n = 12L * V;
     const int nrhs = P0.nrhs, ns = P0.n_shift;
     const int nbv = nblocks_for(n);
-    CHK(ensure(c->ws_bX, (size_t)nrhs * ns * n * sizeof(double2)));
-    CHK(ensure(c->ws_bZ, (size_t)nrhs * ns * n * sizeof(double2)));
-    CHK(ensure(c->ws_by, (size_t)nrhs * n * sizeof(double2)));
-    CHK(ensure(c->ws_beta, (size_t)nrhs * n * sizeof(double2)));
-    CHK(ensure(c->ws_bA, (size_t)nrhs * n * sizeof(double2)));
-    CHK(ensure(c->ws_bB, (size_t)nrhs * n * sizeof(double2)));
-    CHK(ensure(c->ws_bdots, (size_t)nrhs * ns * 2 * nbv * sizeof(double)));
+    CHK(ensure(c, c->ws_bX, (size_t)nrhs * ns * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_bZ, (size_t)nrhs * ns * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_by, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_beta, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_bA, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_bB, (size_t)nrhs * n * sizeof(double2)));
+    CHK(ensure(c, c->ws_bdots, (size_t)nrhs * ns * 2 * nbv * sizeof(double)));
     double2 *X = (double2 *)c->ws_bX.p, *Z = (double2 *)c->ws_bZ.p, *y = (double2 *)c->ws_by.p;
     double2 *eta2 = (double2 *)c->ws_beta.p, *tA = (double2 *)c->ws_bA.p, *tB = (double2 *)c->ws_bB.p;
 

@@ -21,7 +21,7 @@ import torch  # noqa: F401  -- loads torch's HIP runtime first; libmsb binds to 
 
 __all__ = [
     "MsbError", "Lattice", "SolveInfo", "Context", "lib", "library_path",
-    "neuberger_pfe", "wilson_apply", "mshift_bicgstabl", "mshift_cg", "pfe_sign_apply",
+    "neuberger_pfe", "wilson_apply", "mshift_bicgstabl", "mshift_bicgstabl_noalloc", "mshift_cg", "pfe_sign_apply",
     "pfe_sign_backward", "spectral_radius",
     "G5_LEFT", "NEG_MU", "DAGGER", "MIXED", "PERSISTENT", "OVERLAP", "ADJOINT", "REFINE", "DEFERRED", "OP_WILSON",
     "OK", "ERR_ARG", "ERR_HIP", "ERR_OOM", "NOT_CONVERGED", "BREAKDOWN",
@@ -87,6 +87,7 @@ def lib():
         L.wilson_apply.argtypes = [_P, _P, _P, _I, _I]
         L.mshift_bicgstabl.argtypes = [_P, _D, _I, _DP, _DP, _I, _I, _D, _I, _I, _I, _I,
                                        _P, _P, _P, ctypes.POINTER(_Info)]
+        L.mshift_bicgstabl_noalloc.argtypes = L.mshift_bicgstabl.argtypes
         L.mshift_cg.argtypes = [_P, _D, _I, _DP, _DP, _I, _D, _I, _I, _I, _I, _P, _P, _P,
                                 ctypes.POINTER(_Info)]
         L.pfe_sign_apply.argtypes = [_P, _D, _I, _DP, _DP, _I, _D, _I, _I, _I, _I, _P, _P,
@@ -100,7 +101,7 @@ def lib():
         L.msb_profile_read.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_longlong), _DP, _DP]
         for f in ("msb_create", "msb_set_stream", "msb_neuberger_pfe", "msb_spectral_radius",
                   "msb_profile_enable", "msb_profile_read",
-                  "wilson_apply", "mshift_bicgstabl", "mshift_cg", "pfe_sign_apply", "pfe_sign_backward",
+                  "wilson_apply", "mshift_bicgstabl", "mshift_bicgstabl_noalloc", "mshift_cg", "pfe_sign_apply", "pfe_sign_backward",
                   "msb_low_modes", "pfe_sign_apply_deflated"):
             getattr(L, f).restype = _I
         _LIB = L
@@ -256,23 +257,47 @@ class Context:
     def mshift_bicgstabl(self, b: torch.Tensor, a_scale: float, shifts, weights, l: int,
                          tol: float, max_outer: int, pass_: int = 1, flags: int = 0,
                          want_shifts: bool = False, force_iters=None, true_resid: bool = False,
-                         allow=(OK,), shadow: Optional[torch.Tensor] = None):
+                         allow=(OK,), shadow: Optional[torch.Tensor] = None, y: Optional[torch.Tensor] = None):
         """y = sum_s w_s (A + sigma_s)^{-1} b; returns (y, info, x_shifts or None).
 
         shifts/weights: (n_shift,) for one set, or (nrhs, n_shift) per rhs.
         pass_: 1 single pass, 2 double pass, 3 pseudo-double pass (the Mv
         outputs of the first pass kept in device memory and summed after the
         sweep).  shadow: optional shadow residual r~ of BiCGstab(l) (default
-        b; a random r~ for point sources under OP_WILSON)."""
+        b; a random r~ for point sources under OP_WILSON).  y: optional
+        output tensor (written)."""
+        return self._mshift("mshift_bicgstabl", b, a_scale, shifts, weights, l, tol, max_outer, pass_, flags,
+                            want_shifts, force_iters, true_resid, allow, shadow, y)
+
+    def mshift_bicgstabl_noalloc(self, b: torch.Tensor, a_scale: float, shifts, weights, l: int,
+                                 tol: float, max_outer: int, pass_: int = 1, flags: int = 0,
+                                 want_shifts: bool = False, force_iters=None, true_resid: bool = False,
+                                 allow=(OK,), shadow: Optional[torch.Tensor] = None,
+                                 y: Optional[torch.Tensor] = None, x_shifts: Optional[torch.Tensor] = None):
+        """mshift_bicgstabl with the library's workspace taken from its fixed
+        device scratch array (no device allocation in the call); pass_ 1 or 2.
+        Pass y (and x_shifts) to keep this call itself free of allocations."""
+        return self._mshift("mshift_bicgstabl_noalloc", b, a_scale, shifts, weights, l, tol, max_outer, pass_,
+                            flags, want_shifts, force_iters, true_resid, allow, shadow, y, x_shifts)
+
+    def _mshift(self, fn, b, a_scale, shifts, weights, l, tol, max_outer, pass_, flags, want_shifts,
+                force_iters, true_resid, allow, shadow, y=None, x_shifts=None):
         b = _spinors(b, self.V, "b")
         nrhs = b.shape[0]
         sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64))
         wt = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
         per = 1 if sh.ndim == 2 else 0
         ns = sh.shape[-1]
-        y = torch.empty_like(b)
-        xs = torch.zeros((nrhs, ns, 12, self.V), dtype=torch.complex128, device=b.device) \
-            if want_shifts else None
+        if y is None:
+            y = torch.empty_like(b)
+        elif y.shape != b.shape or y.dtype != b.dtype or y.device != b.device or not y.is_contiguous():
+            raise ValueError("y must be a contiguous tensor of b's shape, dtype and device")
+        xs = x_shifts
+        if xs is None and want_shifts:
+            xs = torch.zeros((nrhs, ns, 12, self.V), dtype=torch.complex128, device=b.device)
+        if xs is not None and (tuple(xs.shape) != (nrhs, ns, 12, self.V) or xs.dtype != torch.complex128
+                               or xs.device != b.device or not xs.is_contiguous()):
+            raise ValueError(f"x_shifts must be a contiguous complex128 tensor of shape ({nrhs}, {ns}, 12, {self.V})")
         info, keep = self._info(nrhs, ns, force_iters, true_resid or bool(flags & REFINE))
         if shadow is not None:
             shadow = _spinors(shadow, self.V, "shadow")
@@ -280,7 +305,7 @@ class Context:
                 raise ValueError("shadow must have the shape and device of b")
             info.shadow = shadow.data_ptr()     # shadow (a local) outlives the call
         self._sync_stream()
-        rc = lib().mshift_bicgstabl(self._h, float(a_scale), ns, _dptr(sh), _dptr(wt), per, int(l),
+        rc = getattr(lib(), fn)(self._h, float(a_scale), ns, _dptr(sh), _dptr(wt), per, int(l),
                                     float(tol), int(max_outer), int(pass_), int(flags), nrhs,
                                     _P(b.data_ptr()), _P(y.data_ptr()),
                                     _P(xs.data_ptr() if xs is not None else None), ctypes.byref(info))
@@ -402,6 +427,10 @@ def spectral_radius(ctx: Context, start, iters=100):
 
 def mshift_bicgstabl(ctx: Context, b, a_scale, shifts, weights, l, tol, max_outer, pass_=1, **kw):
     return ctx.mshift_bicgstabl(b, a_scale, shifts, weights, l, tol, max_outer, pass_, **kw)
+
+
+def mshift_bicgstabl_noalloc(ctx: Context, b, a_scale, shifts, weights, l, tol, max_outer, pass_=1, **kw):
+    return ctx.mshift_bicgstabl_noalloc(b, a_scale, shifts, weights, l, tol, max_outer, pass_, **kw)
 
 
 def mshift_cg(ctx: Context, b, a_scale, shifts, weights, tol, max_iter, pass_=1, **kw):
