@@ -58,7 +58,15 @@ typedef enum {
     MSB_ERR_HIP = 2,        /* a HIP runtime call failed                        */
     MSB_ERR_OOM = 3,        /* workspace allocation failed                      */
     MSB_NOT_CONVERGED = 4,  /* max_outer reached; y and info are still filled   */
-    MSB_BREAKDOWN = 5       /* BiCG/MR/shift breakdown; partial y is returned   */
+    MSB_BREAKDOWN = 5,      /* BiCG/MR/shift breakdown; partial y is returned   */
+    MSB_REDUCED_ACCURACY = 6 /* MSB_MIXED without MSB_REFINE: every shift met tol
+                               on its recursive (FP32-updated) residual and the
+                               seed's residual was recomputed in FP64, but the
+                               shifts' FP64 true residuals are not shown to be
+                               <= tol (they stall near eps_32 times the
+                               condition number of A + sigma_s); y and info are
+                               filled.  MSB_REFINE (pass 1) checks and
+                               corrects every shift in FP64 instead.        */
 } msb_status;
 
 /* flags for wilson_apply */
@@ -119,6 +127,10 @@ typedef struct {
                                A point source with r~ = b breaks down under
                                MSB_OP_WILSON (D_w's hops change the site
                                parity); a random r~ avoids it.               */
+    int stored_iters;       /* out (pass = 3): outer iterations whose Mv outputs
+                               were kept in the store; those after them were
+                               regenerated (see msb_set_store_limit); -1 for
+                               the other passes                             */
 } msb_solve_info;
 
 /* Create a context on the current HIP device.  links: device pointer to
@@ -139,6 +151,17 @@ int msb_neuberger_pfe(int n, double *sigma, double *weight);
  * start [12][V] complex128: Rayleigh quotient after iters normalised steps.
  * The scale convention of the solvers is a_scale = 1 / (1.01 * rho). */
 int msb_spectral_radius(msb_ctx *ctx, const void *start, int iters, double *rho);
+
+/* Device memory the pseudo-double pass (pass = 3) of this context may use
+ * for its store of Mv outputs, in bytes; 0 (the default): whatever can be
+ * allocated.  The store grows by chunks of 8 outer iterations; once the next
+ * chunk would pass the limit (or cannot be allocated), no further iteration
+ * is stored: the first pass continues as the double pass's first pass (the
+ * seed's state at that iteration is kept), and after the sweep y is
+ * completed by replaying the remaining iterations from that state (Section
+ * 2: option 2 as far as memory allows, option 1 beyond).  The result is the
+ * pseudo-double pass's to rounding; info->stored_iters reports the split. */
+int msb_set_store_limit(msb_ctx *ctx, unsigned long long bytes);
 
 /* Kernel timing of later calls on this context, a measurement aid: with
  * enable != 0 every kernel launch of the solvers is bracketed by a pair of HIP
@@ -174,8 +197,10 @@ int wilson_apply(msb_ctx *ctx, const void *in, void *out, int nrhs, int flags);
  *                       2 M l Mv outputs in device memory (2 M l vectors
  *                       per right-hand side, plus M FP64 vectors with
  *                       MSB_MIXED), and y is summed from them after the
- *                       sweep: 2 M l Mv.  Not with MSB_PERSISTENT.  Fails
- *                       with MSB_ERR_OOM when the vectors do not fit.
+ *                       sweep: 2 M l Mv.  Not with MSB_PERSISTENT.  When
+ *                       they do not fit (or pass msb_set_store_limit), the
+ *                       iterations beyond the store are regenerated as in
+ *                       the double pass.
  *   flags            MSB_MIXED, MSB_PERSISTENT, MSB_ADJOINT, MSB_REFINE (pass 1),
  *                    MSB_DEFERRED (pass 1, not with MSB_PERSISTENT),
  *                    MSB_OP_WILSON (A = a D_w; not with MSB_ADJOINT)

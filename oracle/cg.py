@@ -27,9 +27,10 @@ and matching the shifted CG's own recurrences gives
     beta^s_k = beta_k (zeta_k / zeta_{k+1})^2,
     x^s += alpha^s_k p^s_k,   p^s_{k+1} = r_{k+1} / zeta_{k+1} + beta^s_k p^s_k,
     p^s_0 = b.
-Freezing: shift s stops at the first k with ||r_k|| / |zeta_k| <= tol ||b||
+Freezing: shift s stops at the first k with ||r_k|| / |zeta_k| <= 0.9 tol ||b||
 (its M_s = k; x^s then holds the terms k' < M_s); the seed stops when no
-shift is active.
+shift is active.  The fraction 0.9 leaves room for the rounding drift between
+the recursive and the true residual, as in the BiCGstab(l) oracle.
 
 Double pass (Neuberger).  Expanding p^s_k over the seed residuals,
     x^s = sum_{i < M_s} (e^s_i / zeta^s_i) r_i,
@@ -49,6 +50,8 @@ from dataclasses import dataclass, field
 from typing import Callable, List, Optional
 
 import numpy as np
+
+from .krylov import FREEZE_FRAC
 
 OK, NOT_CONVERGED, BREAKDOWN = 0, 4, 5
 
@@ -166,7 +169,7 @@ def mshift_cg(a_mv: Callable, b: np.ndarray, sigmas, weights, tol: float, max_it
             zeta[s] = znext[s]
             res = np.sqrt(rr_new) / abs(zeta[s]) / bn
             info.shift_resid[s] = res
-            done = (k + 1 >= force[s]) if force is not None else (res <= tol)
+            done = (k + 1 >= force[s]) if force is not None else (res <= FREEZE_FRAC * tol)
             if done:
                 active[s] = False
                 info.shift_iters[s] = k + 1

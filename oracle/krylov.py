@@ -50,6 +50,19 @@ import numpy as np
 BREAK_REL = 1e-14
 CHOL_REL = 1e-14
 ZETA_MIN = 1e-300
+# a shift whose |zeta psi| would exceed ZETA_MAX has a residual estimate
+# ||r_0|| / (|zeta psi| ||b||) below any tolerance (for any ||r_0|| within
+# 1e20 of ||b||) and 1 / (zeta psi) would underflow: it stops there as
+# converged, its solution complete to rounding
+ZETA_MAX = 1e300
+# outcome of a shift's scalar step
+STEP_OK, STEP_BROKEN, STEP_DONE = 0, 1, 2
+# a shift freezes once its recursive (collinear) residual estimate is at most
+# FREEZE_FRAC * tol, so that the rounding drift between the recursive and the
+# true residual (about 1e-15 relative in FP64) cannot lift the true residual
+# of a frozen shift above tol (the paper's convergence test, Section 2, reads
+# the residual of each shifted system; which estimate is not specified)
+FREEZE_FRAC = 0.9
 
 OK, NOT_CONVERGED, BREAKDOWN = 0, 4, 5
 
@@ -294,32 +307,51 @@ class _ShiftScalars:
     def bicg_step(self, s, alpha, beta):
         """Advance shift s over seed step (alpha_n, beta_n).
 
-        Returns (alpha_s, beta_s, kappa_n, kappa_{n+1}) or None on breakdown.
+        Returns (STEP_OK, (alpha_s, beta_s, kappa_n, kappa_{n+1})), or
+        (STEP_BROKEN, None) when zeta_{n+1} = zeta_n + alpha sigma' pi_n is not
+        finite or cancels to rounding (the shifted BiCG recurrence has no
+        next iterate), or (STEP_DONE, None) when |zeta_{n+1} psi| exceeds
+        ZETA_MAX (converged; see ZETA_MAX).
         """
         z, zp, pp, ps = self.zeta[s], self.zeta_prev[s], self.pi_prev[s], self.psi[s]
         pi_n = z - beta * pp
-        z_next = z + alpha * self.sp[s] * pi_n
-        if not np.isfinite(z_next) or abs(z_next) < ZETA_MIN:
-            return None
+        step = alpha * self.sp[s] * pi_n
+        z_next = z + step
+        with np.errstate(over="ignore", invalid="ignore"):
+            big = not abs(z_next) * abs(ps) <= ZETA_MAX
+            if not np.isfinite(z_next) or abs(z_next) < ZETA_MIN or \
+                    abs(z_next) <= BREAK_REL * (abs(z) + abs(step)):
+                return STEP_BROKEN, None
+        if big:
+            return STEP_DONE, None
         alpha_s = alpha * z / z_next
         beta_s = beta * (zp / z) ** 2
         kap = 1.0 / (z * ps)
         kap_next = 1.0 / (z_next * ps)
         self.zeta_prev[s], self.zeta[s], self.pi_prev[s] = z, z_next, pi_n
-        return alpha_s, beta_s, kap, kap_next
+        return STEP_OK, (alpha_s, beta_s, kap, kap_next)
 
     def mr_step(self, s, gammas):
-        """Shift s's MR data: (q^s, c^s_k for k = 0..l'-1, kappa_n), then psi *= q."""
+        """Shift s's MR data: (STEP_OK, (q^s, c^s_k for k = 0..l'-1, kappa_n)),
+        then psi *= q; or (STEP_BROKEN, None) when q^s = 1 - sum gamma_i
+        (-sigma')^i is not finite or cancels to rounding, or (STEP_DONE, None)
+        when |zeta psi q| exceeds ZETA_MAX."""
         sp = self.sp[s]
         lm = len(gammas)
-        q = 1.0 - sum(gammas[i - 1] * (-sp) ** i for i in range(1, lm + 1))
-        if not np.isfinite(q) or abs(q) < ZETA_MIN:
-            return None
+        terms = [gammas[i - 1] * (-sp) ** i for i in range(1, lm + 1)]
+        q = 1.0 - sum(terms)
+        with np.errstate(over="ignore", invalid="ignore"):
+            big = not abs(self.zeta[s]) * abs(self.psi[s]) * abs(q) <= ZETA_MAX
+            if not np.isfinite(q) or abs(q) < ZETA_MIN or \
+                    abs(q) <= BREAK_REL * (1.0 + sum(abs(t) for t in terms)):
+                return STEP_BROKEN, None
+        if big:
+            return STEP_DONE, None
         c = np.array([sum(gammas[i - 1] * (-sp) ** (i - 1 - k) for i in range(k + 1, lm + 1)) / q
                       for k in range(lm)], dtype=np.complex128)
         kap = 1.0 / (self.zeta[s] * self.psi[s])
         self.psi[s] = self.psi[s] * q
-        return q, c, kap
+        return STEP_OK, (q, c, kap)
 
     def resid_scale(self, s):
         return abs(self.zeta[s] * self.psi[s])
@@ -327,7 +359,7 @@ class _ShiftScalars:
 
 def mshift_bicgstabl(a_mv: Callable, b: np.ndarray, sigmas, weights, l: int,
                      tol: float, max_outer: int, pass_: int = 1,
-                     force_iters=None, monitor=None, keep_shifts=False, shadow=None):
+                     force_iters=None, monitor=None, keep_shifts=False, shadow=None, trace=None):
     """f(A) b ~ sum_s w_s (A + sigma_s)^{-1} b by multi-shift BiCGstab(l).
 
     a_mv      callable v -> A v
@@ -343,6 +375,11 @@ def mshift_bicgstabl(a_mv: Callable, b: np.ndarray, sigmas, weights, l: int,
               admits any r~ with <r~, r_0> != 0; a point source with
               r~ = b meets a structural breakdown on D_w, whose hopping
               term changes the site parity.
+    trace     optional list; for each outer iteration one dict is appended
+              with the MR step's inputs (copies of r_0..r_L before the
+              update), the coefficients applied and the number of completed
+              BiCG steps -- instrumentation for tests, no effect on the
+              iteration.
 
     Returns (y, info) for pass 2 and (y, info, xs) for pass 1 (xs the
     per-shift solutions in caller order).
@@ -392,7 +429,7 @@ def mshift_bicgstabl(a_mv: Callable, b: np.ndarray, sigmas, weights, l: int,
             if j >= 1 and force_iters is None:
                 # Krylov space exhausted: every active shift already meets
                 # its tolerance after the previous step's r-update
-                lim = tol * bn * min(scal.resid_scale(s) for s in np.nonzero(active)[0])
+                lim = FREEZE_FRAC * tol * bn * min(scal.resid_scale(s) for s in np.nonzero(active)[0])
                 if rn0 <= lim:
                     exhausted, l_eff = True, j
                     break
@@ -420,10 +457,11 @@ def mshift_bicgstabl(a_mv: Callable, b: np.ndarray, sigmas, weights, l: int,
             # shifted systems (uses r_i before this step's update)
             stape = {}
             for s in np.nonzero(active)[0]:
-                res = scal.bicg_step(s, alpha, beta)
-                if res is None:
+                kind, res = scal.bicg_step(s, alpha, beta)
+                if kind != STEP_OK:
+                    # the shift stops here (converged, or broken)
                     active[s] = False
-                    info.shift_breakdown[s] = True
+                    info.shift_breakdown[s] = kind == STEP_BROKEN
                     info.shift_iters[s] = m
                     continue
                 alpha_s, beta_s, kap, kap_next = res
@@ -453,13 +491,16 @@ def mshift_bicgstabl(a_mv: Callable, b: np.ndarray, sigmas, weights, l: int,
             g, l_mr = np.zeros(0, dtype=np.complex128), 0
         if l_mr < l:
             seed_broken = True
+        if trace is not None:
+            trace.append({"r": [v.copy() for v in r[: l_eff + 1]], "gammas": g.copy(), "l_eff": l_eff,
+                          "exhausted": exhausted, "steps": len(rec.steps)})
         rec.gammas = g.copy()
         smr = {}
         for s in np.nonzero(active)[0]:
-            res = scal.mr_step(s, g)
-            if res is None:
+            kind, res = scal.mr_step(s, g)
+            if kind != STEP_OK:
                 active[s] = False
-                info.shift_breakdown[s] = True
+                info.shift_breakdown[s] = kind == STEP_BROKEN
                 info.shift_iters[s] = m
                 continue
             q, c, kap = res
@@ -487,7 +528,7 @@ def mshift_bicgstabl(a_mv: Callable, b: np.ndarray, sigmas, weights, l: int,
         for s in np.nonzero(active)[0]:
             res_s = rn / (scal.resid_scale(s) * bn)
             info.shift_resid[s] = res_s
-            done = (m + 1 >= force_iters[s]) if force_iters is not None else (res_s <= tol)
+            done = (m + 1 >= force_iters[s]) if force_iters is not None else (res_s <= FREEZE_FRAC * tol)
             done = done or exhausted
             if done:
                 active[s] = False

@@ -25,6 +25,41 @@ __device__ __forceinline__ const C<T> *usrc(const VecArgs<T> &a, const C<T> *U, 
     return i == a.u_src_i ? a.u_src + (size_t)rhs * a.u_src_rs : U + (size_t)i * n;
 }
 
+// The MR step's view of the seed vectors (see VecArgs::mr_dyn): with mr_dyn
+// the store redirect follows the device's count of completed BiCG steps L,
+// otherwise the fixed r_src_i / u_src_i; lm is the number of MR terms the
+// scalar stage applied (terms beyond it are not read).
+template <typename T>
+struct MRView {
+    int ri = -1, ui = -1, lm = 0;
+    const C<T> *rp = nullptr, *up = nullptr;
+};
+template <typename T>
+__device__ __forceinline__ MRView<T> mr_view(const VecArgs<T> &a, int rhs, int lmax) {
+    MRView<T> v;
+    v.lm = lmax;
+    if (!a.mr_dyn) {
+        v.ri = a.r_src_i;
+        v.ui = a.u_src_i;
+        v.rp = a.r_src ? a.r_src + (size_t)rhs * a.r_src_rs : nullptr;
+        v.up = a.u_src ? a.u_src + (size_t)rhs * a.u_src_rs : nullptr;
+        return v;
+    }
+    const SeedState &S = a.seed[rhs];
+    const int L = S.l_eff;
+    v.lm = S.l_mr < lmax ? S.l_mr : lmax;
+    if (L >= 1) {
+        const C<T> *base = a.st_base + (size_t)rhs * a.st_rs;
+        v.ri = L;
+        v.rp = base + (size_t)(2 * L - 1) * a.n;
+        if (L >= a.l || S.step_flag[L] == 0) {
+            v.ui = L;
+            v.up = base + (size_t)(2 * L - 2) * a.n;
+        }
+    }
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // u_i = r_i - beta u_i for i in [I0, I1]: MODE 0 all of 0..J (the BiCG step's
 // direction update), MODE 1 only u_J (the one the step's Mv needs; the others
@@ -127,13 +162,14 @@ __device__ __forceinline__ void gram_body(const VecArgs<T> &a, int bx, int gx, i
     constexpr int NP = (L + 1) * (L + 2) / 2;
     const long n = a.n;
     const C<T> *R = a.R + (size_t)rhs * (a.l + 1) * n;
+    const MRView<T> mv = mr_view(a, rhs, L);
     double acc[2 * NP];
 #pragma unroll
     for (int p = 0; p < 2 * NP; ++p) acc[p] = 0.0;
     for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
         C<T> r[L + 1];
 #pragma unroll
-        for (int i = 0; i <= L; ++i) r[i] = rsrc(a, R, i, rhs, n)[e];
+        for (int i = 0; i <= L; ++i) r[i] = (i == mv.ri ? mv.rp : R + (size_t)i * n)[e];
         int p = 0;
 #pragma unroll
         for (int i = 0; i <= L; ++i)
@@ -166,11 +202,13 @@ __device__ __forceinline__ void mr_update_body(const VecArgs<T> &a, int bx, int 
     }
     const int nact = SHIFTS ? a.seed[rhs].nact : 0;
     const MRCoef *mc = SHIFTS ? a.mc + (size_t)rhs * NSMAX : nullptr;
+    const MRView<T> mv = mr_view(a, rhs, L);
+    const int lm = mv.lm;     // terms applied (zero coefficients beyond)
     double part[3] = {0.0, 0.0, 0.0};
     for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
         C<T> r[L + 1];
 #pragma unroll
-        for (int i = 0; i <= L; ++i) r[i] = rsrc(a, R, i, rhs, n)[e];
+        for (int i = 0; i <= L; ++i) r[i] = i <= lm ? (i == mv.ri ? mv.rp : R + (size_t)i * n)[e] : mk<T>(0, 0);
         if (SHIFTS) {
             for (int q = 0; q < nact; ++q) {
                 const MRCoef &c = mc[q];
@@ -199,9 +237,10 @@ __device__ __forceinline__ void mr_update_body(const VecArgs<T> &a, int bx, int 
 #pragma unroll
         for (int i = 1; i <= L; ++i) r0 = csub(r0, cmul(g[i], r[i]));
         R[e] = r0;
-        C<T> u0 = usrc(a, U, 0, rhs, n)[e];
+        C<T> u0 = (0 == mv.ui ? mv.up : U)[e];
 #pragma unroll
-        for (int i = 1; i <= L; ++i) u0 = csub(u0, cmul(g[i], usrc(a, U, i, rhs, n)[e]));
+        for (int i = 1; i <= L; ++i)
+            if (i <= lm) u0 = csub(u0, cmul(g[i], (i == mv.ui ? mv.up : U + (size_t)i * n)[e]));
         U[e] = u0;
         if (a.partials) {
             if (rt) {

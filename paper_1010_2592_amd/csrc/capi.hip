@@ -99,6 +99,7 @@ void fill_info(msb_solve_info *info, const msb::SolveReport &R, int nrhs, int n_
     info->reliable_updates = R.reliable;
     info->bytes_model = R.bytes_model;
     info->refined_shifts = R.refined;
+    info->stored_iters = R.stored_iters;
     const size_t m = (size_t)nrhs * n_shift;
     if (info->shift_iters && R.shift_iters.size() == m)
         std::memcpy(info->shift_iters, R.shift_iters.data(), m * sizeof(int));
@@ -108,15 +109,20 @@ void fill_info(msb_solve_info *info, const msb::SolveReport &R, int nrhs, int n_
         std::memcpy(info->shift_true_resid, R.shift_true_resid.data(), m * sizeof(double));
 }
 
-int finish(int rc, const msb::SolveReport &R, msb_solve_info *info, int nrhs, int n_shift) {
+int finish(int rc, const msb::SolveReport &R, msb_solve_info *info, int nrhs, int n_shift, int flags) {
     if (rc != MSB_OK) {
         if (info) info->status = rc;
         return rc;
     }
     int st = R.status;
+    // mixed precision without the per-shift FP64 check: the shifts' true
+    // residuals are not shown to meet tol
+    if (st == MSB_OK && (flags & MSB_MIXED) && !(flags & MSB_REFINE)) st = MSB_REDUCED_ACCURACY;
     if (st == MSB_ERR_ARG) set_error(MSB_ERR_ARG, "right-hand side with a non-finite norm");
     else if (st == MSB_NOT_CONVERGED) set_error(st, "max_outer reached before every shift converged");
     else if (st == MSB_BREAKDOWN) set_error(st, "breakdown of the BiCG, MR or shift recurrence");
+    else if (st == MSB_REDUCED_ACCURACY)
+        set_error(st, "mixed precision without MSB_REFINE: the shifts' FP64 residuals are not checked");
     fill_info(info, R, nrhs, n_shift, st);
     return st;
 }
@@ -182,6 +188,12 @@ int msb_spectral_radius(msb_ctx *ctx, const void *start, int iters, double *rho)
     return msb::spectral_radius(&ctx->c, (const double2 *)start, iters, rho);
 }
 
+int msb_set_store_limit(msb_ctx *ctx, unsigned long long bytes) {
+    if (!ctx) return arg_error("msb_set_store_limit: null context");
+    ctx->c.store_limit = (size_t)bytes;
+    return MSB_OK;
+}
+
 int msb_profile_enable(msb_ctx *ctx, int enable) {
     if (!ctx) return arg_error("msb_profile_enable: null context");
     return msb::profile_enable(&ctx->c, enable != 0);
@@ -216,7 +228,7 @@ int mshift_bicgstabl(msb_ctx *ctx, double a_scale, int n_shift, const double *sh
     msb::SolveReport R;
     const bool want_true = info && info->shift_true_resid && pass == 1;
     rc = msb::solve_mshift(&ctx->c, P, (const double2 *)b, (double2 *)y, (double2 *)x_shifts, want_true, &R);
-    return finish(rc, R, info, nrhs, n_shift);
+    return finish(rc, R, info, nrhs, n_shift, flags);
 }
 
 int mshift_bicgstabl_noalloc(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
@@ -238,7 +250,7 @@ int mshift_bicgstabl_noalloc(msb_ctx *ctx, double a_scale, int n_shift, const do
     msb::SolveReport R;
     const bool want_true = info && info->shift_true_resid && pass == 1;
     rc = msb::solve_noalloc(&ctx->c, P, (const double2 *)b, (double2 *)y, (double2 *)x_shifts, want_true, &R);
-    return finish(rc, R, info, nrhs, n_shift);
+    return finish(rc, R, info, nrhs, n_shift, flags);
 }
 
 int mshift_cg(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts, const double *weights,
@@ -255,7 +267,7 @@ int mshift_cg(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts, c
     P.force_iters = info ? info->force_iters : nullptr;
     msb::SolveReport R;
     rc = msb::solve_cg(&ctx->c, P, (const double2 *)b, (double2 *)y, (double2 *)x_shifts, &R);
-    return finish(rc, R, info, nrhs, n_shift);
+    return finish(rc, R, info, nrhs, n_shift, flags);
 }
 
 int msb_low_modes(msb_ctx *ctx, int nev, int nblock, const void *start, double tol, int degree, int max_iter,
@@ -289,7 +301,7 @@ int pfe_sign_apply_deflated(msb_ctx *ctx, double a_scale, int n_shift, const dou
     msb::SolveReport R;
     rc = msb::sign_apply_deflated(&ctx->c, P, nev, evals, (const double2 *)evecs, (const double2 *)b,
                                   (double2 *)out, (flags & MSB_OVERLAP) != 0, &R);
-    return finish(rc, R, info, nrhs, n_shift);
+    return finish(rc, R, info, nrhs, n_shift, flags);
 }
 
 int pfe_sign_apply(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
@@ -304,7 +316,7 @@ int pfe_sign_apply(msb_ctx *ctx, double a_scale, int n_shift, const double *shif
     P.force_iters = info ? info->force_iters : nullptr;
     msb::SolveReport R;
     rc = msb::sign_apply(&ctx->c, P, (const double2 *)b, (double2 *)out, (flags & MSB_OVERLAP) != 0, &R);
-    return finish(rc, R, info, nrhs, n_shift);
+    return finish(rc, R, info, nrhs, n_shift, flags);
 }
 
 int pfe_sign_backward(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
@@ -324,7 +336,7 @@ int pfe_sign_backward(msb_ctx *ctx, double a_scale, int n_shift, const double *s
     msb::SolveReport R;
     rc = msb::sign_backward(&ctx->c, P, (const double2 *)b, (const double2 *)eta, mode, (double2 *)grad_b,
                             grad_w, grad_sigma, (double2 *)grad_links, &R);
-    return finish(rc, R, info, nrhs, n_shift);
+    return finish(rc, R, info, nrhs, n_shift, flags);
 }
 
 }  // extern "C"

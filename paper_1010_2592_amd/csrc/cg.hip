@@ -155,7 +155,7 @@ __global__ __launch_bounds__(BLOCK) void k_cg_beta(CGArgs a) {
         H.zeta_prev = H.zeta;
         H.zeta = zn;
         H.res = sqrt(rrn) / fabs(zn) / S.bnorm;
-        const bool done = S.forced ? (S.k + 1 >= H.force) : (H.res <= S.tol);
+        const bool done = S.forced ? (S.k + 1 >= H.force) : (H.res <= FREEZE_FRAC * S.tol);
         if (done || !isfinite(H.res)) {
             H.active = 0;
             H.iters = S.k + 1;

@@ -20,6 +20,15 @@ constexpr int PMAX = 2 * (LMAX + 1) * (LMAX + 2) / 2;  // doubles per partial ro
 constexpr double BREAK_REL = 1e-14;
 constexpr double CHOL_REL = 1e-14;
 constexpr double ZETA_MIN = 1e-300;
+// a shift freezes once its recursive residual estimate is at most
+// FREEZE_FRAC tol: the rounding drift between the recursive and the true
+// residual (about 1e-15 relative in FP64) then cannot lift the true residual
+// above tol
+constexpr double FREEZE_FRAC = 0.9;
+// a shift whose |zeta psi| would exceed this has a residual estimate
+// ||r_0|| / (|zeta psi| ||b||) below any tolerance (for ||r_0|| within 1e20 of
+// ||b||) and 1 / (zeta psi) would underflow: it stops there as converged
+constexpr double ZETA_MAX = 1e300;
 
 enum Status { S_OK = 0, S_ERR_ARG = 1, S_ERR_HIP = 2, S_ERR_OOM = 3,
               S_NOT_CONVERGED = 4, S_BREAKDOWN = 5 };
@@ -52,6 +61,9 @@ template <typename Z> __host__ __device__ inline Z cfma(Z s, Z b, Z a) {
 }
 __host__ __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 __host__ __device__ inline double cabsd(double2 a) { return sqrt(a.x * a.x + a.y * a.y); }
+// modulus without intermediate overflow or underflow (the shifts' zeta and
+// psi range far beyond 1e+-154)
+__host__ __device__ inline double cmod(double2 a) { return hypot(a.x, a.y); }
 __host__ __device__ inline double2 cdiv(double2 a, double2 b) {
     // Smith's algorithm: scale by the larger component of b
     double2 r;
@@ -169,7 +181,10 @@ struct ShiftState {
     double2 zeta, zeta_prev, pi_prev, psi;
     double sp;      // sigma' = sigma_s - sigma_0
     double res;     // last collinear residual estimate
-    int active, iters, broken, force;
+    int active, iters, force;
+    int broken;     // stopped because zeta or q cancelled or is not finite
+    int stopped;    // stopped inside an outer iteration (broken, or |zeta psi|
+                    // past ZETA_MAX): iteration `iters` still applied part
 };
 
 struct StepCoef {   // one active shift, one BiCG step

@@ -135,6 +135,15 @@ struct VecArgs {
     const C<T> *u_src = nullptr;
     long u_src_rs = 0;
     int u_src_i = -1;
+    // the MR step of the pseudo-double pass and of the deferred single pass
+    // (mr_dyn = 1): r_L and u_L, L the BiCG steps the outer iteration
+    // completed, are read from the iteration's store slots (slot t at
+    // st_base + rhs * st_rs + t n) unless a step updated them since: r_L
+    // always (its first update would be step L's r-update), u_L unless step
+    // L made its u-step before a gamma breakdown
+    const C<T> *st_base = nullptr;
+    long st_rs = 0;
+    int mr_dyn = 0;
 };
 
 // mode: 0 u_0..u_j, 1 u_j only, 2 u_0..u_{j-1} (see seed_u_body)
@@ -294,7 +303,7 @@ constexpr int PERSIST_GROUP = 32;      // blocks per first-level barrier group
 constexpr int PERSIST_MAX_GROUPS = 64; // per XCD
 // Barrier and timing state of a persistent launch (zeroed before it).
 struct PersistCtl {
-    unsigned long long bar;                              // XCD arrivals (8 per barrier)
+    unsigned long long bar;                              // XCD arrivals (one per XCD in use)
     int abort;                                           // set when a wait exceeds its bound
     int pad;
     unsigned long long ticks[PERSIST_CLASSES];           // wall-clock ticks per timing class
@@ -302,6 +311,8 @@ struct PersistCtl {
     unsigned long long xbar[8], xrel[8];                 // per XCD: group arrivals, release
     unsigned long long gbar[8 * PERSIST_MAX_GROUPS];     // per group: block arrivals
     unsigned long long grel[8 * PERSIST_MAX_GROUPS];     // per group: release
+    unsigned long long xcount[8];                        // census: blocks found on each XCD
+    unsigned long long census;                           // census: blocks counted
 };
 struct PersistArgs {
     const POp *ops = nullptr;

@@ -10,18 +10,22 @@
 // first pass) until no right-hand side is still running, or runs once (the
 // double-pass replay, whose every outer iteration is known in advance).
 //
-// Grid barrier: a three-level tree of monotone counters.  Blocks are dealt
-// to XCDs round-robin (block b runs on XCD b % 8); inside an XCD they form
-// groups of PERSIST_GROUP.  Every work-item first waits for its own stores to
-// reach its XCD's L2; the last block of a group to arrive arrives at its XCD,
-// and the last group of an XCD writes that L2 back (agent-scope release) and
-// arrives at the global counter.  Release runs down the same tree, and every
+// Grid barrier: a three-level tree of monotone counters.  At the start of
+// the launch every block reads the hardware ID of the XCD it runs on and
+// takes a rank among the blocks of that XCD (a census behind one flat
+// barrier), so the tree below follows where the blocks really run, whatever
+// order the dispatcher dealt them in and however many XCDs the device has.
+// Inside an XCD the blocks form groups of PERSIST_GROUP.  Every work-item
+// first waits for its own stores to reach its XCD's L2; the last block of a
+// group to arrive arrives at its XCD, and the last group of an XCD writes
+// that L2 back (agent-scope release) and arrives at the global counter.  Release runs down the same tree, and every
 // block ends with an agent-scope acquire (invalidating stale lines), so
 // blocks on different XCDs see each other's results.  One L2 write-back per
 // XCD instead of one per block is what makes this barrier about 7x cheaper
 // than a flat one.  The launch is cooperative, so every block is resident and
 // each wait ends; a wait that still exceeds its bound raises the abort flag,
 // which every waiting block sees and leaves on, so no wave stays behind.
+#include "barrier_tree.h"
 #include "blas_dev.h"
 #include "scalar_dev.h"
 #include "stencil_dev.h"
@@ -47,18 +51,55 @@ __device__ __forceinline__ bool spin_until(unsigned long long *p, unsigned long 
     return true;
 }
 
-__device__ __forceinline__ bool grid_barrier(PersistCtl *ctl, unsigned long long number) {
+// The XCD (accelerator complex die) this wave runs on: hardware register
+// XCC_ID, bits 0..3.
+__device__ __forceinline__ int xcc_id() {
+    return (int)(__builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & 15u);
+}
+
+// A block's place in the barrier tree, from the census.
+struct TreePos {
+    int x, k, nx, nxcd;   // XCD, rank among its blocks, blocks on it, XCDs in use
+};
+
+// Census (thread 0 of every block): count the blocks on each XCD and give
+// each block its rank there; every block waits until all are counted (the
+// launch is cooperative, so all are resident).  False if the XCD ID is out
+// of range or a wait exceeds its bound (abort flag raised).
+__device__ __forceinline__ bool census(PersistCtl *ctl, TreePos *pos) {
+    const int x = xcc_id();
+    if (x < 0 || x >= 8) {
+        __hip_atomic_store(&ctl->abort, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+    }
+    pos->x = x;
+    pos->k = (int)__hip_atomic_fetch_add(&ctl->xcount[x], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the count above is visible before this arrival is (release), and every
+    // count after the wait (acquire)
+    __hip_atomic_fetch_add(&ctl->census, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (!spin_until(&ctl->census, (unsigned long long)gridDim.x, &ctl->abort)) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    pos->nx = (int)__hip_atomic_load(&ctl->xcount[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    pos->nxcd = 0;
+    for (int i = 0; i < 8; ++i)
+        pos->nxcd += __hip_atomic_load(&ctl->xcount[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0 ? 1 : 0;
+    if (tree::group_of(0, pos->nx, PERSIST_GROUP).ng > PERSIST_MAX_GROUPS) {
+        __hip_atomic_store(&ctl->abort, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool grid_barrier(PersistCtl *ctl, unsigned long long number, const TreePos &pos) {
     __shared__ int ok_sh;
     // s_waitcnt vmcnt(0): this work-item's stores have reached the L2
     __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        const int x = blockIdx.x & 7;                       // XCD
-        const int k = blockIdx.x >> 3;                      // rank inside the XCD
-        const int nx = ((int)gridDim.x - x + 7) / 8;        // blocks on this XCD
-        const int g = k / PERSIST_GROUP, ng = (nx + PERSIST_GROUP - 1) / PERSIST_GROUP;
-        const int gsize = (g == ng - 1) ? nx - g * PERSIST_GROUP : PERSIST_GROUP;
+        const int x = pos.x;
+        const tree::Group tg = tree::group_of(pos.k, pos.nx, PERSIST_GROUP);
+        const int g = tg.g, ng = tg.ng, gsize = tg.gsize;
         const int gi = x * PERSIST_MAX_GROUPS + g;
         const unsigned long long a =
             __hip_atomic_fetch_add(&ctl->gbar[gi], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
@@ -68,7 +109,7 @@ __device__ __forceinline__ bool grid_barrier(PersistCtl *ctl, unsigned long long
             if (ax == number * (unsigned long long)ng) {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // write this XCD's L2 back
                 __hip_atomic_fetch_add(&ctl->bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = spin_until(&ctl->bar, number * 8ull, &ctl->abort);
+                ok = spin_until(&ctl->bar, number * (unsigned long long)pos.nxcd, &ctl->abort);
                 __hip_atomic_store(&ctl->xrel[x], number, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 ok = spin_until(&ctl->xrel[x], number, &ctl->abort);
@@ -340,6 +381,12 @@ __device__ __forceinline__ void exec_op(const POp &op) {
 
 template <typename T, int L>
 __global__ __launch_bounds__(BLOCK) void k_persistent(PersistArgs pa) {
+    __shared__ TreePos pos_sh;
+    __shared__ int census_ok;
+    if (threadIdx.x == 0) census_ok = census(pa.ctl, &pos_sh) ? 1 : 0;
+    __syncthreads();
+    if (!census_ok) return;
+    const TreePos pos = pos_sh;
     unsigned long long number = 0;
     const bool timer = pa.timing && blockIdx.x == 0 && threadIdx.x == 0;
     long long t0 = timer ? wall_clock64() : 0;
@@ -347,7 +394,7 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(PersistArgs pa) {
         for (int k = 0; k < pa.nops; ++k) {
             const POp &op = pa.ops[k];
             exec_op<T, L>(op);
-            if (!grid_barrier(pa.ctl, ++number)) return;
+            if (!grid_barrier(pa.ctl, ++number, pos)) return;
             if (timer) {
                 const long long t1 = wall_clock64();
                 pa.ctl->ticks[op.cls] += (unsigned long long)(t1 - t0);

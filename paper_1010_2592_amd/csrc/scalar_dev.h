@@ -85,10 +85,10 @@ __device__ __forceinline__ void sc_beta_body(const ScalarArgs &a, int rhs) {
         for (int q = 0; q < S.nact; ++q) {
             const ShiftState &H = a.sh[(size_t)rhs * NSMAX + S.act[q]];
             if (!H.active) continue;
-            const double sc = cabsd(cmul(H.zeta, H.psi));
+            const double sc = cmod(cmul(H.zeta, H.psi));
             mn = sc < mn ? sc : mn;
         }
-        if (S.rnorm0 <= S.tol * S.bnorm * mn) {
+        if (S.rnorm0 <= FREEZE_FRAC * S.tol * S.bnorm * mn) {
             S.exhausted = 1;
             S.bicg_on = 0;
             S.l_eff = j;
@@ -171,10 +171,17 @@ __device__ __forceinline__ void sc_alpha_body(const ScalarArgs &a, int rhs) {
         const double2 z = H.zeta, zp = H.zeta_prev, pp = H.pi_prev, ps = H.psi;
         const double sp = H.sp;
         const double2 pi_n = csub(z, cmul(beta, pp));
-        const double2 z_next = cadd(z, cscale(cmul(alpha, pi_n), sp));
-        if (!cfinite(z_next) || cabsd(z_next) < ZETA_MIN) {
+        const double2 step = cscale(cmul(alpha, pi_n), sp);
+        const double2 z_next = cadd(z, step);
+        // zeta_{n+1} not finite or cancelled to rounding: the shifted
+        // recurrence has no next iterate (broken); |zeta_{n+1} psi| beyond
+        // ZETA_MAX: converged
+        const bool brk = !cfinite(z_next) || cmod(z_next) < ZETA_MIN ||
+                         cmod(z_next) <= BREAK_REL * (cmod(z) + cmod(step));
+        if (brk || !(cmod(z_next) * cmod(ps) <= ZETA_MAX)) {
             H.active = 0;
-            H.broken = 1;
+            H.broken = brk ? 1 : 0;
+            H.stopped = 1;
             H.iters = S.m;
             c.live = 0;
             continue;
@@ -302,10 +309,17 @@ __device__ __forceinline__ void sc_mr_body(const ScalarArgs &a, int rhs) {
         }
         const double sp = H.sp;
         double2 qs = d2(1, 0);
-        for (int i = 1; i <= lm; ++i) qs = csub(qs, cmul(g[i - 1], cpowi_neg(sp, i)));
-        if (!cfinite(qs) || cabsd(qs) < ZETA_MIN) {
+        double qterms = 1.0;
+        for (int i = 1; i <= lm; ++i) {
+            const double2 t = cmul(g[i - 1], cpowi_neg(sp, i));
+            qs = csub(qs, t);
+            qterms += cmod(t);
+        }
+        const bool brk = !cfinite(qs) || cmod(qs) < ZETA_MIN || cmod(qs) <= BREAK_REL * qterms;
+        if (brk || !(cmod(H.zeta) * cmod(H.psi) * cmod(qs) <= ZETA_MAX)) {
             H.active = 0;
-            H.broken = 1;
+            H.broken = brk ? 1 : 0;
+            H.stopped = 1;
             H.iters = S.m;
             c.live = 0;
             continue;
@@ -338,7 +352,7 @@ __device__ __forceinline__ void sc_rel_body(const ScalarArgs &a, int rhs) {
     for (int q = 0; q < S.nact; ++q) {
         const ShiftState &H = a.sh[(size_t)rhs * NSMAX + S.act[q]];
         if (!H.active) continue;
-        const bool due = S.forced ? (S.m + 1 >= H.force) : (rn / (cabsd(cmul(H.zeta, H.psi)) * S.bnorm) <= S.tol);
+        const bool due = S.forced ? (S.m + 1 >= H.force) : (rn / (cmod(cmul(H.zeta, H.psi)) * S.bnorm) <= FREEZE_FRAC * S.tol);
         freeze = freeze || due;
     }
     S.rel = (rn <= 0.1 * S.rmax || freeze || S.exhausted) ? 1 : 0;
@@ -373,9 +387,9 @@ __device__ __forceinline__ void sc_conv_body(const ScalarArgs &a, int rhs) {
     for (int q = threadIdx.x; q < S.nact; q += BLOCK) {
         ShiftState &H = a.sh[(size_t)rhs * NSMAX + S.act[q]];
         if (!H.active) continue;
-        const double res = rn / (cabsd(cmul(H.zeta, H.psi)) * S.bnorm);
+        const double res = rn / (cmod(cmul(H.zeta, H.psi)) * S.bnorm);
         H.res = res;
-        bool done = S.forced ? (S.m + 1 >= H.force) : (res <= S.tol);
+        bool done = S.forced ? (S.m + 1 >= H.force) : (res <= FREEZE_FRAC * S.tol);
         // an exhausted Krylov space ends the solve; in mixed precision the
         // residual was just recomputed in FP64, so a shift that still misses
         // its tolerance is reported as not converged

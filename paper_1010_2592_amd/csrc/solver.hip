@@ -226,7 +226,7 @@ void ctx_destroy(Ctx *c) {
                       &c->ws_rsig, &c->ws_rw, &c->ws_Bm, &c->ws_schist, &c->ws_dc, &c->ws_ones,
                       &c->ws_cg_r, &c->ws_cg_p, &c->ws_cg_w, &c->ws_cg_P, &c->ws_cg_seed, &c->ws_cg_shift,
                       &c->ws_cg_coef, &c->ws_cg_tape, &c->ws_cg_c, &c->ws_cg_n, &c->ws_eY, &c->ws_eW,
-                      &c->ws_eZ, &c->ws_eP, &c->ws_eS, &c->ws_eG, &c->ws_sp};
+                      &c->ws_eZ, &c->ws_eP, &c->ws_eS, &c->ws_eG, &c->ws_sp, &c->ws_hs, &c->ws_hs64};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (DevBuf &b : c->pstore)
@@ -340,10 +340,12 @@ struct SweepResult {
 
 // One right-hand side.  tape: recorded full steps (and a trailing u-step on a
 // gamma breakdown); outer: per-outer-iteration record; gam: MR coefficients;
-// sp, w: relative shifts and weights; iters, broken: per-shift M_s.
+// sp, w: relative shifts and weights; iters, stopped: per-shift M_s and
+// whether the shift stopped inside outer iteration M_s (a guard of its
+// recurrences), which then still took part in that iteration up to there.
 static void sweep_rhs(int l, int M, const TapeStep *tape, const TapeOuter *outer,
                       const double2 *gam, int ns, const double *sp, const double *w,
-                      const int *iters, const int *broken, int max_outer, SweepResult *res) {
+                      const int *iters, const int *stopped, int max_outer, SweepResult *res) {
     struct Sh {
         cd as, bs, kap, kapn;
         bool live;
@@ -363,7 +365,7 @@ static void sweep_rhs(int l, int M, const TapeStep *tape, const TapeOuter *outer
     for (int m = 0; m < M; ++m) {
         std::vector<char> act(ns, 0);
         for (int s = 0; s < ns; ++s)
-            act[s] = alive[s] && (m < iters[s] || (broken[s] && m == iters[s]));
+            act[s] = alive[s] && (m < iters[s] || (stopped[s] && m == iters[s]));
         for (int j = 0; j < outer[m].l_eff; ++j) {
             const int n = n0[m] + j;
             const cd alpha = toc(tape[n].alpha), beta = toc(tape[n].beta);
@@ -373,8 +375,12 @@ static void sweep_rhs(int l, int M, const TapeStep *tape, const TapeOuter *outer
                 if (!act[s]) continue;
                 const cd z = zeta[s], zp = zprev[s];
                 const cd pi_n = z - beta * piprev[s];
-                const cd zn = z + alpha * sp[s] * pi_n;
-                if (!std::isfinite(zn.real()) || !std::isfinite(zn.imag()) || std::abs(zn) < ZETA_MIN) {
+                const cd step = alpha * sp[s] * pi_n;
+                const cd zn = z + step;
+                // the guards of the device recurrences (broken or converged)
+                if (!std::isfinite(zn.real()) || !std::isfinite(zn.imag()) || std::abs(zn) < ZETA_MIN ||
+                    std::abs(zn) <= BREAK_REL * (std::abs(z) + std::abs(step)) ||
+                    !(std::abs(zn) * std::abs(psi[s]) <= ZETA_MAX)) {
                     act[s] = alive[s] = 0;
                     continue;
                 }
@@ -394,12 +400,16 @@ static void sweep_rhs(int l, int M, const TapeStep *tape, const TapeOuter *outer
             q.live = false;
             if (!act[s] || lm == 0) continue;
             cd qs = 1.0;
+            double qterms = 1.0;
             for (int i = 1; i <= lm; ++i) {
                 double p = 1.0;
                 for (int k = 0; k < i; ++k) p *= -sp[s];
-                qs -= toc(gam[(size_t)m * LMAX + i - 1]) * p;
+                const cd t = toc(gam[(size_t)m * LMAX + i - 1]) * p;
+                qs -= t;
+                qterms += std::abs(t);
             }
-            if (!std::isfinite(qs.real()) || !std::isfinite(qs.imag()) || std::abs(qs) < ZETA_MIN) {
+            if (!std::isfinite(qs.real()) || !std::isfinite(qs.imag()) || std::abs(qs) < ZETA_MIN ||
+                std::abs(qs) <= BREAK_REL * qterms || !(std::abs(zeta[s]) * std::abs(psi[s]) * std::abs(qs) <= ZETA_MAX)) {
                 act[s] = alive[s] = 0;
                 continue;
             }
@@ -697,6 +707,9 @@ static int run_persistent(Ctx *c, const std::vector<POp> &ops, int iters, bool l
     PersistCtl host;
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipMemcpy(&host, c->ws_pctl.p, sizeof(PersistCtl), hipMemcpyDeviceToHost));
+    if (host.abort == 2)
+        return set_error(S_ERR_HIP, "persistent launch: the XCD census found an XCD ID outside 0..7 or more blocks "
+                                    "on one XCD than the barrier tree holds");
     if (host.abort) return set_error(S_ERR_HIP, "persistent launch: a grid barrier wait exceeded its bound");
     if (c->prof) {
         int khz = 0;
@@ -794,6 +807,12 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         CHK(ensure(c, c->ws_replay_outer, (size_t)nrhs * max_outer * sizeof(ReplayOuter)));
         CHK(ensure(c, c->ws_cb, (size_t)nrhs * sizeof(double2)));
         if (pass3 && mixed) CHK(ensure(c, c->ws_ones, (size_t)nrhs * sizeof(double2)));
+        if (pass3) {
+            // the seed's state (r_0, u_0; x in FP64 with mixed precision) at
+            // the first outer iteration whose Mv outputs the store cannot hold
+            CHK(ensure(c, c->ws_hs, (size_t)nrhs * 2 * n * cs));
+            if (mixed) CHK(ensure(c, c->ws_hs64, (size_t)nrhs * n * sizeof(double2)));
+        }
     }
     if (!P.persistent)
         CHK(ensure(c, c->ws_sp, (size_t)nrhs * (SPMAX * (sizeof(long) + sizeof(double2)) + (1 + NBL) * sizeof(int)) +
@@ -1033,16 +1052,24 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     // precision also the FP64 S x of its reliable update, [PSC][rhs][n]
     constexpr int PSC = 8;
     const long ps_rs = (long)PSC * 2 * l * n;
-    auto pstore_chunk = [&](int k) -> int {
+    // Storage chunk k for outer iterations k PSC .. k PSC + PSC - 1: false
+    // when it would pass the context's store limit or cannot be allocated;
+    // the solve then stores no further iteration (m_split) and regenerates
+    // those after the sweep from the seed state saved where the store ended:
+    // the pseudo-double pass where memory allows, the double pass beyond.
+    const size_t chunk_bytes = (size_t)nrhs * ps_rs * cs + (mixed ? (size_t)nrhs * PSC * n * sizeof(double2) : 0);
+    auto pstore_chunk = [&](int k) -> bool {
+        if (c->store_limit && (size_t)(k + 1) * chunk_bytes > c->store_limit) return false;
         while ((int)c->pstore.size() <= k) c->pstore.push_back(DevBuf{});
-        CHK(ensure(c, c->pstore[k], (size_t)nrhs * ps_rs * cs));
+        if (ensure(c, c->pstore[k], (size_t)nrhs * ps_rs * cs)) return false;
         if (mixed) {
             while ((int)c->prel.size() <= k) c->prel.push_back(DevBuf{});
-            CHK(ensure(c, c->prel[k], (size_t)nrhs * PSC * n * sizeof(double2)));
+            if (ensure(c, c->prel[k], (size_t)nrhs * PSC * n * sizeof(double2))) return false;
             launch_zero<double>(st, (double2 *)c->prel[k].p, (long)nrhs * PSC * n, 0, 1);
         }
-        return 0;
+        return true;
     };
+    int m_split = max_outer;       // pass 3: the first outer iteration not stored
     if (pass3 && mixed) {
         CHK(ensure(c, c->ws_ones, (size_t)nrhs * sizeof(double2)));
         std::vector<double2> ones(nrhs, double2{1.0, 0.0});
@@ -1076,7 +1103,8 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         // Mv output t of this outer iteration (t = 2j: u_{j+1}, 2j + 1:
         // r_{j+1}): its slot in the pass-3 store, or in the deferred single
         // pass's basis (after B_0 = r_0, B_1 = u_0)
-        const bool stored = pass3 || deferred;
+        const bool keep = pass3 && m < m_split;   // pass 3: this iteration's outputs are stored
+        const bool stored = keep || deferred;
         const long store_rs = pass3 ? ps_rs : (long)nb * n;
         auto slot = [&](int t) {
             return pass3 ? (C<T> *)c->pstore[m / PSC].p + ((size_t)(m % PSC) * 2 * l + t) * n
@@ -1146,7 +1174,15 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             if (sparse_rt) sparse_dot_of(e, e2.out, e2.gate, nr_run, stored ? store_rs : vs);
         }
         v.gate = g_run;
-        from_store(v, l, l);         // r_l and u_l: read by the MR step only
+        // the MR step reads r_L and u_L (L = the steps the iteration
+        // completed, l unless a breakdown ended it early) from the store
+        // where no step updated them since
+        from_store(v, -1, -1);
+        if (stored) {
+            v.mr_dyn = 1;
+            v.st_base = slot(0);
+            v.st_rs = store_rs;
+        }
         e.gram(v, nrhs, nbv, CL_SEED, nr_run * (l + 1.0) * nd * cB);
         s.nblk = nbv;
         e.scalar(OP_SC_MR, s, nrhs);
@@ -1157,7 +1193,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                     nr_run * ((2.0 * (l + 1) + (sparse_rt ? 2 : 3)) * cB + (mixed ? 32.0 : 0.0)) * nd +
                         (shifts_step ? nsh_act * ((l + 2.0) * cB + 32.0) * nd : 0.0));
         if (sparse_rt) sparse_dot_of(e, R, v.gate, nr_run, vs);
-        from_store(v, -1, -1);
+        v.mr_dyn = 0;
         if (deferred) {
             // every shift's update over the iteration, from the basis: read the
             // 2l+2 basis vectors once, each active shift's u^s_0 and x^s (FP64)
@@ -1168,7 +1204,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         }
         if (mixed) {
             e.scalar(OP_SC_REL, s, nrhs);
-            if (pass3)   // keep S x of the update: slot += 1 * S x (the slot starts at zero)
+            if (keep)   // keep S x of the update: slot += 1 * S x (the slot starts at zero)
                 reliable_update(e, v, g_rel, (double2 *)c->prel[m / PSC].p + (size_t)(m % PSC) * nrhs * n,
                                 CoefRef{(const char *)c->ws_ones.p, (long)sizeof(double2)}, nr_run);
             else
@@ -1191,7 +1227,17 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         double nsh_act = (double)nrhs * ns;      // active shifts over those
         Emit<T> el(c, Emit<T>::LAUNCH);
         for (int m = 0; m < max_outer; ++m) {
-            if (pass3 && m % PSC == 0) CHK(pstore_chunk(m / PSC));
+            if (pass3 && m < m_split && m % PSC == 0 && !pstore_chunk(m / PSC)) {
+                (void)hipGetLastError();
+                m_split = m;
+                // the seed's state at the start of outer iteration m, for the replay
+                HIPCHK(hipMemcpy2DAsync(c->ws_hs.p, n * cs, R, vs * cs, n * cs, nrhs, hipMemcpyDeviceToDevice, st));
+                HIPCHK(hipMemcpy2DAsync((char *)c->ws_hs.p + (size_t)nrhs * n * cs, n * cs, Uv, vs * cs, n * cs, nrhs,
+                                        hipMemcpyDeviceToDevice, st));
+                if (mixed)
+                    HIPCHK(hipMemcpyAsync(c->ws_hs64.p, XH, (size_t)nrhs * n * sizeof(double2),
+                                          hipMemcpyDeviceToDevice, st));
+            }
             emit_outer(el, nr_run, nsh_act, m);
             HIPCHK(hipGetLastError());
             HIPCHK(hipMemcpyAsync(hseed, seed, nrhs * sizeof(SeedState), hipMemcpyDeviceToHost, st));
@@ -1291,7 +1337,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 spv[s] = H.sp;
                 wv[s] = P.weights[(size_t)r * ns + s];
                 it[s] = H.iters;
-                br[s] = H.broken;
+                br[s] = H.stopped;
             }
             SweepResult sr;
             sweep_rhs(l, fs[r].m, &tp[(size_t)r * max_steps], &to[(size_t)r * max_outer],
@@ -1310,26 +1356,40 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         HIPCHK(hipMemcpyAsync(dro, router.data(), router.size() * sizeof(ReplayOuter), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(c->ws_cb.p, cb.data(), nrhs * sizeof(double2), hipMemcpyHostToDevice, st));
 
+        // outer iterations [0, m_rep) are summed from the store (pass 3), the
+        // rest regenerated by the replay (pass 2: all of them)
+        const int m_rep = pass3 ? std::min(m_split, Mmax) : 0;
+        rep->stored_iters = pass3 ? m_rep : -1;
         if (pass3) {
             // pseudo-double pass: y = c_b b + sum_t c_t v_t over the stored Mv outputs
-            Prof p(c, CL_OTHER, nrhs * nd * (32.0 + 16.0 + (double)Mmax * (2.0 * l * cB + (mixed ? 16.0 : 0.0))));
+            Prof p(c, CL_OTHER, nrhs * nd * (32.0 + 16.0 + (double)m_rep * (2.0 * l * cB + (mixed ? 16.0 : 0.0))));
             launch_yinit(st, y, b, (const double2 *)c->ws_cb.p, n, nrhs, nbv);
-            for (int m0 = 0; m0 < Mmax; m0 += PSC) {
-                const int mc = std::min(PSC, Mmax - m0);
+            for (int m0 = 0; m0 < m_rep; m0 += PSC) {
+                const int mc = std::min(PSC, m_rep - m0);
                 launch_pstore_sum<T>(st, y, (const C<T> *)c->pstore[m0 / PSC].p, ps_rs,
                                      mixed ? (const double2 *)c->prel[m0 / PSC].p : nullptr, (long)nrhs * n, drs, dro,
                                      Mcap, l, m0, mc, n, nrhs, nbv);
             }
             HIPCHK(hipGetLastError());
-        } else {
-        // pass 2: regenerate the Mv outputs and accumulate y
-        {
+        }
+        if (m_rep < Mmax) {
+        // regenerate the Mv outputs of outer iterations m_rep.. and accumulate y
+        if (m_rep == 0) {
             Prof p(c, CL_OTHER, nrhs * nd * (2.0 * (l + 1) * cB + 16.0 + cB + 32.0));
             launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
             launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
             launch_convert_in<T>(st, R, b, n, vs, n, nrhs);
             launch_yinit(st, y, b, (const double2 *)c->ws_cb.p, n, nrhs, nbv);
             if (mixed) launch_zero<double>(st, XH, (long)nrhs * n, 0, 1);
+        } else {
+            // the seed's state saved at the start of outer iteration m_rep
+            Prof p(c, CL_OTHER, nrhs * nd * (4.0 * cB + (mixed ? 32.0 : 0.0)));
+            HIPCHK(hipMemcpy2DAsync(R, vs * cs, c->ws_hs.p, n * cs, n * cs, nrhs, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpy2DAsync(Uv, vs * cs, (const char *)c->ws_hs.p + (size_t)nrhs * n * cs, n * cs, n * cs,
+                                    nrhs, hipMemcpyDeviceToDevice, st));
+            if (mixed)
+                HIPCHK(hipMemcpyAsync(XH, c->ws_hs64.p, (size_t)nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice,
+                                      st));
         }
         const long rstride = (long)Mcap * l * sizeof(ReplayStep);
         VecArgs<T> vb = va;
@@ -1341,7 +1401,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         e2.y = y;
         e2.y_rs = n;
         Emit<T> e(c, P.persistent ? Emit<T>::RECORD : Emit<T>::LAUNCH, true);
-        for (int m = 0; m < Mmax; ++m) {
+        for (int m = m_rep; m < Mmax; ++m) {
             int nr_m = 0;      // right-hand sides whose replay reaches outer iteration m
             for (int r = 0; r < nrhs; ++r) nr_m += (fs[r].m > m) ? 1 : 0;
             for (int j = 0; j < l; ++j) {
@@ -1410,7 +1470,13 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             CHK(run_persistent<T>(c, e.ops, 1, false, l, seed, nrhs, e.cls_bytes));
             for (Ctx::SRec &q : c->srecs) q.pending = false;
         }
-        rep->mv *= 2;
+        // the replayed Mv (pass 2: as many as the first pass)
+        for (int r = 0; r < nrhs; ++r)
+            for (int m = m_rep; m < fs[r].m; ++m)
+                for (int j = 0; j < l; ++j) {
+                    const int f = rsteps[((size_t)r * Mcap + m) * l + j].flag;
+                    rep->mv += (f >= 1 ? 1 : 0) + (f >= 2 ? 1 : 0);
+                }
         }
     }
 
@@ -1601,7 +1667,7 @@ static int solve_refined(Ctx *c, const SolveParams &P, const double2 *b, double2
                 // other residual of it counts as failing
                 const double rel = bnorm[r] > 0 ? rn[r] / bnorm[r] : (rn[r] > 0 ? INFINITY : 0.0);
                 rep->shift_true_resid[(size_t)r * ns + s] = rel;
-                if (!(rel <= P.tol)) {
+                if (!(rel <= FREEZE_FRAC * P.tol)) {
                     failing += 1;
                     if (round == ROUNDS || !std::isfinite(rel)) continue;   // last round: report only
                     HIPCHK(hipMemcpyAsync(RB + batch.size() * n, R + (size_t)r * n, n * sizeof(double2),

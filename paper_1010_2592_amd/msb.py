@@ -24,10 +24,14 @@ __all__ = [
     "neuberger_pfe", "wilson_apply", "mshift_bicgstabl", "mshift_bicgstabl_noalloc", "mshift_cg", "pfe_sign_apply",
     "pfe_sign_backward", "spectral_radius",
     "G5_LEFT", "NEG_MU", "DAGGER", "MIXED", "PERSISTENT", "OVERLAP", "ADJOINT", "REFINE", "DEFERRED", "OP_WILSON",
-    "OK", "ERR_ARG", "ERR_HIP", "ERR_OOM", "NOT_CONVERGED", "BREAKDOWN",
+    "OK", "ERR_ARG", "ERR_HIP", "ERR_OOM", "NOT_CONVERGED", "BREAKDOWN", "REDUCED_ACCURACY", "SUCCESS",
 ]
 
-OK, ERR_ARG, ERR_HIP, ERR_OOM, NOT_CONVERGED, BREAKDOWN = 0, 1, 2, 3, 4, 5
+OK, ERR_ARG, ERR_HIP, ERR_OOM, NOT_CONVERGED, BREAKDOWN, REDUCED_ACCURACY = 0, 1, 2, 3, 4, 5, 6
+# statuses of a completed solve: MSB_OK, and MSB_REDUCED_ACCURACY (mixed
+# precision without the per-shift FP64 check); the default `allow` of the
+# solver methods (info.status tells them apart)
+SUCCESS = (OK, REDUCED_ACCURACY)
 G5_LEFT, NEG_MU, DAGGER, MIXED, PERSISTENT, OVERLAP, ADJOINT, REFINE, DEFERRED = 1, 2, 4, 8, 16, 32, 64, 128, 256
 OP_WILSON = 512     # A = a D_w instead of a (gamma5 D_w)^2 (multi-mass propagators)
 
@@ -58,7 +62,8 @@ class _Info(ctypes.Structure):
                 ("shift_resid", ctypes.POINTER(ctypes.c_double)),
                 ("shift_true_resid", ctypes.POINTER(ctypes.c_double)),
                 ("force_iters", ctypes.POINTER(ctypes.c_int)),
-                ("refined_shifts", ctypes.c_int), ("shadow", ctypes.c_void_p)]
+                ("refined_shifts", ctypes.c_int), ("shadow", ctypes.c_void_p),
+                ("stored_iters", ctypes.c_int)]
 
 
 _LIB = None
@@ -97,10 +102,11 @@ def lib():
                                               _P, _P, ctypes.POINTER(_Info)]
         L.pfe_sign_backward.argtypes = [_P, _D, _I, _DP, _DP, _I, _D, _I, _I, _I, _P, _P, _I,
                                         _P, _DP, _DP, _P, ctypes.POINTER(_Info)]
+        L.msb_set_store_limit.argtypes = [_P, ctypes.c_ulonglong]
         L.msb_profile_enable.argtypes = [_P, _I]
         L.msb_profile_read.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_longlong), _DP, _DP]
         for f in ("msb_create", "msb_set_stream", "msb_neuberger_pfe", "msb_spectral_radius",
-                  "msb_profile_enable", "msb_profile_read",
+                  "msb_set_store_limit", "msb_profile_enable", "msb_profile_read",
                   "wilson_apply", "mshift_bicgstabl", "mshift_bicgstabl_noalloc", "mshift_cg", "pfe_sign_apply", "pfe_sign_backward",
                   "msb_low_modes", "pfe_sign_apply_deflated"):
             getattr(L, f).restype = _I
@@ -108,7 +114,7 @@ def lib():
     return _LIB
 
 
-def _check(rc: int, allow=(OK,)):
+def _check(rc: int, allow=SUCCESS):
     if rc not in allow:
         raise MsbError(rc, lib().msb_last_error().decode())
     return rc
@@ -158,6 +164,7 @@ class SolveInfo:
     shift_resid: np.ndarray
     shift_true_resid: Optional[np.ndarray]
     refined_shifts: int = 0
+    stored_iters: int = -1
 
 
 def neuberger_pfe(n: int):
@@ -195,6 +202,10 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_store_limit(self, nbytes: int):
+        """Bytes the pseudo-double pass may keep in its store (0: no limit)."""
+        _check(lib().msb_set_store_limit(self._h, int(nbytes)))
 
     def _sync_stream(self):
         _check(lib().msb_set_stream(self._h, _stream_handle()))
@@ -252,12 +263,13 @@ class Context:
         return SolveInfo(info.status, info.outer_iters, info.bicg_steps, info.mv_count,
                          info.dot_count, info.axpy_count, info.reliable_updates, info.bytes_model,
                          it.reshape(nrhs, ns).copy(), rs.reshape(nrhs, ns).copy(),
-                         None if tr is None else tr.reshape(nrhs, ns).copy(), info.refined_shifts)
+                         None if tr is None else tr.reshape(nrhs, ns).copy(), info.refined_shifts,
+                         info.stored_iters)
 
     def mshift_bicgstabl(self, b: torch.Tensor, a_scale: float, shifts, weights, l: int,
                          tol: float, max_outer: int, pass_: int = 1, flags: int = 0,
                          want_shifts: bool = False, force_iters=None, true_resid: bool = False,
-                         allow=(OK,), shadow: Optional[torch.Tensor] = None, y: Optional[torch.Tensor] = None):
+                         allow=SUCCESS, shadow: Optional[torch.Tensor] = None, y: Optional[torch.Tensor] = None):
         """y = sum_s w_s (A + sigma_s)^{-1} b; returns (y, info, x_shifts or None).
 
         shifts/weights: (n_shift,) for one set, or (nrhs, n_shift) per rhs.
@@ -272,7 +284,7 @@ class Context:
     def mshift_bicgstabl_noalloc(self, b: torch.Tensor, a_scale: float, shifts, weights, l: int,
                                  tol: float, max_outer: int, pass_: int = 1, flags: int = 0,
                                  want_shifts: bool = False, force_iters=None, true_resid: bool = False,
-                                 allow=(OK,), shadow: Optional[torch.Tensor] = None,
+                                 allow=SUCCESS, shadow: Optional[torch.Tensor] = None,
                                  y: Optional[torch.Tensor] = None, x_shifts: Optional[torch.Tensor] = None):
         """mshift_bicgstabl with the library's workspace taken from its fixed
         device scratch array (no device allocation in the call); pass_ 1 or 2.
@@ -313,7 +325,7 @@ class Context:
         return y, self._pack_info(info, keep, nrhs, ns), xs
 
     def mshift_cg(self, b: torch.Tensor, a_scale: float, shifts, weights, tol: float, max_iter: int,
-                  pass_: int = 1, want_shifts: bool = False, force_iters=None, allow=(OK,)):
+                  pass_: int = 1, want_shifts: bool = False, force_iters=None, allow=SUCCESS):
         """Multi-shift CG (the context must have mu = 0): y = sum_s w_s (A + sigma_s)^{-1} b;
         returns (y, info, x_shifts or None).  pass_: 1 single, 2 double, 3 pseudo-double."""
         b = _spinors(b, self.V, "b")
@@ -334,7 +346,7 @@ class Context:
         return y, self._pack_info(info, keep, nrhs, ns), xs
 
     def low_modes(self, nev: int, start: torch.Tensor, tol: float = 1e-10, degree: int = 24,
-                  max_iter: int = 200, allow=(OK,)):
+                  max_iter: int = 200, allow=SUCCESS):
         """Low modes of H = gamma5 D_w (mu = 0): (evals [nev] sorted by |lambda|,
         evecs [nev][12][V], resid [nev], iterations).  start: [nblock][12][V]
         complex128 start block, nblock > nev."""
@@ -351,7 +363,7 @@ class Context:
 
     def pfe_sign_apply_deflated(self, b: torch.Tensor, a_scale: float, shifts, weights, l: int, tol: float,
                                 max_outer: int, evals, evecs: torch.Tensor, pass_: int = 1, flags: int = 0,
-                                allow=(OK,)):
+                                allow=SUCCESS):
         """sign(H) b (or the overlap with OVERLAP) with the low modes (evals,
         evecs) deflated; mu = 0."""
         b = _spinors(b, self.V, "b")
@@ -373,7 +385,7 @@ class Context:
 
     def pfe_sign_apply(self, b: torch.Tensor, a_scale: float, shifts, weights, l: int, tol: float,
                        max_outer: int, pass_: int = 1, flags: int = 0, force_iters=None,
-                       allow=(OK,)):
+                       allow=SUCCESS):
         b = _spinors(b, self.V, "b")
         nrhs = b.shape[0]
         sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64))
@@ -390,7 +402,7 @@ class Context:
 
     def pfe_sign_backward(self, b: torch.Tensor, eta: torch.Tensor, a_scale: float, shifts, weights,
                           l: int, tol: float, max_outer: int, mode: int = 0, flags: int = 0,
-                          grad_links: Optional[torch.Tensor] = None, force_iters=None, allow=(OK,)):
+                          grad_links: Optional[torch.Tensor] = None, force_iters=None, allow=SUCCESS):
         """Gradients of Re<eta, y>, y = f(A) b (mode 0) or sign(H) b (mode 1).
 
         Returns (grad_b, grad_w, grad_sigma, grad_links, info); grad_links is

@@ -39,7 +39,7 @@ def test_headline_forced_parity_sampled_sources(headline):
     from paper_1010_2592_amd import msb
     wk, U, ctx, a, sig, w, b = headline
     force = np.full(len(sig), 2)
-    allow = (msb.OK, msb.NOT_CONVERGED)
+    allow = (msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY)
     log("headline batch, forced 2 outer iterations: pass 3 and deferred pass 1")
     y3, i3, _ = ctx.mshift_bicgstabl(b, a, sig, w, 4, wk.tol, 2, 3, force_iters=force, allow=allow)
     yd, idf, _ = ctx.mshift_bicgstabl(b, a, sig, w, 4, wk.tol, 2, 1, flags=msb.DEFERRED, force_iters=force,
@@ -72,4 +72,4 @@ def test_headline_converged_properties(headline):
         worst = max(worst, float((torch.linalg.vector_norm(r.reshape(12, -1), dim=1) / bn).max()))
         del x, t, r
     log(f"  M = {i3.outer_iters}, pass 3 vs pass 1 {d:.2e}, worst true residual {worst:.2e}")
-    assert worst <= 1.05 * wk.tol
+    assert worst <= wk.tol

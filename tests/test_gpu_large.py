@@ -53,7 +53,7 @@ def test_full_size_single_and_double_pass(big, l):
     y1, i1, xs = ctx.mshift_bicgstabl(b, a, sig, w, l, wk.tol, 3000, 1, want_shifts=True)
     tr = true_residuals(ctx, a, sig, b, xs)
     log(f"  M = {i1.outer_iters}, max true residual {tr.max():.3e}, max collinear {i1.shift_resid.max():.3e}")
-    assert tr.max() <= 1.2 * wk.tol
+    assert tr.max() <= wk.tol
     del xs
     torch.cuda.empty_cache()
     log(f"24x24x24x48 l={l}: double pass FP64")
@@ -77,5 +77,5 @@ def test_full_size_mixed_refined(big):
     d = float(torch.linalg.vector_norm(ym - y64) / torch.linalg.vector_norm(y64))
     log(f"  refined {im.refined_shifts} shifts, max true residual {tr.max():.3e} "
         f"(library {im.shift_true_resid.max():.3e}), y vs FP64 {d:.3e}")
-    assert tr.max() <= 1.05 * wk.tol
+    assert tr.max() <= wk.tol
     assert d <= 1e-6

@@ -13,6 +13,7 @@ from oracle import dirac as od
 from oracle import krylov as ok
 from oracle import pfe
 from tests.helpers import A_SCALE_BOUND, cuda, host, log, problem, rel
+from tests.test_gpu_solver import parity_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -68,15 +69,16 @@ def test_persistent_every_l_matches_oracle(l):
     wk, U, op, a, sig, w, b = problem("4x4x4x8")
     force = np.full(len(sig), 3)
     ref = ok.mshift_bicgstabl(lambda v: op.a_op(v, a), b[0], sig, w, l, wk.tol, 3, 1, force_iters=force)[0]
+    bound = parity_bound(op, a, b[0], sig, w, l, wk.tol, force, ref)
     ctx = ctx_for(wk, U)
-    allow = (msb.OK, msb.NOT_CONVERGED)
+    allow = (msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY)
     for pass_ in (1, 2):
         y0 = ctx.mshift_bicgstabl(cuda(b), a, sig, w, l, wk.tol, 3, pass_, force_iters=force, allow=allow)[0]
         y1 = ctx.mshift_bicgstabl(cuda(b), a, sig, w, l, wk.tol, 3, pass_, flags=msb.PERSISTENT,
                                   force_iters=force, allow=allow)[0]
         assert same(y0, y1), (l, pass_)
-        # l = 1 amplifies rounding (see the solver tests); l >= 2 stays at 1e-10
-        assert rel(host(y1)[0], ref) <= (1e-6 if l == 1 else 1e-10), (l, pass_)
+        log(f"  persistent l={l} pass {pass_}: y vs oracle {rel(host(y1)[0], ref):.2e} (bound {bound:.1e})")
+        assert rel(host(y1)[0], ref) <= bound, (l, pass_)
 
 
 def test_persistent_twelve_point_sources_production_lattice():
@@ -92,7 +94,7 @@ def test_persistent_twelve_point_sources_production_lattice():
     a = A_SCALE_BOUND
     force = np.full(len(sig), 2)
     ctx = ctx_for(wk, U)
-    allow = (msb.OK, msb.NOT_CONVERGED)
+    allow = (msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY)
     for flags in (0, msb.MIXED):
         for pass_ in (1, 2):
             y0 = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 4, wk.tol, 2, pass_, flags=flags, force_iters=force,

@@ -103,7 +103,7 @@ def test_true_residuals_meet_tolerance():
     for s in range(len(sig)):
         r = np.linalg.norm(b[0] - S(xs[s]) - sig[s] * xs[s]) / np.linalg.norm(b[0])
         assert abs(r - info.shift_true_resid[0, s]) <= 1e-6 * r + 1e-15
-        assert r <= 1.5 * wk.tol
+        assert r <= wk.tol
 
 
 def test_batched_rhs_with_separate_shift_sets():
@@ -231,7 +231,7 @@ def test_mixed_precision_against_fp64_oracle(name):
     y1, i1, xs = ctx.mshift_bicgstabl(cuda(b), a, sig, w, l, wk.tol, 3000, 1, flags=msb.MIXED,
                                       want_shifts=True, true_resid=True)
     y2, i2, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, l, wk.tol, 3000, 2, flags=msb.MIXED)
-    assert i1.reliable_updates > 0 and i1.status == 0 and i2.status == 0
+    assert i1.reliable_updates > 0 and i1.status == i2.status == msb.REDUCED_ACCURACY
     xs = host(xs)[0]
     s0 = int(np.argmin(sig))
     S = op.seed_op(a, 0.0)
@@ -262,7 +262,7 @@ def test_production_lattice_fixed_iterations():
     ctx = ctx_for(wk, U)
     for pass_ in (1, 2):
         y, info, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 2, wk.tol, 2, pass_, force_iters=force,
-                                          allow=(msb.OK, msb.NOT_CONVERGED))
+                                          allow=(msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY))
         assert rel(host(y)[0], ref) <= 1e-10, pass_
 
 
@@ -287,7 +287,7 @@ def test_mixed_precision_refined_meets_tolerance(name):
         for s_ in range(len(sig)):
             res = np.linalg.norm(bb[r] - op.a_op(xs[r, s_], a) - sig[s_] * xs[r, s_]) / nb
             worst = max(worst, res)
-            assert res <= wk.tol * 1.05, (r, s_, res)
+            assert res <= wk.tol, (r, s_, res)
             assert abs(res - info.shift_true_resid[r, s_]) <= 1e-3 * wk.tol + 1e-6 * res
     y_ref = oracle_run(op, a, bb[0], sig, w, l, wk.tol * 1e-2, 3000, 1)[0]
     err = rel(host(y)[0], y_ref)
@@ -317,7 +317,7 @@ def test_l8_every_form_matches_oracle():
     # l = 8 amplifies rounding: the oracle's own two passes differ by ~2e-10
     bound = parity_bound(op, a, b[0], sig, w, 8, wk.tol, force, y1)
     ctx = ctx_for(wk, U)
-    allow = (msb.OK, msb.NOT_CONVERGED)
+    allow = (msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY)
     for pass_, flags, ref in ((1, 0, y1), (1, msb.DEFERRED, y1), (2, 0, y2), (3, 0, y2)):
         y, info, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 8, wk.tol, 3, pass_, flags=flags, force_iters=force,
                                           allow=allow)

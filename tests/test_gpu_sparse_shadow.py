@@ -38,7 +38,7 @@ def test_sparse_shadow_matches_dense_path_and_oracle(pass_):
     rt = sparse_shadow(wk.dims, counts, 72)
     ctx = msb.Context(msb.Lattice(wk.dims, wk.mass, wk.mu, wk.bc_t), cuda(U))
     force = np.full(len(sig), 3)
-    allow = (msb.OK, msb.NOT_CONVERGED)
+    allow = (msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY)
     y0, i0, _ = ctx.mshift_bicgstabl(cuda(bb), a, sig, w, 2, wk.tol, 3, pass_, shadow=cuda(rt),
                                      force_iters=force, allow=allow)
     if pass_ != 3:
@@ -78,7 +78,7 @@ def test_unit_point_sources_bitwise_with_dense_path():
     wk, U, op, a, sig, w, b = problem("8x8x8x8")
     pts = wl.point_sources(wk.dims)
     force = np.full(len(sig), 3)
-    allow = (msb.OK, msb.NOT_CONVERGED)
+    allow = (msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY)
     ctx = msb.Context(msb.Lattice(wk.dims, wk.mass, wk.mu, wk.bc_t), cuda(U))
     for flags in (0, msb.MIXED):
         for pass_ in (1, 2):
@@ -128,7 +128,7 @@ def test_single_random_entry_bitwise_with_dense_path(precision):
     bb = wl.gaussian_source(wk.dims, 77, 3)
     rt = sparse_shadow(wk.dims, [1, 1, 1], 78)
     force = np.full(len(sig), 3)
-    allow = (msb.OK, msb.NOT_CONVERGED)
+    allow = (msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY)
     flags = msb.MIXED if precision == "mixed" else 0
     ctx = msb.Context(msb.Lattice(wk.dims, wk.mass, wk.mu, wk.bc_t), cuda(U))
     for pass_ in (1, 2):

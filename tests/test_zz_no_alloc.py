@@ -52,7 +52,7 @@ def test_noalloc_matches_allocating_entry_point(setup, pass_, flags_name):
         d = _max_rel(y1, y0)
         log(f"  M = {i1.outer_iters} (allocating: {i0.outer_iters}), y difference {d:.2e}, "
             f"bitwise {bool(torch.equal(y1, y0))}")
-        assert i1.status == i0.status == msb.OK
+        assert i1.status == i0.status == (msb.REDUCED_ACCURACY if flags & msb.MIXED else msb.OK)
         assert np.array_equal(i1.shift_iters, i0.shift_iters)
         assert i1.mv_count == i0.mv_count
         assert d <= 1e-12
