@@ -146,6 +146,48 @@ __device__ inline double block_sum(const double *p, int n) {
     return result;
 }
 
+// Up to NR sums at once: out[r] = the sum of p[rows[r] * stride + i] for
+// i < n (r < cnt), returned to every thread.  Each row is added in exactly
+// block_sum's order (per-thread strided partial sums, the same shuffle tree,
+// the four wavefront sums in order), so the results are bitwise block_sum's;
+// the rows share one pass over the block instead of one pass each.
+template <int NR>
+__device__ inline void block_sum_rows(const double *p, long stride, const int *rows, int cnt, int n,
+                                      double (&out)[NR]) {
+    __shared__ double sh[NR][BLOCK / 64];
+    __shared__ double res[NR];
+    double x[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) x[r] = 0.0;
+    for (int i = threadIdx.x; i < n; i += BLOCK) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            if (r < cnt) x[r] += p[(size_t)rows[r] * stride + i];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x[r] += __shfl_down(x[r], off, 64);
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) sh[r][wave] = x[r];
+    }
+    __syncthreads();
+    if (threadIdx.x < NR) {
+        const int r = threadIdx.x;
+        double s = sh[r][0];
+#pragma unroll
+        for (int w = 1; w < BLOCK / 64; ++w) s += sh[r][w];
+        res[r] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) out[r] = res[r];
+}
+
 // ---------------------------------------------------------------------------
 // Device-resident solver state (one per right-hand side) and the per-step
 // coefficient tables that the scalar kernels write and the vector kernels

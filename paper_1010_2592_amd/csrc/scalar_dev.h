@@ -19,6 +19,17 @@ __device__ inline const double *prow(const ScalarArgs &a, int rhs) {
     return a.part + (size_t)rhs * PMAX * a.ps;
 }
 
+// the sums of partial rows 0, 1, 2 (re, im of an inner product, a squared
+// norm) in one pass, bitwise those of three block_sum calls
+__device__ inline void sum3(const double *row, long ps, int n, double &s0, double &s1, double &s2) {
+    const int rows[3] = {0, 1, 2};
+    double o[3];
+    block_sum_rows<3>(row, ps, rows, 3, n, o);
+    s0 = o[0];
+    s1 = o[1];
+    s2 = o[2];
+}
+
 __device__ __forceinline__ void sc_init_body(const ScalarArgs &a, int rhs) {
     SeedState &S = a.seed[rhs];
     const double *row = prow(a, rhs);
@@ -71,9 +82,8 @@ __device__ __forceinline__ void sc_beta_body(const ScalarArgs &a, int rhs) {
     if (!S.run || !S.bicg_on) return;
     const int j = a.j;
     const double *row = prow(a, rhs);
-    const double re = block_sum(row, a.nblk);
-    const double im = block_sum(row + a.ps, a.nblk);
-    const double rj2 = block_sum(row + 2 * a.ps, a.nblk);
+    double re, im, rj2;
+    sum3(row, a.ps, a.nblk, re, im, rj2);
     double r02 = 0.0;
     if (j >= 1) r02 = block_sum(row + 3 * a.ps, a.nblk2);
     if (threadIdx.x != 0) return;
@@ -123,9 +133,8 @@ __device__ __forceinline__ void sc_alpha_body(const ScalarArgs &a, int rhs) {
     if (!S.run || !S.bicg_on) return;
     const int j = a.j;
     const double *row = prow(a, rhs);
-    const double re = block_sum(row, a.nblk);
-    const double im = block_sum(row + a.ps, a.nblk);
-    const double u2 = block_sum(row + 2 * a.ps, a.nblk);
+    double re, im, u2;
+    sum3(row, a.ps, a.nblk, re, im, u2);
     __shared__ int ok;
     __shared__ double2 sh_alpha, sh_beta;
     if (threadIdx.x == 0) {
@@ -231,18 +240,34 @@ __device__ __forceinline__ void sc_mr_body(const ScalarArgs &a, int rhs) {
         for (int ii = 0; ii < i; ++ii) p += l + 1 - ii;
         return p + (k - i);
     };
+    // the pairs (i, k) in the Gram kernel's order, 8 pairs (16 partial rows)
+    // per pass over the partials
+    constexpr int NB = 8;
+    int pi_[NB], pk_[NB], rows[2 * NB];
+    int cnt = 0;
     for (int i = 0; i <= L; ++i) {
         for (int k = (i == 0 ? 1 : i); k <= L; ++k) {
-            const int p = pidx(i, k);
-            const double re = block_sum(row + (2 * p) * a.ps, a.nblk);
-            const double im = block_sum(row + (2 * p + 1) * a.ps, a.nblk);
-            if (threadIdx.x == 0) {
-                if (i == 0) {
-                    cvec[k - 1] = d2(re, -im);   // <r_k, r_0> = conj(<r_0, r_k>)
-                } else {
-                    G[i - 1][k - 1] = d2(re, im);
-                    G[k - 1][i - 1] = d2(re, -im);
+            pi_[cnt] = i;
+            pk_[cnt] = k;
+            rows[2 * cnt] = 2 * pidx(i, k);
+            rows[2 * cnt + 1] = 2 * pidx(i, k) + 1;
+            ++cnt;
+            const bool last = i == L && k == L;
+            if (cnt == NB || last) {
+                double sums[2 * NB];
+                block_sum_rows<2 * NB>(row, a.ps, rows, 2 * cnt, a.nblk, sums);
+                if (threadIdx.x == 0) {
+                    for (int q = 0; q < cnt; ++q) {
+                        const double re = sums[2 * q], im = sums[2 * q + 1];
+                        if (pi_[q] == 0) {
+                            cvec[pk_[q] - 1] = d2(re, -im);   // <r_k, r_0> = conj(<r_0, r_k>)
+                        } else {
+                            G[pi_[q] - 1][pk_[q] - 1] = d2(re, im);
+                            G[pk_[q] - 1][pi_[q] - 1] = d2(re, -im);
+                        }
+                    }
                 }
+                cnt = 0;
             }
         }
     }
@@ -362,9 +387,8 @@ __device__ __forceinline__ void sc_conv_body(const ScalarArgs &a, int rhs) {
     SeedState &S = a.seed[rhs];
     if (!S.run) return;
     const double *row = prow(a, rhs);
-    const double re = block_sum(row, a.nblk);
-    const double im = block_sum(row + a.ps, a.nblk);
-    const double r02 = block_sum(row + 2 * a.ps, a.nblk);
+    double re, im, r02;
+    sum3(row, a.ps, a.nblk, re, im, r02);
     __shared__ double rn;
     if (threadIdx.x == 0) {
         rn = sqrt(r02);

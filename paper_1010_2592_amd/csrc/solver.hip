@@ -1372,14 +1372,16 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             }
             HIPCHK(hipGetLastError());
         }
-        if (m_rep < Mmax) {
+        // pass 2 always passes here: y = c_b b is set here even where no
+        // right-hand side iterated (Mmax = 0); pass 3 set it above
+        if (!pass3 || m_rep < Mmax) {
         // regenerate the Mv outputs of outer iterations m_rep.. and accumulate y
         if (m_rep == 0) {
             Prof p(c, CL_OTHER, nrhs * nd * (2.0 * (l + 1) * cB + 16.0 + cB + 32.0));
             launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
             launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
             launch_convert_in<T>(st, R, b, n, vs, n, nrhs);
-            launch_yinit(st, y, b, (const double2 *)c->ws_cb.p, n, nrhs, nbv);
+            if (!pass3) launch_yinit(st, y, b, (const double2 *)c->ws_cb.p, n, nrhs, nbv);
             if (mixed) launch_zero<double>(st, XH, (long)nrhs * n, 0, 1);
         } else {
             // the seed's state saved at the start of outer iteration m_rep
