@@ -473,6 +473,67 @@ def cpu_baseline(wk, a, sig, w, l, M_gpu, nproc=12, K=CPU_ITERS):
             {k: y for k, _, _, y in res})
 
 
+def shift_true_residuals(ctx, b, a, sig, xs):
+    """||b - (A + sigma_s) x_s|| / ||b|| per (rhs, shift) in FP64, with A
+    applied by wilson_apply."""
+    import numpy as np
+    import torch
+    from paper_1010_2592_amd import msb
+    bn = torch.linalg.vector_norm(b.reshape(b.shape[0], -1), dim=1)
+    tr = np.zeros((b.shape[0], len(sig)))
+    for s in range(len(sig)):
+        x = xs[:, s].contiguous()
+        t = ctx.wilson_apply(ctx.wilson_apply(x, msb.G5_LEFT), msb.G5_LEFT)
+        r = b - a * t - sig[s] * x
+        tr[:, s] = (torch.linalg.vector_norm(r.reshape(b.shape[0], -1), dim=1) / bn).cpu().numpy()
+        del x, t, r
+    return tr
+
+
+def mixed_floor_block(ctx, b, a, sig, w, l, tols=(1e-4, 1e-6, 1e-8)):
+    """Where mixed precision without refinement pays: for each tolerance, the
+    FP64 pseudo-double pass's time beside the mixed deferred single pass's
+    (one warm-up, median of VARIANT_REPS) and the mixed run's per-shift FP64
+    true residuals (an untimed run of the same form that keeps the x_s).  The
+    mixed run reaches tol only where its FP32 floor lies below it; the largest
+    tol it misses and the floor itself are the break-even figures."""
+    import numpy as np
+    import torch
+    from paper_1010_2592_amd import msb
+    allow = (msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY)
+    out = {}
+    for tol in tols:
+        row = {}
+        for name, pass_, flags in (("fp64-3pass", 3, 0), ("mixed-deferred", 1, msb.MIXED | msb.DEFERRED)):
+            ts = []
+            for rep in range(VARIANT_REPS + 1):
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                y, info, _ = ctx.mshift_bicgstabl(b, a, sig, w, l, tol, 2000, pass_, flags=flags, allow=allow)
+                e1.record()
+                torch.cuda.synchronize()
+                if rep:
+                    ts.append(e0.elapsed_time(e1))
+                del y
+            row[name] = {"ms": round(float(np.median(ts)), 2), "outer_iters": info.outer_iters,
+                         "status": info.status}
+        _, info, xs = ctx.mshift_bicgstabl(b, a, sig, w, l, tol, 2000, 1, flags=msb.MIXED | msb.DEFERRED,
+                                           want_shifts=True, allow=allow)
+        tr = shift_true_residuals(ctx, b, a, sig, xs)
+        del xs
+        torch.cuda.empty_cache()
+        row["mixed-deferred"].update({"max_true_resid": float(tr.max()),
+                                      "median_true_resid": float(np.median(tr)),
+                                      "worst_shift": int(np.unravel_index(np.argmax(tr), tr.shape)[1]),
+                                      "seed_true_resid_max": float(tr[:, 0].max()),
+                                      "meets_tol": bool(tr.max() <= tol)})
+        out[f"{tol:.0e}"] = row
+        log(f"[bench] mixed floor tol {tol:.0e}: {row}")
+    return out
+
+
 def true_residual_check(ctx, b, a, sig, w, l, tol, y_head):
     """Every shift's FP64 true residual ||b - (A + sigma_s) x_s|| / ||b|| for
     the 12-source batch, from the deferred single pass (which keeps the x_s and
@@ -484,14 +545,7 @@ def true_residual_check(ctx, b, a, sig, w, l, tol, y_head):
     from paper_1010_2592_amd import msb
     y1, info, xs = ctx.mshift_bicgstabl(b, a, sig, w, l, tol, 2000, 1, flags=msb.DEFERRED, want_shifts=True,
                                         allow=(msb.OK, msb.NOT_CONVERGED))
-    bn = torch.linalg.vector_norm(b.reshape(b.shape[0], -1), dim=1)
-    tr = np.zeros((b.shape[0], len(sig)))
-    for s in range(len(sig)):
-        x = xs[:, s].contiguous()
-        t = ctx.wilson_apply(ctx.wilson_apply(x, msb.G5_LEFT), msb.G5_LEFT)
-        r = b - a * t - sig[s] * x
-        tr[:, s] = (torch.linalg.vector_norm(r.reshape(b.shape[0], -1), dim=1) / bn).cpu().numpy()
-        del x, t, r
+    tr = shift_true_residuals(ctx, b, a, sig, xs)
     d = float(torch.linalg.vector_norm(y1 - y_head) / torch.linalg.vector_norm(y_head))
     out = {"max_true_resid": float(tr.max()), "max_shift_resid": float(np.max(info.shift_resid)),
            "freeze_threshold": 0.9 * tol, "pass1_vs_headline_y": d, "status": info.status}
@@ -516,6 +570,9 @@ def main():
                     help="one launch per stage, or the whole pass in one cooperative launch")
     ap.add_argument("--variants", default="all", choices=("all", "none"))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the true-residual check after the timed steps (profiler runs: its solves "
+                         "would be counted with the headline's)")
     ap.add_argument("--max-outer", type=int, default=2000)
     ap.add_argument("--block", default=None, choices=("mu0", "propagators", "deflation", "cfg4"),
                     help="run only this extra block on the headline inputs and print its JSON "
@@ -613,15 +670,20 @@ def main():
             log(f"[bench]   {k:16s} {v['count']:7d} launches {v['ms']:10.2f} ms {gbs:8.0f} GB/s")
 
     # ---- accuracy of the headline result (outside the timed region) ----
-    accuracy = true_residual_check(ctx, b, a, sig, w, l, wk.tol, y)
+    if args.no_accuracy:
+        accuracy = {"max_true_resid": None, "skipped": "--no-accuracy"}
+    else:
+        accuracy = true_residual_check(ctx, b, a, sig, w, l, wk.tol, y)
     accuracy["headline_shift_resid_max"] = float(np.max(info.shift_resid))
     log(f"[bench] accuracy: {accuracy}")
     # the headline form at CPU_ITERS forced outer iterations, for the oracle
     # comparison of the CPU leg
-    yK = ctx.mshift_bicgstabl(b, a, sig, w, l, wk.tol, CPU_ITERS, args.pass_,
-                              flags=solver_flags(mixed, persistent, refine, deferred),
-                              force_iters=np.full(len(sig), CPU_ITERS),
-                              allow=(msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY))[0].cpu().numpy()
+    yK = None
+    if not args.no_cpu:
+        yK = ctx.mshift_bicgstabl(b, a, sig, w, l, wk.tol, CPU_ITERS, args.pass_,
+                                  flags=solver_flags(mixed, persistent, refine, deferred),
+                                  force_iters=np.full(len(sig), CPU_ITERS),
+                                  allow=(msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY))[0].cpu().numpy()
 
     result = {
         "metric": METRIC,
@@ -709,6 +771,7 @@ def main():
             del yv
             torch.cuda.empty_cache()
         result["variants"] = comps
+        result["mixed_floor"] = mixed_floor_block(ctx, b, a, sig, w, l)
 
     ctx.close()
     torch.cuda.empty_cache()
