@@ -731,7 +731,7 @@ def main():
                  (2, True, False, False, False), (1, True, False, True, False),
                  (1, False, False, False, True), (1, True, False, False, True), (1, True, False, True, True),
                  (1, False, True, False, False), (2, False, True, False, False), (1, True, True, False, False),
-                 (2, True, True, False, False), (3, False, False, False, False), (3, True, False, False, False)]
+                 (1, True, True, True, False), (2, True, True, False, False), (3, False, False, False, False), (3, True, False, False, False)]
         for (p, mx, pe, rf, df) in forms:
             name = (f"{p}pass-{'mixed' if mx else 'fp64'}{'-refine' if rf else ''}{'-deferred' if df else ''}"
                     f"-{'persistent' if pe else 'stages'}")

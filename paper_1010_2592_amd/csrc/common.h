@@ -125,12 +125,32 @@ __device__ inline void wave_reduce_store(double (&v)[NV], double *out, long stri
     }
 }
 
+// Loads per row that the block sums below issue before their first add.  The
+// partials they read usually come from another XCD's writes, so each load is
+// a trip to memory, and one trip per add would serialise them.  A translation
+// unit may lower it before including this header (the persistent kernel,
+// whose register budget is the maximum over all its stages, sets 1); the
+// sums are the same bits for any value.
+#ifndef MSB_SUM_PREFETCH
+#define MSB_SUM_PREFETCH 8
+#endif
+
 // Sum of p[0..n) by all BLOCK threads of one block, returned to every thread.
+// Each thread adds p[t], p[t + BLOCK], ... in that order.
 __device__ inline double block_sum(const double *p, int n) {
     __shared__ double sh[BLOCK / 64];
     __shared__ double result;
+    constexpr int U = MSB_SUM_PREFETCH;
     double x = 0.0;
-    for (int i = threadIdx.x; i < n; i += BLOCK) x += p[i];
+    int i = threadIdx.x;
+    for (; i + (U - 1) * BLOCK < n; i += U * BLOCK) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = p[i + u * BLOCK];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x += v[u];
+    }
+    for (; i < n; i += BLOCK) x += p[i];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
@@ -156,13 +176,30 @@ __device__ inline void block_sum_rows(const double *p, long stride, const int *r
                                       double (&out)[NR]) {
     __shared__ double sh[NR][BLOCK / 64];
     __shared__ double res[NR];
+    constexpr int U = NR <= 4 ? MSB_SUM_PREFETCH : (MSB_SUM_PREFETCH + 1) / 2;   // loads per row in flight
     double x[NR];
+    const double *pr[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) x[r] = 0.0;
-    for (int i = threadIdx.x; i < n; i += BLOCK) {
+    for (int r = 0; r < NR; ++r) {
+        x[r] = 0.0;
+        pr[r] = p + (size_t)rows[r < cnt ? r : 0] * stride;
+    }
+    int i = threadIdx.x;
+    for (; i + (U - 1) * BLOCK < n; i += U * BLOCK) {
+        double v[NR][U];
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-            if (r < cnt) x[r] += p[(size_t)rows[r] * stride + i];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[r][u] = r < cnt ? pr[r][i + u * BLOCK] : 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[r] += v[r][u];
+    }
+    for (; i < n; i += BLOCK) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            if (r < cnt) x[r] += pr[r][i];
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll

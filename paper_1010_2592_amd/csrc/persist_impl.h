@@ -25,6 +25,9 @@
 // than a flat one.  The launch is cooperative, so every block is resident and
 // each wait ends; a wait that still exceeds its bound raises the abort flag,
 // which every waiting block sees and leaves on, so no wave stays behind.
+// one load per partial in flight in the block sums: this kernel's register
+// budget is the maximum over all its stages (the sums are the same bits)
+#define MSB_SUM_PREFETCH 1
 #include "barrier_tree.h"
 #include "blas_dev.h"
 #include "scalar_dev.h"

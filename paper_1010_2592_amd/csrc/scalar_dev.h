@@ -232,6 +232,11 @@ __device__ __forceinline__ void sc_mr_body(const ScalarArgs &a, int rhs) {
     __shared__ double2 G[LMAX][LMAX];
     __shared__ double2 cvec[LMAX];
     __shared__ double2 g[LMAX];
+    // the Cholesky factor and the forward-substitution vector, used by
+    // thread 0 alone: in LDS, since indexed at run time they would otherwise
+    // live in scratch memory, whose dependent accesses dominated the kernel
+    __shared__ double2 Lm[LMAX][LMAX];
+    __shared__ double2 zz[LMAX];
     __shared__ int lmr_sh;
     const double *row = prow(a, rhs);
     // pair index of (i, k), i <= k, in the gram kernel's order over 0..l
@@ -240,9 +245,10 @@ __device__ __forceinline__ void sc_mr_body(const ScalarArgs &a, int rhs) {
         for (int ii = 0; ii < i; ++ii) p += l + 1 - ii;
         return p + (k - i);
     };
-    // the pairs (i, k) in the Gram kernel's order, 8 pairs (16 partial rows)
-    // per pass over the partials
-    constexpr int NB = 8;
+    // the pairs (i, k) in the Gram kernel's order, 4 pairs (8 partial rows)
+    // per pass over the partials (more would cost the persistent kernel, which
+    // inlines this body, an occupancy step)
+    constexpr int NB = 4;
     int pi_[NB], pk_[NB], rows[2 * NB];
     int cnt = 0;
     for (int i = 0; i <= L; ++i) {
@@ -273,7 +279,6 @@ __device__ __forceinline__ void sc_mr_body(const ScalarArgs &a, int rhs) {
     }
     if (threadIdx.x == 0) {
         int n = L;
-        double2 Lm[LMAX][LMAX];
         int kok = n;
         if (n > 0) {
             double dmax = 0.0;
@@ -295,7 +300,6 @@ __device__ __forceinline__ void sc_mr_body(const ScalarArgs &a, int rhs) {
             }
         }
         n = kok;
-        double2 zz[LMAX];
         for (int i = 0; i < n; ++i) {
             double2 acc = cvec[i];
             for (int p = 0; p < i; ++p) acc = csub(acc, cmul(Lm[i][p], zz[p]));

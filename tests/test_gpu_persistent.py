@@ -130,3 +130,29 @@ def test_persistent_timing_hook_reports_stage_classes():
     # first pass and again in the replay
     assert st["count"] == 2 * 4 * 4 * info.outer_iters
     assert st["ms"] > 0 and st["bytes"] > 0
+
+
+def test_persistent_mixed_refined_meets_tolerance():
+    """Complex64 compute with FP64 reductions, the single pass in one
+    cooperative launch, then FP64 correction solves for the shifts whose
+    FP64 residual the FP32 vectors left above tol: the main solve is
+    bitwise the per-stage one, and every shift of every source ends at a
+    true residual <= tol (recomputed here with the oracle's operator)."""
+    from paper_1010_2592_amd import msb
+    wk, U, op, a, sig, w, b = problem("8x8x8x8")
+    bb = wl.gaussian_source(wk.dims, 97, 3)
+    ctx = ctx_for(wk, U)
+    flags = msb.MIXED | msb.REFINE
+    y0, i0, x0 = ctx.mshift_bicgstabl(cuda(bb), a, sig, w, 4, wk.tol, 3000, 1, flags=flags, want_shifts=True)
+    y1, i1, x1 = ctx.mshift_bicgstabl(cuda(bb), a, sig, w, 4, wk.tol, 3000, 1, flags=flags | msb.PERSISTENT,
+                                      want_shifts=True)
+    assert i1.status == msb.OK and i1.refined_shifts > 0
+    assert same(y0, y1) and same(x0, x1)
+    xs = host(x1)
+    worst = 0.0
+    for r in range(3):
+        nb = np.linalg.norm(bb[r])
+        for s in range(len(sig)):
+            worst = max(worst, np.linalg.norm(bb[r] - op.a_op(xs[r, s], a) - sig[s] * xs[r, s]) / nb)
+    log(f"  persistent mixed + refine: worst true residual {worst:.2e}, refined {i1.refined_shifts}")
+    assert worst <= wk.tol
