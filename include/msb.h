@@ -169,6 +169,12 @@ int msb_set_store_limit(msb_ctx *ctx, unsigned long long bytes);
  * recording.  Synchronises the stream. */
 int msb_profile_enable(msb_ctx *ctx, int enable);
 
+/* Which kernel classes msb_profile_enable records: bit k of mask for class k
+ * (the classes of msb_profile_read; all of them on a new context).  The
+ * events themselves take time on the stream, so a measurement of one class
+ * records that class alone.  Synchronises the stream. */
+int msb_profile_classes(msb_ctx *ctx, unsigned mask);
+
 /* Totals of the recorded launches per kernel class k < n_classes (host arrays
  * of n_classes): count[k] launches, ms[k] summed event time, bytes[k] summed
  * algorithmic HBM bytes (every operand of a launch read or written once).

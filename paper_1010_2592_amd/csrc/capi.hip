@@ -199,6 +199,11 @@ int msb_profile_enable(msb_ctx *ctx, int enable) {
     return msb::profile_enable(&ctx->c, enable != 0);
 }
 
+int msb_profile_classes(msb_ctx *ctx, unsigned mask) {
+    if (!ctx) return arg_error("msb_profile_classes: null context");
+    return msb::profile_classes(&ctx->c, mask);
+}
+
 int msb_profile_read(msb_ctx *ctx, int n_classes, long long *count, double *ms, double *bytes) {
     if (!ctx || !count || !ms || !bytes || n_classes < 1) return arg_error("msb_profile_read: bad argument");
     return msb::profile_read(&ctx->c, n_classes, count, ms, bytes);

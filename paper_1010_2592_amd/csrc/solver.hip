@@ -121,7 +121,7 @@ static hipEvent_t pool_get(Ctx *c) {
 
 Prof::Prof(Ctx *c_, int cls_, double bytes_) : c(c_), cls(cls_), bytes(bytes_) {
     c->bytes_acc += bytes;
-    if (c->prof) {
+    if (c->prof && cls >= 0 && cls < 32 && ((c->prof_mask >> cls) & 1u)) {
         e0 = pool_get(c);
         if (e0) (void)hipEventRecord(e0, c->stream);
     }
@@ -143,6 +143,12 @@ int profile_enable(Ctx *c, bool on) {
     c->recs.clear();
     c->srecs.clear();
     c->ev_used = 0;
+    return 0;
+}
+
+int profile_classes(Ctx *c, unsigned mask) {
+    HIPCHK(c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+    c->prof_mask = mask;
     return 0;
 }
 

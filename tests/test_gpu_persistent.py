@@ -156,3 +156,23 @@ def test_persistent_mixed_refined_meets_tolerance():
             worst = max(worst, np.linalg.norm(bb[r] - op.a_op(xs[r, s], a) - sig[s] * xs[r, s]) / nb)
     log(f"  persistent mixed + refine: worst true residual {worst:.2e}, refined {i1.refined_shifts}")
     assert worst <= wk.tol
+
+
+def test_timing_hook_class_mask():
+    """msb_profile_classes: with the stencil class alone selected, only the
+    stencil launches are recorded (4 per BiCG step: two Mv of two stencils),
+    every other class stays empty; the default records them all."""
+    from paper_1010_2592_amd import msb
+    wk, U, op, a, sig, w, b = problem("8x8x8x8")
+    ctx = ctx_for(wk, U)
+    ctx.profile_enable(True, classes=("stencil",))
+    _, info, _ = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 4, wk.tol, 2000, 3)
+    prof = ctx.profile_read()
+    assert prof["stencil"]["count"] == 4 * 4 * info.outer_iters
+    assert all(v["count"] == 0 for k, v in prof.items() if k != "stencil")
+    ctx.profile_enable(True)
+    ctx.mshift_bicgstabl(cuda(b), a, sig, w, 4, wk.tol, 2000, 3)
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    assert prof["stencil"]["count"] == 4 * 4 * info.outer_iters
+    assert prof["seed_vector"]["count"] > 0 and prof["scalar"]["count"] > 0
