@@ -169,11 +169,15 @@ int msb_set_store_limit(msb_ctx *ctx, unsigned long long bytes);
  * recording.  Synchronises the stream. */
 int msb_profile_enable(msb_ctx *ctx, int enable);
 
-/* Which kernel classes msb_profile_enable records: bit k of mask for class k
- * (the classes of msb_profile_read; all of them on a new context).  The
- * events themselves take time on the stream, so a measurement of one class
- * records that class alone.  Synchronises the stream. */
-int msb_profile_classes(msb_ctx *ctx, unsigned mask);
+/* Which launches msb_profile_enable records: those of the kernel classes
+ * whose bit k is set in mask (the classes of msb_profile_read), and of those
+ * every stride-th one (stride >= 1, counted over the selected launches from
+ * this call on); all classes, stride 1 on a new context.  The events take
+ * time on the stream (stencil launches carry theirs in the dispatch, about
+ * 8 us each), so a measurement of one kernel's average records that class
+ * alone, sampled with a stride coprime to its launch pattern.  Synchronises
+ * the stream.  MSB_ERR_ARG for stride < 1. */
+int msb_profile_classes(msb_ctx *ctx, unsigned mask, int stride);
 
 /* Totals of the recorded launches per kernel class k < n_classes (host arrays
  * of n_classes): count[k] launches, ms[k] summed event time, bytes[k] summed

@@ -199,9 +199,10 @@ int msb_profile_enable(msb_ctx *ctx, int enable) {
     return msb::profile_enable(&ctx->c, enable != 0);
 }
 
-int msb_profile_classes(msb_ctx *ctx, unsigned mask) {
+int msb_profile_classes(msb_ctx *ctx, unsigned mask, int stride) {
     if (!ctx) return arg_error("msb_profile_classes: null context");
-    return msb::profile_classes(&ctx->c, mask);
+    if (stride < 1) return arg_error("msb_profile_classes: stride must be >= 1");
+    return msb::profile_classes(&ctx->c, mask, stride);
 }
 
 int msb_profile_read(msb_ctx *ctx, int n_classes, long long *count, double *ms, double *bytes) {

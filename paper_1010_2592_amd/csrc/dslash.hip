@@ -26,6 +26,8 @@
 // Which operands exist is a compile-time property of the mode: run-time null
 // checks inside the unrolled epilogue made the compiler keep every epilogue
 // load live at once and spill.
+#include <hip/hip_ext.h>
+
 #include "stencil_dev.h"
 
 namespace msb {
@@ -157,11 +159,41 @@ __global__ __launch_bounds__(BLOCK) void link_force_kernel(LinkForceArgs a) {
 
 }  // namespace
 
+namespace {
+thread_local hipEvent_t t_start = nullptr, t_stop = nullptr;
+thread_local bool t_taken = false;
+
+// one stencil dispatch, with the armed timing events if any
+template <typename T>
+void dispatch(void (*kernel)(DslashArgs<T>), dim3 grid, dim3 block, hipStream_t st, const DslashArgs<T> &a) {
+    if (t_start) {
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, t_start, t_stop, 0, a);
+        t_start = t_stop = nullptr;
+        t_taken = true;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, a);
+    }
+}
+}  // namespace
+
+void stencil_timing_arm(hipEvent_t start, hipEvent_t stop) {
+    t_start = start;
+    t_stop = stop;
+    t_taken = false;
+}
+
+bool stencil_timing_taken() {
+    const bool k = t_taken;
+    t_start = t_stop = nullptr;
+    t_taken = false;
+    return k;
+}
+
 template <typename T>
 void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in) {
     if (nrhs >= CHUNK_MIN_RHS) {
         dim3 grid((unsigned)dslash_chunk_prepare(a, nrhs)), block(64 * chunk_waves<T>());
-#define MSB_DS(E, G5) hipLaunchKernelGGL((dslash_chunk_kernel<T, E, G5>), grid, block, 0, st, a)
+#define MSB_DS(E, G5) dispatch<T>(dslash_chunk_kernel<T, E, G5>, grid, block, st, a)
         if (g5in) {
             if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, true);
             else if (epi == EPI_MV) MSB_DS(EPI_MV, true);
@@ -181,7 +213,7 @@ void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in
         return;
     }
     dim3 grid((unsigned)dslash_prepare(a, nrhs)), block(BLOCK);
-#define MSB_DS(E, G5) hipLaunchKernelGGL((dslash_kernel<T, E, G5>), grid, block, 0, st, a)
+#define MSB_DS(E, G5) dispatch<T>(dslash_kernel<T, E, G5>, grid, block, st, a)
     if (g5in) {
         if (epi == EPI_PLAIN) MSB_DS(EPI_PLAIN, true);
         else if (epi == EPI_MV) MSB_DS(EPI_MV, true);

@@ -54,6 +54,12 @@ struct DslashArgs {
 // and nrhs.
 template <typename T>
 void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in);
+// Timing of the next launch_dslash on this host thread: its kernel is
+// dispatched with start and stop events that the dispatch itself records
+// (no event packets of their own on the stream around it).  stencil_timing_
+// taken() reports, and clears, whether a launch consumed the pair.
+void stencil_timing_arm(hipEvent_t start, hipEvent_t stop);
+bool stencil_timing_taken();
 
 // Launch geometry of the site-block stencil: sets nsb, nrhs, per and sstride
 // and returns the number of (virtual) blocks, 8 per, so that block p runs on

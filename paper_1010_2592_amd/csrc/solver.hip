@@ -121,18 +121,32 @@ static hipEvent_t pool_get(Ctx *c) {
 
 Prof::Prof(Ctx *c_, int cls_, double bytes_) : c(c_), cls(cls_), bytes(bytes_) {
     c->bytes_acc += bytes;
-    if (c->prof && cls >= 0 && cls < 32 && ((c->prof_mask >> cls) & 1u)) {
+    if (c->prof && cls >= 0 && cls < 32 && ((c->prof_mask >> cls) & 1u) && c->prof_seq++ % c->prof_stride == 0) {
         e0 = pool_get(c);
-        if (e0) (void)hipEventRecord(e0, c->stream);
+        if (cls == CL_STENCIL) {
+            // every stencil-class scope holds one launch_dslash: its dispatch
+            // records the pair itself
+            e1 = e0 ? pool_get(c) : nullptr;
+            if (e1) {
+                stencil_timing_arm(e0, e1);
+                armed = true;
+            }
+        } else if (e0) {
+            (void)hipEventRecord(e0, c->stream);
+        }
     }
 }
 
 Prof::~Prof() {
+    if (armed) {
+        if (stencil_timing_taken()) c->recs.push_back(Ctx::Rec{cls, bytes, e0, e1});
+        return;
+    }
     if (c->prof && e0) {
-        hipEvent_t e1 = pool_get(c);
-        if (e1) {
-            (void)hipEventRecord(e1, c->stream);
-            c->recs.push_back(Ctx::Rec{cls, bytes, e0, e1});
+        hipEvent_t e1b = pool_get(c);
+        if (e1b) {
+            (void)hipEventRecord(e1b, c->stream);
+            c->recs.push_back(Ctx::Rec{cls, bytes, e0, e1b});
         }
     }
 }
@@ -146,9 +160,11 @@ int profile_enable(Ctx *c, bool on) {
     return 0;
 }
 
-int profile_classes(Ctx *c, unsigned mask) {
+int profile_classes(Ctx *c, unsigned mask, int stride) {
     HIPCHK(c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
     c->prof_mask = mask;
+    c->prof_stride = stride;
+    c->prof_seq = 0;
     return 0;
 }
 

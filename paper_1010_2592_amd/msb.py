@@ -104,7 +104,7 @@ def lib():
                                         _P, _DP, _DP, _P, ctypes.POINTER(_Info)]
         L.msb_set_store_limit.argtypes = [_P, ctypes.c_ulonglong]
         L.msb_profile_enable.argtypes = [_P, _I]
-        L.msb_profile_classes.argtypes = [_P, ctypes.c_uint]
+        L.msb_profile_classes.argtypes = [_P, ctypes.c_uint, _I]
         L.msb_profile_read.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_longlong), _DP, _DP]
         for f in ("msb_create", "msb_set_stream", "msb_neuberger_pfe", "msb_spectral_radius",
                   "msb_set_store_limit", "msb_profile_enable", "msb_profile_classes", "msb_profile_read",
@@ -214,16 +214,17 @@ class Context:
     # -- kernel timing ------------------------------------------------------
     PROFILE_CLASSES = ("stencil", "shift_update", "shift_mr_update", "seed_vector", "scalar", "other")
 
-    def profile_enable(self, on: bool = True, classes=None):
+    def profile_enable(self, on: bool = True, classes=None, stride: int = 1):
         """Record kernel timings from now on (on=False stops); classes: the
-        names of PROFILE_CLASSES to record, None for all."""
+        names of PROFILE_CLASSES to record, None for all; stride: every
+        stride-th of those launches."""
         self._sync_stream()
         mask = 0xFFFFFFFF
         if classes is not None:
             mask = 0
             for k in classes:
                 mask |= 1 << self.PROFILE_CLASSES.index(k)
-        _check(lib().msb_profile_classes(self._h, mask))
+        _check(lib().msb_profile_classes(self._h, mask, int(stride)))
         _check(lib().msb_profile_enable(self._h, 1 if on else 0))
 
     def profile_read(self):

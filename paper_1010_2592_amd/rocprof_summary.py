@@ -174,7 +174,8 @@ def main():
               f"it is not part of a step; warm-up and timed steps): {len(st)} launches, average "
               f"{st_avg_us:.1f} us.  "
               f"bench.py's live HIP-event figure over its timed steps in the same run: "
-              f"{roof['avg_launch_us']:.1f} us over {roof['launches']} launches "
+              f"{roof['avg_launch_us']:.1f} us over {roof.get('launches_sampled', roof.get('launches'))} "
+              f"launches (every {roof.get('sample_stride', 1)}th stencil launch of those steps) "
               f"({100 * abs(roof['avg_launch_us'] - st_avg_us) / st_avg_us:.1f} % apart).\n")
     md.append("## HBM traffic (rocprofv3 --pmc, one counter per run)\n\nCommands:\n")
     md.append(f"    {a.cmd_fetch}\n    {a.cmd_write}\n")

@@ -161,7 +161,8 @@ def test_persistent_mixed_refined_meets_tolerance():
 def test_timing_hook_class_mask():
     """msb_profile_classes: with the stencil class alone selected, only the
     stencil launches are recorded (4 per BiCG step: two Mv of two stencils),
-    every other class stays empty; the default records them all."""
+    every other class stays empty; the default records them all; a stride
+    records every stride-th selected launch."""
     from paper_1010_2592_amd import msb
     wk, U, op, a, sig, w, b = problem("8x8x8x8")
     ctx = ctx_for(wk, U)
@@ -176,3 +177,13 @@ def test_timing_hook_class_mask():
     ctx.profile_enable(False)
     assert prof["stencil"]["count"] == 4 * 4 * info.outer_iters
     assert prof["seed_vector"]["count"] > 0 and prof["scalar"]["count"] > 0
+    # every third stencil launch: the first, the fourth, ...
+    ctx.profile_enable(True, classes=("stencil",), stride=3)
+    ctx.mshift_bicgstabl(cuda(b), a, sig, w, 4, wk.tol, 2000, 3)
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    assert prof["stencil"]["count"] == (4 * 4 * info.outer_iters + 2) // 3
+    assert prof["stencil"]["ms"] > 0
+    with pytest.raises(msb.MsbError) as e:
+        ctx.profile_enable(True, stride=0)
+    assert e.value.status == msb.ERR_ARG
