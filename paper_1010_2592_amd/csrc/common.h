@@ -16,6 +16,7 @@ constexpr int LMAX = 8;          // largest MR degree l
 constexpr int NSMAX = 64;        // largest number of shifts per right-hand side
 constexpr int BLOCK = 256;       // threads per block of every vector kernel
 constexpr int NBMAX = 2048;      // largest number of blocks per RHS in a reduction
+constexpr int GRAM_NBMAX = 512;  // blocks per RHS of the MR Gram matrix pass
 constexpr int PMAX = 2 * (LMAX + 1) * (LMAX + 2) / 2;  // doubles per partial row
 constexpr double BREAK_REL = 1e-14;
 constexpr double CHOL_REL = 1e-14;
@@ -136,21 +137,21 @@ __device__ inline void wave_reduce_store(double (&v)[NV], double *out, long stri
 #endif
 
 // Sum of p[0..n) by all BLOCK threads of one block, returned to every thread.
-// Each thread adds p[t], p[t + BLOCK], ... in that order.
+// Each thread adds p[t], p[t + BLOCK], ... in that order; a group of loads
+// that runs past n adds +0.0 in their place, which leaves the sum's bits
+// alone (the sum starts at +0.0 and round-to-nearest never makes it -0.0).
 __device__ inline double block_sum(const double *p, int n) {
     __shared__ double sh[BLOCK / 64];
     __shared__ double result;
     constexpr int U = MSB_SUM_PREFETCH;
     double x = 0.0;
-    int i = threadIdx.x;
-    for (; i + (U - 1) * BLOCK < n; i += U * BLOCK) {
+    for (int i = threadIdx.x; i < n; i += U * BLOCK) {
         double v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = p[i + u * BLOCK];
+        for (int u = 0; u < U; ++u) v[u] = i + u * BLOCK < n ? p[i + u * BLOCK] : 0.0;
 #pragma unroll
         for (int u = 0; u < U; ++u) x += v[u];
     }
-    for (; i < n; i += BLOCK) x += p[i];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
@@ -184,22 +185,16 @@ __device__ inline void block_sum_rows(const double *p, long stride, const int *r
         x[r] = 0.0;
         pr[r] = p + (size_t)rows[r < cnt ? r : 0] * stride;
     }
-    int i = threadIdx.x;
-    for (; i + (U - 1) * BLOCK < n; i += U * BLOCK) {
+    for (int i = threadIdx.x; i < n; i += U * BLOCK) {
         double v[NR][U];
 #pragma unroll
         for (int r = 0; r < NR; ++r)
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[r][u] = r < cnt ? pr[r][i + u * BLOCK] : 0.0;
+            for (int u = 0; u < U; ++u) v[r][u] = (r < cnt && i + u * BLOCK < n) ? pr[r][i + u * BLOCK] : 0.0;
 #pragma unroll
         for (int r = 0; r < NR; ++r)
 #pragma unroll
             for (int u = 0; u < U; ++u) x[r] += v[r][u];
-    }
-    for (; i < n; i += BLOCK) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-            if (r < cnt) x[r] += pr[r][i];
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll

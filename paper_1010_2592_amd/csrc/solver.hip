@@ -1205,9 +1205,14 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             v.st_base = slot(0);
             v.st_rs = store_rs;
         }
-        e.gram(v, nrhs, nbv, CL_SEED, nr_run * (l + 1.0) * nd * cB);
-        s.nblk = nbv;
+        // the Gram matrix: (l+1)(l+2) partial sums per block, so fewer,
+        // longer blocks than the other seed kernels (their reduction and
+        // scattered partial stores would otherwise dominate the pass)
+        const int nbg = std::min(nbv, GRAM_NBMAX);
+        e.gram(v, nrhs, nbg, CL_SEED, nr_run * (l + 1.0) * nd * cB);
+        s.nblk = nbg;
         e.scalar(OP_SC_MR, s, nrhs);
+        s.nblk = nbv;   // the stages below read the MR update's nbv partials
         v.partials = 1;
         // seed: read r_0..r_l, u_0..u_l, rt, write r_0, u_0; shift s: read
         // u^s_0..u^s_l, x^s, write u^s_0, x^s
