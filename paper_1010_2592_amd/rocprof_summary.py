@@ -76,6 +76,14 @@ def counter_values(db, counter):
                        "order by dispatch_id", (counter,)).fetchall()
 
 
+def solve_dispatches(rows):
+    """Counter rows of the solves: dispatches after the first solve begins
+    (its sc_init kernel), as for the trace; the spectral-radius estimate's
+    single-source stencils before it would dilute the per-launch average."""
+    t0 = min((d for n, d, v in rows if "sc_init" in n), default=-1)
+    return [(n, d, v) for n, d, v in rows if d > t0]
+
+
 def scale(rows):
     """Counter units per byte from the 1 GiB copies (the three largest copy dispatches)."""
     copies = sorted((v for n, d, v in rows if "copyBuffer" in n), reverse=True)[:3]
@@ -149,8 +157,8 @@ def main():
     fr = counter_values(a.fetch, "FETCH_SIZE")
     wr = counter_values(a.write, "WRITE_SIZE")
     fs, ws = scale(fr), scale(wr)
-    f_st = [v for n, d, v in fr if is_stencil(n)]
-    w_st = [v for n, d, v in wr if is_stencil(n)]
+    f_st = [v for n, d, v in solve_dispatches(fr) if is_stencil(n)]
+    w_st = [v for n, d, v in solve_dispatches(wr) if is_stencil(n)]
     fetch_b = sum(f_st) / len(f_st) * fs * 1024.0
     write_b = sum(w_st) / len(w_st) * ws * 1024.0
     traffic = fetch_b + write_b
@@ -188,7 +196,8 @@ def main():
     md.append(f"| algorithmic (bench.py model) | {alg / 1e6:.1f} MB |")
     md.append(f"| traffic / algorithmic | {traffic / alg:.2f} |\n")
     md.append(f"Roofline of the timed steps: {roof['achieved']:.0f} GB/s algorithmic of {roof['peak']:.0f} "
-              f"GB/s ({100 * roof['frac']:.1f} %); {len(f_st)} / {len(w_st)} stencil dispatches counted.\n")
+              f"GB/s ({100 * roof['frac']:.1f} %); {len(f_st)} / {len(w_st)} stencil dispatches of the solves "
+              f"counted (from the first solve's sc_init on, as in the trace table).\n")
     os.makedirs(os.path.dirname(os.path.abspath(a.md)), exist_ok=True)
     with open(a.md, "w") as f:
         f.write("\n".join(md))
