@@ -6,16 +6,22 @@
 writes the kernel table of one kernel-trace run (any bench.py command).  The
 form below is the stencil's: trace, counters and the traffic record.
 
-    python -m paper_1010_2592_amd.rocprof_summary --trace T.db --fetch F.db --write W.db \
+    python -m paper_1010_2592_amd.rocprof_summary --trace T.db --miss M.db --write W.db \
         --bench-json B.json --workload "16x16x16x32 12 rhs mixed pass 1 refine" \
         --md profiles/X.md --json profiles/dslash_traffic.json --cmd-trace "..." --cmd-fetch "..." --cmd-write "..."
 
 Inputs are the rocpd databases rocprofv3 writes (-d DIR -o NAME gives
 DIR/NAME_results.db) of three runs of the same bench command: a kernel trace
-with --stats, a FETCH_SIZE counter run and a WRITE_SIZE counter run (each
-counter in a run of its own).  The counter runs include bench.py
---calibrate-copy: three copies of a 1 GiB tensor, whose counter readings give
-the factor from counter units to bytes (1048576 KiB read and written).
+with --stats, a TCC_MISS_sum counter run (or FETCH_SIZE, --fetch) and a
+WRITE_SIZE counter run (each counter in a run of its own).  Bytes read from
+beyond L2 are 64 x TCC_MISS: the L2 counts its misses in 64-byte sectors
+and the memory requests of a miss fetch exactly those sectors (128-byte
+requests for two, 64-byte for one).  FETCH_SIZE's expression takes 128-byte
+requests from TCC_BUBBLE, which reads zero on this part, and so counts them
+as 64 bytes: a factor that a copy (all 128-byte requests) calibrates to 2
+but that overstates a kernel issuing 64-byte requests too.  The counter runs
+include bench.py --calibrate-copy: three copies of a 1 GiB tensor, which
+check each reading (1048576 KiB read and written) and give its factor.
 
 Outputs: a markdown summary (kernel table, stencil launch statistics, HBM
 bytes per stencil launch against the algorithmic bytes) and the JSON record
@@ -137,7 +143,8 @@ def main():
         return trace_main(sys.argv[2:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--fetch", default=None, help="FETCH_SIZE run (older records)")
+    ap.add_argument("--miss", default=None, help="TCC_MISS_sum run")
     ap.add_argument("--write", required=True)
     ap.add_argument("--bench-json", required=True, help="bench.py output line of the trace run")
     ap.add_argument("--workload", required=True)
@@ -154,7 +161,13 @@ def main():
     tot = sum(r[3] for r in rows)
     st = stencil_launches(a.trace)
     st_avg_us = sum(d for _, d in st) / len(st) / 1e3
-    fr = counter_values(a.fetch, "FETCH_SIZE")
+    if a.miss:
+        # 64-byte sectors; the copy check gives its factor in KiB units
+        fr = [(n, d, v * 64.0 / 1024.0) for n, d, v in counter_values(a.miss, "TCC_MISS_sum")]
+        read_name = "64 B x TCC_MISS_sum"
+    else:
+        fr = counter_values(a.fetch, "FETCH_SIZE")
+        read_name = "FETCH_SIZE"
     wr = counter_values(a.write, "WRITE_SIZE")
     fs, ws = scale(fr), scale(wr)
     f_st = [v for n, d, v in solve_dispatches(fr) if is_stencil(n)]
@@ -185,12 +198,12 @@ def main():
               f"{roof['avg_launch_us']:.1f} us over {roof.get('launches_sampled', roof.get('launches'))} "
               f"launches (every {roof.get('sample_stride', 1)}th stencil launch of those steps) "
               f"({100 * abs(roof['avg_launch_us'] - st_avg_us) / st_avg_us:.1f} % apart).\n")
-    md.append("## HBM traffic (rocprofv3 --pmc, one counter per run)\n\nCommands:\n")
+    md.append("## Traffic beyond L2 (rocprofv3 --pmc, one counter per run)\n\nCommands:\n")
     md.append(f"    {a.cmd_fetch}\n    {a.cmd_write}\n")
-    md.append(f"Calibration (1 GiB copy, 1048576 KiB read and written): FETCH_SIZE x{fs:.3f}, "
+    md.append(f"Check (1 GiB copy, 1048576 KiB read and written): {read_name} x{fs:.3f}, "
               f"WRITE_SIZE x{ws:.3f}.\n")
     md.append("| per stencil launch | bytes |\n|---|---|")
-    md.append(f"| FETCH_SIZE (scaled) | {fetch_b / 1e6:.1f} MB |")
+    md.append(f"| read ({read_name}, scaled) | {fetch_b / 1e6:.1f} MB |")
     md.append(f"| WRITE_SIZE (scaled) | {write_b / 1e6:.1f} MB |")
     md.append(f"| traffic | {traffic / 1e6:.1f} MB |")
     md.append(f"| algorithmic (bench.py model) | {alg / 1e6:.1f} MB |")
@@ -204,7 +217,8 @@ def main():
     rec = {"kernel": "Wilson stencil (dslash_kernel and dslash_chunk_kernel, all epilogues and precisions)",
            "sources": STENCIL_SOURCES, "sources_sha256_16": sources_hash(),
            "workload": a.workload, "traffic_bytes_per_launch": round(traffic),
-           "fetch_scale": fs, "write_scale": ws, "algorithmic_bytes_per_launch": alg,
+           "read_counter": read_name, "read_scale": fs, "write_scale": ws,
+           "algorithmic_bytes_per_launch": alg,
            "summary": os.path.relpath(os.path.abspath(a.md), ROOT)}
     with open(a.json, "w") as f:
         json.dump(rec, f, indent=1)
