@@ -325,3 +325,30 @@ def test_l8_every_form_matches_oracle():
             f"M {info.outer_iters}")
         assert info.outer_iters == 3
         assert rel(host(y)[0], ref) <= bound
+
+
+@pytest.mark.parametrize("pass_", [1, 2, 3])
+@pytest.mark.parametrize("m_forced", [2, 6])
+def test_l1_short_runs_match_oracle_at_1e10(pass_, m_forced):
+    """BiCGstab(1) at the plain 1e-10 bound: over a few forced outer
+    iterations its rounding has not yet been amplified (the oracle's own
+    sensitivity stays far below 1e-10, checked here), so y and, for the
+    single pass, every x_s match the oracle to 1e-10 -- the bound the long
+    runs widen only because BiCGstab(1) itself amplifies rounding."""
+    wk, U, op, a, sig, w, b = problem("4x4x4x8")
+    force = np.full(len(sig), m_forced, dtype=np.int32)
+    y0, i0, X0 = oracle_run(op, a, b[0], sig, w, 1, wk.tol, 2000, 1, force=force)
+    rng = np.random.default_rng(777)
+    bp = b[0] * (1 + 1e-15 * rng.standard_normal(b[0].shape))
+    sens = rel(oracle_run(op, a, bp, sig, w, 1, wk.tol, 2000, 1, force=force)[0], y0)
+    ctx = ctx_for(wk, U)
+    y, info, xs = ctx.mshift_bicgstabl(cuda(b), a, sig, w, 1, wk.tol, 2000, pass_, force_iters=force,
+                                       want_shifts=pass_ == 1)
+    err = rel(host(y)[0], y0)
+    log(f"  l=1 pass {pass_} M={m_forced}: oracle sensitivity {sens:.1e}, rel err {err:.2e}")
+    assert 30 * sens <= 1e-10
+    assert np.array_equal(info.shift_iters[0], i0.shift_iters)
+    assert err <= 1e-10
+    if pass_ == 1:
+        for s in range(len(sig)):
+            assert rel(host(xs)[0, s], X0[s]) <= 1e-10, s
