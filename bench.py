@@ -8,10 +8,13 @@ spin-colour point sources at the origin solved as one batch; tolerance 1e-8 on
 every shift's relative residual.
 
 One step = one f(A) b evaluation of the 12-source batch in the headline form
-(--pass, --precision, --deferred, --refine).  The default is the fastest form
-that meets the tolerance on every shift: the pseudo-double pass in FP64 (the
-seed's 2 M l Mv outputs kept in HBM, y summed from them with the transposed
-sweep's coefficients; the same y as the single pass to rounding).  The
+(--pass, --precision, --deferred, --seed-basis, --refine).  The default is the
+fastest form that meets the tolerance on every shift: the pseudo-double pass
+in FP64 (the seed's 2 M l Mv outputs kept in HBM, y summed from them with the
+transposed sweep's coefficients; the same y as the single pass to rounding),
+with the seed's BiCG steps in basis form (each step writes only the two
+vectors its Mv reads; the others stay coefficients on the outer iteration's
+basis until the MR step).  The
 single pass (per-step or deferred shift updates), the double pass and the
 mixed-precision forms (FP32 stencil and vectors, FP64 reductions,
 accumulators and reliable updates; with per-shift refinement to reach the
@@ -52,17 +55,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def solver_flags(mixed, persistent, refine=False, deferred=False):
+def solver_flags(mixed, persistent, refine=False, deferred=False, basis=False):
     from paper_1010_2592_amd import msb
     return ((msb.MIXED if mixed else 0) | (msb.PERSISTENT if persistent else 0) | (msb.REFINE if refine else 0)
-            | (msb.DEFERRED if deferred else 0))
+            | (msb.DEFERRED if deferred else 0) | (msb.SEED_BASIS if basis else 0))
 
 
 def run_variant(ctx, b, a, sig, w, l, tol, max_outer, pass_, mixed, persistent=False, profile=False,
-                refine=False, deferred=False):
+                refine=False, deferred=False, basis=False):
     import torch
     from paper_1010_2592_amd import msb
-    flags = solver_flags(mixed, persistent, refine, deferred)
+    flags = solver_flags(mixed, persistent, refine, deferred, basis)
     if profile:
         ctx.profile_enable(True)
     torch.cuda.synchronize()
@@ -79,9 +82,10 @@ def run_variant(ctx, b, a, sig, w, l, tol, max_outer, pass_, mixed, persistent=F
     return y, info, e0.elapsed_time(e1), prof
 
 
-def workload_key(pass_, precision, refine, persistent, deferred=False):
+def workload_key(pass_, precision, refine, persistent, deferred=False, basis=False):
     return (f"{WORKLOAD} 12 rhs {precision} pass {pass_}" + (" deferred" if deferred else "")
-            + (" refine" if refine else "") + (" persistent" if persistent else ""))
+            + (" seed basis" if basis else "") + (" refine" if refine else "")
+            + (" persistent" if persistent else ""))
 
 
 def measured_traffic(key):
@@ -568,6 +572,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
     ap.add_argument("--deferred", default="auto", choices=("auto", "on", "off"),
                     help="pass 1: shift vectors updated once per outer iteration; auto: on for pass 1")
+    ap.add_argument("--seed-basis", default="auto", choices=("auto", "on", "off"),
+                    help="passes 2, 3 (FP64, stages): the seed's lower vectors as coefficients on the "
+                         "outer iteration's basis; auto: on where it applies")
     ap.add_argument("--refine", default="auto", choices=("auto", "on", "off"),
                     help="per-shift FP64 true residual + refinement (pass 1); auto: on for mixed pass 1")
     ap.add_argument("--launch", default="stages", choices=("stages", "persistent"),
@@ -633,11 +640,12 @@ def main():
     persistent = args.launch == "persistent"
     refine = args.pass_ == 1 and (args.refine == "on" or (args.refine == "auto" and mixed))
     deferred = args.pass_ == 1 and args.deferred != "off" and not persistent
+    basis = args.pass_ != 1 and not mixed and not persistent and args.seed_basis != "off"
     log(f"[bench] spectral radius {rho:.6f}; headline pass={args.pass_} {args.precision} {args.launch}")
 
     for i in range(args.warmup):
         _, info, ms, _ = run_variant(ctx, b, a, sig, w, l, wk.tol, args.max_outer, args.pass_, mixed, persistent,
-                                     refine=refine, deferred=deferred)
+                                     refine=refine, deferred=deferred, basis=basis)
         log(f"[bench] warmup {i}: {ms:.1f} ms, M={info.outer_iters}, status {info.status}")
 
     # ---- timed steps (library timing hook on the stencil launches only, every
@@ -653,7 +661,7 @@ def main():
     y = None
     for k in range(args.steps):
         y, info, _ = ctx.mshift_bicgstabl(b, a, sig, w, l, wk.tol, args.max_outer, args.pass_,
-                                          flags=solver_flags(mixed, persistent, refine, deferred),
+                                          flags=solver_flags(mixed, persistent, refine, deferred, basis),
                                           allow=(msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY))
         infos.append(info)
     e1.record()
@@ -674,7 +682,7 @@ def main():
     # every kernel class, from one more (untimed) step with all of them recorded
     ctx.profile_enable(True)
     ctx.mshift_bicgstabl(b, a, sig, w, l, wk.tol, args.max_outer, args.pass_,
-                         flags=solver_flags(mixed, persistent, refine, deferred),
+                         flags=solver_flags(mixed, persistent, refine, deferred, basis),
                          allow=(msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY))
     prof_all = ctx.profile_read()
     ctx.profile_enable(False)
@@ -695,7 +703,7 @@ def main():
     yK = None
     if not args.no_cpu:
         yK = ctx.mshift_bicgstabl(b, a, sig, w, l, wk.tol, CPU_ITERS, args.pass_,
-                                  flags=solver_flags(mixed, persistent, refine, deferred),
+                                  flags=solver_flags(mixed, persistent, refine, deferred, basis),
                                   force_iters=np.full(len(sig), CPU_ITERS),
                                   allow=(msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY))[0].cpu().numpy()
 
@@ -714,7 +722,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{WORKLOAD} Wilson-Dirac mu=0.05 m=-2, 12 point sources, "
                                f"Neuberger N_s={wk.n_shift}, BiCGstab(l={l}), tol {wk.tol}",
-                   "pass": args.pass_, "precision": args.precision, "deferred": deferred, "refine": refine,
+                   "pass": args.pass_, "precision": args.precision, "deferred": deferred, "seed_basis": basis,
+                   "refine": refine,
                    "launch": args.launch,
                    "rhs": nrhs,
                    "n_shift": wk.n_shift, "l": l, "outer_iters": info.outer_iters,
@@ -727,7 +736,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(workload_key(args.pass_, args.precision, refine, persistent,
-                                                              deferred)),
+                                                              deferred, basis)),
                      "kernel": "dslash (Wilson stencil, all epilogues)",
                      "launches_sampled": st["count"], "sample_stride": STENCIL_SAMPLE,
                      "avg_launch_us": round(st["ms"] * 1e3 / max(st["count"], 1), 2),
@@ -742,23 +751,29 @@ def main():
     if args.variants == "all":
         comps = {}
         ref = None
-        forms = [(1, False, False, False, False), (2, False, False, False, False), (1, True, False, False, False),
-                 (2, True, False, False, False), (1, True, False, True, False),
-                 (1, False, False, False, True), (1, True, False, False, True), (1, True, False, True, True),
-                 (1, False, True, False, False), (2, False, True, False, False), (1, True, True, False, False),
-                 (1, True, True, True, False), (2, True, True, False, False), (3, False, False, False, False), (3, True, False, False, False)]
-        for (p, mx, pe, rf, df) in forms:
+        # (pass, mixed, persistent, refine, deferred, seed basis)
+        forms = [(1, False, False, False, False, False), (2, False, False, False, False, False),
+                 (2, False, False, False, False, True), (1, True, False, False, False, False),
+                 (2, True, False, False, False, False), (1, True, False, True, False, False),
+                 (1, False, False, False, True, False), (1, True, False, False, True, False),
+                 (1, True, False, True, True, False), (1, False, True, False, False, False),
+                 (2, False, True, False, False, False), (1, True, True, False, False, False),
+                 (1, True, True, True, False, False), (2, True, True, False, False, False),
+                 (3, False, False, False, False, False), (3, False, False, False, False, True),
+                 (3, True, False, False, False, False)]
+        for (p, mx, pe, rf, df, sb) in forms:
             name = (f"{p}pass-{'mixed' if mx else 'fp64'}{'-refine' if rf else ''}{'-deferred' if df else ''}"
-                    f"-{'persistent' if pe else 'stages'}")
+                    f"{'-basis' if sb else ''}-{'persistent' if pe else 'stages'}")
             try:
                 # one warm-up, then the median of VARIANT_REPS runs (the
                 # last of them with the kernel timing hook on)
                 run_variant(ctx, b, a, sig, w, l, wk.tol, min(args.max_outer, 400), p, mx, pe, refine=rf,
-                            deferred=df)
+                            deferred=df, basis=sb)
                 times = []
                 for rep in range(VARIANT_REPS):
                     yv, iv, msv, pv = run_variant(ctx, b, a, sig, w, l, wk.tol, min(args.max_outer, 400), p,
-                                                  mx, pe, profile=rep == VARIANT_REPS - 1, refine=rf, deferred=df)
+                                                  mx, pe, profile=rep == VARIANT_REPS - 1, refine=rf, deferred=df,
+                                                  basis=sb)
                     times.append(msv)
                     if rep < VARIANT_REPS - 1:
                         del yv

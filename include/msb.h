@@ -90,6 +90,16 @@ typedef enum {
                                space.  Not with MSB_ADJOINT, pfe_sign_apply or
                                pfe_sign_backward (which need the Hermitian
                                kernel H = gamma5 D_w).                          */
+#define MSB_SEED_BASIS 1024 /* pass 2, 3 (FP64, not MSB_MIXED or MSB_PERSISTENT):
+                               the seed's BiCG steps of Section 2 update only
+                               the two vectors the step's Mv reads; every
+                               other r_i, u_i of the outer iteration is kept
+                               as coefficients on its 2l+2 basis vectors (r_0,
+                               u_0 and the Mv outputs) and formed from them
+                               for the MR step.  Same iterates up to rounding,
+                               fewer vector passes per outer iteration (about
+                               2/3 of them at l = 4); + nrhs * n * 32 bytes of
+                               workspace.                                     */
 #define MSB_REFINE    128   /* pass 1: after the solve, the FP64 true residual of
                                every shift; shifts above tol get refinement
                                solves (A + sigma_s) d = r_s, x_s += d (<= 3
@@ -213,7 +223,8 @@ int wilson_apply(msb_ctx *ctx, const void *in, void *out, int nrhs, int flags);
  *                       the double pass.
  *   flags            MSB_MIXED, MSB_PERSISTENT, MSB_ADJOINT, MSB_REFINE (pass 1),
  *                    MSB_DEFERRED (pass 1, not with MSB_PERSISTENT),
- *                    MSB_OP_WILSON (A = a D_w; not with MSB_ADJOINT)
+ *                    MSB_OP_WILSON (A = a D_w; not with MSB_ADJOINT),
+ *                    MSB_SEED_BASIS (pass 2 or 3, FP64, one launch per stage)
  *   b                device [nrhs][12][V] complex128
  *   y                device [nrhs][12][V] complex128 (written)
  *   x_shifts         device [nrhs][n_shift][12][V] complex128 or NULL

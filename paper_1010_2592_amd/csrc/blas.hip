@@ -268,6 +268,22 @@ __global__ void k_axpy_host(double2 *y, const double2 *x, double2 a, long n) {
         y[e] = cfma(a, x[e], y[e]);
 }
 
+// basis form of the seed (FP64)
+__global__ __launch_bounds__(BLOCK) void k_basis_axpy(BasisArgs<double> a) {
+    basis_axpy_body(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+__global__ __launch_bounds__(BLOCK) void k_basis_r0norm(BasisArgs<double> a) {
+    basis_r0norm_body(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+template <int L>
+__global__ __launch_bounds__(BLOCK) void k_basis_gram(BasisArgs<double> a) {
+    basis_gram_body<L>(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+template <int L>
+__global__ __launch_bounds__(BLOCK) void k_basis_mr_update(BasisArgs<double> a) {
+    basis_mr_update_body<L>(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -558,5 +574,28 @@ void launch_sparse_dot(hipStream_t st, const SparseDotArgs &a, int nrhs) {
 INST(double)
 INST(float)
 #undef INST
+
+void launch_basis_axpy(hipStream_t st, const BasisArgs<double> &a, int nrhs, int nblk) {
+    hipLaunchKernelGGL(k_basis_axpy, dim3(nblk, nrhs), dim3(BLOCK), 0, st, a);
+}
+void launch_basis_r0norm(hipStream_t st, const BasisArgs<double> &a, int nrhs, int nblk) {
+    hipLaunchKernelGGL(k_basis_r0norm, dim3(nblk, nrhs), dim3(BLOCK), 0, st, a);
+}
+void launch_basis_gram(hipStream_t st, const BasisArgs<double> &a, int nrhs, int nblk) {
+    dim3 g(nblk, nrhs), b(BLOCK);
+    switch (a.l) {
+#define C_(L) case L: hipLaunchKernelGGL((k_basis_gram<L>), g, b, 0, st, a); break;
+        C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8)
+#undef C_
+    }
+}
+void launch_basis_mr_update(hipStream_t st, const BasisArgs<double> &a, int nrhs, int nblk) {
+    dim3 g(nblk, nrhs), b(BLOCK);
+    switch (a.l) {
+#define C_(L) case L: hipLaunchKernelGGL((k_basis_mr_update<L>), g, b, 0, st, a); break;
+        C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8)
+#undef C_
+    }
+}
 
 }  // namespace msb

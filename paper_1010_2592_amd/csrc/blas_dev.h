@@ -282,5 +282,144 @@ __device__ __forceinline__ void rel_update_body(const VecArgs<T> &a, const doubl
     block_reduce_store<3>(p, a.part + (size_t)rhs * PMAX * a.ps + bx, a.ps);
 }
 
+// ---------------------------------------------------------------------------
+// Basis form of the seed (MSB_SEED_BASIS, FP64).  Vector b of the basis of
+// right-hand side rhs, element e.
+__device__ __forceinline__ double2 bvec(const BasisArgs<double> &a, int b, int rhs, long e) {
+    return a.bv[b][(size_t)rhs * a.brs[b] + e];
+}
+
+// dst = x - c y (the direction update u_j = r_j - beta u_j before the step's
+// first Mv, the residual update r_j = r_j - alpha u_{j+1} before its second),
+// ||dst||^2 into partial row prow
+__device__ __forceinline__ void basis_axpy_body(const BasisArgs<double> &a, int bx, int gx, int rhs) {
+    if (!gate_open(a.gate, rhs)) return;
+    const long n = a.n;
+    const double2 c = ld(a.c, rhs);
+    const double2 *x = a.x + (size_t)rhs * a.x_rs, *y = a.y + (size_t)rhs * a.y_rs;
+    double2 *d = a.dst + (size_t)rhs * a.dst_rs;
+    double part[1] = {0.0};
+    for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
+        const double2 v = csub(x[e], cmul(c, y[e]));
+        d[e] = v;
+        part[0] += v.x * v.x + v.y * v.y;
+    }
+    if (a.prow >= 0)
+        block_reduce_store<1>(part, a.part + (size_t)rhs * PMAX * a.ps + (size_t)a.prow * a.ps + bx, a.ps);
+}
+
+// ||r_0||^2 into partial row 3, r_0 formed from the first nbu basis vectors
+// with the coefficients sc_exh wrote (gated on its check)
+__device__ __forceinline__ void basis_r0norm_body(const BasisArgs<double> &a, int bx, int gx, int rhs) {
+    if (!gate_open(a.gate, rhs)) return;
+    __shared__ double2 cf[NBB];
+    for (int b = threadIdx.x; b < NBB; b += BLOCK) cf[b] = a.sb[rhs].r[0][b];
+    __syncthreads();
+    const long n = a.n;
+    const int nbu = a.nbu;
+    double part[1] = {0.0};
+    for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
+        double2 r = d2(0, 0);
+        for (int b = 0; b < nbu; ++b) r = cfma(cf[b], bvec(a, b, rhs, e), r);
+        part[0] += r.x * r.x + r.y * r.y;
+    }
+    block_reduce_store<1>(part, a.part + (size_t)rhs * PMAX * a.ps + 3 * a.ps + bx, a.ps);
+}
+
+// Basis vectors the MR step reads: those of the L = l_eff steps the outer
+// iteration completed (r_i and u_i, i <= L, lie in B_0 .. B_{2L+1})
+__device__ __forceinline__ int basis_used(const SeedState &S) { return 2 * S.l_eff + 2; }
+
+// The MR step's Gram matrix, conj(r_i) r_k for 0 <= i <= k <= L in the order
+// of the explicit form's partials, each r_i formed in registers from the
+// basis with the coefficients of sc_basis
+template <int L>
+__device__ __forceinline__ void basis_gram_body(const BasisArgs<double> &a, int bx, int gx, int rhs) {
+    if (!gate_open(a.gate, rhs)) return;
+    constexpr int NP = (L + 1) * (L + 2) / 2;
+    constexpr int NBL = 2 * L + 2;
+    __shared__ double2 cr[L + 1][NBL];
+    for (int k = threadIdx.x; k < (L + 1) * NBL; k += BLOCK) cr[k / NBL][k % NBL] = a.sb[rhs].r[k / NBL][k % NBL];
+    __syncthreads();
+    const int nbu = basis_used(a.seed[rhs]);
+    const long n = a.n;
+    double acc[2 * NP];
+#pragma unroll
+    for (int p = 0; p < 2 * NP; ++p) acc[p] = 0.0;
+    for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
+        double2 B[NBL];
+#pragma unroll
+        for (int b = 0; b < NBL; ++b) B[b] = b < nbu ? bvec(a, b, rhs, e) : d2(0, 0);
+        double2 r[L + 1];
+#pragma unroll
+        for (int i = 0; i <= L; ++i) {
+            double2 v = d2(0, 0);
+#pragma unroll
+            for (int b = 0; b < NBL; ++b) v = cfma(cr[i][b], B[b], v);
+            r[i] = v;
+        }
+        int p = 0;
+#pragma unroll
+        for (int i = 0; i <= L; ++i)
+#pragma unroll
+            for (int k = i; k <= L; ++k) {
+                acc[2 * p] += r[i].x * r[k].x + r[i].y * r[k].y;
+                acc[2 * p + 1] += r[i].x * r[k].y - r[i].y * r[k].x;
+                ++p;
+            }
+    }
+    block_reduce_store<2 * NP>(acc, a.part + (size_t)rhs * PMAX * a.ps + bx, a.ps);
+}
+
+// The MR update: r_0 = r_0 - sum_i gamma_i r_i and u_0 = u_0 - sum_i gamma_i u_i
+// (i = 1 .. l_mr), formed from the basis with the combined coefficients and
+// written over B_0 and B_1; partials <r~, r_0> (rows 0, 1; left at zero for
+// the sparse list) and ||r_0||^2 (row 2)
+template <int L>
+__device__ __forceinline__ void basis_mr_update_body(const BasisArgs<double> &a, int bx, int gx, int rhs) {
+    if (!gate_open(a.gate, rhs)) return;
+    constexpr int NBL = 2 * L + 2;
+    const SeedState &S = a.seed[rhs];
+    __shared__ double2 c_r[NBL], c_u[NBL];
+    if (threadIdx.x < NBL) {
+        const int b = threadIdx.x;
+        const SeedBasis &SB = a.sb[rhs];
+        const int lm = S.l_mr < L ? S.l_mr : L;
+        double2 vr = SB.r[0][b], vu = SB.u[0][b];
+        for (int i = 1; i <= lm; ++i) {
+            vr = csub(vr, cmul(S.gam[i - 1], SB.r[i][b]));
+            vu = csub(vu, cmul(S.gam[i - 1], SB.u[i][b]));
+        }
+        c_r[b] = vr;
+        c_u[b] = vu;
+    }
+    __syncthreads();
+    const int nbu = basis_used(S);
+    const long n = a.n;
+    double2 *R0 = a.R0 + (size_t)rhs * a.r0_rs, *U0 = a.U0 + (size_t)rhs * a.u0_rs;
+    const double2 *rt = a.rt ? a.rt + (size_t)rhs * n : nullptr;
+    double part[3] = {0.0, 0.0, 0.0};
+    for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
+        double2 B[NBL];
+#pragma unroll
+        for (int b = 0; b < NBL; ++b) B[b] = b < nbu ? bvec(a, b, rhs, e) : d2(0, 0);
+        double2 r0 = d2(0, 0), u0 = d2(0, 0);
+#pragma unroll
+        for (int b = 0; b < NBL; ++b) {
+            r0 = cfma(c_r[b], B[b], r0);
+            u0 = cfma(c_u[b], B[b], u0);
+        }
+        R0[e] = r0;
+        U0[e] = u0;
+        if (rt) {
+            const double2 t = rt[e];
+            part[0] += t.x * r0.x + t.y * r0.y;
+            part[1] += t.x * r0.y - t.y * r0.x;
+        }
+        part[2] += r0.x * r0.x + r0.y * r0.y;
+    }
+    block_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + bx, a.ps);
+}
+
 }  // namespace dev
 }  // namespace msb

@@ -48,8 +48,13 @@ int make_params(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
         return arg_error(w + ": pass = 3 runs with one launch per stage, not MSB_PERSISTENT");
     if (nrhs < 1 || nrhs > 4096) return arg_error(w + ": nrhs must be in 1..4096");
     if (flags & ~(MSB_MIXED | MSB_PERSISTENT | MSB_ADJOINT | MSB_OVERLAP | MSB_REFINE | MSB_DEFERRED |
-                  MSB_OP_WILSON))
+                  MSB_OP_WILSON | MSB_SEED_BASIS))
         return arg_error(w + ": unknown flag bits");
+    if ((flags & MSB_SEED_BASIS) && pass == 1)
+        return arg_error(w + ": MSB_SEED_BASIS is a form of the double pass (pass = 2 or 3)");
+    if ((flags & MSB_SEED_BASIS) && (flags & (MSB_MIXED | MSB_PERSISTENT)))
+        return arg_error(w + ": MSB_SEED_BASIS runs in FP64 with one launch per stage (not MSB_MIXED, "
+                             "MSB_PERSISTENT)");
     if ((flags & MSB_OP_WILSON) && (flags & MSB_ADJOINT))
         return arg_error(w + ": MSB_OP_WILSON (A = a D_w) has no MSB_ADJOINT form");
     if ((flags & MSB_DEFERRED) && pass != 1)
@@ -75,6 +80,7 @@ int make_params(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
     P->refine = (flags & MSB_REFINE) != 0;
     P->deferred = (flags & MSB_DEFERRED) != 0;
     P->op_wilson = (flags & MSB_OP_WILSON) != 0;
+    P->seed_basis = (flags & MSB_SEED_BASIS) != 0;
     P->nrhs = nrhs;
     P->shifts.resize((size_t)nrhs * n_shift);
     P->weights.resize((size_t)nrhs * n_shift);
@@ -246,8 +252,8 @@ int mshift_bicgstabl_noalloc(msb_ctx *ctx, double a_scale, int n_shift, const do
                          pass, flags & ~MSB_OVERLAP, nrhs, "mshift_bicgstabl_noalloc", &P);
     if (rc) return rc;
     if (pass != 1 && pass != 2) return arg_error("mshift_bicgstabl_noalloc: pass must be 1 or 2");
-    if (flags & (MSB_PERSISTENT | MSB_REFINE))
-        return arg_error("mshift_bicgstabl_noalloc: MSB_PERSISTENT and MSB_REFINE are not offered");
+    if (flags & (MSB_PERSISTENT | MSB_REFINE | MSB_SEED_BASIS))
+        return arg_error("mshift_bicgstabl_noalloc: MSB_PERSISTENT, MSB_REFINE and MSB_SEED_BASIS are not offered");
     if (!b || !y) return arg_error("mshift_bicgstabl_noalloc: b and y are required");
     if (x_shifts && pass != 1) return arg_error("mshift_bicgstabl_noalloc: x_shifts needs pass = 1");
     if (flags & MSB_OVERLAP) return arg_error("mshift_bicgstabl_noalloc: MSB_OVERLAP applies to pfe_sign_apply");

@@ -249,6 +249,19 @@ struct SeedState {
     // flag 0 no step, 1 u-update and Mv only (gamma breakdown), 2 full step
     double2 step_beta[LMAX], step_alpha[LMAX];
     int step_flag[LMAX];
+    // basis form (MSB_SEED_BASIS): this BiCG step's exhaustion test needs
+    // ||r_0||, formed from the basis (set by the necessary-condition check)
+    int exh_check;
+};
+
+// Basis form of the seed (MSB_SEED_BASIS): the outer iteration's vectors as
+// coefficients on its basis B_0 = r_0, B_1 = u_0 at the start of the
+// iteration, B_{2+2j} = S u_j and B_{3+2j} = S r_j of BiCG step j:
+//   r_i = sum_b r[i][b] B_b,  u_i = sum_b u[i][b] B_b  (i = 0..l).
+constexpr int NBB = 2 * LMAX + 2;
+struct SeedBasis {
+    double2 r[LMAX + 1][NBB];
+    double2 u[LMAX + 1][NBB];
 };
 
 struct ShiftState {

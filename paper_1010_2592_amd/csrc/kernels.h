@@ -152,6 +152,44 @@ struct VecArgs {
     int mr_dyn = 0;
 };
 
+// Basis form of the seed (MSB_SEED_BASIS, FP64): the vectors of the basis
+// kernels.  Vector b of the outer iteration's basis (see SeedBasis) of right-
+// hand side r is at bv[b] + r * brs[b].
+template <typename T>
+struct BasisArgs {
+    long n = 0;
+    int l = 0;
+    Gate gate{};
+    const C<T> *bv[NBB] = {};
+    long brs[NBB] = {};
+    const SeedBasis *sb = nullptr;    // [rhs]
+    const SeedState *seed = nullptr;
+    double *part = nullptr;
+    long ps = NBMAX;
+    // axpy: dst = x - c y with c per right-hand side; ||dst||^2 into partial
+    // row prow when prow >= 0
+    C<T> *dst = nullptr;
+    long dst_rs = 0;
+    const C<T> *x = nullptr;
+    long x_rs = 0;
+    const C<T> *y = nullptr;
+    long y_rs = 0;
+    CoefRef c{};
+    int prow = -1;
+    // r_0 from the basis: the first nbu basis vectors, ||r_0||^2 into row 3
+    int nbu = 0;
+    // MR update: r_0 and u_0 written over B_0 and B_1; <r~, r_0> (rt, or left
+    // at zero for the sparse list) and ||r_0||^2 into rows 0..2
+    C<T> *R0 = nullptr;
+    C<T> *U0 = nullptr;
+    long r0_rs = 0, u0_rs = 0;
+    const C<T> *rt = nullptr;
+};
+void launch_basis_axpy(hipStream_t, const BasisArgs<double> &, int nrhs, int nblk);
+void launch_basis_r0norm(hipStream_t, const BasisArgs<double> &, int nrhs, int nblk);
+void launch_basis_gram(hipStream_t, const BasisArgs<double> &, int nrhs, int nblk);
+void launch_basis_mr_update(hipStream_t, const BasisArgs<double> &, int nrhs, int nblk);
+
 // mode: 0 u_0..u_j, 1 u_j only, 2 u_0..u_{j-1} (see seed_u_body)
 template <typename T> void launch_seed_u(hipStream_t, const VecArgs<T> &, int j, int nrhs, int nblk, int mode = 0);
 // fused: the r-update also applies the step's deferred u_0..u_{j-1} update
@@ -256,6 +294,10 @@ struct ScalarArgs {
     StepCoef *sc_hist = nullptr;    // deferred: [rhs][LMAX][NSMAX] every step's shift coefficients
     DeferCoef *dc = nullptr;        // deferred: [rhs][NSMAX] the iteration's coefficients
     int shadow = 0;                 // init: ||r~|| from partial row 5 (r~ other than b)
+    // basis form (MSB_SEED_BASIS)
+    int basis = 0;
+    double norm_a = 0;              // an upper bound of ||S|| (2-norm)
+    SeedBasis *sb = nullptr;        // [rhs]
 };
 
 void launch_sc_init(hipStream_t, const ScalarArgs &, int nrhs);
@@ -265,6 +307,8 @@ void launch_sc_mr(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_conv(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_rel(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_defer(hipStream_t, const ScalarArgs &, int nrhs);
+void launch_sc_basis(hipStream_t, const ScalarArgs &, int nrhs);
+void launch_sc_exh(hipStream_t, const ScalarArgs &, int nrhs);
 
 // ---- persistent execution --------------------------------------------------
 // The stages of a solve, recorded as a table of operations that one
@@ -287,6 +331,8 @@ enum OpKind : int {
     OP_SC_REL,
     OP_SC_CONV,
     OP_SC_DEFER,      // per-stage launches only (the deferred single pass)
+    OP_SC_BASIS,      // per-stage launches only (the basis form of the seed)
+    OP_SC_EXH,
 };
 constexpr int POP_BLOB = 512;
 struct alignas(16) POp {

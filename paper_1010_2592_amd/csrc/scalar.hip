@@ -35,6 +35,8 @@ __global__ __launch_bounds__(BLOCK) void sc_mr(ScalarArgs a) { sc_mr_body(a, blo
 __global__ __launch_bounds__(BLOCK) void sc_rel(ScalarArgs a) { sc_rel_body(a, blockIdx.x); }
 __global__ __launch_bounds__(BLOCK) void sc_conv(ScalarArgs a) { sc_conv_body(a, blockIdx.x); }
 __global__ __launch_bounds__(BLOCK) void sc_defer(ScalarArgs a) { sc_defer_body(a, blockIdx.x); }
+__global__ __launch_bounds__(BLOCK) void sc_basis(ScalarArgs a) { sc_basis_body(a, blockIdx.x); }
+__global__ __launch_bounds__(BLOCK) void sc_exh(ScalarArgs a) { sc_exh_body(a, blockIdx.x); }
 
 }  // namespace
 
@@ -58,6 +60,12 @@ void launch_sc_conv(hipStream_t st, const ScalarArgs &a, int nrhs) {
 }
 void launch_sc_defer(hipStream_t st, const ScalarArgs &a, int nrhs) {
     hipLaunchKernelGGL(sc_defer, dim3(nrhs), dim3(BLOCK), 0, st, a);
+}
+void launch_sc_basis(hipStream_t st, const ScalarArgs &a, int nrhs) {
+    hipLaunchKernelGGL(sc_basis, dim3(nrhs), dim3(BLOCK), 0, st, a);
+}
+void launch_sc_exh(hipStream_t st, const ScalarArgs &a, int nrhs) {
+    hipLaunchKernelGGL(sc_exh, dim3(nrhs), dim3(BLOCK), 0, st, a);
 }
 
 }  // namespace msb

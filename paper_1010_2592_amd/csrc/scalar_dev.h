@@ -87,8 +87,11 @@ __device__ __forceinline__ void sc_beta_body(const ScalarArgs &a, int rhs) {
     double r02 = 0.0;
     if (j >= 1) r02 = block_sum(row + 3 * a.ps, a.nblk2);
     if (threadIdx.x != 0) return;
-    if (j >= 1) S.rnorm0 = sqrt(r02);
-    if (j >= 1 && !S.forced && S.nact > 0) {
+    // basis form: ||r_0|| exists only where sc_exh found that the test could
+    // fire; elsewhere it cannot (||r_0|| >= ||r_{j-1}|| / ||S||^(j-1))
+    const bool have_r0 = !a.basis || S.exh_check;
+    if (j >= 1 && have_r0) S.rnorm0 = sqrt(r02);
+    if (j >= 1 && have_r0 && !S.forced && S.nact > 0) {
         // Krylov space exhausted: every active shift already meets its
         // tolerance after the previous step's r-update
         double mn = 1e308;
@@ -522,6 +525,91 @@ __device__ __forceinline__ void sc_defer_body(const ScalarArgs &a, int rhs) {
         }
         d.live = 1;
     }
+}
+
+// The seed's step recurrences of this outer iteration (the steps it completed,
+// step_flag), replayed on the coefficients of its basis: r_i and u_i as sums
+// over B (see SeedBasis), R[i][b] and U[i][b].  Steps in the order and with
+// the arithmetic of the explicit form: u_i = r_i - beta u_i (i <= j),
+// u_{j+1} = S u_j, then r_i = r_i - alpha u_{i+1} (i <= j), r_{j+1} = S r_j.
+__device__ inline void seed_basis_replay(const SeedState &S, int l, double2 (*R)[NBB], double2 (*U)[NBB]) {
+    for (int i = 0; i <= l; ++i)
+        for (int b = 0; b < NBB; ++b) R[i][b] = U[i][b] = d2(0, 0);
+    R[0][0] = d2(1, 0);
+    U[0][1] = d2(1, 0);
+    for (int j = 0; j < l; ++j) {
+        const int flag = S.step_flag[j];
+        if (flag == 0) break;
+        const double2 beta = S.step_beta[j];
+        for (int i = 0; i <= j; ++i)
+            for (int b = 0; b < NBB; ++b) U[i][b] = csub(R[i][b], cmul(beta, U[i][b]));
+        U[j + 1][2 + 2 * j] = d2(1, 0);
+        if (flag == 1) break;
+        const double2 alpha = S.step_alpha[j];
+        for (int i = 0; i <= j; ++i)
+            for (int b = 0; b < NBB; ++b) R[i][b] = csub(R[i][b], cmul(alpha, U[i + 1][b]));
+        R[j + 1][3 + 2 * j] = d2(1, 0);
+    }
+}
+
+// Basis form, before the MR step: every r_i and u_i of the outer iteration as
+// coefficients on its basis.
+__device__ __forceinline__ void sc_basis_body(const ScalarArgs &a, int rhs) {
+    const SeedState &S = a.seed[rhs];
+    if (!S.run) return;
+    __shared__ double2 R[LMAX + 1][NBB], U[LMAX + 1][NBB];
+    if (threadIdx.x == 0) seed_basis_replay(S, a.l, R, U);
+    __syncthreads();
+    SeedBasis &B = a.sb[rhs];
+    for (int k = threadIdx.x; k < (LMAX + 1) * NBB; k += BLOCK) {
+        const int i = k / NBB, b = k % NBB;
+        B.r[i][b] = R[i][b];
+        B.u[i][b] = U[i][b];
+    }
+}
+
+// Basis form, before step j >= 1: could the exhaustion test of this step
+// fire?  It reads ||r_0|| after step j-1, which the basis form does not
+// form; but then r_{j-1} = S^(j-1) r_0 (the steps keep r_{i+1} = S r_i), so
+// ||r_0|| >= ||r_{j-1}|| / ||S||^(j-1), with norm_a an upper bound of ||S||.
+// Where ||r_{j-1}|| (partial row 4, from the step's r-update) is within
+// twice that factor of the test's threshold, exh_check is set and r_0's
+// coefficients are written for the kernel that forms it; otherwise the test
+// cannot fire and is left out.
+__device__ __forceinline__ void sc_exh_body(const ScalarArgs &a, int rhs) {
+    SeedState &S = a.seed[rhs];
+    if (!S.run || !S.bicg_on) {
+        if (threadIdx.x == 0) S.exh_check = 0;
+        return;
+    }
+    const int j = a.j;
+    const double *row = prow(a, rhs);
+    const double rj1 = sqrt(block_sum(row + 4 * a.ps, a.nblk2));
+    __shared__ int check;
+    __shared__ double2 R[LMAX + 1][NBB], U[LMAX + 1][NBB];
+    if (threadIdx.x == 0) {
+        check = 0;
+        if (!S.forced && S.nact > 0) {
+            double mn = 1e308;
+            for (int q = 0; q < S.nact; ++q) {
+                const ShiftState &H = a.sh[(size_t)rhs * NSMAX + S.act[q]];
+                if (!H.active) continue;
+                const double sc = cmod(cmul(H.zeta, H.psi));
+                mn = sc < mn ? sc : mn;
+            }
+            double fac = 2.0;
+            for (int k = 0; k < j - 1; ++k) fac *= a.norm_a;
+            if (rj1 <= fac * FREEZE_FRAC * S.tol * S.bnorm * mn) {
+                check = 1;
+                seed_basis_replay(S, a.l, R, U);
+            }
+        }
+        S.exh_check = check;
+    }
+    __syncthreads();
+    if (!check) return;
+    SeedBasis &B = a.sb[rhs];
+    for (int b = threadIdx.x; b < NBB; b += BLOCK) B.r[0][b] = R[0][b];
 }
 
 }  // namespace dev

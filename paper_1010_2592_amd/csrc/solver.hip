@@ -25,6 +25,7 @@
 #include <complex>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "ctx.h"
@@ -248,7 +249,8 @@ void ctx_destroy(Ctx *c) {
                       &c->ws_rsig, &c->ws_rw, &c->ws_Bm, &c->ws_schist, &c->ws_dc, &c->ws_ones,
                       &c->ws_cg_r, &c->ws_cg_p, &c->ws_cg_w, &c->ws_cg_P, &c->ws_cg_seed, &c->ws_cg_shift,
                       &c->ws_cg_coef, &c->ws_cg_tape, &c->ws_cg_c, &c->ws_cg_n, &c->ws_eY, &c->ws_eW,
-                      &c->ws_eZ, &c->ws_eP, &c->ws_eS, &c->ws_eG, &c->ws_sp, &c->ws_hs, &c->ws_hs64};
+                      &c->ws_eZ, &c->ws_eP, &c->ws_eS, &c->ws_eG, &c->ws_sp, &c->ws_hs, &c->ws_hs64,
+                      &c->ws_bw, &c->ws_sb};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (DevBuf &b : c->pstore)
@@ -681,10 +683,37 @@ struct Emit {
             launch_defer_update<T>(st, a, nrhs, nblk);
         }
     }
+    // basis form of the seed (FP64, per-stage launches only)
+    void basis_axpy(const BasisArgs<double> &a, int nrhs, int nblk, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_basis_axpy(st, a, nrhs, nblk);
+        }
+    }
+    void basis_r0norm(const BasisArgs<double> &a, int nrhs, int nblk, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_basis_r0norm(st, a, nrhs, nblk);
+        }
+    }
+    void basis_gram(const BasisArgs<double> &a, int nrhs, int nblk, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_basis_gram(st, a, nrhs, nblk);
+        }
+    }
+    void basis_mr_update(const BasisArgs<double> &a, int nrhs, int nblk, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_basis_mr_update(st, a, nrhs, nblk);
+        }
+    }
     void scalar(int kind, const ScalarArgs &a, int nrhs) {
         if (launching(CL_SCALAR, 0.0)) {
             Prof p(c, CL_SCALAR, 0);
             switch (kind) {
+            case OP_SC_BASIS: launch_sc_basis(st, a, nrhs); break;
+            case OP_SC_EXH: launch_sc_exh(st, a, nrhs); break;
             case OP_SC_BETA: launch_sc_beta(st, a, nrhs); break;
             case OP_SC_ALPHA: launch_sc_alpha(st, a, nrhs); break;
             case OP_SC_MR: launch_sc_mr(st, a, nrhs); break;
@@ -836,6 +865,13 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             if (mixed) CHK(ensure(c, c->ws_hs64, (size_t)nrhs * n * sizeof(double2)));
         }
     }
+    // basis form of the seed: the two vectors each BiCG step feeds its Mv
+    // (u_j, r_j after their updates) and the basis coefficients
+    const bool basis = P.seed_basis && !mixed && !P.persistent && !pass1;
+    if (basis) {
+        CHK(ensure(c, c->ws_bw, (size_t)2 * nrhs * n * cs));
+        CHK(ensure(c, c->ws_sb, (size_t)nrhs * sizeof(SeedBasis)));
+    }
     if (!P.persistent)
         CHK(ensure(c, c->ws_sp, (size_t)nrhs * (SPMAX * (sizeof(long) + sizeof(double2)) + (1 + NBL) * sizeof(int)) +
                                     256));
@@ -967,6 +1003,19 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     sa.record = pass1 ? 0 : 1;            // the double and pseudo-double passes record the tape
     sa.nblk = nbv;
     sa.shadow = P.shadow ? 1 : 0;
+    if (basis) {
+        // ||S|| <= a ||D||^2 + max |sigma0| (a ||D|| + ... for A = a D), with
+        // ||D|| <= |4 + m| + 6 + 2 cosh(mu): each of the eight hops is a
+        // projector (1 -+ gamma) / 2 of norm 1 times a unitary link and a shift,
+        // scaled by 1 or exp(+-mu) in time
+        const double dn = std::fabs(4.0 + c->mass) + 6.0 + 2.0 * std::cosh(c->mu);
+        double s0 = 0.0;
+        for (int r = 0; r < nrhs; ++r)
+            s0 = std::max(s0, std::fabs(*std::min_element(&P.shifts[(size_t)r * ns], &P.shifts[(size_t)r * ns] + ns)));
+        sa.basis = 1;
+        sa.norm_a = (P.op_wilson ? P.a_scale * dn : P.a_scale * dn * dn) + s0;
+        sa.sb = (SeedBasis *)c->ws_sb.p;
+    }
     if (deferred) {
         sa.sc_hist = (StepCoef *)c->ws_schist.p;
         sa.dc = (DeferCoef *)c->ws_dc.p;
@@ -1139,6 +1188,129 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
             if (x.u_src_i >= 1) x.u_src = slot(2 * (ui - 1));
             x.r_src_rs = x.u_src_rs = store_rs;
         };
+        if constexpr (std::is_same<T, double>::value) {
+            if (basis) {
+                // basis form of the seed: each step updates only the two
+                // vectors its Mv read (into the work vectors WU, WR); the
+                // iteration's r_i and u_i are coefficients on its basis B
+                // (B_0 = r_0, B_1 = u_0 at the start, the Mv outputs after:
+                // the store slots of pass 3, else rows 1..l of U and R),
+                // formed from it for the Gram matrix and the MR update
+                BasisArgs<double> ba;
+                ba.n = n;
+                ba.l = l;
+                ba.sb = (const SeedBasis *)c->ws_sb.p;
+                ba.seed = seed;
+                ba.part = part;
+                ba.ps = ps;
+                ba.bv[0] = R;
+                ba.brs[0] = vs;
+                ba.bv[1] = Uv;
+                ba.brs[1] = vs;
+                for (int j = 0; j < l; ++j) {
+                    ba.bv[2 + 2 * j] = keep ? slot(2 * j) : Uv + (size_t)(j + 1) * n;
+                    ba.bv[3 + 2 * j] = keep ? slot(2 * j + 1) : R + (size_t)(j + 1) * n;
+                    ba.brs[2 + 2 * j] = ba.brs[3 + 2 * j] = keep ? store_rs : vs;
+                }
+                double2 *WU = (double2 *)c->ws_bw.p, *WR = WU + (size_t)nrhs * n;
+                Gate g_exh;
+                g_exh.seed = seed;
+                g_exh.need_bicg = 1;
+                g_exh.flag = &seed[0].exh_check;
+                g_exh.flag_stride = (long)sizeof(SeedState) / (long)sizeof(int);
+                g_exh.need = 1;
+                g_exh.eq = 1;
+                for (int j = 0; j < l; ++j) {
+                    s.j = j;
+                    s.nblk2 = nbv;
+                    if (j >= 1) {
+                        // could this step's exhaustion test fire?  Then r_0
+                        // after step j-1 (in B_0 .. B_2j) and its norm
+                        e.scalar(OP_SC_EXH, s, nrhs);
+                        BasisArgs<double> bn = ba;
+                        bn.gate = g_exh;
+                        bn.nbu = 2 * j + 1;
+                        e.basis_r0norm(bn, nrhs, nbv, CL_SEED, 0.0);
+                    }
+                    s.nblk = (j == 0) ? nbv : nbd;
+                    e.scalar(OP_SC_BETA, s, nrhs);
+                    const int xi = (j == 0) ? 0 : 2 * j + 1;   // r_j before this step
+                    const int yi = (j == 0) ? 1 : 2 * j;       // u_j before this step
+                    // u_j = r_j - beta u_j
+                    BasisArgs<double> bu = ba;
+                    bu.gate = g_bicg;
+                    bu.dst = WU;
+                    bu.dst_rs = n;
+                    bu.x = ba.bv[xi];
+                    bu.x_rs = ba.brs[xi];
+                    bu.y = ba.bv[yi];
+                    bu.y_rs = ba.brs[yi];
+                    bu.c = va.beta;
+                    e.basis_axpy(bu, nrhs, nbv, CL_SEED, nr_run * 3.0 * nd * cB);
+                    // u_{j+1} = S u_j into B_{2+2j}
+                    DslashArgs<T> f1 = d1, f2 = d2;
+                    f1.in = WU;
+                    f1.in_rs = n;
+                    f1.out = tmp;
+                    f1.gate = g_bicg;
+                    if (!opw) e.ds(f1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
+                    f2.in = opw ? WU : tmp;
+                    f2.in_rs = n;
+                    f2.out = (C<T> *)ba.bv[2 + 2 * j];
+                    f2.out_rs = ba.brs[2 + 2 * j];
+                    f2.v = WU;
+                    f2.v_rs = n;
+                    f2.gate = g_bicg;
+                    e.ds(f2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
+                    if (sparse_rt) sparse_dot_of(e, f2.out, f2.gate, nr_run, f2.out_rs);
+                    s.nblk = nbd;
+                    e.scalar(OP_SC_ALPHA, s, nrhs);
+                    // r_j = r_j - alpha u_{j+1}, ||r_j||^2 into row 4
+                    BasisArgs<double> br = ba;
+                    br.gate = g_bicg;
+                    br.dst = WR;
+                    br.dst_rs = n;
+                    br.x = ba.bv[xi];
+                    br.x_rs = ba.brs[xi];
+                    br.y = ba.bv[2 + 2 * j];
+                    br.y_rs = ba.brs[2 + 2 * j];
+                    br.c = va.alpha;
+                    br.prow = 4;
+                    e.basis_axpy(br, nrhs, nbv, CL_SEED, nr_run * 3.0 * nd * cB);
+                    // r_{j+1} = S r_j into B_{3+2j}
+                    f1.in = WR;
+                    if (!opw) e.ds(f1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_run));
+                    f2.in = opw ? WR : tmp;
+                    f2.out = (C<T> *)ba.bv[3 + 2 * j];
+                    f2.out_rs = ba.brs[3 + 2 * j];
+                    f2.v = WR;
+                    e.ds(f2, nrhs, mv_epi, CL_STENCIL, ds_bytes(mv_epi, nr_run));
+                    if (sparse_rt) sparse_dot_of(e, f2.out, f2.gate, nr_run, f2.out_rs);
+                }
+                // the MR step from the basis
+                s.nblk = nbv;
+                e.scalar(OP_SC_BASIS, s, nrhs);
+                const int nbg = std::min(nbv, GRAM_NBMAX);
+                BasisArgs<double> bg = ba;
+                bg.gate = g_run;
+                e.basis_gram(bg, nrhs, nbg, CL_SEED, nr_run * (2.0 * l + 2) * nd * cB);
+                s.nblk = nbg;
+                e.scalar(OP_SC_MR, s, nrhs);
+                s.nblk = nbv;
+                BasisArgs<double> bm = ba;
+                bm.gate = g_run;
+                bm.R0 = R;
+                bm.r0_rs = vs;
+                bm.U0 = Uv;
+                bm.u0_rs = vs;
+                bm.rt = sparse_rt ? nullptr : rt;
+                e.basis_mr_update(bm, nrhs, nbv, CL_SEED,
+                                  nr_run * (2.0 * l + 4 + (sparse_rt ? 0 : 1)) * nd * cB);
+                if (sparse_rt) sparse_dot_of(e, R, g_run, nr_run, vs);
+                e.scalar(OP_SC_CONV, s, nrhs);
+                return;
+            }
+        }
         for (int j = 0; j < l; ++j) {
             s.j = j;
             s.nblk = (j == 0) ? nbv : nbd;

@@ -24,6 +24,7 @@ __all__ = [
     "neuberger_pfe", "wilson_apply", "mshift_bicgstabl", "mshift_bicgstabl_noalloc", "mshift_cg", "pfe_sign_apply",
     "pfe_sign_backward", "spectral_radius",
     "G5_LEFT", "NEG_MU", "DAGGER", "MIXED", "PERSISTENT", "OVERLAP", "ADJOINT", "REFINE", "DEFERRED", "OP_WILSON",
+    "SEED_BASIS",
     "OK", "ERR_ARG", "ERR_HIP", "ERR_OOM", "NOT_CONVERGED", "BREAKDOWN", "REDUCED_ACCURACY", "SUCCESS",
 ]
 
@@ -34,6 +35,7 @@ OK, ERR_ARG, ERR_HIP, ERR_OOM, NOT_CONVERGED, BREAKDOWN, REDUCED_ACCURACY = 0, 1
 SUCCESS = (OK, REDUCED_ACCURACY)
 G5_LEFT, NEG_MU, DAGGER, MIXED, PERSISTENT, OVERLAP, ADJOINT, REFINE, DEFERRED = 1, 2, 4, 8, 16, 32, 64, 128, 256
 OP_WILSON = 512     # A = a D_w instead of a (gamma5 D_w)^2 (multi-mass propagators)
+SEED_BASIS = 1024   # passes 2, 3: the seed's lower vectors as coefficients on the iteration's basis
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 

@@ -183,6 +183,7 @@ def main():
     md.append("Workload: bench.py headline (16^3x32, mu = 0.05, m = -2, Neuberger N_s = 30, "
               "BiCGstab(l = 4), tol 1e-8, the 12 point sources in one batch); "
               f"form: {bench['config'].get('pass')}-pass, {bench['config'].get('precision')}, "
+              f"seed basis {bench['config'].get('seed_basis', False)}, "
               f"refine {bench['config'].get('refine')}, {bench['config'].get('launch')} launches.\n")
     md.append("## Kernel trace\n\nCommand (from the repository root on the MI355X box):\n")
     md.append(f"    {a.cmd_trace}\n")

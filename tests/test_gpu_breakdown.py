@@ -2,7 +2,8 @@
 inputs of tests/breakdown_cases.py (built with the oracle's operator) and the
 oracle's iteration as the reference: status, every shift's M_s, y and every
 x_s, for the per-step and deferred single pass, the double and the
-pseudo-double pass, and the persistent launch.
+pseudo-double pass (explicit and basis form of the seed), and the persistent
+launch.
 
   * gamma breakdown in step 1 (l = 2, 3): the partial step, the completion
     of the direction updates it owes, the MR step over the completed step;
@@ -29,6 +30,7 @@ from tests.helpers import cuda, host, log
 pytestmark = pytest.mark.gpu
 
 FORMS = [("pass1", 1, 0), ("pass1-deferred", 1, "DEFERRED"), ("pass2", 2, 0), ("pass3", 3, 0),
+         ("pass2-basis", 2, "SEED_BASIS"), ("pass3-basis", 3, "SEED_BASIS"),
          ("pass1-persistent", 1, "PERSISTENT"), ("pass2-persistent", 2, "PERSISTENT")]
 
 

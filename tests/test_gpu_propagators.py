@@ -26,7 +26,8 @@ def setup(dims, seed, mu):
     return U, op, ctx, MASSES - m0
 
 
-@pytest.mark.parametrize("form", ["pass1", "deferred", "pass2", "pass3", "persistent1", "persistent2"])
+@pytest.mark.parametrize("form", ["pass1", "deferred", "pass2", "pass3", "pass2-basis", "pass3-basis",
+                                  "persistent1", "persistent2"])
 def test_forced_matches_oracle(form):
     from paper_1010_2592_amd import msb
     dims = (4, 4, 4, 8)
@@ -35,9 +36,11 @@ def test_forced_matches_oracle(form):
     w = np.array([1.0, 0.5, 0.25, 2.0, 1.5])
     y1, i1, X1 = ok.mshift_bicgstabl(op.dw, b, sig, w, 2, 1e-10, 500, 1)
     y2 = ok.mshift_bicgstabl(op.dw, b, sig, w, 2, 1e-10, 500, 2, force_iters=i1.shift_iters)[0]
-    pass_ = {"pass1": 1, "deferred": 1, "pass2": 2, "pass3": 3, "persistent1": 1, "persistent2": 2}[form]
+    pass_ = {"pass1": 1, "deferred": 1, "pass2": 2, "pass3": 3, "pass2-basis": 2, "pass3-basis": 3,
+             "persistent1": 1, "persistent2": 2}[form]
     flags = msb.OP_WILSON | (msb.DEFERRED if form == "deferred" else 0) | \
-        (msb.PERSISTENT if form.startswith("persistent") else 0)
+        (msb.PERSISTENT if form.startswith("persistent") else 0) | \
+        (msb.SEED_BASIS if form.endswith("basis") else 0)
     y, info, xs = ctx.mshift_bicgstabl(cuda(b[None]), 1.0, sig, w, 2, 1e-10, 500, pass_, flags=flags,
                                        want_shifts=(pass_ == 1), force_iters=i1.shift_iters)
     ref = y1 if pass_ == 1 else y2
