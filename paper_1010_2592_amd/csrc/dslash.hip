@@ -234,6 +234,41 @@ void launch_dslash(hipStream_t st, DslashArgs<T> a, int nrhs, int epi, bool g5in
 
 template void launch_dslash<double>(hipStream_t, DslashArgs<double>, int, int, bool);
 
+namespace {
+__global__ __launch_bounds__(256) void k_link_gershgorin(const double2 *U, int V, double *blockmax) {
+    __shared__ double red[256];
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    double g = 0.0;
+    if (idx < 4L * V) {
+        const int nu = (int)(idx / V), s = (int)(idx % V);
+        double2 u[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) u[i][j] = U[((size_t)nu * 9 + 3 * i + j) * V + s];
+        for (int k = 0; k < 3; ++k) {
+            double row = 0.0;
+            for (int l = 0; l < 3; ++l) {
+                double2 m = d2(0, 0);
+                for (int i = 0; i < 3; ++i) m = cadd(m, cmulc(u[i][k], u[i][l]));   // conj(u_ik) u_il
+                row += (l == k) ? m.x : sqrt(m.x * m.x + m.y * m.y);
+            }
+            g = row > g ? row : g;
+        }
+    }
+    red[threadIdx.x] = g;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x + w] > red[threadIdx.x] ? red[threadIdx.x + w]
+                                                                                        : red[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) blockmax[blockIdx.x] = red[0];
+}
+}  // namespace
+
+void launch_link_gershgorin(hipStream_t st, const double2 *U, int V, double *blockmax) {
+    hipLaunchKernelGGL(k_link_gershgorin, dim3(link_gershgorin_blocks(V)), dim3(256), 0, st, U, V, blockmax);
+}
+
 void launch_link_force(hipStream_t st, const LinkForceArgs &a) {
     const int nb = nblocks_for(a.g.V);
     hipLaunchKernelGGL(link_force_kernel, dim3(nb), dim3(BLOCK), 0, st, a);

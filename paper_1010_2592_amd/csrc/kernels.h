@@ -107,6 +107,12 @@ struct LinkForceArgs {
     double2 *G = nullptr;      // [4][3][3][V], accumulated (+=)
 };
 void launch_link_force(hipStream_t st, const LinkForceArgs &a);
+// Per block of 256 links (U [4][3][3][V], 4V links), the largest Gershgorin
+// bound max_k (Re M_kk + sum_{l != k} |M_kl|) of M = U^+ U over its links: an
+// upper bound of ||U||_2^2 (exactly 1 up to rounding for unitary links).
+// blockmax: device [nblk], nblk = ceil(4V / 256).
+void launch_link_gershgorin(hipStream_t st, const double2 *U, int V, double *blockmax);
+inline int link_gershgorin_blocks(int V) { return (4 * V + 255) / 256; }
 
 // ---- vector kernels ------------------------------------------------------
 template <typename T>

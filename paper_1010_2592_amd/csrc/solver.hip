@@ -232,7 +232,24 @@ int ctx_create(Ctx *c, const int dims[4], double mass, double mu, int bc_t, cons
     HIPCHK(hipMemcpyAsync(c->U64, lk, nl * sizeof(double2), hipMemcpyDeviceToDevice, st));
     launch_convert_in<float>(st, c->U32, c->U64, (long)nl, 0, 0, 1);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(st));
+    // the links' norm bound: sqrt of the largest Gershgorin bound of U^+ U,
+    // widened by 1e-12 for the rounding of its sums
+    const int nbl = link_gershgorin_blocks(c->g.V);
+    double *gb = nullptr;
+    if (hipMalloc(&gb, nbl * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(S_ERR_OOM, "link allocation failed");
+    }
+    launch_link_gershgorin(st, c->U64, c->g.V, gb);
+    std::vector<double> hg(nbl);
+    const hipError_t e1 = hipMemcpyAsync(hg.data(), gb, nbl * sizeof(double), hipMemcpyDeviceToHost, st);
+    const hipError_t e2 = hipStreamSynchronize(st);
+    (void)hipFree(gb);
+    HIPCHK(e1);
+    HIPCHK(e2);
+    double gmax = 0.0;
+    for (double v : hg) gmax = std::isfinite(v) ? std::max(gmax, v) : INFINITY;
+    c->link_norm = std::sqrt(gmax * (1.0 + 1e-12));
     return 0;
 }
 
@@ -1005,10 +1022,13 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     sa.shadow = P.shadow ? 1 : 0;
     if (basis) {
         // ||S|| <= a ||D||^2 + max |sigma0| (a ||D|| + ... for A = a D), with
-        // ||D|| <= |4 + m| + 6 + 2 cosh(mu): each of the eight hops is a
-        // projector (1 -+ gamma) / 2 of norm 1 times a unitary link and a shift,
-        // scaled by 1 or exp(+-mu) in time
-        const double dn = std::fabs(4.0 + c->mass) + 6.0 + 2.0 * std::cosh(c->mu);
+        // ||D|| <= |4 + m| + L (3 sqrt(2) + sqrt(2 cosh(2 mu))), L the links'
+        // norm bound: the hops along nu are P- A + P+ B with orthogonal spin
+        // projectors P-+ = (1 -+ gamma_nu) / 2 and A, B a link times a shift
+        // (||A||, ||B|| <= L, scaled by exp(+-mu) in time), so
+        // ||(P- A + P+ B) v||^2 = ||P- A v||^2 + ||P+ B v||^2 <= (||A||^2 + ||B||^2) ||v||^2
+        const double dn = std::fabs(4.0 + c->mass) +
+                          c->link_norm * (3.0 * std::sqrt(2.0) + std::sqrt(2.0 * std::cosh(2.0 * c->mu)));
         double s0 = 0.0;
         for (int r = 0; r < nrhs; ++r)
             s0 = std::max(s0, std::fabs(*std::min_element(&P.shifts[(size_t)r * ns], &P.shifts[(size_t)r * ns] + ns)));

@@ -158,6 +158,42 @@ def test_basis_free_field_exhaustion():
             assert rel(host(y)[0], ref) <= 1e-12, (pass_, l)
 
 
+def test_basis_exhaustion_in_step_three_scaled_links():
+    """Three plane waves on free links scaled by 1.3 (not unitary: the norm
+    bound of the exhaustion gate takes the links' own norm): the Krylov space
+    has dimension 3, so at l = 4 the test fires in step 3 of the first outer
+    iteration in both forms, and y is the exact sum over the waves."""
+    from paper_1010_2592_amd import msb
+    dims = (4, 4, 4, 8)
+    Lx, Ly, Lz, Lt = dims
+    mu, m, c = 0.05, -2.0, 1.3
+    U = c * wl.free_links(dims)
+    a = 1 / 60.0
+    t, z, y_, x = np.meshgrid(np.arange(Lt), np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing="ij")
+    waves, lams = [], []
+    for k, p in enumerate(([2 * np.pi / Lx, 4 * np.pi / Ly, 0.0, np.pi * 7 / Lt],
+                           [0.0, 2 * np.pi / Ly, 2 * np.pi / Lz, np.pi / Lt],
+                           [6 * np.pi / Lx, 0.0, 4 * np.pi / Lz, np.pi * 3 / Lt])):
+        q = np.array(p, dtype=complex)
+        q[3] -= 1j * mu
+        phase = np.exp(1j * (p[0] * x + p[1] * y_ + p[2] * z + p[3] * t)).reshape(-1)
+        waves.append(((np.arange(1, 13) + k) * (1 + 0.5j * (k + 1)))[:, None] * phase[None, :])
+        lams.append(a * ((4 + m - c * np.sum(np.cos(q))) ** 2 + c * c * np.sum(np.sin(q) ** 2)))
+    assert min(abs(lams[i] - lams[j]) for i in range(3) for j in range(i)) > 1e-3
+    b = sum(waves)
+    sig, w = pfe.neuberger(10)
+    ref = sum(w[s] * sum(v / (lam + sig[s]) for v, lam in zip(waves, lams)) for s in range(10))
+    ctx = msb.Context(msb.Lattice(dims, m, mu, -1), cuda(U))
+    for pass_ in (2, 3):
+        for flags in (0, msb.SEED_BASIS):
+            y, info, _ = ctx.mshift_bicgstabl(cuda(b[None]), a, sig, w, 4, 1e-8, 50, pass_, flags=flags)
+            d = rel(host(y)[0], ref)
+            log(f"  three waves, links x{c}, pass {pass_} flags {flags}: M {info.outer_iters}, "
+                f"steps {info.bicg_steps}, {d:.2e}")
+            assert info.status == 0 and info.outer_iters == 1 and info.bicg_steps == 3, (pass_, flags)
+            assert d <= 1e-11, (pass_, flags)
+
+
 @pytest.mark.parametrize("pass_", [2, 3])
 def test_basis_sparse_shadow(pass_):
     """Point sources with r~ = b (one nonzero entry: the index-list path of
