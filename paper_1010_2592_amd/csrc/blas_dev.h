@@ -347,6 +347,9 @@ __device__ __forceinline__ void basis_gram_body(const BasisArgs<double> &a, int 
 #pragma unroll
     for (int p = 0; p < 2 * NP; ++p) acc[p] = 0.0;
     for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
+        // the coefficients are read from LDS in every pass: kept in registers
+        // across the loop they would take (L+1)(2L+2) complex registers
+        asm volatile("" ::: "memory");
         double2 B[NBL];
 #pragma unroll
         for (int b = 0; b < NBL; ++b) B[b] = b < nbu ? bvec(a, b, rhs, e) : d2(0, 0);
@@ -400,6 +403,7 @@ __device__ __forceinline__ void basis_mr_update_body(const BasisArgs<double> &a,
     const double2 *rt = a.rt ? a.rt + (size_t)rhs * n : nullptr;
     double part[3] = {0.0, 0.0, 0.0};
     for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
+        asm volatile("" ::: "memory");   // coefficients from LDS in every pass (as in the Gram kernel)
         double2 B[NBL];
 #pragma unroll
         for (int b = 0; b < NBL; ++b) B[b] = b < nbu ? bvec(a, b, rhs, e) : d2(0, 0);
