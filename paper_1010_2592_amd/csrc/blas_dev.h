@@ -320,7 +320,8 @@ __device__ __forceinline__ void basis_r0norm_body(const BasisArgs<double> &a, in
     double part[1] = {0.0};
     for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
         double2 r = d2(0, 0);
-        for (int b = 0; b < nbu; ++b) r = cfma(cf[b], bvec(a, b, rhs, e), r);
+        for (int b = 0; b < nbu; ++b)
+            if (b != 1) r = cfma(cf[b], bvec(a, b, rhs, e), r);   // no r_i holds u_0 (B_1)
         part[0] += r.x * r.x + r.y * r.y;
     }
     block_reduce_store<1>(part, a.part + (size_t)rhs * PMAX * a.ps + 3 * a.ps + bx, a.ps);
@@ -332,7 +333,10 @@ __device__ __forceinline__ int basis_used(const SeedState &S) { return 2 * S.l_e
 
 // The MR step's Gram matrix, conj(r_i) r_k for 0 <= i <= k <= L in the order
 // of the explicit form's partials, each r_i formed in registers from the
-// basis with the coefficients of sc_basis
+// basis with the coefficients of sc_basis.  B_1 = u_0 is not read: the steps
+// add multiples of u_0 to the u_i only (r_i - alpha u_{i+1} with i + 1 >= 1,
+// and u_i for i >= 1 never takes up u_0), so its coefficient in every r_i is
+// exactly zero.
 template <int L>
 __device__ __forceinline__ void basis_gram_body(const BasisArgs<double> &a, int bx, int gx, int rhs) {
     if (!gate_open(a.gate, rhs)) return;
@@ -352,13 +356,14 @@ __device__ __forceinline__ void basis_gram_body(const BasisArgs<double> &a, int 
         asm volatile("" ::: "memory");
         double2 B[NBL];
 #pragma unroll
-        for (int b = 0; b < NBL; ++b) B[b] = b < nbu ? bvec(a, b, rhs, e) : d2(0, 0);
+        for (int b = 0; b < NBL; ++b) B[b] = (b < nbu && b != 1) ? bvec(a, b, rhs, e) : d2(0, 0);
         double2 r[L + 1];
 #pragma unroll
         for (int i = 0; i <= L; ++i) {
             double2 v = d2(0, 0);
 #pragma unroll
-            for (int b = 0; b < NBL; ++b) v = cfma(cr[i][b], B[b], v);
+            for (int b = 0; b < NBL; ++b)
+                if (b != 1) v = cfma(cr[i][b], B[b], v);
             r[i] = v;
         }
         int p = 0;

@@ -532,23 +532,23 @@ __device__ __forceinline__ void sc_defer_body(const ScalarArgs &a, int rhs) {
 // over B (see SeedBasis), R[i][b] and U[i][b].  Steps in the order and with
 // the arithmetic of the explicit form: u_i = r_i - beta u_i (i <= j),
 // u_{j+1} = S u_j, then r_i = r_i - alpha u_{i+1} (i <= j), r_{j+1} = S r_j.
-__device__ inline void seed_basis_replay(const SeedState &S, int l, double2 (*R)[NBB], double2 (*U)[NBB]) {
-    for (int i = 0; i <= l; ++i)
-        for (int b = 0; b < NBB; ++b) R[i][b] = U[i][b] = d2(0, 0);
-    R[0][0] = d2(1, 0);
-    U[0][1] = d2(1, 0);
+// The recurrences act on each basis index b alone: one work-item per b
+// (column b of R and U).
+__device__ inline void seed_basis_replay_col(const SeedState &S, int l, int b, double2 (*R)[NBB],
+                                             double2 (*U)[NBB]) {
+    for (int i = 0; i <= l; ++i) R[i][b] = U[i][b] = d2(0, 0);
+    if (b == 0) R[0][0] = d2(1, 0);
+    if (b == 1) U[0][1] = d2(1, 0);
     for (int j = 0; j < l; ++j) {
         const int flag = S.step_flag[j];
         if (flag == 0) break;
         const double2 beta = S.step_beta[j];
-        for (int i = 0; i <= j; ++i)
-            for (int b = 0; b < NBB; ++b) U[i][b] = csub(R[i][b], cmul(beta, U[i][b]));
-        U[j + 1][2 + 2 * j] = d2(1, 0);
+        for (int i = 0; i <= j; ++i) U[i][b] = csub(R[i][b], cmul(beta, U[i][b]));
+        if (b == 2 + 2 * j) U[j + 1][b] = d2(1, 0);
         if (flag == 1) break;
         const double2 alpha = S.step_alpha[j];
-        for (int i = 0; i <= j; ++i)
-            for (int b = 0; b < NBB; ++b) R[i][b] = csub(R[i][b], cmul(alpha, U[i + 1][b]));
-        R[j + 1][3 + 2 * j] = d2(1, 0);
+        for (int i = 0; i <= j; ++i) R[i][b] = csub(R[i][b], cmul(alpha, U[i + 1][b]));
+        if (b == 3 + 2 * j) R[j + 1][b] = d2(1, 0);
     }
 }
 
@@ -558,13 +558,13 @@ __device__ __forceinline__ void sc_basis_body(const ScalarArgs &a, int rhs) {
     const SeedState &S = a.seed[rhs];
     if (!S.run) return;
     __shared__ double2 R[LMAX + 1][NBB], U[LMAX + 1][NBB];
-    if (threadIdx.x == 0) seed_basis_replay(S, a.l, R, U);
-    __syncthreads();
+    const int b = threadIdx.x;
+    if (b >= NBB) return;
+    seed_basis_replay_col(S, a.l, b, R, U);
     SeedBasis &B = a.sb[rhs];
-    for (int k = threadIdx.x; k < (LMAX + 1) * NBB; k += BLOCK) {
-        const int i = k / NBB, b = k % NBB;
-        B.r[i][b] = R[i][b];
-        B.u[i][b] = U[i][b];
+    for (int i = 0; i <= LMAX; ++i) {
+        B.r[i][b] = i <= a.l ? R[i][b] : d2(0, 0);
+        B.u[i][b] = i <= a.l ? U[i][b] : d2(0, 0);
     }
 }
 
@@ -599,17 +599,16 @@ __device__ __forceinline__ void sc_exh_body(const ScalarArgs &a, int rhs) {
             }
             double fac = 2.0;
             for (int k = 0; k < j - 1; ++k) fac *= a.norm_a;
-            if (rj1 <= fac * FREEZE_FRAC * S.tol * S.bnorm * mn) {
-                check = 1;
-                seed_basis_replay(S, a.l, R, U);
-            }
+            if (rj1 <= fac * FREEZE_FRAC * S.tol * S.bnorm * mn) check = 1;
         }
         S.exh_check = check;
     }
     __syncthreads();
     if (!check) return;
-    SeedBasis &B = a.sb[rhs];
-    for (int b = threadIdx.x; b < NBB; b += BLOCK) B.r[0][b] = R[0][b];
+    const int b = threadIdx.x;
+    if (b >= NBB) return;
+    seed_basis_replay_col(S, a.l, b, R, U);
+    a.sb[rhs].r[0][b] = R[0][b];
 }
 
 }  // namespace dev

@@ -1313,7 +1313,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 const int nbg = std::min(nbv, GRAM_NBMAX);
                 BasisArgs<double> bg = ba;
                 bg.gate = g_run;
-                e.basis_gram(bg, nrhs, nbg, CL_SEED, nr_run * (2.0 * l + 2) * nd * cB);
+                e.basis_gram(bg, nrhs, nbg, CL_SEED, nr_run * (2.0 * l + 1) * nd * cB);   // all but B_1
                 s.nblk = nbg;
                 e.scalar(OP_SC_MR, s, nrhs);
                 s.nblk = nbv;
