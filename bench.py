@@ -500,7 +500,8 @@ def shift_true_residuals(ctx, b, a, sig, xs):
 
 def mixed_floor_block(ctx, b, a, sig, w, l, tols=(1e-4, 1e-6, 1e-8)):
     """Where mixed precision without refinement pays: for each tolerance, the
-    FP64 pseudo-double pass's time beside the mixed deferred single pass's
+    FP64 pseudo-double pass's time (the headline form: seed in basis form)
+    beside the mixed deferred single pass's
     (one warm-up, median of VARIANT_REPS) and the mixed run's per-shift FP64
     true residuals (an untimed run of the same form that keeps the x_s).  The
     mixed run reaches tol only where its FP32 floor lies below it; the largest
@@ -512,7 +513,8 @@ def mixed_floor_block(ctx, b, a, sig, w, l, tols=(1e-4, 1e-6, 1e-8)):
     out = {}
     for tol in tols:
         row = {}
-        for name, pass_, flags in (("fp64-3pass", 3, 0), ("mixed-deferred", 1, msb.MIXED | msb.DEFERRED)):
+        for name, pass_, flags in (("fp64-3pass-basis", 3, msb.SEED_BASIS),
+                                   ("mixed-deferred", 1, msb.MIXED | msb.DEFERRED)):
             ts = []
             for rep in range(VARIANT_REPS + 1):
                 torch.cuda.synchronize()
