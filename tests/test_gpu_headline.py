@@ -1,12 +1,14 @@
 """The configuration bench.py times: 16^3x32, the 12 point sources in one
 batch (chunked stencil), N_s = 30, BiCGstab(4), tol 1e-8, FP64.
 
-  * fixed iterations: the pseudo-double pass and the deferred single pass,
-    forced to 2 outer iterations, against the oracle's iteration for two
-    sampled sources (the oracle cannot run all 12 at this size in seconds);
-  * to convergence: pass 3's y equals the single pass's y, whose every
-    shift solution (12 x 30) meets the tolerance in its true residual,
-    formed with wilson_apply (itself pinned to the oracle elementwise).
+  * fixed iterations: the pseudo-double pass (explicit seed and the bench's
+    basis form) and the deferred single pass, forced to 2 outer iterations,
+    against the oracle's iteration for two sampled sources (the oracle
+    cannot run all 12 at this size in seconds);
+  * to convergence: pass 3's y (both forms of the seed) equals the single
+    pass's y, whose every shift solution (12 x 30) meets the tolerance in
+    its true residual, formed with wilson_apply (itself pinned to the oracle
+    elementwise).
 """
 import numpy as np
 import pytest
@@ -42,15 +44,17 @@ def test_headline_forced_parity_sampled_sources(headline):
     allow = (msb.OK, msb.NOT_CONVERGED, msb.REDUCED_ACCURACY)
     log("headline batch, forced 2 outer iterations: pass 3 and deferred pass 1")
     y3, i3, _ = ctx.mshift_bicgstabl(b, a, sig, w, 4, wk.tol, 2, 3, force_iters=force, allow=allow)
+    yb, ib, _ = ctx.mshift_bicgstabl(b, a, sig, w, 4, wk.tol, 2, 3, flags=msb.SEED_BASIS, force_iters=force,
+                                     allow=allow)
     yd, idf, _ = ctx.mshift_bicgstabl(b, a, sig, w, 4, wk.tol, 2, 1, flags=msb.DEFERRED, force_iters=force,
                                       allow=allow)
     op = od.Dirac(U, wk.dims, wk.mass, wk.mu, wk.bc_t)
     ps = wl.point_sources(wk.dims)
     for k in (0, 7):
         ref = ok.mshift_bicgstabl(lambda v: op.a_op(v, a), ps[k], sig, w, 4, wk.tol, 2, 1, force_iters=force)[0]
-        e3, ed = rel(host(y3)[k], ref), rel(host(yd)[k], ref)
-        log(f"  source {k}: pass 3 {e3:.2e}, deferred pass 1 {ed:.2e}")
-        assert e3 <= 1e-10 and ed <= 1e-10, k
+        e3, eb, ed = rel(host(y3)[k], ref), rel(host(yb)[k], ref), rel(host(yd)[k], ref)
+        log(f"  source {k}: pass 3 {e3:.2e}, pass 3 seed basis {eb:.2e}, deferred pass 1 {ed:.2e}")
+        assert e3 <= 1e-10 and eb <= 1e-10 and ed <= 1e-10, k
 
 
 def test_headline_converged_properties(headline):
@@ -59,10 +63,13 @@ def test_headline_converged_properties(headline):
     wk, U, ctx, a, sig, w, b = headline
     log("headline batch to convergence: pass 3 vs single pass, true residuals")
     y3, i3, _ = ctx.mshift_bicgstabl(b, a, sig, w, 4, wk.tol, 400, 3)
+    yb, ib, _ = ctx.mshift_bicgstabl(b, a, sig, w, 4, wk.tol, 400, 3, flags=msb.SEED_BASIS)
     y1, i1, xs = ctx.mshift_bicgstabl(b, a, sig, w, 4, wk.tol, 400, 1, want_shifts=True)
     d = float(torch.linalg.vector_norm(y3 - y1) / torch.linalg.vector_norm(y1))
-    assert np.array_equal(i3.shift_iters, i1.shift_iters)
-    assert d <= 1e-10
+    db = float(torch.linalg.vector_norm(yb - y1) / torch.linalg.vector_norm(y1))
+    assert np.array_equal(i3.shift_iters, i1.shift_iters) and np.array_equal(ib.shift_iters, i1.shift_iters)
+    assert d <= 1e-10 and db <= 1e-10
+    del yb
     bn = torch.linalg.vector_norm(b.reshape(12, -1), dim=1)
     worst = 0.0
     for s in range(len(sig)):
@@ -71,5 +78,5 @@ def test_headline_converged_properties(headline):
         r = b - a * t - sig[s] * x
         worst = max(worst, float((torch.linalg.vector_norm(r.reshape(12, -1), dim=1) / bn).max()))
         del x, t, r
-    log(f"  M = {i3.outer_iters}, pass 3 vs pass 1 {d:.2e}, worst true residual {worst:.2e}")
+    log(f"  M = {i3.outer_iters}, pass 3 vs pass 1 {d:.2e} (seed basis {db:.2e}), worst true residual {worst:.2e}")
     assert worst <= wk.tol

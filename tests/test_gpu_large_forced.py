@@ -83,7 +83,8 @@ def check(name, errs, bound):
 
 
 FORMS = [("pass 1", 1, 0, True), ("pass 1 deferred", 1, "DEFERRED", True), ("pass 2", 2, 0, False),
-         ("pass 3", 3, 0, False)]
+         ("pass 3", 3, 0, False), ("pass 2 seed basis", 2, "SEED_BASIS", False),
+         ("pass 3 seed basis", 3, "SEED_BASIS", False)]
 
 
 @pytest.fixture(scope="module")
