@@ -96,9 +96,10 @@ typedef enum {
                                other r_i, u_i of the outer iteration is kept
                                as coefficients on its 2l+2 basis vectors (r_0,
                                u_0 and the Mv outputs) and formed from them
-                               for the MR step.  Same iterates up to rounding,
-                               fewer vector passes per outer iteration (about
-                               2/3 of them at l = 4); + nrhs * n * 32 bytes of
+                               for the MR step; the double pass's replay
+                               likewise.  Same iterates up to rounding, fewer
+                               vector passes per outer iteration (about 2/3
+                               of them at l = 4); + nrhs * n * 32 bytes of
                                workspace.                                     */
 #define MSB_REFINE    128   /* pass 1: after the solve, the FP64 true residual of
                                every shift; shifts above tol get refinement

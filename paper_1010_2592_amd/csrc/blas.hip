@@ -283,6 +283,10 @@ template <int L>
 __global__ __launch_bounds__(BLOCK) void k_basis_mr_update(BasisArgs<double> a) {
     basis_mr_update_body<L>(a, blockIdx.x, gridDim.x, blockIdx.y);
 }
+template <int L>
+__global__ __launch_bounds__(BLOCK) void k_basis_combine(BasisArgs<double> a) {
+    basis_combine_body<L>(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
 
 }  // namespace
 
@@ -593,6 +597,14 @@ void launch_basis_mr_update(hipStream_t st, const BasisArgs<double> &a, int nrhs
     dim3 g(nblk, nrhs), b(BLOCK);
     switch (a.l) {
 #define C_(L) case L: hipLaunchKernelGGL((k_basis_mr_update<L>), g, b, 0, st, a); break;
+        C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8)
+#undef C_
+    }
+}
+void launch_basis_combine(hipStream_t st, const BasisArgs<double> &a, int nrhs, int nblk) {
+    dim3 g(nblk, nrhs), b(BLOCK);
+    switch (a.l) {
+#define C_(L) case L: hipLaunchKernelGGL((k_basis_combine<L>), g, b, 0, st, a); break;
         C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8)
 #undef C_
     }

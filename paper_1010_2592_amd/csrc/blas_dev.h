@@ -430,5 +430,38 @@ __device__ __forceinline__ void basis_mr_update_body(const BasisArgs<double> &a,
     block_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + bx, a.ps);
 }
 
+// Replay of the double pass in basis form: r_0 and u_0 after the outer
+// iteration, written over B_0 and B_1 (no partial sums: the replay takes no
+// inner products)
+template <int L>
+__device__ __forceinline__ void basis_combine_body(const BasisArgs<double> &a, int bx, int gx, int rhs) {
+    if (!gate_open(a.gate, rhs)) return;
+    constexpr int NBL = 2 * L + 2;
+    const SeedBasis &SB = a.sb[rhs];
+    __shared__ double2 c_r[NBL], c_u[NBL];
+    if (threadIdx.x < NBL) {
+        c_r[threadIdx.x] = SB.r[0][threadIdx.x];
+        c_u[threadIdx.x] = SB.u[0][threadIdx.x];
+    }
+    __syncthreads();
+    const int nbu = SB.nbu;
+    const long n = a.n;
+    double2 *R0 = a.R0 + (size_t)rhs * a.r0_rs, *U0 = a.U0 + (size_t)rhs * a.u0_rs;
+    for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
+        asm volatile("" ::: "memory");   // coefficients from LDS in every pass
+        double2 B[NBL];
+#pragma unroll
+        for (int b = 0; b < NBL; ++b) B[b] = b < nbu ? bvec(a, b, rhs, e) : d2(0, 0);
+        double2 r0 = d2(0, 0), u0 = d2(0, 0);
+#pragma unroll
+        for (int b = 0; b < NBL; ++b) {
+            r0 = cfma(c_r[b], B[b], r0);
+            u0 = cfma(c_u[b], B[b], u0);
+        }
+        R0[e] = r0;
+        U0[e] = u0;
+    }
+}
+
 }  // namespace dev
 }  // namespace msb

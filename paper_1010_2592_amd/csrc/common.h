@@ -262,6 +262,11 @@ constexpr int NBB = 2 * LMAX + 2;
 struct SeedBasis {
     double2 r[LMAX + 1][NBB];
     double2 u[LMAX + 1][NBB];
+    // replay of the double pass: r[0], u[0] hold r_0, u_0 after the outer
+    // iteration's MR step, formed from the first nbu basis vectors (0: the
+    // iteration leaves r_0 and u_0 as they are)
+    int nbu;
+    int pad_[3];
 };
 
 struct ShiftState {

@@ -192,6 +192,10 @@ struct BasisArgs {
     const C<T> *rt = nullptr;
 };
 void launch_basis_axpy(hipStream_t, const BasisArgs<double> &, int nrhs, int nblk);
+// replay of the double pass in basis form: r_0, u_0 after outer iteration
+// m from the basis with the coefficients of sc_basis_replay (sb[rhs].r[0],
+// u[0], over the first sb[rhs].nbu basis vectors), written over B_0, B_1
+void launch_basis_combine(hipStream_t, const BasisArgs<double> &, int nrhs, int nblk);
 void launch_basis_r0norm(hipStream_t, const BasisArgs<double> &, int nrhs, int nblk);
 void launch_basis_gram(hipStream_t, const BasisArgs<double> &, int nrhs, int nblk);
 void launch_basis_mr_update(hipStream_t, const BasisArgs<double> &, int nrhs, int nblk);
@@ -314,6 +318,16 @@ void launch_sc_conv(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_rel(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_defer(hipStream_t, const ScalarArgs &, int nrhs);
 void launch_sc_basis(hipStream_t, const ScalarArgs &, int nrhs);
+// Replay of the double pass in basis form: outer iteration m's recorded step
+// coefficients and MR coefficients (rs [rhs][Mcap][l], ro [rhs][Mcap]) as the
+// combined coefficients of r_0 and u_0 after the iteration (sb[rhs])
+struct BasisReplayArgs {
+    const ReplayStep *rs = nullptr;
+    const ReplayOuter *ro = nullptr;
+    int Mcap = 0, l = 0, m = 0;
+    SeedBasis *sb = nullptr;
+};
+void launch_sc_basis_replay(hipStream_t, const BasisReplayArgs &, int nrhs);
 void launch_sc_exh(hipStream_t, const ScalarArgs &, int nrhs);
 
 // ---- persistent execution --------------------------------------------------

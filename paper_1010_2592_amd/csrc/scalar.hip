@@ -37,6 +37,7 @@ __global__ __launch_bounds__(BLOCK) void sc_conv(ScalarArgs a) { sc_conv_body(a,
 __global__ __launch_bounds__(BLOCK) void sc_defer(ScalarArgs a) { sc_defer_body(a, blockIdx.x); }
 __global__ __launch_bounds__(BLOCK) void sc_basis(ScalarArgs a) { sc_basis_body(a, blockIdx.x); }
 __global__ __launch_bounds__(BLOCK) void sc_exh(ScalarArgs a) { sc_exh_body(a, blockIdx.x); }
+__global__ __launch_bounds__(64) void sc_basis_replay(BasisReplayArgs a) { sc_basis_replay_body(a, blockIdx.x); }
 
 }  // namespace
 
@@ -66,6 +67,9 @@ void launch_sc_basis(hipStream_t st, const ScalarArgs &a, int nrhs) {
 }
 void launch_sc_exh(hipStream_t st, const ScalarArgs &a, int nrhs) {
     hipLaunchKernelGGL(sc_exh, dim3(nrhs), dim3(BLOCK), 0, st, a);
+}
+void launch_sc_basis_replay(hipStream_t st, const BasisReplayArgs &a, int nrhs) {
+    hipLaunchKernelGGL(sc_basis_replay, dim3(nrhs), dim3(64), 0, st, a);
 }
 
 }  // namespace msb

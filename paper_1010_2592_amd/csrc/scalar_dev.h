@@ -534,22 +534,33 @@ __device__ __forceinline__ void sc_defer_body(const ScalarArgs &a, int rhs) {
 // u_{j+1} = S u_j, then r_i = r_i - alpha u_{i+1} (i <= j), r_{j+1} = S r_j.
 // The recurrences act on each basis index b alone: one work-item per b
 // (column b of R and U).
-__device__ inline void seed_basis_replay_col(const SeedState &S, int l, int b, double2 (*R)[NBB],
-                                             double2 (*U)[NBB]) {
+// STEP(j, flag, beta, alpha) gives step j's flag and coefficients.
+template <typename STEP>
+__device__ inline void basis_replay_col(const STEP &step, int l, int b, double2 (*R)[NBB], double2 (*U)[NBB]) {
     for (int i = 0; i <= l; ++i) R[i][b] = U[i][b] = d2(0, 0);
     if (b == 0) R[0][0] = d2(1, 0);
     if (b == 1) U[0][1] = d2(1, 0);
     for (int j = 0; j < l; ++j) {
-        const int flag = S.step_flag[j];
+        int flag;
+        double2 beta, alpha;
+        step(j, flag, beta, alpha);
         if (flag == 0) break;
-        const double2 beta = S.step_beta[j];
         for (int i = 0; i <= j; ++i) U[i][b] = csub(R[i][b], cmul(beta, U[i][b]));
         if (b == 2 + 2 * j) U[j + 1][b] = d2(1, 0);
         if (flag == 1) break;
-        const double2 alpha = S.step_alpha[j];
         for (int i = 0; i <= j; ++i) R[i][b] = csub(R[i][b], cmul(alpha, U[i + 1][b]));
         if (b == 3 + 2 * j) R[j + 1][b] = d2(1, 0);
     }
+}
+__device__ inline void seed_basis_replay_col(const SeedState &S, int l, int b, double2 (*R)[NBB],
+                                             double2 (*U)[NBB]) {
+    basis_replay_col(
+        [&](int j, int &flag, double2 &beta, double2 &alpha) {
+            flag = S.step_flag[j];
+            beta = S.step_beta[j];
+            alpha = S.step_alpha[j];
+        },
+        l, b, R, U);
 }
 
 // Basis form, before the MR step: every r_i and u_i of the outer iteration as
@@ -565,6 +576,39 @@ __device__ __forceinline__ void sc_basis_body(const ScalarArgs &a, int rhs) {
     for (int i = 0; i <= LMAX; ++i) {
         B.r[i][b] = i <= a.l ? R[i][b] : d2(0, 0);
         B.u[i][b] = i <= a.l ? U[i][b] : d2(0, 0);
+    }
+}
+
+// Replay of the double pass in basis form, after outer iteration m's steps:
+// the recorded steps replayed on the basis coefficients, then the recorded
+// MR step, r_0 - sum_i gamma_i r_i and u_0 - sum_i gamma_i u_i (i <= lm),
+// with the arithmetic of the first pass's MR update.
+__device__ __forceinline__ void sc_basis_replay_body(const BasisReplayArgs &a, int rhs) {
+    __shared__ double2 R[LMAX + 1][NBB], U[LMAX + 1][NBB];
+    const ReplayStep *rs = a.rs + ((size_t)rhs * a.Mcap + a.m) * a.l;
+    const ReplayOuter &ro = a.ro[(size_t)rhs * a.Mcap + a.m];
+    const int b = threadIdx.x;
+    if (b >= NBB) return;
+    basis_replay_col(
+        [&](int j, int &flag, double2 &beta, double2 &alpha) {
+            flag = rs[j].flag;
+            beta = rs[j].beta;
+            alpha = rs[j].alpha;
+        },
+        a.l, b, R, U);
+    const int lm = ro.lm < a.l ? ro.lm : a.l;
+    double2 vr = R[0][b], vu = U[0][b];
+    for (int i = 1; i <= lm; ++i) {
+        vr = csub(vr, cmul(ro.gam[i - 1], R[i][b]));
+        vu = csub(vu, cmul(ro.gam[i - 1], U[i][b]));
+    }
+    SeedBasis &B = a.sb[rhs];
+    B.r[0][b] = vr;
+    B.u[0][b] = vu;
+    if (b == 0) {
+        int le = 0;
+        while (le < a.l && rs[le].flag == 2) ++le;
+        B.nbu = (rs[0].flag == 0 && ro.lm == 0) ? 0 : 2 * le + 2;
     }
 }
 

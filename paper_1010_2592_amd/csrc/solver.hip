@@ -725,6 +725,18 @@ struct Emit {
             launch_basis_mr_update(st, a, nrhs, nblk);
         }
     }
+    void basis_combine(const BasisArgs<double> &a, int nrhs, int nblk, int cls, double bytes) {
+        if (launching(cls, bytes)) {
+            Prof p(c, cls, bytes);
+            launch_basis_combine(st, a, nrhs, nblk);
+        }
+    }
+    void basis_replay(const BasisReplayArgs &a, int nrhs) {
+        if (launching(CL_SCALAR, 0.0)) {
+            Prof p(c, CL_SCALAR, 0);
+            launch_sc_basis_replay(st, a, nrhs);
+        }
+    }
     void scalar(int kind, const ScalarArgs &a, int nrhs) {
         if (launching(CL_SCALAR, 0.0)) {
             Prof p(c, CL_SCALAR, 0);
@@ -1625,6 +1637,94 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         for (int m = m_rep; m < Mmax; ++m) {
             int nr_m = 0;      // right-hand sides whose replay reaches outer iteration m
             for (int r = 0; r < nrhs; ++r) nr_m += (fs[r].m > m) ? 1 : 0;
+            if constexpr (std::is_same<T, double>::value) {
+                if (basis) {
+                    // the replay in basis form: the first pass's two vector
+                    // updates per step (recorded beta, alpha), its Mv outputs
+                    // into rows 1..l of U and R, then r_0 and u_0 from the
+                    // basis with the recorded MR coefficients
+                    BasisArgs<double> ba;
+                    ba.n = n;
+                    ba.l = l;
+                    ba.sb = (const SeedBasis *)c->ws_sb.p;
+                    ba.bv[0] = R;
+                    ba.bv[1] = Uv;
+                    for (int t = 0; t < 2 * l + 2; ++t) ba.brs[t] = vs;
+                    for (int j = 0; j < l; ++j) {
+                        ba.bv[2 + 2 * j] = Uv + (size_t)(j + 1) * n;
+                        ba.bv[3 + 2 * j] = R + (size_t)(j + 1) * n;
+                    }
+                    double2 *WU = (double2 *)c->ws_bw.p, *WR = WU + (size_t)nrhs * n;
+                    for (int j = 0; j < l; ++j) {
+                        const size_t idx = (size_t)m * l + j;
+                        Gate gu;
+                        gu.flag = &drs[idx].flag;
+                        gu.flag_stride = rstride / (long)sizeof(int);
+                        gu.need = 1;
+                        Gate gr = gu;
+                        gr.need = 2;
+                        const int xi = (j == 0) ? 0 : 2 * j + 1, yi = (j == 0) ? 1 : 2 * j;
+                        BasisArgs<double> bu = ba;
+                        bu.gate = gu;
+                        bu.dst = WU;
+                        bu.dst_rs = n;
+                        bu.x = ba.bv[xi];
+                        bu.x_rs = vs;
+                        bu.y = ba.bv[yi];
+                        bu.y_rs = vs;
+                        bu.c = CoefRef{(const char *)&drs[idx].beta, rstride};
+                        e.basis_axpy(bu, nrhs, nbv, CL_SEED, nr_m * 3.0 * nd * cB);
+                        DslashArgs<T> f1 = e1, f2 = e2;
+                        f1.in = WU;
+                        f1.in_rs = n;
+                        f1.out = tmp;
+                        f1.gate = gu;
+                        if (!opw) e.ds(f1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_m));
+                        f2.in = opw ? WU : tmp;
+                        f2.in_rs = n;
+                        f2.out = (C<T> *)ba.bv[2 + 2 * j];
+                        f2.v = WU;
+                        f2.v_rs = n;
+                        f2.ycoef = CoefRef{(const char *)&drs[idx].cu, rstride};
+                        f2.gate = gu;
+                        e.ds(f2, nrhs, EPI_MV_Y, CL_STENCIL, ds_bytes(EPI_MV_Y, nr_m));
+                        BasisArgs<double> br = bu;
+                        br.gate = gr;
+                        br.dst = WR;
+                        br.y = ba.bv[2 + 2 * j];
+                        br.c = CoefRef{(const char *)&drs[idx].alpha, rstride};
+                        e.basis_axpy(br, nrhs, nbv, CL_SEED, nr_m * 3.0 * nd * cB);
+                        f1.in = WR;
+                        f1.gate = gr;
+                        if (!opw) e.ds(f1, nrhs, EPI_PLAIN, CL_STENCIL, ds_bytes(EPI_PLAIN, nr_m));
+                        f2.in = opw ? WR : tmp;
+                        f2.out = (C<T> *)ba.bv[3 + 2 * j];
+                        f2.v = WR;
+                        f2.ycoef = CoefRef{(const char *)&drs[idx].cr, rstride};
+                        f2.gate = gr;
+                        e.ds(f2, nrhs, EPI_MV_Y, CL_STENCIL, ds_bytes(EPI_MV_Y, nr_m));
+                    }
+                    BasisReplayArgs ra;
+                    ra.rs = drs;
+                    ra.ro = dro;
+                    ra.Mcap = Mcap;
+                    ra.l = l;
+                    ra.m = m;
+                    ra.sb = (SeedBasis *)c->ws_sb.p;
+                    e.basis_replay(ra, nrhs);
+                    BasisArgs<double> bm = ba;
+                    bm.gate.flag = &((const SeedBasis *)c->ws_sb.p)[0].nbu;
+                    bm.gate.flag_stride = (long)sizeof(SeedBasis) / (long)sizeof(int);
+                    bm.gate.need = 1;
+                    bm.R0 = R;
+                    bm.r0_rs = vs;
+                    bm.U0 = Uv;
+                    bm.u0_rs = vs;
+                    e.basis_combine(bm, nrhs, nbv, CL_SEED, nr_m * (2.0 * l + 4) * nd * cB);
+                    HIPCHK(hipGetLastError());
+                    continue;
+                }
+            }
             for (int j = 0; j < l; ++j) {
                 const size_t idx = (size_t)m * l + j;
                 Gate gu;
