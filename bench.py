@@ -575,8 +575,8 @@ def main():
     ap.add_argument("--deferred", default="auto", choices=("auto", "on", "off"),
                     help="pass 1: shift vectors updated once per outer iteration; auto: on for pass 1")
     ap.add_argument("--seed-basis", default="auto", choices=("auto", "on", "off"),
-                    help="passes 2, 3 (FP64, stages): the seed's lower vectors as coefficients on the "
-                         "outer iteration's basis; auto: on where it applies")
+                    help="passes 2, 3 and the deferred pass 1 (FP64, stages): the seed's lower vectors as "
+                         "coefficients on the outer iteration's basis; auto: on where it applies")
     ap.add_argument("--refine", default="auto", choices=("auto", "on", "off"),
                     help="per-shift FP64 true residual + refinement (pass 1); auto: on for mixed pass 1")
     ap.add_argument("--launch", default="stages", choices=("stages", "persistent"),
@@ -642,7 +642,7 @@ def main():
     persistent = args.launch == "persistent"
     refine = args.pass_ == 1 and (args.refine == "on" or (args.refine == "auto" and mixed))
     deferred = args.pass_ == 1 and args.deferred != "off" and not persistent
-    basis = args.pass_ != 1 and not mixed and not persistent and args.seed_basis != "off"
+    basis = (args.pass_ != 1 or deferred) and not mixed and not persistent and args.seed_basis != "off"
     log(f"[bench] spectral radius {rho:.6f}; headline pass={args.pass_} {args.precision} {args.launch}")
 
     for i in range(args.warmup):
@@ -757,7 +757,8 @@ def main():
         forms = [(1, False, False, False, False, False), (2, False, False, False, False, False),
                  (2, False, False, False, False, True), (1, True, False, False, False, False),
                  (2, True, False, False, False, False), (1, True, False, True, False, False),
-                 (1, False, False, False, True, False), (1, True, False, False, True, False),
+                 (1, False, False, False, True, False), (1, False, False, False, True, True),
+                 (1, True, False, False, True, False),
                  (1, True, False, True, True, False), (1, False, True, False, False, False),
                  (2, False, True, False, False, False), (1, True, True, False, False, False),
                  (1, True, True, True, False, False), (2, True, True, False, False, False),

@@ -90,7 +90,8 @@ typedef enum {
                                space.  Not with MSB_ADJOINT, pfe_sign_apply or
                                pfe_sign_backward (which need the Hermitian
                                kernel H = gamma5 D_w).                          */
-#define MSB_SEED_BASIS 1024 /* pass 2, 3 (FP64, not MSB_MIXED or MSB_PERSISTENT):
+#define MSB_SEED_BASIS 1024 /* pass 2, 3, or 1 with MSB_DEFERRED (FP64, not
+                               MSB_MIXED or MSB_PERSISTENT):
                                the seed's BiCG steps of Section 2 update only
                                the two vectors the step's Mv reads; every
                                other r_i, u_i of the outer iteration is kept
@@ -225,7 +226,8 @@ int wilson_apply(msb_ctx *ctx, const void *in, void *out, int nrhs, int flags);
  *   flags            MSB_MIXED, MSB_PERSISTENT, MSB_ADJOINT, MSB_REFINE (pass 1),
  *                    MSB_DEFERRED (pass 1, not with MSB_PERSISTENT),
  *                    MSB_OP_WILSON (A = a D_w; not with MSB_ADJOINT),
- *                    MSB_SEED_BASIS (pass 2 or 3, FP64, one launch per stage)
+ *                    MSB_SEED_BASIS (pass 2 or 3, or 1 with MSB_DEFERRED; FP64,
+ *                    one launch per stage)
  *   b                device [nrhs][12][V] complex128
  *   y                device [nrhs][12][V] complex128 (written)
  *   x_shifts         device [nrhs][n_shift][12][V] complex128 or NULL

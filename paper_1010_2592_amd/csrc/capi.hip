@@ -50,8 +50,9 @@ int make_params(msb_ctx *ctx, double a_scale, int n_shift, const double *shifts,
     if (flags & ~(MSB_MIXED | MSB_PERSISTENT | MSB_ADJOINT | MSB_OVERLAP | MSB_REFINE | MSB_DEFERRED |
                   MSB_OP_WILSON | MSB_SEED_BASIS))
         return arg_error(w + ": unknown flag bits");
-    if ((flags & MSB_SEED_BASIS) && pass == 1)
-        return arg_error(w + ": MSB_SEED_BASIS is a form of the double pass (pass = 2 or 3)");
+    if ((flags & MSB_SEED_BASIS) && pass == 1 && !(flags & MSB_DEFERRED))
+        return arg_error(w + ": MSB_SEED_BASIS needs pass = 2 or 3, or pass = 1 with MSB_DEFERRED (the per-step "
+                             "shift updates read every r_i of every step)");
     if ((flags & MSB_SEED_BASIS) && (flags & (MSB_MIXED | MSB_PERSISTENT)))
         return arg_error(w + ": MSB_SEED_BASIS runs in FP64 with one launch per stage (not MSB_MIXED, "
                              "MSB_PERSISTENT)");

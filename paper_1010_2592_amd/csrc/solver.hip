@@ -896,7 +896,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     }
     // basis form of the seed: the two vectors each BiCG step feeds its Mv
     // (u_j, r_j after their updates) and the basis coefficients
-    const bool basis = P.seed_basis && !mixed && !P.persistent && !pass1;
+    const bool basis = P.seed_basis && !mixed && !P.persistent && (!pass1 || deferred);
     if (basis) {
         CHK(ensure(c, c->ws_bw, (size_t)2 * nrhs * n * cs));
         CHK(ensure(c, c->ws_sb, (size_t)nrhs * sizeof(SeedBasis)));
@@ -1226,8 +1226,9 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 // vectors its Mv read (into the work vectors WU, WR); the
                 // iteration's r_i and u_i are coefficients on its basis B
                 // (B_0 = r_0, B_1 = u_0 at the start, the Mv outputs after:
-                // the store slots of pass 3, else rows 1..l of U and R),
-                // formed from it for the Gram matrix and the MR update
+                // the store slots of pass 3 or the deferred single pass's
+                // basis slots, else rows 1..l of U and R), formed from it
+                // for the Gram matrix and the MR update
                 BasisArgs<double> ba;
                 ba.n = n;
                 ba.l = l;
@@ -1240,9 +1241,9 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 ba.bv[1] = Uv;
                 ba.brs[1] = vs;
                 for (int j = 0; j < l; ++j) {
-                    ba.bv[2 + 2 * j] = keep ? slot(2 * j) : Uv + (size_t)(j + 1) * n;
-                    ba.bv[3 + 2 * j] = keep ? slot(2 * j + 1) : R + (size_t)(j + 1) * n;
-                    ba.brs[2 + 2 * j] = ba.brs[3 + 2 * j] = keep ? store_rs : vs;
+                    ba.bv[2 + 2 * j] = stored ? slot(2 * j) : Uv + (size_t)(j + 1) * n;
+                    ba.bv[3 + 2 * j] = stored ? slot(2 * j + 1) : R + (size_t)(j + 1) * n;
+                    ba.brs[2 + 2 * j] = ba.brs[3 + 2 * j] = stored ? store_rs : vs;
                 }
                 double2 *WU = (double2 *)c->ws_bw.p, *WR = WU + (size_t)nrhs * n;
                 Gate g_exh;
@@ -1339,6 +1340,14 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 e.basis_mr_update(bm, nrhs, nbv, CL_SEED,
                                   nr_run * (2.0 * l + 4 + (sparse_rt ? 0 : 1)) * nd * cB);
                 if (sparse_rt) sparse_dot_of(e, R, g_run, nr_run, vs);
+                if (deferred) {
+                    // every shift's update over the iteration from the basis
+                    // (B_0, B_1 from the snapshot: the MR update has just
+                    // overwritten r_0 and u_0)
+                    e.scalar(OP_SC_DEFER, s, nrhs);
+                    v.gate = g_run;
+                    e.defer_update(v, nrhs, nbv, CL_SHIFT_MR, nr_run * nb * nd * cB + nsh_act * (2.0 * cB + 32.0) * nd);
+                }
                 e.scalar(OP_SC_CONV, s, nrhs);
                 return;
             }

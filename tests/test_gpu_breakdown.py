@@ -2,8 +2,8 @@
 inputs of tests/breakdown_cases.py (built with the oracle's operator) and the
 oracle's iteration as the reference: status, every shift's M_s, y and every
 x_s, for the per-step and deferred single pass, the double and the
-pseudo-double pass (explicit and basis form of the seed), and the persistent
-launch.
+pseudo-double pass (explicit and basis form of the seed; the deferred single
+pass in both forms too), and the persistent launch.
 
   * gamma breakdown in step 1 (l = 2, 3): the partial step, the completion
     of the direction updates it owes, the MR step over the completed step;
@@ -31,6 +31,7 @@ pytestmark = pytest.mark.gpu
 
 FORMS = [("pass1", 1, 0), ("pass1-deferred", 1, "DEFERRED"), ("pass2", 2, 0), ("pass3", 3, 0),
          ("pass2-basis", 2, "SEED_BASIS"), ("pass3-basis", 3, "SEED_BASIS"),
+         ("pass1-deferred-basis", 1, "DEFERRED|SEED_BASIS"),
          ("pass1-persistent", 1, "PERSISTENT"), ("pass2-persistent", 2, "PERSISTENT")]
 
 
@@ -64,7 +65,7 @@ def compare_forms(ctx, a, b, sig, w, l, tol, max_outer, y0, i0, X0, bound, shado
     from paper_1010_2592_amd import msb
     allow = (msb.OK, msb.NOT_CONVERGED, msb.BREAKDOWN)
     for name, pass_, fl in FORMS:
-        flags = getattr(msb, fl) if fl else 0
+        flags = sum(getattr(msb, f) for f in fl.split("|")) if fl else 0
         want = pass_ == 1
         y, info, xs = ctx.mshift_bicgstabl(cuda(b[None]), a, sig, w, l, tol, max_outer, pass_, flags=flags,
                                            want_shifts=want, allow=allow, force_iters=force,
