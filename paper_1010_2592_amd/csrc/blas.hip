@@ -87,26 +87,40 @@ __global__ __launch_bounds__(BLOCK) void k_defer_update(VecArgs<T> a) {
     const int nact = a.seed[rhs].nact;
     const C<T> *B = a.Bm + (size_t)rhs * NB * n;
     const DeferCoef *dc = a.dc + (size_t)rhs * NSMAX;
+    // one shift's update of element e from its loaded u^s_0 and x^s
+    auto upd = [&](const DeferCoef &d, const C<T> (&b)[NB], long e, C<T> u0, double2 x0) {
+        const double2 u0d = d2((double)u0.x, (double)u0.y);
+        C<T> un = cmul(cvt<T>(d.cu[NB]), u0);
+        double2 xn = cfma(d.cx[NB], u0d, x0);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            un = cfma(cvt<T>(d.cu[k]), b[k], un);
+            xn = cfma(d.cx[k], d2((double)b[k].x, (double)b[k].y), xn);
+        }
+        a.W0[((size_t)rhs * a.nshift + d.s) * n + e] = un;
+        a.X[((size_t)rhs * a.nshift + d.s) * n + e] = xn;
+    };
     for (long e = (long)blockIdx.x * BLOCK + threadIdx.x; e < n; e += (long)gridDim.x * BLOCK) {
         C<T> b[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) b[k] = B[k * n + e];
-        for (int q = 0; q < nact; ++q) {
+        // two shifts at a time: their four loads issue together (every
+        // shift's vectors exist; a shift that stopped is loaded, not written)
+        int q = 0;
+        for (; q + 1 < nact; q += 2) {
+            const DeferCoef &d0 = dc[q], &d1 = dc[q + 1];
+            const size_t o0 = ((size_t)rhs * a.nshift + d0.s) * n + e, o1 = ((size_t)rhs * a.nshift + d1.s) * n + e;
+            const C<T> u0 = a.W0[o0], u1 = a.W0[o1];
+            const double2 x0 = a.X[o0], x1 = a.X[o1];
+            if (d0.live) upd(d0, b, e, u0, x0);
+            if (d1.live) upd(d1, b, e, u1, x1);
+        }
+        if (q < nact) {
             const DeferCoef &d = dc[q];
-            if (!d.live) continue;
-            C<T> *W = a.W0 + ((size_t)rhs * a.nshift + d.s) * n;
-            double2 *X = a.X + ((size_t)rhs * a.nshift + d.s) * n;
-            const C<T> u0 = W[e];
-            const double2 u0d = d2((double)u0.x, (double)u0.y);
-            C<T> un = cmul(cvt<T>(d.cu[NB]), u0);
-            double2 xn = cfma(d.cx[NB], u0d, X[e]);
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                un = cfma(cvt<T>(d.cu[k]), b[k], un);
-                xn = cfma(d.cx[k], d2((double)b[k].x, (double)b[k].y), xn);
+            if (d.live) {
+                const size_t o = ((size_t)rhs * a.nshift + d.s) * n + e;
+                upd(d, b, e, a.W0[o], a.X[o]);
             }
-            W[e] = un;
-            X[e] = xn;
         }
     }
 }
