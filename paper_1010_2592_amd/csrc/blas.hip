@@ -100,10 +100,20 @@ __global__ __launch_bounds__(BLOCK) void k_defer_update(VecArgs<T> a) {
         a.W0[((size_t)rhs * a.nshift + d.s) * n + e] = un;
         a.X[((size_t)rhs * a.nshift + d.s) * n + e] = xn;
     };
+    // basis vectors this outer iteration wrote (r_0, u_0, then the Mv outputs
+    // of the steps it made): the slots after them hold whatever an earlier
+    // call left, which zero coefficients must not meet (0 * NaN)
+    int nbw = 2;
+    for (int j = 0; j < L; ++j) {
+        const int f = a.seed[rhs].step_flag[j];
+        if (f >= 1) nbw = 3 + 2 * j;
+        if (f == 2) nbw = 4 + 2 * j;
+        if (f < 2) break;
+    }
     for (long e = (long)blockIdx.x * BLOCK + threadIdx.x; e < n; e += (long)gridDim.x * BLOCK) {
         C<T> b[NB];
 #pragma unroll
-        for (int k = 0; k < NB; ++k) b[k] = B[k * n + e];
+        for (int k = 0; k < NB; ++k) b[k] = k < nbw ? B[k * n + e] : mk<T>(0, 0);
         // two shifts at a time: their four loads issue together (every
         // shift's vectors exist; a shift that stopped is loaded, not written)
         int q = 0;
@@ -296,6 +306,10 @@ __global__ __launch_bounds__(BLOCK) void k_basis_gram(BasisArgs<double> a) {
 template <int L>
 __global__ __launch_bounds__(BLOCK) void k_basis_mr_update(BasisArgs<double> a) {
     basis_mr_update_body<L>(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+template <int L>
+__global__ __launch_bounds__(64) void k_basis_spec(BasisArgs<double> a) {
+    basis_spec_body<L>(a, blockIdx.x);
 }
 template <int L>
 __global__ __launch_bounds__(BLOCK) void k_basis_combine(BasisArgs<double> a) {
@@ -611,6 +625,13 @@ void launch_basis_mr_update(hipStream_t st, const BasisArgs<double> &a, int nrhs
     dim3 g(nblk, nrhs), b(BLOCK);
     switch (a.l) {
 #define C_(L) case L: hipLaunchKernelGGL((k_basis_mr_update<L>), g, b, 0, st, a); break;
+        C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8)
+#undef C_
+    }
+}
+void launch_basis_spec(hipStream_t st, const BasisArgs<double> &a, int nrhs) {
+    switch (a.l) {
+#define C_(L) case L: hipLaunchKernelGGL((k_basis_spec<L>), dim3(nrhs), dim3(64), 0, st, a); break;
         C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8)
 #undef C_
     }

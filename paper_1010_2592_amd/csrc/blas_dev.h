@@ -407,6 +407,15 @@ __device__ __forceinline__ void basis_mr_update_body(const BasisArgs<double> &a,
     double2 *R0 = a.R0 + (size_t)rhs * a.r0_rs, *U0 = a.U0 + (size_t)rhs * a.u0_rs;
     const double2 *rt = a.rt ? a.rt + (size_t)rhs * n : nullptr;
     double part[3] = {0.0, 0.0, 0.0};
+    // with the sparse r~ (basis_spec_body, before this kernel: r_0 and u_0
+    // are overwritten here): <r~, r_0> into rows 0, 1 and the next outer
+    // iteration's first direction update with its beta
+    double2 *WU = a.wu ? a.wu + (size_t)rhs * n : nullptr;
+    const double2 bspec = S.beta_spec;
+    if (WU && bx == 0 && threadIdx.x == 0) {
+        part[0] = S.spec_rho1.x;
+        part[1] = S.spec_rho1.y;
+    }
     for (long e = (long)bx * BLOCK + threadIdx.x; e < n; e += (long)gx * BLOCK) {
         asm volatile("" ::: "memory");   // coefficients from LDS in every pass (as in the Gram kernel)
         double2 B[NBL];
@@ -420,6 +429,7 @@ __device__ __forceinline__ void basis_mr_update_body(const BasisArgs<double> &a,
         }
         R0[e] = r0;
         U0[e] = u0;
+        if (WU) WU[e] = csub(r0, cmul(bspec, u0));
         if (rt) {
             const double2 t = rt[e];
             part[0] += t.x * r0.x + t.y * r0.y;
@@ -428,6 +438,49 @@ __device__ __forceinline__ void basis_mr_update_body(const BasisArgs<double> &a,
         part[2] += r0.x * r0.x + r0.y * r0.y;
     }
     block_reduce_store<3>(part, a.part + (size_t)rhs * PMAX * a.ps + bx, a.ps);
+}
+
+// Basis form with a sparse r~, after the MR step's coefficients and before
+// the MR update overwrites r_0 and u_0: r_0 after the MR step at the list's
+// entries (the MR update's combined coefficients), <r~, r_0>, and the next
+// outer iteration's beta = alpha rho_1 / rho_0 with rho_0 <- -omega rho_0
+// (as its first step will find it), into seed_w[rhs] (one block per rhs).
+template <int L>
+__device__ __forceinline__ void basis_spec_body(const BasisArgs<double> &a, int rhs) {
+    if (!gate_open(a.gate, rhs)) return;
+    constexpr int NBL = 2 * L + 2;
+    const SeedState &S = a.seed[rhs];
+    __shared__ double2 c_r[NBL];
+    __shared__ double2 rk[SPARSE_MAX];
+    if (threadIdx.x < NBL) {
+        const int b = threadIdx.x;
+        const SeedBasis &SB = a.sb[rhs];
+        const int lm = S.l_mr < L ? S.l_mr : L;
+        double2 vr = SB.r[0][b];
+        for (int i = 1; i <= lm; ++i) vr = csub(vr, cmul(S.gam[i - 1], SB.r[i][b]));
+        c_r[b] = vr;
+    }
+    __syncthreads();
+    const int nbu = basis_used(S);
+    const int nk = a.sp_cnt[rhs];
+    if ((int)threadIdx.x < nk) {
+        const long e = a.sp_idx[(size_t)rhs * a.sp_max + threadIdx.x];
+        double2 r0 = d2(0, 0);
+        for (int b = 0; b < nbu; ++b) r0 = cfma(c_r[b], bvec(a, b, rhs, e), r0);
+        rk[threadIdx.x] = r0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double p0 = 0.0, p1 = 0.0;
+        for (int k = 0; k < nk; ++k) {
+            const double2 t = a.sp_val[(size_t)rhs * a.sp_max + k], o = rk[k];
+            p0 += t.x * o.x + t.y * o.y;
+            p1 += t.x * o.y - t.y * o.x;
+        }
+        const double2 rho0 = cneg(cmul(S.omega, S.rho0));
+        a.seed_w[rhs].spec_rho1 = d2(p0, p1);
+        a.seed_w[rhs].beta_spec = cdiv(cmul(S.alpha, d2(p0, p1)), rho0);
+    }
 }
 
 // Replay of the double pass in basis form: r_0 and u_0 after the outer

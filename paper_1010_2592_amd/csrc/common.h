@@ -252,7 +252,16 @@ struct SeedState {
     // basis form (MSB_SEED_BASIS): this BiCG step's exhaustion test needs
     // ||r_0||, formed from the basis (set by the necessary-condition check)
     int exh_check;
+    // basis form with a sparse r~: the first direction update of the next
+    // outer iteration, u_0 = r_0 - beta u_0, made by the MR update with the
+    // beta it computed (beta_spec); wu_ready: the next step 0 found the same
+    // beta, so its own direction update is left out
+    double2 beta_spec;
+    double2 spec_rho1;   // <r~, r_0> after the MR step, from the list's entries
+    int wu_ready;
 };
+// at most this many nonzero entries of r~ for the index-list inner products
+constexpr int SPARSE_MAX = 16;
 
 // Basis form of the seed (MSB_SEED_BASIS): the outer iteration's vectors as
 // coefficients on its basis B_0 = r_0, B_1 = u_0 at the start of the

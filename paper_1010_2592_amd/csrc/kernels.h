@@ -190,6 +190,15 @@ struct BasisArgs {
     C<T> *U0 = nullptr;
     long r0_rs = 0, u0_rs = 0;
     const C<T> *rt = nullptr;
+    // MR update with a sparse r~ (wu set): <r~, r_0> from r_0 at the list's
+    // entries (into rows 0, 1), the next outer iteration's beta from it
+    // (seed_w[rhs].beta_spec) and u_0 = r_0 - beta u_0 into wu ([rhs][n])
+    C<T> *wu = nullptr;
+    SeedState *seed_w = nullptr;
+    const long *sp_idx = nullptr;     // [rhs][sp_max]
+    const double2 *sp_val = nullptr;  // [rhs][sp_max]
+    const int *sp_cnt = nullptr;      // [rhs], at most SPARSE_MAX
+    int sp_max = 0;
 };
 void launch_basis_axpy(hipStream_t, const BasisArgs<double> &, int nrhs, int nblk);
 // replay of the double pass in basis form: r_0, u_0 after outer iteration
@@ -199,6 +208,9 @@ void launch_basis_combine(hipStream_t, const BasisArgs<double> &, int nrhs, int 
 void launch_basis_r0norm(hipStream_t, const BasisArgs<double> &, int nrhs, int nblk);
 void launch_basis_gram(hipStream_t, const BasisArgs<double> &, int nrhs, int nblk);
 void launch_basis_mr_update(hipStream_t, const BasisArgs<double> &, int nrhs, int nblk);
+// sparse r~: <r~, r_0> after the MR step and the next iteration's beta, from
+// the basis before the MR update (one block per right-hand side)
+void launch_basis_spec(hipStream_t, const BasisArgs<double> &, int nrhs);
 
 // mode: 0 u_0..u_j, 1 u_j only, 2 u_0..u_{j-1} (see seed_u_body)
 template <typename T> void launch_seed_u(hipStream_t, const VecArgs<T> &, int j, int nrhs, int nblk, int mode = 0);
@@ -306,6 +318,7 @@ struct ScalarArgs {
     int shadow = 0;                 // init: ||r~|| from partial row 5 (r~ other than b)
     // basis form (MSB_SEED_BASIS)
     int basis = 0;
+    int spec = 0;                   // the MR update forms the next u_0 update (sparse r~)
     double norm_a = 0;              // an upper bound of ||S|| (2-norm)
     SeedBasis *sb = nullptr;        // [rhs]
 };

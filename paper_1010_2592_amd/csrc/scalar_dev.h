@@ -57,6 +57,8 @@ __device__ __forceinline__ void sc_init_body(const ScalarArgs &a, int rhs) {
         S.mv = S.dots = S.axpys = S.reliable = 0;
         S.rel = 0;
         S.rmax = S.bnorm;
+        S.beta_spec = d2(NAN, NAN);
+        S.wu_ready = 0;
         for (int i = 0; i < LMAX; ++i) S.step_flag[i] = 0;
         S.nact = 0;
         for (int s = 0; s < S.nshift; ++s) {
@@ -87,6 +89,7 @@ __device__ __forceinline__ void sc_beta_body(const ScalarArgs &a, int rhs) {
     double r02 = 0.0;
     if (j >= 1) r02 = block_sum(row + 3 * a.ps, a.nblk2);
     if (threadIdx.x != 0) return;
+    if (j == 0) S.wu_ready = 0;
     // basis form: ||r_0|| exists only where sc_exh found that the test could
     // fire; elsewhere it cannot (||r_0|| >= ||r_{j-1}|| / ||S||^(j-1))
     const bool have_r0 = !a.basis || S.exh_check;
@@ -119,6 +122,11 @@ __device__ __forceinline__ void sc_beta_body(const ScalarArgs &a, int rhs) {
         return;
     }
     const double2 beta = cdiv(cmul(S.alpha, rho1), S.rho0);
+    if (j == 0 && a.spec) {
+        // the MR update already made u_0 = r_0 - beta u_0 with this beta
+        S.wu_ready = (beta.x == S.beta_spec.x && beta.y == S.beta_spec.y) ? 1 : 0;
+        S.beta_spec = d2(NAN, NAN);
+    }
     S.rho0 = rho1;
     S.beta = beta;
     S.step_beta[j] = beta;

@@ -725,6 +725,12 @@ struct Emit {
             launch_basis_mr_update(st, a, nrhs, nblk);
         }
     }
+    void basis_spec(const BasisArgs<double> &a, int nrhs) {
+        if (launching(CL_SCALAR, 0.0)) {
+            Prof p(c, CL_SCALAR, 0);
+            launch_basis_spec(st, a, nrhs);
+        }
+    }
     void basis_combine(const BasisArgs<double> &a, int nrhs, int nblk, int cls, double bytes) {
         if (launching(cls, bytes)) {
             Prof p(c, cls, bytes);
@@ -844,7 +850,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     const bool deferred = pass1 && P.deferred;
     const int nb = 2 * l + 2;                  // deferred: basis vectors per outer iteration
     const int wslots = deferred ? 1 : l + 1;   // shift vectors kept per shift
-    constexpr int SPMAX = 16;                  // sparse shadow residual: entries per rhs
+    constexpr int SPMAX = SPARSE_MAX;          // sparse shadow residual: entries per rhs
     constexpr int NBL = 256;                   // blocks of its scan
     CHK(ensure(c, c->ws_R, (size_t)nrhs * (l + 1) * n * cs));
     CHK(ensure(c, c->ws_U, (size_t)nrhs * (l + 1) * n * cs));
@@ -1045,6 +1051,7 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         for (int r = 0; r < nrhs; ++r)
             s0 = std::max(s0, std::fabs(*std::min_element(&P.shifts[(size_t)r * ns], &P.shifts[(size_t)r * ns] + ns)));
         sa.basis = 1;
+        sa.spec = sparse_rt ? 1 : 0;
         sa.norm_a = (P.op_wilson ? P.a_scale * dn : P.a_scale * dn * dn) + s0;
         sa.sb = (SeedBasis *)c->ws_sb.p;
     }
@@ -1269,9 +1276,16 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                     e.scalar(OP_SC_BETA, s, nrhs);
                     const int xi = (j == 0) ? 0 : 2 * j + 1;   // r_j before this step
                     const int yi = (j == 0) ? 1 : 2 * j;       // u_j before this step
-                    // u_j = r_j - beta u_j
+                    // u_j = r_j - beta u_j (at j = 0 made by the previous MR
+                    // update where its beta was this step's)
                     BasisArgs<double> bu = ba;
                     bu.gate = g_bicg;
+                    if (j == 0 && sa.spec) {
+                        bu.gate.flag = &seed[0].wu_ready;
+                        bu.gate.flag_stride = (long)sizeof(SeedState) / (long)sizeof(int);
+                        bu.gate.need = 0;
+                        bu.gate.eq = 1;
+                    }
                     bu.dst = WU;
                     bu.dst_rs = n;
                     bu.x = ba.bv[xi];
@@ -1279,7 +1293,8 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                     bu.y = ba.bv[yi];
                     bu.y_rs = ba.brs[yi];
                     bu.c = va.beta;
-                    e.basis_axpy(bu, nrhs, nbv, CL_SEED, nr_run * 3.0 * nd * cB);
+                    const bool made = j == 0 && sa.spec && m > 0;   // left out (unless the betas differ)
+                    e.basis_axpy(bu, nrhs, nbv, CL_SEED, made ? 0.0 : nr_run * 3.0 * nd * cB);
                     // u_{j+1} = S u_j into B_{2+2j}
                     DslashArgs<T> f1 = d1, f2 = d2;
                     f1.in = WU;
@@ -1337,9 +1352,23 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
                 bm.U0 = Uv;
                 bm.u0_rs = vs;
                 bm.rt = sparse_rt ? nullptr : rt;
-                e.basis_mr_update(bm, nrhs, nbv, CL_SEED,
-                                  nr_run * (2.0 * l + 4 + (sparse_rt ? 0 : 1)) * nd * cB);
-                if (sparse_rt) sparse_dot_of(e, R, g_run, nr_run, vs);
+                if (sa.spec) {
+                    // with the sparse r~: <r~, r_0> and the next outer
+                    // iteration's beta from the basis before the MR update
+                    // overwrites r_0 and u_0, then the update also makes that
+                    // iteration's first direction update
+                    bm.seed_w = seed;
+                    bm.sp_idx = spa.idx;
+                    bm.sp_val = spa.val;
+                    bm.sp_cnt = spa.cnt;
+                    bm.sp_max = spa.spmax;
+                    e.basis_spec(bm, nrhs);
+                    bm.wu = WU;
+                }
+                // 2l + 2 basis vectors read, r_0 and u_0 written, and r~ read
+                // (dense) or the next u_0 update written (sparse)
+                e.basis_mr_update(bm, nrhs, nbv, CL_SEED, nr_run * (2.0 * l + 5) * nd * cB);
+                if (sparse_rt && !sa.spec) sparse_dot_of(e, R, g_run, nr_run, vs);
                 if (deferred) {
                     // every shift's update over the iteration from the basis
                     // (B_0, B_1 from the snapshot: the MR update has just
