@@ -256,7 +256,8 @@ int mshift_bicgstabl(msb_ctx *ctx, double a_scale, int n_shift,
  * grow the context's own workspace.
  *   pass   1 or 2 (the pseudo-double pass keeps a store that grows with the
  *          iteration count, so it is not offered here)
- *   flags  those of mshift_bicgstabl except MSB_PERSISTENT and MSB_REFINE
+ *   flags  those of mshift_bicgstabl except MSB_PERSISTENT, MSB_REFINE and
+ *          MSB_SEED_BASIS
  * Returns MSB_ERR_ARG, before anything is queued, when the workspace would
  * exceed the array.  With c = 16 bytes (8 with MSB_MIXED) and n = 12 V it
  * is about nrhs * n * c * (2 l + 3) for the seed (+ 3 * 16 n per rhs with
