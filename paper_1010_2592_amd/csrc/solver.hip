@@ -1040,13 +1040,15 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
     sa.shadow = P.shadow ? 1 : 0;
     if (basis) {
         // ||S|| <= a ||D||^2 + max |sigma0| (a ||D|| + ... for A = a D), with
-        // ||D|| <= |4 + m| + L (3 sqrt(2) + sqrt(2 cosh(2 mu))), L the links'
-        // norm bound: the hops along nu are P- A + P+ B with orthogonal spin
-        // projectors P-+ = (1 -+ gamma_nu) / 2 and A, B a link times a shift
-        // (||A||, ||B|| <= L, scaled by exp(+-mu) in time), so
-        // ||(P- A + P+ B) v||^2 = ||P- A v||^2 + ||P+ B v||^2 <= (||A||^2 + ||B||^2) ||v||^2
-        const double dn = std::fabs(4.0 + c->mass) +
-                          c->link_norm * (3.0 * std::sqrt(2.0) + std::sqrt(2.0 * std::cosh(2.0 * c->mu)));
+        // ||D|| <= |4 + m| + L (3 + exp|mu|), L the links' norm bound: the
+        // hops along nu are P- A + P+ B with orthogonal spin projectors
+        // P-+ = (1 -+ gamma_nu) / 2 and A, B a link times a shift, which act
+        // on colour and site and so commute with them; hence
+        // ||(P- A + P+ B) v||^2 = ||A P- v||^2 + ||B P+ v||^2
+        //                       <= L^2 (||P- v||^2 + ||P+ v||^2) = L^2 ||v||^2,
+        // with A, B scaled by exp(+-mu) in time (the free field reaches the
+        // bound: |4 + m| + 4 at momentum pi in every direction, mu = 0)
+        const double dn = std::fabs(4.0 + c->mass) + c->link_norm * (3.0 + std::exp(std::fabs(c->mu)));
         double s0 = 0.0;
         for (int r = 0; r < nrhs; ++r)
             s0 = std::max(s0, std::fabs(*std::min_element(&P.shifts[(size_t)r * ns], &P.shifts[(size_t)r * ns] + ns)));
