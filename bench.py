@@ -269,8 +269,9 @@ def deflation_block(wk, U, b, sig, w, l, with_cpu=True):
 
 def config4_block():
     """The 24^3x48 configuration (one Gaussian source, N_s = 58, tol 1e-8,
-    mu = 0.05): every FP64 form for l = 2 and 6, each in a context of its own
-    (one warm-up, then one timed solve), with the vectors each form holds."""
+    mu = 0.05): every FP64 form for l = 2 and 6 (the seed in explicit and in
+    basis form), each in a context of its own (one warm-up, then one timed
+    solve), with the vectors each form holds."""
     import numpy as np
     import torch
 
@@ -289,8 +290,10 @@ def config4_block():
     a = 1.0 / (1.01 * rho)
     out, ref = {}, {}
     for l in wk.ells:
-        for name, pass_, flags in (("1pass", 1, 0), ("1pass-deferred", 1, msb.DEFERRED), ("2pass", 2, 0),
-                                   ("3pass", 3, 0)):
+        for name, pass_, flags in (("1pass", 1, 0), ("1pass-deferred", 1, msb.DEFERRED),
+                                   ("1pass-deferred-basis", 1, msb.DEFERRED | msb.SEED_BASIS), ("2pass", 2, 0),
+                                   ("2pass-basis", 2, msb.SEED_BASIS), ("3pass", 3, 0),
+                                   ("3pass-basis", 3, msb.SEED_BASIS)):
             ctx = msb.Context(msb.Lattice(wk.dims, wk.mass, wk.mu, wk.bc_t), U)
             times = []
             for rep in range(2):
@@ -303,8 +306,10 @@ def config4_block():
                 torch.cuda.synchronize()
                 times.append(e0.elapsed_time(e1))
             M = info.outer_iters
-            held = {"1pass": wk.n_shift * (l + 1), "1pass-deferred": wk.n_shift + 2 * l + 2, "2pass": 0,
-                    "3pass": 2 * M * l}[name]
+            # vectors beyond the seed's (the basis form adds its two work vectors)
+            held = {"1pass": wk.n_shift * (l + 1), "1pass-deferred": wk.n_shift + 2 * l + 2,
+                    "1pass-deferred-basis": wk.n_shift + 2 * l + 4, "2pass": 0, "2pass-basis": 2,
+                    "3pass": 2 * M * l, "3pass-basis": 2 * M * l + 2}[name]
             key = f"l{l}-{name}"
             if l not in ref:
                 ref[l] = y

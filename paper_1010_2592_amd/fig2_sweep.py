@@ -13,7 +13,8 @@ Gaussian source, Neuberger poles for each N_s, a = 1 / (1.01 rho) from the
 library's power iteration.  Times: HIP events around each call on the
 context's stream, median of --reps runs after one warm-up run.  Forms:
 1-pass (the paper's per-step shift updates), 1-pass deferred, 2-pass,
-3-pass (pseudo-double).  Output: one line per measurement as it finishes, a
+3-pass (pseudo-double), and the last three with the seed's BiCG steps in
+basis form (MSB_SEED_BASIS).  Output: one line per measurement as it finishes, a
 markdown table at the end, and the raw numbers as JSON with --json.
 """
 from __future__ import annotations
@@ -30,7 +31,8 @@ if ROOT not in sys.path:
 
 
 FORMS = (("1-pass", 1, "plain"), ("1-pass deferred", 1, "deferred"), ("2-pass", 2, "plain"),
-         ("3-pass", 3, "plain"))
+         ("3-pass", 3, "plain"), ("1-pass deferred basis", 1, "deferred basis"), ("2-pass basis", 2, "basis"),
+         ("3-pass basis", 3, "basis"))
 
 
 def sweep(dims, ml, ls, ns_list, reps, log=print):
@@ -58,7 +60,8 @@ def sweep(dims, ml, ls, ns_list, reps, log=print):
             sig, w = msb.neuberger_pfe(ns)
             force = np.full(ns, M, dtype=np.int32)
             for name, pass_, kind in FORMS:
-                flags = msb.DEFERRED if kind == "deferred" else 0
+                flags = (msb.DEFERRED if kind.startswith("deferred") else 0) | \
+                    (msb.SEED_BASIS if kind.endswith("basis") else 0)
                 times = []
                 for r in range(reps + 1):
                     torch.cuda.synchronize()
