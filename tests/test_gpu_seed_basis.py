@@ -92,6 +92,56 @@ def test_basis_batch_with_shift_sets_matches_explicit(pass_):
             assert d <= max(bound, 10 * wk.tol)
 
 
+def test_basis_batched_shift_sets_forced_matches_oracle():
+    """Three right-hand sides, rhs 1 with a padded 6-pole set, each forced to
+    the oracle's freeze iterations: passes 2 and 3 in basis form against the
+    oracle's iteration of every right-hand side."""
+    from paper_1010_2592_amd import msb
+    wk, U, op, a, sig, w, b = problem("4x4x4x8")
+    bb = wl.gaussian_source(wk.dims, 77, 3)
+    s2, w2 = pfe.neuberger(6)
+    sets_s = np.zeros((3, 10))
+    sets_w = np.zeros((3, 10))
+    sets_s[0], sets_w[0] = sig, w
+    sets_s[2], sets_w[2] = sig, w
+    sets_s[1, :6], sets_w[1, :6] = s2, w2
+    sets_s[1, 6:], sets_w[1, 6:] = s2[-1] * 2, 0.0
+    refs, iters = [], []
+    for r in range(3):
+        yr, ir, _ = oracle_run(op, a, bb[r], sets_s[r], sets_w[r], 2, wk.tol, 2000, 1)
+        refs.append(yr)
+        iters.append(ir.shift_iters)
+    ctx = ctx_for(wk, U)
+    for pass_ in (2, 3):
+        y, info, _ = ctx.mshift_bicgstabl(cuda(bb), a, sets_s, sets_w, 2, wk.tol, 2000, pass_,
+                                          flags=msb.SEED_BASIS, force_iters=np.stack(iters))
+        for r in range(3):
+            d = rel(host(y)[r], refs[r])
+            log(f"  shift sets, pass {pass_}, rhs {r}: {d:.2e}")
+            assert d <= 1e-10, (pass_, r)
+
+
+@pytest.mark.parametrize("l", [2, 4])
+def test_basis_point_sources_forced_matches_oracle(l):
+    """Point sources (r~ = b with one nonzero entry: the sparse list, with
+    which the MR update also makes the next outer iteration's first
+    direction update), each forced to the oracle's freeze iterations, pass 3
+    in basis form against the oracle's iteration at its parity bound."""
+    from paper_1010_2592_amd import msb
+    wk, U, op, a, sig, w, b = problem("4x4x4x8")
+    ps = wl.point_sources(wk.dims)[[0, 7]]
+    ctx = ctx_for(wk, U)
+    for k in range(2):
+        y1, i1, _ = oracle_run(op, a, ps[k], sig, w, l, wk.tol, 2000, 1)
+        bound = parity_bound(op, a, ps[k], sig, w, l, wk.tol, i1.shift_iters, y1)
+        y, info, _ = ctx.mshift_bicgstabl(cuda(ps[k:k + 1]), a, sig, w, l, wk.tol, 2000, 3, flags=msb.SEED_BASIS,
+                                          force_iters=i1.shift_iters)
+        d = rel(host(y)[0], y1)
+        log(f"  point source {k}, l={l}: {d:.2e} (bound {bound:.1e}), M {info.outer_iters}")
+        assert np.array_equal(info.shift_iters[0], i1.shift_iters)
+        assert d <= bound, k
+
+
 def test_basis_production_lattice_fixed_iterations():
     """16^3x32 (one of the 12 point sources), 2 forced outer iterations of
     l = 4, N_s = 30: the basis form against the oracle's iteration."""
