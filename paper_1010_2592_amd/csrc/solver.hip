@@ -979,8 +979,14 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         Prof p(c, CL_OTHER, nrhs * nd * cB * (2.0 * (l + 1) + (pass1 ? ns * (double)wslots : 0.0)) +
                                 (pass1 ? nrhs * nd * ns * 16.0 : 0.0) + (mixed ? nrhs * nd * 16.0 : 0.0) +
                                 nrhs * nd * (16.0 + cB) + nrhs * nd * cB);
-        launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
-        launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
+        if (basis) {
+            // the basis form reads rows 1..l of R and U only where a step of
+            // the current outer iteration wrote them: u_0 = 0 is all it needs
+            launch_zero<T>(st, Uv, n, vs, nrhs);
+        } else {
+            launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
+            launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
+        }
         if (pass1) {
             launch_zero<T>(st, W, (long)nrhs * ns * wslots * n, 0, 1);
             launch_zero<double>(st, X, (long)nrhs * ns * n, 0, 1);
@@ -1649,8 +1655,12 @@ static int solve_impl(Ctx *c, const SolveParams &P, const double2 *b, double2 *y
         // regenerate the Mv outputs of outer iterations m_rep.. and accumulate y
         if (m_rep == 0) {
             Prof p(c, CL_OTHER, nrhs * nd * (2.0 * (l + 1) * cB + 16.0 + cB + 32.0));
-            launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
-            launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
+            if (basis) {
+                launch_zero<T>(st, Uv, n, vs, nrhs);   // as at the start of the first pass
+            } else {
+                launch_zero<T>(st, R, (long)nrhs * (l + 1) * n, 0, 1);
+                launch_zero<T>(st, Uv, (long)nrhs * (l + 1) * n, 0, 1);
+            }
             launch_convert_in<T>(st, R, b, n, vs, n, nrhs);
             if (!pass3) launch_yinit(st, y, b, (const double2 *)c->ws_cb.p, n, nrhs, nbv);
             if (mixed) launch_zero<double>(st, XH, (long)nrhs * n, 0, 1);
